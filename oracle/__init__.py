@@ -1,0 +1,113 @@
+"""CPU oracle for the EBIT interface step (TEST INFRASTRUCTURE ONLY).
+
+A plain, slow, single-threaded FP64 implementation of what the GPU path
+computes, written from Pan et al., arXiv 2309.00338 (Sec. 2.1-2.5). Only the
+tests, the smoke check and the benchmark's CPU-baseline leg may import it; the
+product library never does, and it shares no source with the product.
+
+Every function below updates or reads numpy arrays laid out exactly as the
+library's host state (row-major, x fastest). Parity unpinned parts are listed
+in the test-suite docstrings where each pin lives.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from .build import LIB, build_oracle
+
+COUNTERS = (
+    "markers", "annihilated", "three_landers", "ties", "fit_fallback", "fit_reject",
+    "parity_fallback", "three_crossings", "cv_set", "cv_conflict", "cv_unresolved",
+    "wall_violation", "invariant_fail", "hf_fail", "interfacial",
+)
+
+OK, ERR_ARG, ERR_CFL, ERR_DOMAIN = 0, 1, 3, 4
+
+_lib = None
+_u8p = ctypes.POINTER(ctypes.c_uint8)
+_f64p = ctypes.POINTER(ctypes.c_double)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build_oracle()
+        lib = ctypes.CDLL(LIB)
+        lib.or_sweep.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _u8p, _u8p, _f64p, _f64p, _f64p,
+                                 _f64p, ctypes.c_double, ctypes.c_int, _i64p]
+        lib.or_step.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _u8p, _u8p, _f64p, _f64p, _f64p,
+                                _f64p, ctypes.c_double, ctypes.c_int64, ctypes.c_int, _i64p]
+        lib.or_fraction.argtypes = [ctypes.c_int, ctypes.c_int, _u8p, _u8p, _f64p, _f64p, _f64p]
+        lib.or_curvature.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _u8p, _f64p, _f64p, _i64p]
+        for f in (lib.or_sweep, lib.or_step, lib.or_fraction, lib.or_curvature):
+            f.restype = ctypes.c_int
+        assert lib.or_counter_count() == len(COUNTERS)
+        _lib = lib
+    return _lib
+
+
+def _p(a, t):
+    assert a.flags.c_contiguous
+    return a.ctypes.data_as(t)
+
+
+def _check(st):
+    assert st.c.dtype == np.uint8 and st.c.shape == (st.ny + 1, st.nx + 1)
+    assert st.cc.dtype == np.uint8 and st.cc.shape == (st.ny, st.nx)
+    assert st.hoff.dtype == np.float64 and st.hoff.shape == (st.ny + 1, st.nx)
+    assert st.voff.dtype == np.float64 and st.voff.shape == (st.ny, st.nx + 1)
+
+
+def new_counters():
+    return np.zeros(len(COUNTERS), np.int64)
+
+
+def counters_dict(arr):
+    return {k: int(v) for k, v in zip(COUNTERS, arr)}
+
+
+def sweep(st, u, v, dt, direction, counters=None):
+    """One 1D sweep in place (direction 0 = x with u, 1 = y with v)."""
+    _check(st)
+    cnt = new_counters() if counters is None else counters
+    u = np.ascontiguousarray(u, np.float64)
+    v = np.ascontiguousarray(v, np.float64)
+    rc = _load().or_sweep(st.nx, st.ny, st.h, _p(st.c, _u8p), _p(st.cc, _u8p), _p(st.hoff, _f64p),
+                          _p(st.voff, _f64p), _p(u, _f64p), _p(v, _f64p), float(dt), int(direction),
+                          _p(cnt, _i64p))
+    return rc, cnt
+
+
+def step(st, u, v, dt, xy_only=False, counters=None):
+    """One time step (two sweeps) in place; advances st.step."""
+    _check(st)
+    cnt = new_counters() if counters is None else counters
+    u = np.ascontiguousarray(u, np.float64)
+    v = np.ascontiguousarray(v, np.float64)
+    rc = _load().or_step(st.nx, st.ny, st.h, _p(st.c, _u8p), _p(st.cc, _u8p), _p(st.hoff, _f64p),
+                         _p(st.voff, _f64p), _p(u, _f64p), _p(v, _f64p), float(dt), int(st.step),
+                         1 if xy_only else 0, _p(cnt, _i64p))
+    st.step += 1
+    return rc, cnt
+
+
+def fraction(st):
+    _check(st)
+    C = np.empty((st.ny, st.nx), np.float64)
+    _load().or_fraction(st.nx, st.ny, _p(st.c, _u8p), _p(st.cc, _u8p), _p(st.hoff, _f64p), _p(st.voff, _f64p),
+                        _p(C, _f64p))
+    return C
+
+
+def curvature(st, C, counters=None):
+    _check(st)
+    cnt = new_counters() if counters is None else counters
+    C = np.ascontiguousarray(C, np.float64)
+    K = np.empty((st.ny, st.nx), np.float64)
+    _load().or_curvature(st.nx, st.ny, st.h, _p(st.c, _u8p), _p(C, _f64p), _p(K, _f64p), _p(cnt, _i64p))
+    return K, cnt
