@@ -1,0 +1,169 @@
+/*
+ * ebit.h: C-ABI of the MI355X (gfx950) EBIT interface step.
+ *
+ * The step is the kinematic part of the Edge-Based Interface Tracking method
+ * of Pan, Long, Chirco, Scardovelli, Popinet and Zaleski (arXiv 2309.00338) on
+ * a uniform 2D grid with four closed walls, in FP64:
+ *   - markers on grid edges advected by explicit Euler with a bilinear
+ *     velocity, one direction at a time (Sec. 2.1, Eq. Eq_marker_dis);
+ *   - unaligned markers re-intersected with the grid lines by the circle fit
+ *     (Sec. 2.2);
+ *   - corner and centre Color Vertices updated (Sec. 2.3);
+ *   - markers removed or merged by the corner colours (Sec. 2.4);
+ *   - volume fraction from markers and Color Vertices, and height-function
+ *     curvature of that fraction (Sec. 2.5).
+ *
+ * Index space. Node (i,j) sits at the integer point (i,j), 0 <= i <= nx,
+ * 0 <= j <= ny; cell (i,j) is [i,i+1] x [j,j+1]. H(i,j) is the edge from node
+ * (i,j) to (i+1,j); its marker sits at (i + hoff, j). V(i,j) joins (i,j) and
+ * (i,j+1); its marker sits at (i, j + voff). A marker exists on an edge iff
+ * the colours of its two end nodes differ (Sec. 2.4); offsets elsewhere are
+ * ignored. Every array is row-major with x fastest:
+ *   node_color (ny+1) x (nx+1) uint8 in {0,1}   (corner Color Vertex)
+ *   cell_color  ny    x  nx    uint8 in {0,1}   (centre Color Vertex)
+ *   hoff       (ny+1) x  nx    double in [0,1]
+ *   voff        ny    x (nx+1) double in [0,1]
+ *   u           ny    x (nx+1) double  x-face velocity at (i, j+1/2)
+ *   v          (ny+1) x  nx    double  y-face velocity at (i+1/2, j)
+ *   C, K        ny    x  nx    double  volume fraction, curvature
+ * Colour 1 is the reference phase. Velocities and K are in physical units
+ * (cell size h); offsets are in cell widths.
+ *
+ * Asynchrony and errors. Every call that takes a handle enqueues its work on
+ * the handle's HIP stream and returns at once; nothing aborts and no C++
+ * exception crosses this boundary. Argument errors are returned immediately.
+ * Errors detected on the device (EBIT_ERR_CFL: some marker would move more
+ * than half a cell in one sweep; EBIT_ERR_DOMAIN: a marker would leave the
+ * grid) are latched and returned by the next ebit_sync, ebit_get_state or
+ * ebit_stats call; the state is then undefined until ebit_set_state.
+ *
+ * Ownership. The caller owns every device buffer (workspace, u, v, C, K) and
+ * keeps the workspace alive until ebit_destroy. The handle owns only a small
+ * host struct. One host thread per handle at a time; handles on different
+ * streams are independent.
+ */
+#ifndef EBIT_H
+#define EBIT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  EBIT_OK = 0,
+  EBIT_ERR_ARG = 1,    /* bad argument (null, size, non-finite, out of range) */
+  EBIT_ERR_STATE = 2,  /* call out of order (e.g. curvature of a stale C) */
+  EBIT_ERR_CFL = 3,    /* a marker displacement exceeded half a cell */
+  EBIT_ERR_DOMAIN = 4, /* a marker would have left the grid */
+  EBIT_ERR_DEVICE = 5, /* a HIP runtime call failed */
+  EBIT_ERR_NOMEM = 6   /* workspace too small / host allocation failed */
+};
+
+/* Sweep order (Sec. 2.1 splits each step into an x and a y sweep; the paper
+ * does not fix their order). ALTERNATE: step n runs x then y when n is even,
+ * y then x when n is odd. XY: always x then y. */
+enum { EBIT_SWEEP_ALTERNATE = 0u, EBIT_SWEEP_XY = 1u };
+
+typedef struct {
+  int32_t nx, ny;  /* cells along x and y, each >= 4 */
+  double h;        /* physical cell size, > 0 */
+  uint32_t flags;  /* EBIT_SWEEP_* */
+} ebit_grid;
+
+/* Host-side state (Sec. 2.1-2.3): corner colours, centre colours and marker
+ * offsets, laid out as in the header comment. Offsets are read only where the
+ * end colours differ and must lie in [0,1] there. */
+typedef struct {
+  const uint8_t *node_color;
+  const uint8_t *cell_color;
+  const double *hoff;
+  const double *voff;
+} ebit_state;
+
+/* Device counters, accumulated since create/set_state/ebit_stats_reset. */
+typedef struct {
+  int64_t markers;         /* markers at the start of each sweep, summed */
+  int64_t annihilated;     /* aligned markers removed by pairing (Sec. 2.4) */
+  int64_t three_landers;   /* edges that received three aligned markers */
+  int64_t ties;            /* decisions within 1e-12 of degenerate */
+  int64_t fit_fallback;    /* unaligned markers placed by the straight line */
+  int64_t fit_reject;      /* circle roots discarded for leaving their edge */
+  int64_t parity_fallback; /* colours and crossings disagree (mid-edge) */
+  int64_t three_crossings; /* new unaligned edges crossed three times */
+  int64_t cv_set;          /* centre CVs set by the aligned-marker rule */
+  int64_t cv_conflict;     /* left and right rules disagreed */
+  int64_t cv_unresolved;   /* 4-marker cells the rule did not reach */
+  int64_t wall_violation;  /* wall-normal motion of a wall marker */
+  int64_t invariant_fail;  /* lander parity differs from the colours */
+  int64_t hf_fail;         /* interfacial cells with no valid height */
+  int64_t interfacial;     /* cells with >= 2 markers seen by curvature */
+} ebit_counters;
+
+typedef struct ebit_handle ebit_handle;
+
+/* Bytes of device workspace a grid needs (both state buffers, tile tables,
+ * lists, counters). Returns EBIT_ERR_ARG for an invalid grid. */
+int ebit_workspace_bytes(const ebit_grid *grid, size_t *bytes);
+
+/* Validate the host state `init`, upload it into the caller's device
+ * workspace `ws_dev` (ws_bytes >= ebit_workspace_bytes) and return a handle
+ * bound to `hip_stream` (a hipStream_t; NULL = default stream). Synchronous
+ * with respect to the host buffers. EBIT_ERR_ARG for a bad grid, a colour not
+ * in {0,1} or an offset outside [0,1] (or non-finite) on a marker edge;
+ * EBIT_ERR_NOMEM if the workspace is too small. */
+int ebit_create(const ebit_grid *grid, const ebit_state *init, void *ws_dev, size_t ws_bytes, void *hip_stream,
+                ebit_handle **out);
+
+/* One time step of Eq. (Eq_marker_dis) with face velocities u_dev, v_dev
+ * (device, layout above) taken at t_n, as two 1D sweeps (Sec. 2.1): aligned
+ * markers move along their line and flip the nodes they cross (Sec. 2.3);
+ * unaligned markers are re-placed on the grid lines by the circle fit
+ * (Sec. 2.2); centre colours follow rules (1)-(5) of Sec. 2.3; markers that
+ * meet on one edge annihilate (Sec. 2.4). dt may be negative (a time factor
+ * of the field may be folded into dt). Asynchronous; CFL/DOMAIN latch. */
+int ebit_advect(ebit_handle *h, const double *u_dev, const double *v_dev, double dt);
+
+/* Volume fraction of colour 1 in every cell (Sec. 2.5: the straight segment
+ * between the cell's markers, the centre CV choosing the pairing of a
+ * four-marker cell). Writes all ny*nx entries of C_dev (device). */
+int ebit_fraction(ebit_handle *h, double *C_dev);
+
+/* Height-function curvature of the fraction C_dev produced by ebit_fraction
+ * on the current state (Sec. 2.5), on a 7x3 stencil oriented by the corner
+ * colours. Writes all ny*nx entries of K_dev: 0 in cells with fewer than two
+ * markers, NaN where no height is valid, else kappa (> 0 for a convex
+ * colour-1 region). EBIT_ERR_STATE if the state advanced since ebit_fraction. */
+int ebit_curvature(ebit_handle *h, const double *C_dev, double *K_dev);
+
+/* ebit_fraction followed by ebit_curvature in one pass (same results). */
+int ebit_fraction_curvature(ebit_handle *h, double *C_dev, double *K_dev);
+
+/* Copy the current state to host buffers (any may be NULL) and the step
+ * counter; waits on the stream and returns a latched device error. */
+int ebit_get_state(ebit_handle *h, uint8_t *node_color, uint8_t *cell_color, double *hoff, double *voff,
+                   int64_t *step);
+
+/* Replace the state (validated as in ebit_create), clear the latched error
+ * and the counters. Synchronous. */
+int ebit_set_state(ebit_handle *h, const ebit_state *state, int64_t step);
+
+/* Read the counters (waits on the stream; returns a latched device error). */
+int ebit_stats(ebit_handle *h, ebit_counters *out);
+int ebit_stats_reset(ebit_handle *h);
+
+/* Wait for the handle's stream; return the latched device error, if any. */
+int ebit_sync(ebit_handle *h);
+
+/* Free the host struct; the workspace stays the caller's. */
+int ebit_destroy(ebit_handle *h);
+
+const char *ebit_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EBIT_H */

@@ -1,0 +1,82 @@
+// Internal definitions shared by the gfx950 kernels and the host runtime.
+#ifndef EBIT_INTERNAL_H
+#define EBIT_INTERNAL_H
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace ebit {
+
+constexpr int TS = 16;             // tile edge in cells
+constexpr double TIE_EPS = 1e-12;  // near-degenerate decision threshold
+
+// counter slots (same order as the public ebit_stats fields)
+enum {
+  C_MARKERS = 0,
+  C_ANNIHILATED,
+  C_THREE_LANDERS,
+  C_TIES,
+  C_FIT_FALLBACK,
+  C_FIT_REJECT,
+  C_PARITY_FALLBACK,
+  C_THREE_CROSSINGS,
+  C_CV_SET,
+  C_CV_CONFLICT,
+  C_CV_UNRESOLVED,
+  C_WALL_VIOLATION,
+  C_INVARIANT_FAIL,
+  C_HF_FAIL,
+  C_INTERFACIAL,
+  NCOUNTERS
+};
+
+enum : uint32_t { ERRBIT_CFL = 1u, ERRBIT_DOMAIN = 2u };
+
+struct SweepParams {
+  int nx, ny, ntx, nty;
+  double lam;
+  const uint8_t *col;
+  const uint8_t *cen;
+  const double *hoff;
+  const double *voff;
+  const double *vel;
+  uint8_t *ncol;
+  uint8_t *ncen;
+  double *nhoff;
+  double *nvoff;
+  const uint32_t *list;
+  const uint32_t *count;
+  uint8_t *has;
+  uint32_t *err;
+  unsigned long long *ctr;
+};
+
+struct FracParams {
+  int nx, ny, ntx, nty;
+  double h;
+  const uint8_t *col;
+  const uint8_t *cen;
+  const double *hoff;
+  const double *voff;
+  const double *Cin;
+  double *Cout;
+  double *Kout;
+  const uint8_t *tinfo;  // per tile: bit 0 near, bit 1 uniform colour
+  int vec;               // rows may use 16-byte stores (even nx, aligned C/K)
+  const uint32_t *list;
+  const uint32_t *count;
+  unsigned long long *ctr;
+};
+
+// launchers (defined with the kernels)
+hipError_t launch_sweep(int dir, const SweepParams &p, int grid, hipStream_t s);
+hipError_t launch_init_has(const uint8_t *col, int nx, int ny, int ntx, int nty, uint8_t *has, uint8_t *nearPrev,
+                           hipStream_t s);
+hipError_t launch_compact(const uint8_t *has, uint8_t *nearPrev, uint8_t *tinfo, const uint8_t *col, int nx, int ntx,
+                          int nty, uint32_t *actList, uint32_t *nearList, uint32_t *counts, int slot, hipStream_t s);
+hipError_t launch_frac_curv(int mode, const FracParams &p, int grid, hipStream_t s);
+
+}  // namespace ebit
+
+#endif

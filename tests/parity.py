@@ -1,0 +1,89 @@
+"""Lockstep GPU-vs-oracle comparison used by the GPU parity tests.
+
+Contract: corner and centre colours (hence marker presence) bit-exact; marker
+offsets within 1e-12 cell widths; C within 1e-12 absolute; curvature within
+1e-10 * max(|kappa_oracle|, 1/(N h)) with NaN in the same cells; counters equal.
+"""
+import numpy as np
+
+import oracle
+
+OFF_TOL = 1e-12
+C_TOL = 1e-12
+K_REL = 1e-10
+
+
+def _first(mask):
+    idx = np.argwhere(mask)
+    return tuple(int(x) for x in idx[0]) if len(idx) else None
+
+
+def compare_state(g, o, where=""):
+    assert g.c.shape == o.c.shape
+    bad = g.c != o.c
+    assert not bad.any(), f"{where}: node colours differ at {bad.sum()} nodes, first (j,i)={_first(bad)}"
+    bad = g.cc != o.cc
+    assert not bad.any(), f"{where}: centre colours differ at {bad.sum()} cells, first (j,i)={_first(bad)}"
+    hp, vp = o.h_present(), o.v_present()
+    dh = np.abs(g.hoff - o.hoff) * hp
+    dv = np.abs(g.voff - o.voff) * vp
+    assert dh.max(initial=0) <= OFF_TOL, f"{where}: hoff max diff {dh.max()} at {_first(dh == dh.max())}"
+    assert dv.max(initial=0) <= OFF_TOL, f"{where}: voff max diff {dv.max()} at {_first(dv == dv.max())}"
+    return float(max(dh.max(initial=0), dv.max(initial=0)))
+
+
+def compare_fields(Cg, Kg, Co, Ko, n, h, where=""):
+    dc = np.abs(Cg - Co)
+    assert dc.max(initial=0) <= C_TOL, f"{where}: C max diff {dc.max()} at {_first(dc == dc.max())}"
+    ng, no = np.isnan(Kg), np.isnan(Ko)
+    assert np.array_equal(ng, no), f"{where}: NaN curvature cells differ, first {_first(ng != no)}"
+    fin = ~no
+    scale = np.maximum(np.abs(Ko[fin]), 1.0 / (n * h))
+    dk = np.abs(Kg[fin] - Ko[fin]) / scale
+    assert dk.max(initial=0) <= K_REL, f"{where}: kappa rel diff {dk.max()}"
+    return float(dc.max(initial=0)), float(dk.max(initial=0))
+
+
+class Lockstep:
+    """Runs the GPU library and the oracle side by side on one workload."""
+
+    def __init__(self, state, u, v, flags=0):
+        import torch
+
+        from paper_2309_00338_amd import ebit
+
+        self.torch = torch
+        self.g = ebit.EbitGrid(state, flags=flags)
+        self.o = state.copy()
+        self.u_h, self.v_h = u, v
+        self.u = torch.from_numpy(np.ascontiguousarray(u)).to("cuda:0")
+        self.v = torch.from_numpy(np.ascontiguousarray(v)).to("cuda:0")
+        self.xy_only = bool(flags & 1)
+        self.ocnt = oracle.new_counters()
+        self.worst = {"off": 0.0, "C": 0.0, "K": 0.0}
+
+    def step(self, dt, check_state=True, check_fields=True, where=""):
+        self.g.advect(self.u, self.v, dt)
+        rc, _ = oracle.step(self.o, self.u_h, self.v_h, dt, xy_only=self.xy_only, counters=self.ocnt)
+        assert rc == oracle.OK, f"{where}: oracle rc {rc}"
+        if check_state:
+            gs = self.g.get_state()
+            assert gs.step == self.o.step
+            self.worst["off"] = max(self.worst["off"], compare_state(gs, self.o, where))
+        if check_fields:
+            self.fields(where)
+
+    def fields(self, where=""):
+        C, K = self.g.fraction_curvature()
+        self.torch.cuda.synchronize()
+        Co = oracle.fraction(self.o)
+        Ko, _ = oracle.curvature(self.o, Co, counters=self.ocnt)
+        dc, dk = compare_fields(C.cpu().numpy(), K.cpu().numpy(), Co, Ko, self.o.nx, self.o.h, where)
+        self.worst["C"] = max(self.worst["C"], dc)
+        self.worst["K"] = max(self.worst["K"], dk)
+
+    def compare_counters(self):
+        gc = self.g.stats()
+        oc = oracle.counters_dict(self.ocnt)
+        assert gc == oc, {k: (gc[k], oc[k]) for k in gc if gc[k] != oc[k]}
+        return gc

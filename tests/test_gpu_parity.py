@@ -1,0 +1,183 @@
+"""GPU parity: the HIP library against the CPU oracle, step by step, through
+the C-ABI (via the thin Python binding), on seeded inputs that span several
+tiles, ragged tails, walls, merges and 4-marker cells."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2309_00338_amd import inputs as I
+from tests.parity import Lockstep, compare_fields, compare_state
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(ls, dts, every=1, fields_every=1):
+    for k, dt in enumerate(dts):
+        ls.step(dt, check_state=(k % every == 0 or k == len(dts) - 1),
+                check_fields=(k % fields_every == 0 or k == len(dts) - 1), where=f"step {k}")
+    return ls.compare_counters()
+
+
+def test_config1_vortex_full_trajectory():
+    """64x64, R = 0.15 at (0.5, 0.75), vortex T = 2, CFL 0.5: all 256 steps."""
+    w = I.single_vortex(64, period=2.0, cfl=0.5)
+    ls = Lockstep(w.state, w.u, w.v)
+    ls.fields("initial")
+    cnt = _run(ls, w.dts)
+    assert cnt["markers"] > 0 and cnt["cv_set"] > 0
+    print("worst", ls.worst, cnt)
+
+
+def test_vortex_T8_topology_changes():
+    w = I.single_vortex(64, period=8.0, cfl=0.5)
+    ls = Lockstep(w.state, w.u, w.v)
+    cnt = _run(ls, w.dts, every=4, fields_every=8)
+    assert cnt["annihilated"] > 0
+    print("worst", ls.worst, cnt)
+
+
+def test_merging_pairs_small():
+    w = I.merging_pairs(n=256, pairs=12, rmin=6.0, rmax=14.0, nsteps=48)
+    ls = Lockstep(w.state, w.u, w.v)
+    cnt = _run(ls, w.dts)
+    assert cnt["annihilated"] > 0
+    print("worst", ls.worst, cnt)
+
+
+def test_cosine_interface_touching_walls():
+    w = I.cosine_interface(n=128, nsteps=48)
+    ls = Lockstep(w.state, w.u, w.v)
+    cnt = _run(ls, w.dts)
+    print("worst", ls.worst, cnt)
+
+
+def test_many_circles_small():
+    w = I.many_circles(n=512, count=150, rmin=3.0, rmax=16.0, period=4.0, nsteps=24)
+    ls = Lockstep(w.state, w.u, w.v)
+    _run(ls, w.dts, every=3, fields_every=3)
+
+
+@pytest.mark.parametrize("nx,ny", [(37, 53), (53, 19), (16, 16), (4, 4), (17, 33)])
+def test_ragged_rectangular_grids(nx, ny):
+    rng = np.random.Generator(np.random.PCG64(nx * 1000 + ny))
+    shapes = []
+    if min(nx, ny) >= 12:
+        r = 0.3 * min(nx, ny)
+        shapes.append(I.Ellipse(nx / 2 + rng.uniform(-1, 1), ny / 2 + rng.uniform(-1, 1), r, 0.7 * r, 0.4))
+    else:
+        shapes.append(I.Circle(nx / 2 + 0.13, ny / 2 - 0.21, 1.3))
+    st = I.init_state(nx, ny, shapes, h=1.0 / max(nx, ny))
+    n = max(nx, ny)
+    # vortex-like divergence-free field on the rectangle from a node stream function
+    x = np.arange(nx + 1) / nx
+    y = np.arange(ny + 1) / ny
+    psi = (np.sin(np.pi * x)[None, :] ** 2) * (np.sin(np.pi * y)[:, None] ** 2) / np.pi
+    psi[0, :] = psi[-1, :] = 0.0
+    psi[:, 0] = psi[:, -1] = 0.0
+    u, v = I.faces_from_psi(psi, st.h)
+    umax = max(np.abs(u).max(), np.abs(v).max(), 1e-30)
+    dt = 0.45 * st.h / umax
+    ls = Lockstep(st, u, v)
+    ls.fields("initial")
+    _run(ls, [dt * math.cos(0.05 * k) for k in range(40)])
+
+
+def test_ellipses_instance():
+    rng = np.random.Generator(np.random.PCG64(44))
+    st, u, v, dts = I.random_instance(rng, 96, 6, steps=60)
+    ls = Lockstep(st, u, v)
+    _run(ls, dts, every=2, fields_every=2)
+
+
+def test_empty_grid_and_full_grid():
+    for fill in (0, 1):
+        st = I.init_state(40, 24, [])
+        st.c[:] = fill
+        st.cc[:] = fill
+        w_u, w_v = I.uniform_faces(40, 24, 0.3, -0.2)
+        ls = Lockstep(st, w_u, w_v)
+        ls.fields("initial")
+        _run(ls, [0.01] * 4)
+
+
+def test_xy_flag_fixed_sweep_order():
+    w = I.single_vortex(48, period=2.0, cfl=0.5)
+    ls = Lockstep(w.state, w.u, w.v, flags=1)
+    _run(ls, w.dts[:60])
+
+
+def test_fraction_and_curvature_calls_match_fused():
+    w = I.single_vortex(64, period=2.0, cfl=0.5)
+    ls = Lockstep(w.state, w.u, w.v)
+    for dt in w.dts[:40]:
+        ls.g.advect(ls.u, ls.v, dt)
+    C1, K1 = ls.g.fraction_curvature()
+    C2 = ls.g.fraction()
+    K2 = ls.g.curvature(C2)
+    assert ls.torch.equal(C1, C2)
+    assert ls.torch.equal(K1.nan_to_num(7.0), K2.nan_to_num(7.0))
+    ls.g.advect(ls.u, ls.v, w.dts[40])
+    from paper_2309_00338_amd import ebit
+
+    with pytest.raises(ebit.EbitError) as e:
+        ls.g.curvature(C2)
+    assert e.value.code == ebit.EBIT_ERR_STATE
+
+
+def test_checkpoint_resume_is_exact():
+    w = I.single_vortex(64, period=2.0, cfl=0.5)
+    from paper_2309_00338_amd import ebit
+
+    import torch
+
+    u = torch.from_numpy(w.u).cuda()
+    v = torch.from_numpy(w.v).cuda()
+    a = ebit.EbitGrid(w.state)
+    for dt in w.dts[:30]:
+        a.advect(u, v, dt)
+    snap = a.get_state()
+    for dt in w.dts[30:60]:
+        a.advect(u, v, dt)
+    end_a = a.get_state()
+    b = ebit.EbitGrid(w.state)
+    b.set_state(snap)
+    for dt in w.dts[30:60]:
+        b.advect(u, v, dt)
+    end_b = b.get_state()
+    assert end_a.step == end_b.step == 60
+    assert np.array_equal(end_a.c, end_b.c) and np.array_equal(end_a.cc, end_b.cc)
+    hp, vp = end_a.h_present(), end_a.v_present()
+    assert np.array_equal(end_a.hoff[hp], end_b.hoff[hp]) and np.array_equal(end_a.voff[vp], end_b.voff[vp])
+
+
+def test_cfl_and_domain_errors_latch():
+    from paper_2309_00338_amd import ebit
+
+    import torch
+
+    w = I.single_vortex(32)
+    g = ebit.EbitGrid(w.state)
+    u = torch.from_numpy(w.u).cuda()
+    v = torch.from_numpy(w.v).cuda()
+    g.advect(u, v, 1.2 / 32)  # |d| up to 1.2 cells: latched, kernels finish
+    with pytest.raises(ebit.EbitError) as e:
+        g.sync()
+    assert e.value.code == ebit.EBIT_ERR_CFL
+    g.set_state(w.state)
+    g.sync()
+    st = I.init_state(16, 16, [I.Circle(1.9, 8.2, 1.5)])
+    g2 = ebit.EbitGrid(st, flags=1)
+    uu, vv = I.uniform_faces(16, 16, -0.45, 0.0)  # 0.45 cells per sweep
+    uu = torch.from_numpy(uu).cuda()
+    vv = torch.from_numpy(vv).cuda()
+    code = 0
+    for _ in range(6):
+        g2.advect(uu, vv, 1.0 / 16)
+        try:
+            g2.sync()
+        except ebit.EbitError as ex:
+            code = ex.code
+            break
+    assert code == ebit.EBIT_ERR_DOMAIN

@@ -529,7 +529,7 @@ def test_cfl_violation_is_reported():
 def test_domain_exit_is_reported():
     n = 16
     st = I.init_state(n, n, [I.Circle(1.9, 8.2, 1.5)])
-    u, v = I.uniform_faces(n, n, -0.45 * n, 0.0)
+    u, v = I.uniform_faces(n, n, -0.45, 0.0)  # 0.45 cells per sweep
     rc = oracle.OK
     for _ in range(6):
         rc, _ = oracle.step(st, u, v, 1.0 / n, xy_only=True)
