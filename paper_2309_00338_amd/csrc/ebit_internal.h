@@ -28,6 +28,9 @@ enum {
   C_INVARIANT_FAIL,
   C_HF_FAIL,
   C_INTERFACIAL,
+  C_TILES_SWEPT,   // diagnostics of the tiled schedule (no oracle counterpart)
+  C_TILES_EMPTY,
+  C_TILES_NEAR,
   NCOUNTERS
 };
 
@@ -47,7 +50,7 @@ struct SweepParams {
   double *nvoff;
   const uint32_t *list;
   const uint32_t *count;
-  uint8_t *has;
+  uint16_t *has;  // per tile: where its markers sit (any / near a side / near a corner)
   uint32_t *err;
   unsigned long long *ctr;
 };
@@ -64,6 +67,9 @@ struct FracParams {
   double *Kout;
   const uint8_t *tinfo;  // per tile: bit 0 near, bit 1 uniform colour
   int vec;               // rows may use 16-byte stores (even nx, aligned C/K)
+  int tileBlocks;        // workgroups [0, tileBlocks) claim near tiles before rows
+  uint32_t *work;        // this launch's claim counters: [tiles, rows]
+  uint32_t *workNext;    // the next launch's, cleared by this one
   const uint32_t *list;
   const uint32_t *count;
   unsigned long long *ctr;
@@ -71,9 +77,9 @@ struct FracParams {
 
 // launchers (defined with the kernels)
 hipError_t launch_sweep(int dir, const SweepParams &p, int grid, hipStream_t s);
-hipError_t launch_init_has(const uint8_t *col, int nx, int ny, int ntx, int nty, uint8_t *has, uint8_t *nearPrev,
+hipError_t launch_init_has(const uint8_t *col, int nx, int ny, int ntx, int nty, uint16_t *has, uint8_t *nearPrev,
                            hipStream_t s);
-hipError_t launch_compact(const uint8_t *has, uint8_t *nearPrev, uint8_t *tinfo, const uint8_t *col, int nx, int ntx,
+hipError_t launch_compact(const uint16_t *has, uint8_t *nearPrev, uint8_t *tinfo, const uint8_t *col, int nx, int ntx,
                           int nty, uint32_t *actList, uint32_t *nearList, uint32_t *counts, int slot, hipStream_t s);
 hipError_t launch_frac_curv(int mode, const FracParams &p, int grid, hipStream_t s);
 

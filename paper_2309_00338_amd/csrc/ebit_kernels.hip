@@ -3,17 +3,22 @@
 // Layout in HBM (one grid): node colours and centre colours as bytes, marker
 // offsets as FP64 structure-of-arrays (hoff, voff), each twice (ping-pong: a
 // sweep reads one copy and writes the other). The grid is cut into 16x16-cell
-// tiles; a tile "has" markers if one of the edges it owns carries one, and is
-// "near" if it or one of its 8 neighbours has markers. Only tiles near the
-// interface (this sweep or the previous one, so both copies stay coherent) are
-// swept; only near tiles do the polygon/height-function work; all other cells
-// get the tile's uniform colour as C and 0 as curvature in a pure write stream.
+// tiles. Each tile keeps a small mask of where its own markers sit (anywhere,
+// within 3 cells of each side, of each corner); a tile is "near" the
+// interface when it holds markers or a neighbour holds markers close to their
+// shared side or corner. Only tiles that are near in this sweep or were near in
+// the previous one (so both copies stay coherent) are swept; only near tiles
+// do polygon and height-function work; every other cell gets its tile's
+// uniform colour as C and 0 as curvature in a pure write stream.
 //
-// Each output (a node colour, an edge offset, a centre colour) is a function
-// of the old state in a small neighbourhood, so a sweep is a gather: no
-// atomics on state, no ordering between tiles, results independent of the
-// schedule. Every FP64 expression is written in one fixed order and the file
-// is compiled with -ffp-contract=off.
+// A sweep is a gather: each output (node colour, edge offset, centre colour)
+// is a function of the old state within two cells, so there are no atomics on
+// state and no ordering between tiles. A workgroup stages its tile plus a
+// 2-cell halo in LDS (colours, centre colours, advected aligned offsets,
+// unaligned displacements), computes new colours and lander choices, gathers
+// the present new unaligned edges into an LDS work list (so circle fits run on
+// consecutive lanes), then sets the centre colours. Every FP64 expression is
+// written in one fixed order and the file is built with -ffp-contract=off.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -23,136 +28,150 @@ namespace ebit {
 
 __device__ __forceinline__ double lerp(double a, double b, double t) { return a + t * (b - a); }
 
+constexpr int HALO = 2;
+constexpr int NH = TS + 2 * HALO + 1;  // staged nodes per side (21)
+constexpr int NE = NH - 1;             // staged cells / edges per side (20)
+constexpr int NN = TS + 1;             // new nodes per side (17)
+
+// marker-position mask bits of a tile
+enum : uint16_t {
+  M_ANY = 1, M_L = 2, M_R = 4, M_B = 8, M_T = 16, M_LB = 32, M_RB = 64, M_LT = 128, M_RT = 256
+};
+constexpr int STRIP = 3;
+
+// mask bits of a marker whose edge touches the local cells [lx0,lx1] x [ly0,ly1]
+__device__ __forceinline__ uint16_t maskAt(int lx0, int lx1, int ly0, int ly1) {
+  const bool l = lx0 < STRIP, r = lx1 >= TS - STRIP, b = ly0 < STRIP, t = ly1 >= TS - STRIP;
+  uint16_t m = M_ANY;
+  if (l) m |= M_L;
+  if (r) m |= M_R;
+  if (b) m |= M_B;
+  if (t) m |= M_T;
+  if (l && b) m |= M_LB;
+  if (r && b) m |= M_RB;
+  if (l && t) m |= M_LT;
+  if (r && t) m |= M_RT;
+  return m;
+}
+// mask of an H edge (i,j) / V edge (i,j) in the tile with origin (x0,y0)
+__device__ __forceinline__ uint16_t maskH(int i, int j, int x0, int y0) {
+  return maskAt(i - x0, i - x0, j - y0 - 1, j - y0);
+}
+__device__ __forceinline__ uint16_t maskV(int i, int j, int x0, int y0) {
+  return maskAt(i - x0 - 1, i - x0, j - y0, j - y0);
+}
+
 // ---------------------------------------------------------------------------
-// Frame of one sweep: "a" runs along the sweep direction, "b" across it.
-// DIR 0 (x sweep): (a,b) = (i,j), aligned edges are H, unaligned edges are V,
-// the velocity is u. DIR 1 (y sweep): (a,b) = (j,i), aligned V, unaligned H, v.
+// Global-memory index map of one sweep: "a" runs along the sweep direction,
+// "b" across it. DIR 0 (x sweep): (a,b) = (i,j), aligned edges are H,
+// unaligned edges are V, the velocity is u. DIR 1: (a,b) = (j,i), aligned V,
+// unaligned H, velocity v.
 // ---------------------------------------------------------------------------
 template <int DIR>
-struct Frame {
+struct GMap {
   int nx, ny, na, nb;
-  double lam;
-  const uint8_t *__restrict__ col;
-  const uint8_t *__restrict__ cen;
-  const double *__restrict__ alo;  // old aligned offsets
-  const double *__restrict__ uno;  // old unaligned offsets
-  const double *__restrict__ vel;
-
-  __device__ Frame(const SweepParams &p) {
-    nx = p.nx;
-    ny = p.ny;
-    na = DIR == 0 ? p.nx : p.ny;
-    nb = DIR == 0 ? p.ny : p.nx;
-    lam = p.lam;
-    col = p.col;
-    cen = p.cen;
-    alo = DIR == 0 ? p.hoff : p.voff;
-    uno = DIR == 0 ? p.voff : p.hoff;
-    vel = p.vel;
-  }
+  __device__ GMap(int nx_, int ny_) : nx(nx_), ny(ny_), na(DIR == 0 ? nx_ : ny_), nb(DIR == 0 ? ny_ : nx_) {}
   __device__ size_t node(int a, int b) const {
     return DIR == 0 ? (size_t)b * (nx + 1) + a : (size_t)a * (nx + 1) + b;
   }
   __device__ size_t ale(int a, int b) const { return DIR == 0 ? (size_t)b * nx + a : (size_t)a * (nx + 1) + b; }
   __device__ size_t une(int a, int b) const { return DIR == 0 ? (size_t)b * (nx + 1) + a : (size_t)a * nx + b; }
   __device__ size_t cell(int a, int b) const { return DIR == 0 ? (size_t)b * nx + a : (size_t)a * nx + b; }
+};
 
-  __device__ int C(int a, int b) const { return col[node(a, b)]; }
-  // aligned edge (a,b), 0 <= a < na, 0 <= b <= nb
+// ---------------------------------------------------------------------------
+// Tile view over the LDS staging (frame coordinates).
+// ---------------------------------------------------------------------------
+// Old segments of a cell, packed: bits 0-1/2-3 the two edges of segment 0,
+// bits 4-5/6-7 those of segment 1, bits 8-9 the number of segments (edges
+// 0 bottom, 1 right, 2 top, 3 left). Two markers make one segment; four
+// markers make two, each joining the pair around a corner whose colour differs
+// from the centre CV, listed by ascending corner (0 BL, 1 BR, 2 TR, 3 TL).
+__device__ __forceinline__ uint16_t segCodeOf(int k0, int k1, int k2, int k3, int cc) {
+  const bool e0 = k0 != k1, e1 = k1 != k2, e2 = k3 != k2, e3 = k0 != k3;
+  const int n = (int)e0 + (int)e1 + (int)e2 + (int)e3;
+  if (n == 2) {
+    int f = -1, g = -1;
+    if (e0) f = 0;
+    if (e1) { if (f < 0) f = 1; else g = 1; }
+    if (e2) { if (f < 0) f = 2; else g = 2; }
+    if (e3) g = 3;
+    return (uint16_t)(f | (g << 2) | (1 << 8));
+  }
+  if (n == 4) {
+    // isolated corners are either {BL, TR} or {BR, TL}
+    if (k0 != cc) return (uint16_t)(3 | (0 << 2) | (1 << 4) | (2 << 6) | (2 << 8));  // (left,bottom), (right,top)
+    return (uint16_t)(0 | (1 << 2) | (2 << 4) | (3 << 6) | (2 << 8));                // (bottom,right), (top,left)
+  }
+  return 0;
+}
+
+struct Tile {
+  int na, nb, a0, b0;
+  const uint8_t (*col)[NH];   // old node colours   [b][a], a in [a0-2, a0+18]
+  const uint16_t (*seg)[NE];  // old cell segments  [b][a], a in [a0-2, a0+17]
+  const uint8_t (*cen)[NE];   // old centre colours [b][a]
+  const double (*sp)[NE];     // aligned (a,b): s' ; a in [a0-2,a0+17], b in [b0-2,b0+18]
+  const double (*dd)[NH];     // unaligned (a,b): d ; a in [a0-2,a0+18], b in [b0-2,b0+17]
+  const double (*tt)[NH];     // unaligned (a,b): t
+  const uint8_t (*ncol)[NN];  // new node colours, a in [a0, a0+16], b in [b0, b0+16]
+  const int8_t (*keep)[NN + 1];  // kept source - t on new aligned edge (t,b), t in [a0-1,a0+16], b in [b0,b0+16]
+
+  __device__ int C(int a, int b) const { return col[b - b0 + HALO][a - a0 + HALO]; }
   __device__ bool presA(int a, int b) const { return C(a, b) != C(a + 1, b); }
-  // unaligned edge (a,b), 0 <= a <= na, 0 <= b < nb
   __device__ bool presU(int a, int b) const { return C(a, b) != C(a, b + 1); }
+  __device__ double spv(int a, int b) const { return sp[b - b0 + HALO][a - a0 + HALO]; }
+  __device__ double dU(int a, int b) const { return dd[b - b0 + HALO][a - a0 + HALO]; }
+  __device__ double tU(int a, int b) const { return tt[b - b0 + HALO][a - a0 + HALO]; }
+  __device__ int cenv(int p, int q) const { return cen[q - b0 + HALO][p - a0 + HALO]; }
+  __device__ uint16_t segc(int p, int q) const { return seg[q - b0 + HALO][p - a0 + HALO]; }
+  __device__ int newC(int a, int b) const { return ncol[b - b0][a - a0]; }
 
-  // face velocity with ghost rows mirrored across the walls
-  __device__ double V(int a, int r) const {
-    r = r < 0 ? 0 : (r > nb - 1 ? nb - 1 : r);
-    return vel[une(a, r)];
-  }
-  // explicit Euler displacement of an aligned marker, bilinear velocity
-  __device__ double dispA(int a, int b, double s) const {
-    double ub = lerp(lerp(V(a, b - 1), V(a + 1, b - 1), s), lerp(V(a, b), V(a + 1, b), s), 0.5);
-    return ub * lam;
-  }
-  __device__ double sp(int a, int b) const {
-    double s = alo[ale(a, b)];
-    return s + dispA(a, b, s);
-  }
-  // displacement of an unaligned marker (gray point), before the wall rule
-  __device__ double rawDispU(int a, int b) const {
-    double t = uno[une(a, b)];
-    double ub = t < 0.5 ? lerp(V(a, b - 1), V(a, b), t + 0.5) : lerp(V(a, b), V(a, b + 1), t - 0.5);
-    return ub * lam;
-  }
-  __device__ double dispU(int a, int b) const { return (a == 0 || a == na) ? 0.0 : rawDispU(a, b); }
-
-  // new corner colour: flipped by each aligned marker that crosses the node
-  __device__ int newC(int a, int b) const {
+  // new corner colour from the old state: flipped by each aligned marker
+  // that crosses the node
+  __device__ int computeNewC(int a, int b) const {
     int c = C(a, b);
     if (a > 0 && a < na) {
-      if (presA(a - 1, b) && sp(a - 1, b) >= 1.0) c ^= 1;
-      if (presA(a, b) && sp(a, b) < 0.0) c ^= 1;
+      if (presA(a - 1, b) && spv(a - 1, b) >= 1.0) c ^= 1;
+      if (presA(a, b) && spv(a, b) < 0.0) c ^= 1;
     }
     return c;
   }
-
-  // aligned markers landing on edge (a,b); returns their number and the kept
-  // source (-1 when none): one lander is kept, of three the middle source.
-  __device__ int landers(int a, int b, int *keep) const {
-    int src[3];
-    int n = 0;
-    if (a >= 1 && presA(a - 1, b) && sp(a - 1, b) >= 1.0) src[n++] = a - 1;
+  // aligned markers landing on edge (a,b): their number and the kept source
+  // (-1 when none): one lander is kept, of three the middle source
+  __device__ int landers(int a, int b, int *keepSrc) const {
+    int n = 0, first = -1, second = -1;
+    if (a >= 1 && presA(a - 1, b) && spv(a - 1, b) >= 1.0) { first = a - 1; n++; }
     if (presA(a, b)) {
-      double s = sp(a, b);
-      if (s >= 0.0 && s < 1.0) src[n++] = a;
+      const double s = spv(a, b);
+      if (s >= 0.0 && s < 1.0) {
+        if (n == 0) first = a;
+        else second = a;
+        n++;
+      }
     }
-    if (a + 1 < na && presA(a + 1, b) && sp(a + 1, b) < 0.0) src[n++] = a + 1;
-    *keep = n == 1 ? src[0] : (n == 3 ? src[1] : -1);
+    if (a + 1 < na && presA(a + 1, b) && spv(a + 1, b) < 0.0) {
+      if (n == 0) first = a + 1;
+      else if (n == 1) second = a + 1;
+      n++;
+    }
+    *keepSrc = n == 1 ? first : (n == 3 ? second : -1);
     return n;
   }
-  // the edge an aligned marker lands on (-1 if it leaves the grid)
   __device__ int landTarget(int p, int q) const {
-    double s = sp(p, q);
-    int t = s >= 1.0 ? p + 1 : (s < 0.0 ? p - 1 : p);
+    const double s = spv(p, q);
+    const int t = s >= 1.0 ? p + 1 : (s < 0.0 ? p - 1 : p);
     return (t < 0 || t >= na) ? -1 : t;
   }
+  // the aligned marker of old edge (p,q) is the one kept on new edge target
   __device__ bool keptOn(int p, int q, int target) const {
     if (landTarget(p, q) != target) return false;
-    int keep;
-    landers(target, q, &keep);
-    return keep == p;
-  }
-
-  // old segments of cell (p,q): edge pairs (0 bottom, 1 right, 2 top, 3 left)
-  __device__ int segments(int p, int q, int8_t s[4]) const {
-    int k0 = C(p, q), k1 = C(p + 1, q), k2 = C(p + 1, q + 1), k3 = C(p, q + 1);
-    bool e0 = k0 != k1, e1 = k1 != k2, e2 = k3 != k2, e3 = k0 != k3;
-    int n = (int)e0 + (int)e1 + (int)e2 + (int)e3;
-    s[0] = s[1] = s[2] = s[3] = -1;
-    if (n == 2) {
-      int w = 0;
-      if (e0) s[w++] = 0;
-      if (e1) s[w++] = 1;
-      if (e2) s[w++] = 2;
-      if (e3) s[w++] = 3;
-      return 1;
-    }
-    if (n == 4) {
-      int cc = cen[cell(p, q)];
-      int kk[4] = {k0, k1, k2, k3};
-      int w = 0;
-      for (int corner = 0; corner < 4; corner++)
-        if (kk[corner] != cc) {
-          s[w++] = (int8_t)((corner + 3) & 3);
-          s[w++] = (int8_t)corner;
-        }
-      return 2;
-    }
-    return 0;
+    return keep[q - b0][target - a0 + 1] == p - target;
   }
 };
 
 struct MRef {
-  int8_t kind;  // 0 aligned, 1 unaligned
+  int kind;  // 0 aligned, 1 unaligned
   int a, b;
 };
 
@@ -165,39 +184,41 @@ __device__ __forceinline__ MRef edgeMarker(int p, int q, int e) {
   return m;
 }
 
-template <int DIR>
-__device__ __forceinline__ void advPoint(const Frame<DIR> &F, MRef m, int a0, int b0, double *X, double *Y) {
+// advected marker in the frame of node (a0,b0): aligned markers move along
+// their line (blue points), unaligned ones off it (gray points)
+__device__ __forceinline__ void advPoint(const Tile &T, MRef m, int a0, int b0, double *X, double *Y) {
   if (m.kind == 0) {
-    *X = (double)(m.a - a0) + F.sp(m.a, m.b);
+    *X = (double)(m.a - a0) + T.spv(m.a, m.b);
     *Y = (double)(m.b - b0);
   } else {
-    *X = (double)(m.a - a0) + F.dispU(m.a, m.b);
-    *Y = (double)(m.b - b0) + F.uno[F.une(m.a, m.b)];
+    *X = (double)(m.a - a0) + T.dU(m.a, m.b);
+    *Y = (double)(m.b - b0) + T.tU(m.a, m.b);
   }
 }
 
-template <int DIR>
-__device__ __forceinline__ bool leftOf(const Frame<DIR> &F, MRef m, int a0) {
-  if (m.kind == 0) return F.sp(m.a, m.b) < (double)(a0 - m.a);
-  return F.dispU(m.a, m.b) < (double)(a0 - m.a);
+// "left of line a = a0" iff x < a0, decided exactly on the offset
+__device__ __forceinline__ bool leftOf(const Tile &T, MRef m, int a0) {
+  if (m.kind == 0) return T.spv(m.a, m.b) < (double)(a0 - m.a);
+  return T.dU(m.a, m.b) < (double)(a0 - m.a);
 }
 
-// chain neighbour of the marker on edge e of old cell (p,q), away from it
-template <int DIR>
-__device__ bool chainNb(const Frame<DIR> &F, int p, int q, int e, MRef *out) {
+// chain neighbour of the marker on edge e of old cell (p,q), away from it:
+// its partner in the cell across edge e
+__device__ bool chainNb(const Tile &T, int p, int q, int e, MRef *out) {
   int pp = p, qq = q;
   if (e == 0) qq = q - 1;
   else if (e == 1) pp = p + 1;
   else if (e == 2) qq = q + 1;
   else pp = p - 1;
-  if (pp < 0 || pp >= F.na || qq < 0 || qq >= F.nb) return false;
-  int eo = (e + 2) & 3;
-  int8_t s[4];
-  F.segments(pp, qq, s);
-  for (int k = 0; k < 4; k += 2) {
-    if (s[k] < 0) continue;
-    if (s[k] == eo) { *out = edgeMarker(pp, qq, s[k + 1]); return true; }
-    if (s[k + 1] == eo) { *out = edgeMarker(pp, qq, s[k]); return true; }
+  if (pp < 0 || pp >= T.na || qq < 0 || qq >= T.nb) return false;
+  const int eo = (e + 2) & 3;
+  const uint32_t c = T.segc(pp, qq);
+  const int nseg = (c >> 8) & 3;
+  for (int k = 0; k < 2; k++) {
+    if (k >= nseg) break;
+    const int eA = (c >> (4 * k)) & 3, eB = (c >> (4 * k + 2)) & 3;
+    if (eA == eo) { *out = edgeMarker(pp, qq, eB); return true; }
+    if (eB == eo) { *out = edgeMarker(pp, qq, eA); return true; }
   }
   return false;
 }
@@ -207,12 +228,12 @@ __device__ bool chainNb(const Frame<DIR> &F, int p, int q, int e, MRef *out) {
 __device__ bool circleRoot(double Xa, double Ya, double Xb, double Yb, double Xc, double Yc, double Xo, double Yo,
                            double X2, double Y2, double X3, double Y3, double ysl, double *root, uint32_t *ties,
                            uint32_t *rejects) {
-  double Qa = Xa * Xa + Ya * Ya;
-  double Qb = Xb * Xb + Yb * Yb;
-  double Qc = Xc * Xc + Yc * Yc;
-  double ca = Xa * (Yb - Yc) + Xb * (Yc - Ya) + Xc * (Ya - Yb);
-  double cc = Qa * (Xb - Xc) + Qb * (Xc - Xa) + Qc * (Xa - Xb);
-  double ce = -(Qa * (Xb * Yc - Xc * Yb) + Qb * (Xc * Ya - Xa * Yc) + Qc * (Xa * Yb - Xb * Ya));
+  const double Qa = Xa * Xa + Ya * Ya;
+  const double Qb = Xb * Xb + Yb * Yb;
+  const double Qc = Xc * Xc + Yc * Yc;
+  const double ca = Xa * (Yb - Yc) + Xb * (Yc - Ya) + Xc * (Ya - Yb);
+  const double cc = Qa * (Xb - Xc) + Qb * (Xc - Xa) + Qc * (Xa - Xb);
+  const double ce = -(Qa * (Xb * Yc - Xc * Yb) + Qb * (Xc * Ya - Xa * Yc) + Qc * (Xa * Yb - Xb * Ya));
   double r;
   if (ca == 0.0) {
     if (cc == 0.0) return false;
@@ -220,8 +241,8 @@ __device__ bool circleRoot(double Xa, double Ya, double Xb, double Yb, double Xc
   } else {
     double disc = cc * cc - 4.0 * ca * ce;
     if (disc < 0.0) disc = 0.0;
-    double sq = sqrt(disc);
-    double q = -0.5 * (cc + (cc >= 0.0 ? sq : -sq));
+    const double sq = sqrt(disc);
+    const double q = -0.5 * (cc + (cc >= 0.0 ? sq : -sq));
     double r1, r2;
     if (q == 0.0) {
       r1 = 0.0;
@@ -230,14 +251,14 @@ __device__ bool circleRoot(double Xa, double Ya, double Xb, double Yb, double Xc
       r1 = q / ca;
       r2 = ce / q;
     }
-    double DX = X3 - X2, DY = Y3 - Y2;
-    double L2 = DX * DX + DY * DY;
-    double so = DX * (Yo - Y2) - DY * (Xo - X2);
-    double s1 = DX * (r1 - Y2) - DY * (0.0 - X2);
-    double s2 = DX * (r2 - Y2) - DY * (0.0 - X2);
+    const double DX = X3 - X2, DY = Y3 - Y2;
+    const double L2 = DX * DX + DY * DY;
+    const double so = DX * (Yo - Y2) - DY * (Xo - X2);
+    const double s1 = DX * (r1 - Y2) - DY * (0.0 - X2);
+    const double s2 = DX * (r2 - Y2) - DY * (0.0 - X2);
     if (fabs(s1) < TIE_EPS * L2 || fabs(s2) < TIE_EPS * L2) (*ties)++;
-    bool q1 = (s1 > 0.0 && so < 0.0) || (s1 < 0.0 && so > 0.0);
-    bool q2 = (s2 > 0.0 && so < 0.0) || (s2 < 0.0 && so > 0.0);
+    const bool q1 = (s1 > 0.0 && so < 0.0) || (s1 < 0.0 && so > 0.0);
+    const bool q2 = (s2 > 0.0 && so < 0.0) || (s2 < 0.0 && so > 0.0);
     if (q1 && !q2) r = r1;
     else if (q2 && !q1) r = r2;
     else r = (fabs(r1 - ysl) <= fabs(r2 - ysl)) ? r1 : r2;
@@ -257,362 +278,558 @@ __device__ __forceinline__ double chordY(double X2, double Y2, double X3, double
   return y;
 }
 
-// Block-local counters, flushed once per block.
-struct BlockCounters {
-  uint32_t v[NCOUNTERS];
+// Counters of one workgroup, in LDS (events are rare next to the work).
+struct Counts {
+  uint32_t *s;
+  __device__ void add(int k, uint32_t v) const {
+    if (v) atomicAdd(&s[k], v);
+  }
 };
 
-// New unaligned marker on line a (interior), row b: returns 1 and its offset
-// when present; fills the centre-CV results for the cell to the right of the
-// line (cell a) and to its left (cell a-1): -1 or the new centre colour.
-template <int DIR>
-__device__ bool newUnaligned(const Frame<DIR> &F, int a, int b, double *yout, int *resRight, int *resLeft,
-                             uint32_t *cnt, bool count) {
+// New unaligned marker on interior line a, row b (present by the new
+// colours): its offset, and the centre-CV results for the cell right of the
+// line (cell a) and left of it (cell a-1): -1 or the new centre colour.
+__device__ double newUnaligned(const Tile &T, int a, int b, int *resRight, int *resLeft, const Counts &cnt, bool count) {
   *resRight = -1;
   *resLeft = -1;
   uint32_t lties = 0, lrej = 0;
-  int cp[4];
-  int8_t cl[4], cr[4];
-  double X2v[4], Y2v[4], X3v[4], Y3v[4], ysl[4];
-  int nxr = 0;
+  // crossing segments of old cells (a-1,b) then (a,b); the first three kept
+  int ncross = 0;
+  int cp0 = 0, cp1 = 0, cp2 = 0, cl0 = 0, cl1 = 0, cl2 = 0, cr0 = 0, cr1 = 0, cr2 = 0;
+  double ys0 = 0.0, ys1 = 0.0, ys2 = 0.0;
   for (int p = a - 1; p <= a; p++) {
-    int8_t s[4];
-    F.segments(p, b, s);
-    for (int k = 0; k < 4; k += 2) {
-      if (s[k] < 0) continue;
-      MRef m1 = edgeMarker(p, b, s[k]), m2 = edgeMarker(p, b, s[k + 1]);
-      bool l1 = leftOf(F, m1, a), l2 = leftOf(F, m2, a);
+    const uint32_t c = T.segc(p, b);
+    const int nseg = (c >> 8) & 3;
+    for (int k = 0; k < 2; k++) {
+      if (k >= nseg) break;
+      const int eA = (c >> (4 * k)) & 3, eB = (c >> (4 * k + 2)) & 3;
+      const bool l1 = leftOf(T, edgeMarker(p, b, eA), a), l2 = leftOf(T, edgeMarker(p, b, eB), a);
       if (l1 == l2) continue;
-      cp[nxr] = p;
-      cl[nxr] = l1 ? s[k] : s[k + 1];
-      cr[nxr] = l1 ? s[k + 1] : s[k];
-      advPoint(F, edgeMarker(p, b, cl[nxr]), a, b, &X2v[nxr], &Y2v[nxr]);
-      advPoint(F, edgeMarker(p, b, cr[nxr]), a, b, &X3v[nxr], &Y3v[nxr]);
-      ysl[nxr] = chordY(X2v[nxr], Y2v[nxr], X3v[nxr], Y3v[nxr]);
-      nxr++;
+      const int el = l1 ? eA : eB, er = l1 ? eB : eA;
+      double X2, Y2, X3, Y3;
+      advPoint(T, edgeMarker(p, b, el), a, b, &X2, &Y2);
+      advPoint(T, edgeMarker(p, b, er), a, b, &X3, &Y3);
+      const double ys = chordY(X2, Y2, X3, Y3);
+      if (ncross == 0) { cp0 = p; cl0 = el; cr0 = er; ys0 = ys; }
+      else if (ncross == 1) { cp1 = p; cl1 = el; cr1 = er; ys1 = ys; }
+      else if (ncross == 2) { cp2 = p; cl2 = el; cr2 = er; ys2 = ys; }
+      ncross++;
     }
   }
   int pick = -1;
-  if (nxr == 1) {
+  if (ncross == 1) {
     pick = 0;
-  } else if (nxr == 3) {
-    if (count) cnt[C_THREE_CROSSINGS]++;
-    for (int x = 0; x < 3 && pick < 0; x++) {
-      int below = 0;
-      for (int y = 0; y < 3; y++) {
-        if (y == x) continue;
-        if (ysl[y] < ysl[x] || (ysl[y] == ysl[x] && y < x)) below++;
-      }
-      if (below == 1) pick = x;
-    }
-    for (int x = 0; x < 3; x++)
-      for (int y = x + 1; y < 3; y++)
-        if (fabs(ysl[x] - ysl[y]) < TIE_EPS) lties++;
+  } else if (ncross == 3) {
+    if (count) cnt.add(C_THREE_CROSSINGS, 1u);
+    // the median by chord height, equal heights ordered by enumeration
+    const int below0 = (ys1 < ys0) + (ys2 < ys0);
+    const int below1 = (ys0 <= ys1) + (ys2 < ys1);
+    const int below2 = (ys0 <= ys2) + (ys1 <= ys2);
+    pick = below0 == 1 ? 0 : (below1 == 1 ? 1 : (below2 == 1 ? 2 : -1));
+    lties += (fabs(ys0 - ys1) < TIE_EPS) + (fabs(ys0 - ys2) < TIE_EPS) + (fabs(ys1 - ys2) < TIE_EPS);
   }
   if (pick < 0) {
     if (count) {
-      cnt[C_PARITY_FALLBACK]++;
-      cnt[C_TIES] += lties;
+      cnt.add(C_PARITY_FALLBACK, 1u);
+      cnt.add(C_TIES, (uint32_t)(lties));
     }
-    *yout = 0.5;
-    return true;
+    return 0.5;
   }
-  double X2 = X2v[pick], Y2 = Y2v[pick], X3 = X3v[pick], Y3 = Y3v[pick];
+  const int p = pick == 0 ? cp0 : (pick == 1 ? cp1 : cp2);
+  const int el = pick == 0 ? cl0 : (pick == 1 ? cl1 : cl2);
+  const int er = pick == 0 ? cr0 : (pick == 1 ? cr1 : cr2);
+  const double ysl = pick == 0 ? ys0 : (pick == 1 ? ys1 : ys2);
+  const MRef m2 = edgeMarker(p, b, el), m3 = edgeMarker(p, b, er);
+  double X2, Y2, X3, Y3;
+  advPoint(T, m2, a, b, &X2, &Y2);
+  advPoint(T, m3, a, b, &X3, &Y3);
   if (fabs(X2) < TIE_EPS || fabs(X3) < TIE_EPS) lties++;
-  int p = cp[pick];
-  MRef m2 = edgeMarker(p, b, cl[pick]), m3 = edgeMarker(p, b, cr[pick]), m1, m4;
-  bool h1 = chainNb(F, p, b, cl[pick], &m1);
-  bool h4 = chainNb(F, p, b, cr[pick], &m4);
+  MRef m1, m4;
+  const bool h1 = chainNb(T, p, b, el, &m1);
+  const bool h4 = chainNb(T, p, b, er, &m4);
   double y;
   uint32_t fb = 0;
   if (X3 == 0.0) {
     y = Y3;
   } else {
-    double X1 = 0, Y1 = 0, X4 = 0, Y4 = 0, rA = 0, rB = 0;
+    double rA = 0, rB = 0;
     bool okA = false, okB = false;
     if (h1) {
-      advPoint(F, m1, a, b, &X1, &Y1);
-      okA = circleRoot(X1, Y1, X2, Y2, X3, Y3, X1, Y1, X2, Y2, X3, Y3, ysl[pick], &rA, &lties, &lrej);
+      double X1, Y1;
+      advPoint(T, m1, a, b, &X1, &Y1);
+      okA = circleRoot(X1, Y1, X2, Y2, X3, Y3, X1, Y1, X2, Y2, X3, Y3, ysl, &rA, &lties, &lrej);
     }
     if (h4) {
-      advPoint(F, m4, a, b, &X4, &Y4);
-      okB = circleRoot(X2, Y2, X3, Y3, X4, Y4, X4, Y4, X2, Y2, X3, Y3, ysl[pick], &rB, &lties, &lrej);
+      double X4, Y4;
+      advPoint(T, m4, a, b, &X4, &Y4);
+      okB = circleRoot(X2, Y2, X3, Y3, X4, Y4, X4, Y4, X2, Y2, X3, Y3, ysl, &rB, &lties, &lrej);
     }
     if (okA && okB) y = (rA + rB) * 0.5;
     else if (okA) y = rA;
     else if (okB) y = rB;
     else {
-      y = ysl[pick];
+      y = ysl;
       fb = 1;
     }
   }
   if (y < TIE_EPS || 1.0 - y < TIE_EPS) lties++;
   if (count) {
-    cnt[C_TIES] += lties;
-    cnt[C_FIT_REJECT] += lrej;
-    cnt[C_FIT_FALLBACK] += fb;
+    cnt.add(C_TIES, (uint32_t)(lties));
+    cnt.add(C_FIT_REJECT, (uint32_t)(lrej));
+    cnt.add(C_FIT_FALLBACK, (uint32_t)(fb));
   }
-  *yout = y;
-
   // Centre-CV candidates: for the cell right of the line, the crossing
   // endpoint on its side (P3) and, if that is an unaligned point, its chain
   // neighbour (P4); for the cell on the left, P2 then P1. A candidate counts
   // when it is an aligned marker kept on that cell's bottom or top edge; the
   // corner it shares with this line is then isolated.
-  for (int side = 0; side < 2; side++) {
-    int cellA = side == 0 ? a : a - 1;
-    if (cellA < 0 || cellA >= F.na) continue;
-    MRef cand[2];
-    int nc = 0;
-    MRef first = side == 0 ? m3 : m2;
-    cand[nc++] = first;
-    if (first.kind == 1) {
-      if (side == 0 && h4) cand[nc++] = m4;
-      if (side == 1 && h1) cand[nc++] = m1;
-    }
-    for (int k = 0; k < nc; k++) {
-      MRef m = cand[k];
-      if (m.kind != 0) continue;
-      if (m.b != b && m.b != b + 1) continue;
-      if (!F.keptOn(m.a, m.b, cellA)) continue;
-      int corner = F.newC(a, m.b);
-      int res = 1 - corner;
-      if (side == 0) *resRight = res;
-      else *resLeft = res;
-      break;
-    }
+  auto qualifies = [&](MRef m, int cellA) -> bool {
+    return m.kind == 0 && (m.b == b || m.b == b + 1) && T.keptOn(m.a, m.b, cellA);
+  };
+  if (a < T.na) {
+    // cell a, right of the line
+    if (qualifies(m3, a)) *resRight = 1 - T.newC(a, m3.b);
+    else if (m3.kind == 1 && h4 && qualifies(m4, a)) *resRight = 1 - T.newC(a, m4.b);
   }
-  return true;
+  if (a >= 1) {
+    // cell a-1, left of the line
+    if (qualifies(m2, a - 1)) *resLeft = 1 - T.newC(a, m2.b);
+    else if (m2.kind == 1 && h1 && qualifies(m1, a - 1)) *resLeft = 1 - T.newC(a, m1.b);
+  }
+  return y;
 }
 
 // ---------------------------------------------------------------------------
 // Sweep kernel: one workgroup per active tile (persistent over the list).
 // ---------------------------------------------------------------------------
 template <int DIR>
-__global__ __launch_bounds__(256) void k_sweep(SweepParams P) {
-  const Frame<DIR> F(P);
-  __shared__ int8_t sRight[TS][TS + 1];  // [lb][la] result for cell right of line
-  __shared__ int8_t sLeft[TS][TS + 1];   // result for cell left of line
+__global__ __launch_bounds__(256, 8) void k_sweep(SweepParams P) {
+  __shared__ uint8_t sCol[NH][NH];
+  __shared__ uint8_t sCen[NE][NE];
+  __shared__ double sSp[NH][NE];
+  __shared__ double sD[NE][NH];
+  __shared__ double sT[NE][NH];
+  __shared__ uint8_t sNcol[NN][NN];
+  __shared__ uint16_t sSeg[NE][NE];
+  __shared__ int8_t sKeep[NN][NN + 1];
+  __shared__ int8_t sRight[TS][NN];  // [lb][la]: result for the cell right of line a
+  __shared__ int8_t sLeft[TS][NN];   // result for the cell left of line a
+  __shared__ uint16_t sWork[TS * NN];
+  __shared__ uint32_t sNWork;
+  __shared__ uint16_t sAdv[2 * NH * NE];  // present halo edges to advect
+  __shared__ uint32_t sNAdv;
+  __shared__ uint32_t sHas;
   __shared__ uint32_t sCnt[NCOUNTERS];
-  __shared__ int sHas;
   __shared__ uint32_t sErr;
+
+  const GMap<DIR> G(P.nx, P.ny);
+  const int na = G.na, nb = G.nb;
+  const double lam = P.lam;
+  const double *__restrict__ alo = DIR == 0 ? P.hoff : P.voff;
+  const double *__restrict__ uno = DIR == 0 ? P.voff : P.hoff;
+  double *__restrict__ aln = DIR == 0 ? P.nhoff : P.nvoff;
+  double *__restrict__ unn = DIR == 0 ? P.nvoff : P.nhoff;
+  const double *__restrict__ vel = P.vel;
+  auto V = [&](int a, int r) -> double {
+    r = r < 0 ? 0 : (r > nb - 1 ? nb - 1 : r);
+    return vel[G.une(a, r)];
+  };
+
   const int tid = threadIdx.x;
   if (tid < NCOUNTERS) sCnt[tid] = 0;
   if (tid == 0) sErr = 0;
-  uint32_t cnt[NCOUNTERS];
-#pragma unroll
-  for (int k = 0; k < NCOUNTERS; k++) cnt[k] = 0;
-  uint32_t err = 0;
+  const Counts cnt{sCnt};
+
+  Tile T;
+  T.na = na;
+  T.nb = nb;
+  T.col = sCol;
+  T.cen = sCen;
+  T.sp = sSp;
+  T.dd = sD;
+  T.tt = sT;
+  T.ncol = sNcol;
+  T.seg = sSeg;
+  T.keep = sKeep;
+
+  // Staging of colours and centre colours: each thread owns two node slots
+  // and two cell slots of the halo (memory order). The next tile's bytes are
+  // fetched into registers while the current tile computes.
+  static_assert(NH * NH <= 512 && NE * NE <= 512, "two staging slots per thread");
+  uint8_t pc0 = 0, pc1 = 0, pe0 = 0, pe1 = 0;
+  auto prefetch = [&](uint32_t tl) {
+    const int px0 = (int)(tl % (uint32_t)P.ntx) * TS, py0 = (int)(tl / (uint32_t)P.ntx) * TS;
+    auto node = [&](int k) -> uint8_t {
+      if (k >= NH * NH) return 0;
+      const int x = px0 - HALO + k % NH, y = py0 - HALO + k / NH;
+      return (x >= 0 && y >= 0 && x <= P.nx && y <= P.ny) ? P.col[(size_t)y * (P.nx + 1) + x] : (uint8_t)0;
+    };
+    auto cell = [&](int k) -> uint8_t {
+      if (k >= NE * NE) return 0;
+      const int x = px0 - HALO + k % NE, y = py0 - HALO + k / NE;
+      return (x >= 0 && y >= 0 && x < P.nx && y < P.ny) ? P.cen[(size_t)y * P.nx + x] : (uint8_t)0;
+    };
+    pc0 = node(tid);
+    pc1 = node(tid + 256);
+    pe0 = cell(tid);
+    pe1 = cell(tid + 256);
+  };
+
   const uint32_t ntile = *P.count;
+  if (blockIdx.x < ntile) prefetch(P.list[blockIdx.x]);
   for (uint32_t it = blockIdx.x; it < ntile; it += gridDim.x) {
-    const uint32_t T = P.list[it];
-    const int tx = (int)(T % (uint32_t)P.ntx), ty = (int)(T / (uint32_t)P.ntx);
+    const uint32_t tile = P.list[it];
+    const int tx = (int)(tile % (uint32_t)P.ntx), ty = (int)(tile / (uint32_t)P.ntx);
     const int x0 = tx * TS, y0 = ty * TS;
     const int a0 = DIR == 0 ? x0 : y0, b0 = DIR == 0 ? y0 : x0;
+    T.a0 = a0;
+    T.b0 = b0;
+    __syncthreads();  // previous tile done with LDS
+    if (tid == 0) {
+      sNWork = 0;
+      sNAdv = 0;
+      sHas = 0;
+    }
+    // --- stage old colours (nodes) and centre colours -----------------------
+    {
+      auto putNode = [&](int k, uint8_t c) {
+        if (k >= NH * NH) return;
+        const int hx = k % NH, hy = k / NH;
+        if (DIR == 0) sCol[hy][hx] = c;
+        else sCol[hx][hy] = c;
+      };
+      auto putCell = [&](int k, uint8_t c) {
+        if (k >= NE * NE) return;
+        const int hx = k % NE, hy = k / NE;
+        if (DIR == 0) sCen[hy][hx] = c;
+        else sCen[hx][hy] = c;
+      };
+      putNode(tid, pc0);
+      putNode(tid + 256, pc1);
+      putCell(tid, pe0);
+      putCell(tid + 256, pe1);
+    }
     __syncthreads();
-    if (tid == 0) sHas = 0;
+    if (it + gridDim.x < ntile) prefetch(P.list[it + gridDim.x]);
+    // a tile whose staged nodes (ghosts staged as 0) all share one colour has
+    // no marker in reach and keeps its state: copy it over and move on
+    {
+      const uint8_t c0 = sCol[0][0];
+      int any = 0;
+      for (int k = tid; k < NH * NH; k += blockDim.x) any |= (&sCol[0][0])[k] != c0;
+      if (!__syncthreads_or(any)) {
+        for (int k = tid; k < NN * NN; k += blockDim.x) {
+          const int li = k % NN, lj = k / NN;
+          const int x = x0 + li, y = y0 + lj;
+          if (x > P.nx || y > P.ny) continue;
+          const int hx = li + HALO, hy = lj + HALO;
+          const uint8_t c = DIR == 0 ? sCol[hy][hx] : sCol[hx][hy];
+          if ((li < TS || x == P.nx) && (lj < TS || y == P.ny)) P.ncol[(size_t)y * (P.nx + 1) + x] = c;
+          if (li < TS && lj < TS && x < P.nx && y < P.ny)
+            P.ncen[(size_t)y * P.nx + x] = DIR == 0 ? sCen[hy][hx] : sCen[hx][hy];
+        }
+        if (tid == 0) {
+          P.has[tile] = 0;
+          cnt.add(C_TILES_EMPTY, 1u);
+        }
+        continue;
+      }
+    }
+    if (tid == 0) cnt.add(C_TILES_SWEPT, 1u);
+    // old segments of the halo cells (frame coordinates)
+    for (int k = tid; k < NE * NE; k += blockDim.x) {
+      const int la = k % NE, lb = k / NE;
+      sSeg[lb][la] = segCodeOf(sCol[lb][la], sCol[lb][la + 1], sCol[lb + 1][la + 1], sCol[lb + 1][la], sCen[lb][la]);
+    }
+    // --- advect the present markers of the halo (Eq. marker_dis) -------------
+    // Aligned edges (a,b): a in [a0-2, a0+17], b in [b0-2, b0+18]; unaligned
+    // edges (a,b): a in [a0-2, a0+18], b in [b0-2, b0+17]. The present ones
+    // are first listed in LDS, then each thread advects one listed marker, so
+    // all offsets and face velocities are fetched in a single round.
+    for (int k = tid; k < NH * NE; k += blockDim.x) {
+      int la, lb;
+      if (DIR == 0) { la = k % NE; lb = k / NE; }
+      else { lb = k % NH; la = k / NH; }
+      int a = a0 - HALO + la, b = b0 - HALO + lb;
+      if (a >= 0 && a < na && b >= 0 && b <= nb && sCol[lb][la] != sCol[lb][la + 1])
+        sAdv[atomicAdd(&sNAdv, 1u)] = (uint16_t)(lb * NE + la);
+      if (DIR == 0) { la = k % NH; lb = k / NH; }
+      else { lb = k % NE; la = k / NE; }
+      a = a0 - HALO + la;
+      b = b0 - HALO + lb;
+      if (a >= 0 && a <= na && b >= 0 && b < nb && sCol[lb][la] != sCol[lb + 1][la])
+        sAdv[atomicAdd(&sNAdv, 1u)] = (uint16_t)(0x8000u | (lb * NH + la));
+    }
     __syncthreads();
-    int has = 0;
-    // phase 1: nodes, aligned edges, unaligned edges on lines a0..a0+TS
-    for (int k = tid; k < (TS + 1) * (TS + 1); k += blockDim.x) {
-      const int li = k % (TS + 1), lj = k / (TS + 1);
-      const int la = DIR == 0 ? li : lj, lb = DIR == 0 ? lj : li;
-      const int a = a0 + la, b = b0 + lb;
-      if (a > F.na || b > F.nb) continue;
-      const bool ownA = la < TS || a == F.na;
-      const bool ownB = lb < TS || b == F.nb;
-      // node
-      if (ownA && ownB) {
-        int c = F.newC(a, b);
-        size_t idx = F.node(a, b);
-        P.ncol[idx] = (uint8_t)c;
-      }
-      // aligned edge (a,b)
-      if (a < F.na && la < TS && ownB) {
-        if (F.presA(a, b)) {
-          cnt[C_MARKERS]++;
-          double s = F.alo[F.ale(a, b)];
-          double d = F.dispA(a, b, s);
-          if (fabs(d) > 0.5) err |= ERRBIT_CFL;
-          double spv = s + d;
-          if ((spv >= 1.0 && a + 1 >= F.na) || (spv < 0.0 && a == 0)) err |= ERRBIT_DOMAIN;
-        }
-        int keep;
-        int n = F.landers(a, b, &keep);
-        if (n == 3) cnt[C_THREE_LANDERS]++;
-        cnt[C_ANNIHILATED] += (uint32_t)(n - (n & 1));
-        const int newpres = F.newC(a, b) != F.newC(a + 1, b);
-        if (newpres != (n & 1)) cnt[C_INVARIANT_FAIL]++;
-        if (keep >= 0) {
-          double spv = F.sp(keep, b);
-          double o = keep < a ? spv - 1.0 : (keep > a ? spv + 1.0 : spv);
-          if (o < TIE_EPS || 1.0 - o < TIE_EPS) cnt[C_TIES]++;
-          if (newpres) (DIR == 0 ? P.nhoff : P.nvoff)[F.ale(a, b)] = o;
-        } else if (newpres) {
-          (DIR == 0 ? P.nhoff : P.nvoff)[F.ale(a, b)] = 0.0;
-        }
-        if (newpres) has = 1;
-      }
-      // unaligned edge (a,b)
-      if (b < F.nb && lb < TS) {
-        const bool own = ownA;
-        if (own && F.presU(a, b)) {
-          cnt[C_MARKERS]++;
-          double d = F.rawDispU(a, b);
-          if (fabs(d) > 0.5) err |= ERRBIT_CFL;
-          if ((a == 0 || a == F.na) && d != 0.0) cnt[C_WALL_VIOLATION]++;
-        }
-        int rR = -1, rL = -1;
-        double *dst = DIR == 0 ? P.nvoff : P.nhoff;
-        if (a == 0 || a == F.na) {
-          // walls hold their markers (colours of wall nodes never change)
-          if (own && F.presU(a, b)) {
-            dst[F.une(a, b)] = F.uno[F.une(a, b)];
-            has = 1;
-          }
-        } else if (F.newC(a, b) != F.newC(a, b + 1)) {
-          double y;
-          newUnaligned(F, a, b, &y, &rR, &rL, cnt, own);
+    {
+      const uint32_t nadv = sNAdv;
+      for (uint32_t w = tid; w < nadv; w += blockDim.x) {
+        const uint32_t code = sAdv[w];
+        if (!(code & 0x8000u)) {
+          const int la = code % NE, lb = code / NE;
+          const int a = a0 - HALO + la, b = b0 - HALO + lb;
+          const double s = alo[G.ale(a, b)];
+          const double ub = lerp(lerp(V(a, b - 1), V(a + 1, b - 1), s), lerp(V(a, b), V(a + 1, b), s), 0.5);
+          const double d = ub * lam;
+          const double spv = s + d;
+          sSp[lb][la] = spv;
+          const bool own = la >= HALO && la < HALO + TS && lb >= HALO && (lb < HALO + TS || b == nb);
           if (own) {
-            dst[F.une(a, b)] = y;
-            has = 1;
+            cnt.add(C_MARKERS, 1u);
+            if (fabs(d) > 0.5) atomicOr(&sErr, ERRBIT_CFL);
+            if ((spv >= 1.0 && a + 1 >= na) || (spv < 0.0 && a == 0)) atomicOr(&sErr, ERRBIT_DOMAIN);
+          }
+        } else {
+          const uint32_t c = code & 0x7fffu;
+          const int la = c % NH, lb = c / NH;
+          const int a = a0 - HALO + la, b = b0 - HALO + lb;
+          const double t = uno[G.une(a, b)];
+          const double v0 = V(a, b - 1), v1 = V(a, b), v2 = V(a, b + 1);
+          const double ub = t < 0.5 ? lerp(v0, v1, t + 0.5) : lerp(v1, v2, t - 0.5);
+          const double d = ub * lam;
+          const bool wall = a == 0 || a == na;
+          sT[lb][la] = t;
+          sD[lb][la] = wall ? 0.0 : d;
+          const bool own = la >= HALO && (la < HALO + TS || a == na) && lb >= HALO && lb < HALO + TS;
+          if (own) {
+            cnt.add(C_MARKERS, 1u);
+            if (fabs(d) > 0.5) atomicOr(&sErr, ERRBIT_CFL);
+            if (wall && d != 0.0) cnt.add(C_WALL_VIOLATION, 1u);
           }
         }
-        sRight[lb][la] = (int8_t)rR;
-        sLeft[lb][la] = (int8_t)rL;
       }
     }
     __syncthreads();
-    // phase 2: centre colours of the tile's cells
-    for (int k = tid; k < TS * TS; k += blockDim.x) {
-      const int li = k % TS, lj = k / TS;
-      const int la = DIR == 0 ? li : lj, lb = DIR == 0 ? lj : li;
+    // --- new corner colours of nodes [a0, a0+16] x [b0, b0+16] ---------------
+    for (int k = tid; k < NN * NN; k += blockDim.x) {
+      const int hx = k % NN, hy = k / NN;
+      const int la = DIR == 0 ? hx : hy, lb = DIR == 0 ? hy : hx;
       const int a = a0 + la, b = b0 + lb;
-      if (a >= F.na || b >= F.nb) continue;
-      int left = sRight[lb][la];       // line a, cell to its right
-      int right = sLeft[lb][la + 1];   // line a+1, cell to its left
-      int cc = F.cen[F.cell(a, b)];
+      int c = 0;
+      if (a <= na && b <= nb) {
+        c = T.computeNewC(a, b);
+        const bool own = (la < TS || a == na) && (lb < TS || b == nb);
+        if (own) P.ncol[G.node(a, b)] = (uint8_t)c;
+      }
+      sNcol[lb][la] = (uint8_t)c;
+    }
+    __syncthreads();
+    uint32_t hasm = 0;
+    // --- new aligned edges (landers): kept sources for t in [a0-1, a0+16] ----
+    for (int k = tid; k < (TS + 2) * NN; k += blockDim.x) {
+      int lt, lb;
+      if (DIR == 0) { lt = k % (TS + 2); lb = k / (TS + 2); }
+      else { lb = k % NN; lt = k / NN; }
+      const int a = a0 - 1 + lt, b = b0 + lb;
+      int8_t kr = -2;
+      if (a >= 0 && a < na && b <= nb) {
+        int keep;
+        const int n = T.landers(a, b, &keep);
+        if (keep >= 0) kr = (int8_t)(keep - a);
+        if (lt >= 1 && lt <= TS && (lb < TS || b == nb)) {
+          if (n == 3) cnt.add(C_THREE_LANDERS, 1u);
+          cnt.add(C_ANNIHILATED, (uint32_t)((uint32_t)(n - (n & 1))));
+          const bool newpres = T.newC(a, b) != T.newC(a + 1, b);
+          if ((int)newpres != (n & 1)) cnt.add(C_INVARIANT_FAIL, 1u);
+          double o = 0.0;
+          if (keep >= 0) {
+            const double spv = T.spv(keep, b);
+            o = keep < a ? spv - 1.0 : (keep > a ? spv + 1.0 : spv);
+            if (o < TIE_EPS || 1.0 - o < TIE_EPS) cnt.add(C_TIES, 1u);
+          }
+          if (newpres) {
+            aln[G.ale(a, b)] = o;
+            hasm |= DIR == 0 ? maskH(a, b, x0, y0) : maskV(b, a, x0, y0);
+          }
+        }
+      }
+      sKeep[lb][lt] = kr;
+    }
+    // --- the unaligned work list ---------------------------------------------
+    for (int k = tid; k < TS * NN; k += blockDim.x) {
+      // unaligned edge on line a in [a0, a0+16], row b in [b0, b0+15]
+      {
+        int la, lb;
+        if (DIR == 0) { la = k % NN; lb = k / NN; }
+        else { lb = k % TS; la = k / TS; }
+        const int a = a0 + la, b = b0 + lb;
+        sRight[lb][la] = -1;
+        sLeft[lb][la] = -1;
+        if (a <= na && b < nb) {
+          const bool own = la < TS || a == na;
+          if (a == 0 || a == na) {
+            // walls hold their markers (wall nodes never change colour)
+            if (own && T.presU(a, b)) {
+              unn[G.une(a, b)] = T.tU(a, b);
+              hasm |= DIR == 0 ? maskV(a, b, x0, y0) : maskH(b, a, x0, y0);
+            }
+          } else if (T.newC(a, b) != T.newC(a, b + 1)) {
+            const uint32_t w = atomicAdd(&sNWork, 1u);
+            sWork[w] = (uint16_t)(lb * NN + la);
+          }
+        }
+      }
+    }
+    __syncthreads();
+    // --- circle fits for the present new unaligned edges ---------------------
+    const uint32_t nwork = sNWork;
+    for (uint32_t w = tid; w < nwork; w += blockDim.x) {
+      const int la = sWork[w] % NN, lb = sWork[w] / NN;
+      const int a = a0 + la, b = b0 + lb;
+      const bool own = la < TS || a == na;
+      int rR, rL;
+      const double y = newUnaligned(T, a, b, &rR, &rL, cnt, own);
+      sRight[lb][la] = (int8_t)rR;
+      sLeft[lb][la] = (int8_t)rL;
+      if (own) {
+        unn[G.une(a, b)] = y;
+        hasm |= DIR == 0 ? maskV(a, b, x0, y0) : maskH(b, a, x0, y0);
+      }
+    }
+    __syncthreads();
+    // --- centre colours of the tile's cells (Sec. 2.3, rules (1)-(5)) --------
+    for (int k = tid; k < TS * TS; k += blockDim.x) {
+      const int hx = k % TS, hy = k / TS;
+      const int la = DIR == 0 ? hx : hy, lb = DIR == 0 ? hy : hx;
+      const int a = a0 + la, b = b0 + lb;
+      if (a >= na || b >= nb) continue;
+      const int left = sRight[lb][la];      // line a, cell to its right
+      const int right = sLeft[lb][la + 1];  // line a+1, cell to its left
+      int cc = T.cenv(a, b);
       if (left >= 0) {
         cc = left;
-        cnt[C_CV_SET]++;
-        if (right >= 0 && right != left) cnt[C_CV_CONFLICT]++;
+        cnt.add(C_CV_SET, 1u);
+        if (right >= 0 && right != left) cnt.add(C_CV_CONFLICT, 1u);
       } else if (right >= 0) {
         cc = right;
-        cnt[C_CV_SET]++;
+        cnt.add(C_CV_SET, 1u);
       } else {
-        int k0 = F.newC(a, b), k1 = F.newC(a + 1, b), k2 = F.newC(a + 1, b + 1), k3 = F.newC(a, b + 1);
-        if ((k0 != k1) + (k1 != k2) + (k3 != k2) + (k0 != k3) == 4) cnt[C_CV_UNRESOLVED]++;
+        const int k0 = T.newC(a, b), k1 = T.newC(a + 1, b), k2 = T.newC(a + 1, b + 1), k3 = T.newC(a, b + 1);
+        if ((k0 != k1) + (k1 != k2) + (k3 != k2) + (k0 != k3) == 4) cnt.add(C_CV_UNRESOLVED, 1u);
       }
-      P.ncen[F.cell(a, b)] = (uint8_t)cc;
+      P.ncen[G.cell(a, b)] = (uint8_t)cc;
     }
-    if (has) sHas = 1;
+    if (hasm) atomicOr(&sHas, hasm);
     __syncthreads();
-    if (tid == 0) P.has[T] = (uint8_t)sHas;
+    if (tid == 0) P.has[tile] = (uint16_t)sHas;
   }
-  // flush counters
-  for (int k = 0; k < NCOUNTERS; k++)
-    if (cnt[k]) atomicAdd(&sCnt[k], cnt[k]);
-  if (err) atomicOr(&sErr, err);
   __syncthreads();
   if (tid < NCOUNTERS && sCnt[tid]) atomicAdd(&P.ctr[tid], (unsigned long long)sCnt[tid]);
   if (tid == 0 && sErr) atomicOr(P.err, sErr);
 }
 
 // ---------------------------------------------------------------------------
-// Tile bookkeeping: marker flags of the uploaded state, then per-sweep
+// Tile bookkeeping: marker masks of an uploaded state, then per-sweep
 // compaction into the active list (near now or near last sweep) and the near
-// list, with wave ballots and one atomic per wave.
+// list. Each workgroup scans 1024 tiles and reserves its list slots with one
+// atomic per list.
 // ---------------------------------------------------------------------------
-__global__ void k_init_has(const uint8_t *__restrict__ col, int nx, int ny, int ntx, int nty, uint8_t *has,
+__global__ void k_init_has(const uint8_t *__restrict__ col, int nx, int ny, int ntx, int nty, uint16_t *has,
                            uint8_t *nearPrev) {
-  const int T = blockIdx.x;
-  if (T >= ntx * nty) return;
-  const int tx = T % ntx, ty = T / ntx;
+  const int tile = blockIdx.x;
+  if (tile >= ntx * nty) return;
+  const int tx = tile % ntx, ty = tile / ntx;
   const int x0 = tx * TS, y0 = ty * TS;
-  __shared__ int sh;
+  __shared__ uint32_t sh;
   if (threadIdx.x == 0) sh = 0;
   __syncthreads();
-  int h = 0;
-  for (int k = threadIdx.x; k < (TS + 1) * (TS + 1); k += blockDim.x) {
-    const int li = k % (TS + 1), lj = k / (TS + 1);
+  uint32_t m = 0;
+  for (int k = threadIdx.x; k < NN * NN; k += blockDim.x) {
+    const int li = k % NN, lj = k / NN;
     const int i = x0 + li, j = y0 + lj;
     if (i > nx || j > ny) continue;
     const bool ownI = li < TS || i == nx;
     const bool ownJ = lj < TS || j == ny;
     const uint8_t c = col[(size_t)j * (nx + 1) + i];
-    if (i < nx && li < TS && ownJ && c != col[(size_t)j * (nx + 1) + i + 1]) h = 1;
-    if (j < ny && lj < TS && ownI && c != col[(size_t)(j + 1) * (nx + 1) + i]) h = 1;
+    if (i < nx && li < TS && ownJ && c != col[(size_t)j * (nx + 1) + i + 1]) m |= maskH(i, j, x0, y0);
+    if (j < ny && lj < TS && ownI && c != col[(size_t)(j + 1) * (nx + 1) + i]) m |= maskV(i, j, x0, y0);
   }
-  if (h) sh = 1;
+  if (m) atomicOr(&sh, m);
   __syncthreads();
   if (threadIdx.x == 0) {
-    has[T] = (uint8_t)sh;
-    nearPrev[T] = 0;
+    has[tile] = (uint16_t)sh;
+    nearPrev[tile] = 0;
   }
 }
 
-__global__ void k_compact(const uint8_t *__restrict__ has, uint8_t *__restrict__ nearPrev,
-                          uint8_t *__restrict__ tinfo, const uint8_t *__restrict__ col, int nx, int ntx, int nty,
-                          uint32_t *actList, uint32_t *nearList, uint32_t *counts, int slot) {
+__device__ __forceinline__ bool nearOf(const uint16_t *__restrict__ has, int tx, int ty, int ntx, int nty) {
+  auto H = [&](int x, int y) -> uint32_t {
+    return (x < 0 || y < 0 || x >= ntx || y >= nty) ? 0u : (uint32_t)has[y * ntx + x];
+  };
+  return (H(tx, ty) & M_ANY) || (H(tx - 1, ty) & M_R) || (H(tx + 1, ty) & M_L) || (H(tx, ty - 1) & M_T) ||
+         (H(tx, ty + 1) & M_B) || (H(tx - 1, ty - 1) & M_RT) || (H(tx + 1, ty - 1) & M_LT) ||
+         (H(tx - 1, ty + 1) & M_RB) || (H(tx + 1, ty + 1) & M_LB);
+}
+
+constexpr int CPT = 4;  // tiles per thread in the compaction
+
+__global__ __launch_bounds__(256) void k_compact(const uint16_t *__restrict__ has, uint8_t *__restrict__ nearPrev,
+                                                 uint8_t *__restrict__ tinfo, const uint8_t *__restrict__ col, int nx,
+                                                 int ntx, int nty, uint32_t *actList, uint32_t *nearList,
+                                                 uint32_t *counts, int slot) {
+  __shared__ uint32_t sA[256], sN[256];
+  __shared__ uint32_t sBaseA, sBaseN;
   const int ntiles = ntx * nty;
-  const int T = blockIdx.x * blockDim.x + threadIdx.x;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  const int tid = threadIdx.x;
+  if (blockIdx.x == 0 && tid == 0) {
     // clear the other slot for the next compaction (nothing reads it now)
     counts[2 * (slot ^ 1)] = 0;
     counts[2 * (slot ^ 1) + 1] = 0;
   }
-  bool act = false, nr = false;
-  if (T < ntiles) {
-    const int tx = T % ntx, ty = T / ntx;
-    int n = 0;
-    for (int oy = -1; oy <= 1; oy++)
-      for (int ox = -1; ox <= 1; ox++) {
-        const int sx = tx + ox, sy = ty + oy;
-        if (sx < 0 || sy < 0 || sx >= ntx || sy >= nty) continue;
-        n |= has[sy * ntx + sx];
-      }
-    nr = n != 0;
-    act = nr || nearPrev[T] != 0;
-    nearPrev[T] = (uint8_t)nr;
-    tinfo[T] = (uint8_t)((nr ? 1 : 0) | (col[(size_t)(ty * TS) * (nx + 1) + tx * TS] << 1));
+  const int base = (blockIdx.x * blockDim.x + tid) * CPT;
+  uint32_t actBits = 0, nearBits = 0;
+  for (int q = 0; q < CPT; q++) {
+    const int t = base + q;
+    if (t >= ntiles) break;
+    const int tx = t % ntx, ty = t / ntx;
+    const bool nr = nearOf(has, tx, ty, ntx, nty);
+    const bool act = nr || nearPrev[t] != 0;
+    nearPrev[t] = (uint8_t)nr;
+    tinfo[t] = (uint8_t)((nr ? 1 : 0) | (col[(size_t)(ty * TS) * (nx + 1) + tx * TS] << 1));
+    actBits |= (uint32_t)act << q;
+    nearBits |= (uint32_t)nr << q;
   }
-  // wave-level compaction: ballot + popcount + mbcnt prefix
-  const uint64_t ba = __ballot(act);
-  const uint64_t bn = __ballot(nr);
-  const int lane = threadIdx.x & 63;
-  const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-  uint32_t baseA = 0, baseN = 0;
-  if (lane == 0) {
-    if (ba) baseA = atomicAdd(&counts[2 * slot], (uint32_t)__popcll(ba));
-    if (bn) baseN = atomicAdd(&counts[2 * slot + 1], (uint32_t)__popcll(bn));
+  // exclusive block scan of the per-thread counts
+  const uint32_t ca = __popc(actBits), cn = __popc(nearBits);
+  sA[tid] = ca;
+  sN[tid] = cn;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const uint32_t xa = tid >= off ? sA[tid - off] : 0, xn = tid >= off ? sN[tid - off] : 0;
+    __syncthreads();
+    sA[tid] += xa;
+    sN[tid] += xn;
+    __syncthreads();
   }
-  baseA = __shfl(baseA, 0);
-  baseN = __shfl(baseN, 0);
-  if (act) actList[baseA + __popcll(ba & below)] = (uint32_t)T;
-  if (nr) nearList[baseN + __popcll(bn & below)] = (uint32_t)T;
+  if (tid == 255) {
+    sBaseA = sA[255] ? atomicAdd(&counts[2 * slot], sA[255]) : 0;
+    sBaseN = sN[255] ? atomicAdd(&counts[2 * slot + 1], sN[255]) : 0;
+  }
+  __syncthreads();
+  uint32_t pa = sBaseA + sA[tid] - ca, pn = sBaseN + sN[tid] - cn;
+  for (int q = 0; q < CPT; q++) {
+    if (actBits >> q & 1) actList[pa++] = (uint32_t)(base + q);
+    if (nearBits >> q & 1) nearList[pn++] = (uint32_t)(base + q);
+  }
 }
 
 // ---------------------------------------------------------------------------
 // Volume fraction and height-function curvature.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int mirrorCell(int k, int n) { return k < 0 ? -1 - k : (k >= n ? 2 * n - 1 - k : k); }
+__device__ __forceinline__ int mirrorNode(int k, int n) { return k < 0 ? -k : (k > n ? 2 * n - k : k); }
 // halo slots farther than one reflection (grids narrower than the halo) are
 // clamped into the grid; the stencils never read them
 __device__ __forceinline__ int haloCell(int k, int n) {
   k = mirrorCell(k, n);
   return k < 0 ? 0 : (k >= n ? n - 1 : k);
 }
-__device__ __forceinline__ int mirrorNode(int k, int n) { return k < 0 ? -k : (k > n ? 2 * n - k : k); }
 
-// area of colour 1 in cell (i,j); also its marker count and BL colour
-__device__ double cellFraction(const FracParams &P, int i, int j, int *nmark, int *cbl) {
+// area of colour 1 in cell (i,j) from its corner colours (BL, BR, TR, TL)
+__device__ double cellFraction(const FracParams &P, int i, int j, int kBL, int kBR, int kTR, int kTL) {
   const size_t W1 = (size_t)P.nx + 1;
-  const int kBL = P.col[(size_t)j * W1 + i], kBR = P.col[(size_t)j * W1 + i + 1];
-  const int kTR = P.col[(size_t)(j + 1) * W1 + i + 1], kTL = P.col[(size_t)(j + 1) * W1 + i];
   const bool pb = kBL != kBR, pr = kBR != kTR, pt = kTL != kTR, pl = kBL != kTL;
   const int n = (int)pb + (int)pr + (int)pt + (int)pl;
-  *nmark = n;
-  *cbl = kBL;
   if (n == 0) return (double)kBL;
   const double hb = pb ? P.hoff[(size_t)j * P.nx + i] : 0.0;
   const double ht = pt ? P.hoff[(size_t)(j + 1) * P.nx + i] : 0.0;
@@ -620,21 +837,30 @@ __device__ double cellFraction(const FracParams &P, int i, int j, int *nmark, in
   const double vr = pr ? P.voff[(size_t)j * W1 + i + 1] : 0.0;
   if (n == 2) {
     // shoelace over the colour-1 corners and both markers, counter-clockwise
-    double px[6], py[6];
-    int m = 0;
-    if (kBL) { px[m] = 0.0; py[m] = 0.0; m++; }
-    if (pb) { px[m] = hb; py[m] = 0.0; m++; }
-    if (kBR) { px[m] = 1.0; py[m] = 0.0; m++; }
-    if (pr) { px[m] = 1.0; py[m] = vr; m++; }
-    if (kTR) { px[m] = 1.0; py[m] = 1.0; m++; }
-    if (pt) { px[m] = ht; py[m] = 1.0; m++; }
-    if (kTL) { px[m] = 0.0; py[m] = 1.0; m++; }
-    if (pl) { px[m] = 0.0; py[m] = vl; m++; }
-    double acc = 0.0;
-    for (int k = 0; k < m; k++) {
-      const int k1 = (k + 1 == m) ? 0 : k + 1;
-      acc += px[k] * py[k1] - px[k1] * py[k];
-    }
+    // from the bottom-left corner; each edge term is added as its second
+    // vertex arrives, the closing edge last
+    double fx = 0.0, fy = 0.0, qx = 0.0, qy = 0.0, acc = 0.0;
+    bool started = false;
+    auto vert = [&](double x, double y) {
+      if (!started) {
+        fx = x;
+        fy = y;
+        started = true;
+      } else {
+        acc += qx * y - x * qy;
+      }
+      qx = x;
+      qy = y;
+    };
+    if (kBL) vert(0.0, 0.0);
+    if (pb) vert(hb, 0.0);
+    if (kBR) vert(1.0, 0.0);
+    if (pr) vert(1.0, vr);
+    if (kTR) vert(1.0, 1.0);
+    if (pt) vert(ht, 1.0);
+    if (kTL) vert(0.0, 1.0);
+    if (pl) vert(0.0, vl);
+    acc += qx * fy - fx * qy;
     return 0.5 * acc;
   }
   // four markers: isolated corner triangles keep their corner colour, the
@@ -648,43 +874,50 @@ __device__ double cellFraction(const FracParams &P, int i, int j, int *nmark, in
 
 // Dense write of one grid row for the cells of uniform (not near) tiles:
 // C = the tile's colour, K = 0. Two cells per thread; rows of even length use
-// 16-byte non-temporal stores.
+// 16-byte non-temporal stores when the buffers allow it.
 typedef double v2d __attribute__((ext_vector_type(2)));
+
+template <int MODE>
+__device__ __forceinline__ void fillPair(const FracParams &P, const uint8_t *trow, size_t rowoff, int i) {
+  const int nx = P.nx;
+  const uint8_t t0 = trow[i / TS];
+  const bool two = i + 1 < nx;
+  const uint8_t t1 = two ? trow[(i + 1) / TS] : (uint8_t)1;
+  if (P.vec && !(t0 & 1) && !(t1 & 1)) {
+    if (MODE & 1) {
+      v2d c = {(double)(t0 >> 1), (double)(t1 >> 1)};
+      __builtin_nontemporal_store(c, (v2d *)&P.Cout[rowoff + i]);
+    }
+    if (MODE & 2) {
+      v2d z = {0.0, 0.0};
+      __builtin_nontemporal_store(z, (v2d *)&P.Kout[rowoff + i]);
+    }
+    return;
+  }
+  if (!(t0 & 1)) {
+    if (MODE & 1) P.Cout[rowoff + i] = (double)(t0 >> 1);
+    if (MODE & 2) P.Kout[rowoff + i] = 0.0;
+  }
+  if (two && !(t1 & 1)) {
+    if (MODE & 1) P.Cout[rowoff + i + 1] = (double)(t1 >> 1);
+    if (MODE & 2) P.Kout[rowoff + i + 1] = 0.0;
+  }
+}
 
 template <int MODE>
 __device__ __forceinline__ void fillRow(const FracParams &P, int j) {
   const uint8_t *trow = P.tinfo + (size_t)(j / TS) * P.ntx;
   const size_t rowoff = (size_t)j * P.nx;
-  const int nx = P.nx;
-  const bool vec = P.vec != 0;
-  for (int i = 2 * (int)threadIdx.x; i < nx; i += 2 * (int)blockDim.x) {
-    const uint8_t t0 = trow[i / TS];
-    const bool two = i + 1 < nx;
-    const uint8_t t1 = two ? trow[(i + 1) / TS] : (uint8_t)1;
-    if (vec && !(t0 & 1) && !(t1 & 1)) {
-      if (MODE & 1) {
-        v2d c = {(double)(t0 >> 1), (double)(t1 >> 1)};
-        __builtin_nontemporal_store(c, (v2d *)&P.Cout[rowoff + i]);
-      }
-      if (MODE & 2) {
-        v2d z = {0.0, 0.0};
-        __builtin_nontemporal_store(z, (v2d *)&P.Kout[rowoff + i]);
-      }
-      continue;
-    }
-    if (!(t0 & 1)) {
-      if (MODE & 1) P.Cout[rowoff + i] = (double)(t0 >> 1);
-      if (MODE & 2) P.Kout[rowoff + i] = 0.0;
-    }
-    if (two && !(t1 & 1)) {
-      if (MODE & 1) P.Cout[rowoff + i + 1] = (double)(t1 >> 1);
-      if (MODE & 2) P.Kout[rowoff + i + 1] = 0.0;
-    }
+  const int step = 2 * (int)blockDim.x;
+  for (int i = 2 * (int)threadIdx.x; i < P.nx; i += 4 * step) {
+#pragma unroll
+    for (int u = 0; u < 4; u++)
+      if (i + u * step < P.nx) fillPair<MODE>(P, trow, rowoff, i + u * step);
   }
 }
 
-// Heights along columns (rows == 0) or rows (rows == 1) around cell (i,j),
-// from the fraction tile in LDS; returns 1 and kappa on success.
+// Heights along columns (rows == 0) or rows (rows == 1) around cell (i,j);
+// returns 1 and kappa on success.
 template <class GetC, class GetN, class GetB>
 __device__ bool hfTry(int i, int j, int rows, double h, GetC getC, GetN getN, GetB getB, double *kap) {
   double y[3];
@@ -716,14 +949,16 @@ __device__ bool hfTry(int i, int j, int rows, double h, GetC getC, GetN getN, Ge
 }
 
 // Fraction and/or curvature of the whole grid in one persistent launch.
-// First the near tiles from the list: C (with marker count and BL colour) of
-// the tile plus a 3-cell halo in LDS, mirrored across walls, then C and/or
-// kappa of the tile's cells. Then the dense rows, where uniform tiles get
-// their colour and zero curvature. MODE 1: C only; 2: kappa from the
-// caller's C; 3: both.
+// First the near tiles from the list: node colours of the tile plus halo in
+// LDS; C, marker count and BL colour of every halo cell (mirrored across
+// walls), polygons only where markers are; then C and/or kappa of the tile's
+// cells. Then the dense rows, where uniform tiles get their colour and zero
+// curvature. MODE 1: C only; 2: kappa from the caller's C; 3: both.
 template <int MODE>
 __global__ __launch_bounds__(256) void k_frac_curv(FracParams P) {
-  constexpr int W = TS + 6;
+  constexpr int W = TS + 6;  // halo cells per side
+  constexpr int WN = W + 1;  // halo nodes per side
+  __shared__ uint8_t sNode[WN][WN];
   __shared__ double sC[W][W];
   __shared__ uint8_t sN[W][W];
   __shared__ uint8_t sB[W][W];
@@ -731,37 +966,75 @@ __global__ __launch_bounds__(256) void k_frac_curv(FracParams P) {
   const int tid = threadIdx.x;
   if (tid < 2) sCnt[tid] = 0;
   uint32_t interf = 0, hffail = 0;
-  const uint32_t ntile = *P.count;
-  for (uint32_t it = blockIdx.x; it < ntile; it += gridDim.x) {
-    const uint32_t T = P.list[it];
-    const int tx = (int)(T % (uint32_t)P.ntx), ty = (int)(T / (uint32_t)P.ntx);
+  const int nx = P.nx, ny = P.ny;
+  // The first tileBlocks workgroups take a static share of the near tiles;
+  // every workgroup then claims uniform rows in chunks, so the row stream
+  // starts at once and absorbs the tile workers as they finish.
+  __shared__ uint32_t sClaim;
+  if (blockIdx.x == 0 && tid == 0) {
+    // the other launch's counters, for the next launch (nothing reads them now)
+    P.workNext[0] = 0;
+    P.workNext[1] = 0;
+  }
+  const bool tileBlock = (int)blockIdx.x < P.tileBlocks;
+  const uint32_t ntile = tileBlock ? *P.count : 0u;
+  uint32_t ntiles_done = 0;
+  for (uint32_t it = blockIdx.x; it < ntile; it += (uint32_t)P.tileBlocks) {
+    __syncthreads();
+    const uint32_t tile = P.list[it];
+    const int tx = (int)(tile % (uint32_t)P.ntx), ty = (int)(tile / (uint32_t)P.ntx);
     const int x0 = tx * TS, y0 = ty * TS;
+    ntiles_done++;
+    for (int k = tid; k < WN * WN; k += blockDim.x) {
+      const int li = k % WN, lj = k / WN;
+      const int gx = x0 - 3 + li, gy = y0 - 3 + lj;
+      uint8_t c = 0;
+      if (gx >= 0 && gy >= 0 && gx <= nx && gy <= ny) c = P.col[(size_t)gy * (nx + 1) + gx];
+      sNode[lj][li] = c;
+    }
     __syncthreads();
     for (int k = tid; k < W * W; k += blockDim.x) {
       const int li = k % W, lj = k / W;
-      const int gi = haloCell(x0 - 3 + li, P.nx), gj = haloCell(y0 - 3 + lj, P.ny);
-      int nm, cbl;
-      double c = cellFraction(P, gi, gj, &nm, &cbl);
-      if (MODE == 2) c = P.Cin[(size_t)gj * P.nx + gi];
+      const int gx = x0 - 3 + li, gy = y0 - 3 + lj;
+      int kBL, kBR, kTR, kTL, gi, gj;
+      if (gx >= 0 && gy >= 0 && gx < nx && gy < ny) {
+        gi = gx;
+        gj = gy;
+        kBL = sNode[lj][li];
+        kBR = sNode[lj][li + 1];
+        kTR = sNode[lj + 1][li + 1];
+        kTL = sNode[lj + 1][li];
+      } else {
+        // ghost cell: the data of its mirror cell
+        gi = haloCell(gx, nx);
+        gj = haloCell(gy, ny);
+        const size_t W1 = (size_t)nx + 1;
+        kBL = P.col[(size_t)gj * W1 + gi];
+        kBR = P.col[(size_t)gj * W1 + gi + 1];
+        kTR = P.col[(size_t)(gj + 1) * W1 + gi + 1];
+        kTL = P.col[(size_t)(gj + 1) * W1 + gi];
+      }
+      const int nm = (kBL != kBR) + (kBR != kTR) + (kTL != kTR) + (kBL != kTL);
+      double c;
+      if (MODE == 2) c = P.Cin[(size_t)gj * nx + gi];
+      else c = cellFraction(P, gi, gj, kBL, kBR, kTR, kTL);
       sC[lj][li] = c;
       sN[lj][li] = (uint8_t)nm;
-      sB[lj][li] = (uint8_t)cbl;
+      sB[lj][li] = (uint8_t)kBL;
     }
     __syncthreads();
     for (int k = tid; k < TS * TS; k += blockDim.x) {
       const int li = k % TS, lj = k / TS;
       const int i = x0 + li, j = y0 + lj;
-      if (i >= P.nx || j >= P.ny) continue;
-      const size_t id = (size_t)j * P.nx + i;
+      if (i >= nx || j >= ny) continue;
+      const size_t id = (size_t)j * nx + i;
       if (MODE & 1) P.Cout[id] = sC[lj + 3][li + 3];
       if (MODE & 2) {
         double kap = 0.0;
         if (sN[lj + 3][li + 3] >= 2) {
           interf++;
-          const uint8_t *col = P.col;
-          const int nx = P.nx, ny = P.ny;
           auto nodeC = [&](int a, int b) -> int {
-            return col[(size_t)mirrorNode(b, ny) * (nx + 1) + mirrorNode(a, nx)];
+            return sNode[mirrorNode(b, ny) - y0 + 3][mirrorNode(a, nx) - x0 + 3];
           };
           int ncx = 0, ncy = 0;
           for (int m = j - 1; m <= j + 2; m++)
@@ -782,7 +1055,15 @@ __global__ __launch_bounds__(256) void k_frac_curv(FracParams P) {
       }
     }
   }
-  for (int j = blockIdx.x; j < P.ny; j += gridDim.x) fillRow<MODE>(P, j);
+  constexpr uint32_t ROWS = 8;
+  for (;;) {
+    __syncthreads();
+    if (tid == 0) sClaim = atomicAdd(&P.work[1], ROWS);
+    __syncthreads();
+    const uint32_t j0 = sClaim;
+    if (j0 >= (uint32_t)ny) break;
+    for (uint32_t j = j0; j < j0 + ROWS && j < (uint32_t)ny; j++) fillRow<MODE>(P, (int)j);
+  }
   if (MODE & 2) {
     if (interf) atomicAdd(&sCnt[0], interf);
     if (hffail) atomicAdd(&sCnt[1], hffail);
@@ -790,6 +1071,7 @@ __global__ __launch_bounds__(256) void k_frac_curv(FracParams P) {
     if (tid == 0) {
       if (sCnt[0]) atomicAdd(&P.ctr[C_INTERFACIAL], (unsigned long long)sCnt[0]);
       if (sCnt[1]) atomicAdd(&P.ctr[C_HF_FAIL], (unsigned long long)sCnt[1]);
+      if (ntiles_done) atomicAdd(&P.ctr[C_TILES_NEAR], (unsigned long long)ntiles_done);
     }
   }
 }
@@ -803,16 +1085,17 @@ hipError_t launch_sweep(int dir, const SweepParams &p, int grid, hipStream_t s) 
   return hipGetLastError();
 }
 
-hipError_t launch_init_has(const uint8_t *col, int nx, int ny, int ntx, int nty, uint8_t *has, uint8_t *nearPrev,
+hipError_t launch_init_has(const uint8_t *col, int nx, int ny, int ntx, int nty, uint16_t *has, uint8_t *nearPrev,
                            hipStream_t s) {
   hipLaunchKernelGGL(k_init_has, dim3(ntx * nty), dim3(256), 0, s, col, nx, ny, ntx, nty, has, nearPrev);
   return hipGetLastError();
 }
 
-hipError_t launch_compact(const uint8_t *has, uint8_t *nearPrev, uint8_t *tinfo, const uint8_t *col, int nx, int ntx,
+hipError_t launch_compact(const uint16_t *has, uint8_t *nearPrev, uint8_t *tinfo, const uint8_t *col, int nx, int ntx,
                           int nty, uint32_t *actList, uint32_t *nearList, uint32_t *counts, int slot, hipStream_t s) {
   const int n = ntx * nty;
-  hipLaunchKernelGGL(k_compact, dim3((n + 255) / 256), dim3(256), 0, s, has, nearPrev, tinfo, col, nx, ntx, nty,
+  const int per = 256 * CPT;
+  hipLaunchKernelGGL(k_compact, dim3((n + per - 1) / per), dim3(256), 0, s, has, nearPrev, tinfo, col, nx, ntx, nty,
                      actList, nearList, counts, slot);
   return hipGetLastError();
 }

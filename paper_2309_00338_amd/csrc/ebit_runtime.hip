@@ -19,14 +19,18 @@ struct ebit_handle {
   hipStream_t stream;
   int ntx, nty, ntiles;
   int nblocks;  // persistent grid for tile kernels
+  int fracTileBlocks;  // of which the fraction pass gives to near tiles
   // state copies [0], [1]
   uint8_t *col[2], *cen[2];
   double *hoff[2], *voff[2];
   int cur;  // copy holding the current state
   // tile tables
-  uint8_t *has, *nearPrev, *tinfo;
+  uint16_t *has;
+  uint8_t *nearPrev, *tinfo;
   uint32_t *actList, *nearList, *counts;  // counts: [act0, near0, act1, near1]
   int slot;                               // counts slot written by the last compaction
+  uint32_t *fracWork;  // claim counters of the fraction pass: two launches x [tiles, rows]
+  int fracParity;
   uint32_t *err;
   unsigned long long *ctr;
   int64_t step;
@@ -61,12 +65,13 @@ void carve(ebit_handle *h, char *base, size_t *total) {
     h->hoff[k] = c.take<double>(base, nh);
     h->voff[k] = c.take<double>(base, nv);
   }
-  h->has = c.take<uint8_t>(base, h->ntiles);
+  h->has = c.take<uint16_t>(base, h->ntiles);
   h->nearPrev = c.take<uint8_t>(base, h->ntiles);
   h->tinfo = c.take<uint8_t>(base, h->ntiles);
   h->actList = c.take<uint32_t>(base, h->ntiles);
   h->nearList = c.take<uint32_t>(base, h->ntiles);
   h->counts = c.take<uint32_t>(base, 4);
+  h->fracWork = c.take<uint32_t>(base, 4);
   h->err = c.take<uint32_t>(base, 1);
   h->ctr = c.take<unsigned long long>(base, NCOUNTERS);
   *total = (c.off + 255) & ~(size_t)255;
@@ -124,6 +129,8 @@ int upload(ebit_handle *h, const ebit_state *s) {
   }
   h->cur = 0;
   HIPCHK(hipMemsetAsync(h->counts, 0, 4 * sizeof(uint32_t), h->stream));
+  HIPCHK(hipMemsetAsync(h->fracWork, 0, 4 * sizeof(uint32_t), h->stream));
+  h->fracParity = 0;
   HIPCHK(hipMemsetAsync(h->err, 0, sizeof(uint32_t), h->stream));
   HIPCHK(hipMemsetAsync(h->ctr, 0, NCOUNTERS * sizeof(unsigned long long), h->stream));
   h->slot = 1;
@@ -189,6 +196,10 @@ FracParams frac_params(ebit_handle *h, const double *Cin, double *Cout, double *
   p.list = h->nearList;
   p.count = h->counts + 2 * h->slot + 1;
   p.ctr = h->ctr;
+  p.tileBlocks = h->fracTileBlocks;
+  p.work = h->fracWork + 2 * h->fracParity;
+  p.workNext = h->fracWork + 2 * (h->fracParity ^ 1);
+  h->fracParity ^= 1;
   p.vec = (h->g.nx % 2 == 0) && ((uintptr_t)Cout % 16 == 0) && ((uintptr_t)Kout % 16 == 0);
   return p;
 }
@@ -230,6 +241,15 @@ int ebit_create(const ebit_grid *grid, const ebit_state *init, void *ws_dev, siz
   int dev = 0, cus = 256;
   if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 256;
   h->nblocks = cus * 8;
+  {
+    double share = 0.5;
+    const char *e = getenv("EBIT_FRAC_TILE_SHARE");
+    if (e) share = atof(e);
+    if (!(share > 0.0)) share = 0.5;
+    if (share > 0.95) share = 0.95;
+    h->fracTileBlocks = (int)(h->nblocks * share);
+    if (h->fracTileBlocks < 1) h->fracTileBlocks = 1;
+  }
   rc = upload(h, init);
   if (rc) {
     free(h);

@@ -25,7 +25,10 @@ COUNTERS = (
     "markers", "annihilated", "three_landers", "ties", "fit_fallback", "fit_reject",
     "parity_fallback", "three_crossings", "cv_set", "cv_conflict", "cv_unresolved",
     "wall_violation", "invariant_fail", "hf_fail", "interfacial",
+    "tiles_swept", "tiles_empty", "tiles_near",
 )
+# counters that describe the GPU schedule and have no oracle counterpart
+SCHEDULE_COUNTERS = ("tiles_swept", "tiles_empty", "tiles_near")
 
 
 class ebit_grid(ctypes.Structure):
