@@ -76,6 +76,8 @@ struct FracParams {
 };
 
 // launchers (defined with the kernels)
+// resident workgroups per CU of: 0/1 the x/y sweep, 2/3/4 fraction modes 1/2/3
+int resident_blocks(int which);
 hipError_t launch_sweep(int dir, const SweepParams &p, int grid, hipStream_t s);
 hipError_t launch_init_has(const uint8_t *col, int nx, int ny, int ntx, int nty, uint16_t *has, uint8_t *nearPrev,
                            hipStream_t s);

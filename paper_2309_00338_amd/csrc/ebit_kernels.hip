@@ -109,12 +109,12 @@ __device__ __forceinline__ uint16_t segCodeOf(int k0, int k1, int k2, int k3, in
 struct Tile {
   int na, nb, a0, b0;
   const uint8_t (*col)[NH];   // old node colours   [b][a], a in [a0-2, a0+18]
-  const uint16_t (*seg)[NE];  // old cell segments  [b][a], a in [a0-2, a0+17]
-  const uint8_t (*cen)[NE];   // old centre colours [b][a]
+  const uint8_t (*cen)[NE];   // old centre colours [b][a], a in [a0-2, a0+17]
   const double (*sp)[NE];     // aligned (a,b): s' ; a in [a0-2,a0+17], b in [b0-2,b0+18]
   const double (*dd)[NH];     // unaligned (a,b): d ; a in [a0-2,a0+18], b in [b0-2,b0+17]
   const double (*tt)[NH];     // unaligned (a,b): t
-  const uint8_t (*ncol)[NN];  // new node colours, a in [a0, a0+16], b in [b0, b0+16]
+  const uint32_t *nrow;       // new node colours, row b-b0 in [0,16], bit a-a0 in [0,16]
+  const uint16_t (*seg)[NE];  // old cell segments [b][a], a in [a0-2, a0+17], b in [b0-2, b0+17]
   const int8_t (*keep)[NN + 1];  // kept source - t on new aligned edge (t,b), t in [a0-1,a0+16], b in [b0,b0+16]
 
   __device__ int C(int a, int b) const { return col[b - b0 + HALO][a - a0 + HALO]; }
@@ -125,18 +125,8 @@ struct Tile {
   __device__ double tU(int a, int b) const { return tt[b - b0 + HALO][a - a0 + HALO]; }
   __device__ int cenv(int p, int q) const { return cen[q - b0 + HALO][p - a0 + HALO]; }
   __device__ uint16_t segc(int p, int q) const { return seg[q - b0 + HALO][p - a0 + HALO]; }
-  __device__ int newC(int a, int b) const { return ncol[b - b0][a - a0]; }
+  __device__ int newC(int a, int b) const { return (nrow[b - b0] >> (a - a0)) & 1; }
 
-  // new corner colour from the old state: flipped by each aligned marker
-  // that crosses the node
-  __device__ int computeNewC(int a, int b) const {
-    int c = C(a, b);
-    if (a > 0 && a < na) {
-      if (presA(a - 1, b) && spv(a - 1, b) >= 1.0) c ^= 1;
-      if (presA(a, b) && spv(a, b) < 0.0) c ^= 1;
-    }
-    return c;
-  }
   // aligned markers landing on edge (a,b): their number and the kept source
   // (-1 when none): one lander is kept, of three the middle source
   __device__ int landers(int a, int b, int *keepSrc) const {
@@ -164,6 +154,7 @@ struct Tile {
     return (t < 0 || t >= na) ? -1 : t;
   }
   // the aligned marker of old edge (p,q) is the one kept on new edge target
+  // (target in [a0-1, a0+16], q in [b0, b0+16])
   __device__ bool keptOn(int p, int q, int target) const {
     if (landTarget(p, q) != target) return false;
     return keep[q - b0][target - a0 + 1] == p - target;
@@ -401,6 +392,10 @@ __device__ double newUnaligned(const Tile &T, int a, int b, int *resRight, int *
 
 // ---------------------------------------------------------------------------
 // Sweep kernel: one workgroup per active tile (persistent over the list).
+// Frame coordinates: halo slot (la, lb) is node (a0-2+la, b0-2+lb). Colours
+// are also kept as one bit mask per frame row, so present edges, new edges
+// and 4-marker cells are found with a few word operations per row and only
+// the edges that carry markers are visited one by one.
 // ---------------------------------------------------------------------------
 template <int DIR>
 __global__ __launch_bounds__(256, 8) void k_sweep(SweepParams P) {
@@ -409,16 +404,17 @@ __global__ __launch_bounds__(256, 8) void k_sweep(SweepParams P) {
   __shared__ double sSp[NH][NE];
   __shared__ double sD[NE][NH];
   __shared__ double sT[NE][NH];
-  __shared__ uint8_t sNcol[NN][NN];
+  __shared__ uint32_t sRow[NH];     // old colours, bit la of frame row lb
+  __shared__ uint32_t sNRow[NN];    // new colours, bit a-a0 of row b-b0
+  __shared__ uint32_t sRecv[NN];    // new aligned edges (a,b) that receive a lander, bit a-a0
   __shared__ uint16_t sSeg[NE][NE];
   __shared__ int8_t sKeep[NN][NN + 1];
+  __shared__ uint32_t sTiles[64];   // this workgroup's first tiles
   __shared__ int8_t sRight[TS][NN];  // [lb][la]: result for the cell right of line a
   __shared__ int8_t sLeft[TS][NN];   // result for the cell left of line a
+  __shared__ uint16_t sAdv[2 * NH * NE];
   __shared__ uint16_t sWork[TS * NN];
-  __shared__ uint32_t sNWork;
-  __shared__ uint16_t sAdv[2 * NH * NE];  // present halo edges to advect
-  __shared__ uint32_t sNAdv;
-  __shared__ uint32_t sHas;
+  __shared__ uint32_t sNAdv, sNWork, sHas;
   __shared__ uint32_t sCnt[NCOUNTERS];
   __shared__ uint32_t sErr;
 
@@ -448,7 +444,7 @@ __global__ __launch_bounds__(256, 8) void k_sweep(SweepParams P) {
   T.sp = sSp;
   T.dd = sD;
   T.tt = sT;
-  T.ncol = sNcol;
+  T.nrow = sNRow;
   T.seg = sSeg;
   T.keep = sKeep;
 
@@ -476,21 +472,30 @@ __global__ __launch_bounds__(256, 8) void k_sweep(SweepParams P) {
   };
 
   const uint32_t ntile = *P.count;
-  if (blockIdx.x < ntile) prefetch(P.list[blockIdx.x]);
+  // this workgroup's tile indices, so no index load waits in the loop
+  if (tid < 64 && blockIdx.x + tid * gridDim.x < ntile) sTiles[tid] = P.list[blockIdx.x + tid * gridDim.x];
+  __syncthreads();
+  auto tileAt = [&](uint32_t it) -> uint32_t {
+    const uint32_t k = (it - blockIdx.x) / gridDim.x;
+    return k < 64 ? sTiles[k] : P.list[it];
+  };
+  if (blockIdx.x < ntile) prefetch(tileAt(blockIdx.x));
   for (uint32_t it = blockIdx.x; it < ntile; it += gridDim.x) {
-    const uint32_t tile = P.list[it];
+    const uint32_t tile = tileAt(it);
     const int tx = (int)(tile % (uint32_t)P.ntx), ty = (int)(tile / (uint32_t)P.ntx);
     const int x0 = tx * TS, y0 = ty * TS;
     const int a0 = DIR == 0 ? x0 : y0, b0 = DIR == 0 ? y0 : x0;
     T.a0 = a0;
     T.b0 = b0;
-    __syncthreads();  // previous tile done with LDS
+    __syncthreads();  // the previous tile is done with LDS
     if (tid == 0) {
       sNWork = 0;
       sNAdv = 0;
       sHas = 0;
     }
-    // --- stage old colours (nodes) and centre colours -----------------------
+    if (tid < NH) sRow[tid] = 0;
+    if (tid < NN) sRecv[tid] = 0;
+    // --- stage old colours and centre colours --------------------------------
     {
       auto putNode = [&](int k, uint8_t c) {
         if (k >= NH * NH) return;
@@ -510,30 +515,73 @@ __global__ __launch_bounds__(256, 8) void k_sweep(SweepParams P) {
       putCell(tid + 256, pe1);
     }
     __syncthreads();
-    if (it + gridDim.x < ntile) prefetch(P.list[it + gridDim.x]);
-    // a tile whose staged nodes (ghosts staged as 0) all share one colour has
-    // no marker in reach and keeps its state: copy it over and move on
+    // colour-1 nodes set their bit in the frame-row masks
     {
-      const uint8_t c0 = sCol[0][0];
-      int any = 0;
-      for (int k = tid; k < NH * NH; k += blockDim.x) any |= (&sCol[0][0])[k] != c0;
-      if (!__syncthreads_or(any)) {
-        for (int k = tid; k < NN * NN; k += blockDim.x) {
-          const int li = k % NN, lj = k / NN;
-          const int x = x0 + li, y = y0 + lj;
-          if (x > P.nx || y > P.ny) continue;
-          const int hx = li + HALO, hy = lj + HALO;
-          const uint8_t c = DIR == 0 ? sCol[hy][hx] : sCol[hx][hy];
-          if ((li < TS || x == P.nx) && (lj < TS || y == P.ny)) P.ncol[(size_t)y * (P.nx + 1) + x] = c;
-          if (li < TS && lj < TS && x < P.nx && y < P.ny)
-            P.ncen[(size_t)y * P.nx + x] = DIR == 0 ? sCen[hy][hx] : sCen[hx][hy];
+      auto bitNode = [&](int k, uint8_t c) {
+        if (k >= NH * NH || !c) return;
+        const int hx = k % NH, hy = k / NH;
+        const int la = DIR == 0 ? hx : hy, lb = DIR == 0 ? hy : hx;
+        atomicOr(&sRow[lb], 1u << la);
+      };
+      bitNode(tid, pc0);
+      bitNode(tid + 256, pc1);
+    }
+    __syncthreads();
+    // --- list the present halo edges -----------------------------------------
+    // aligned (a,b): la in [0,20) with a in [0,na), b = b0-2+lb in [0,nb];
+    // unaligned (a,b): lb in [0,20) with b in [0,nb), la in [0,21) with a in [0,na]
+    const int laMinA = max(0, HALO - a0), laMaxA = min(NE - 1, na - 1 - a0 + HALO);
+    const int laMaxU = min(NH - 1, na - a0 + HALO);
+    const uint32_t maskA = laMaxA >= laMinA ? ((2u << laMaxA) - 1u) & ~((1u << laMinA) - 1u) : 0u;
+    const uint32_t maskU = laMaxU >= laMinA ? ((2u << laMaxU) - 1u) & ~((1u << laMinA) - 1u) : 0u;
+    if (tid < NH) {
+      const int lb = tid, b = b0 - HALO + lb;
+      const uint32_t r = sRow[lb];
+      if (b >= 0 && b <= nb) {
+        uint32_t m = (r ^ (r >> 1)) & maskA;
+        if (m) {
+          uint32_t w = atomicAdd(&sNAdv, (uint32_t)__popc(m));
+          while (m) {
+            const int la = __ffs(m) - 1;
+            m &= m - 1;
+            sAdv[w++] = (uint16_t)(lb * NE + la);
+          }
         }
-        if (tid == 0) {
-          P.has[tile] = 0;
-          cnt.add(C_TILES_EMPTY, 1u);
-        }
-        continue;
       }
+      if (lb < NE && b >= 0 && b < nb) {
+        uint32_t m = (r ^ sRow[lb + 1]) & maskU;
+        if (m) {
+          uint32_t w = atomicAdd(&sNAdv, (uint32_t)__popc(m));
+          while (m) {
+            const int la = __ffs(m) - 1;
+            m &= m - 1;
+            sAdv[w++] = (uint16_t)(0x8000u | (lb * NH + la));
+          }
+        }
+      }
+    }
+    // new colours start from the old ones: node (a0+i, b0+j) = slot (i+2, j+2)
+    if (tid < NN) sNRow[tid] = (sRow[tid + HALO] >> HALO) & ((1u << NN) - 1u);
+    __syncthreads();
+    const uint32_t nadv = sNAdv;
+    if (nadv == 0) {
+      // no marker in reach: the tile keeps its state
+      for (int k = tid; k < NN * NN; k += blockDim.x) {
+        const int li = k % NN, lj = k / NN;
+        const int x = x0 + li, y = y0 + lj;
+        if (x > P.nx || y > P.ny) continue;
+        const int hx = li + HALO, hy = lj + HALO;
+        if ((li < TS || x == P.nx) && (lj < TS || y == P.ny))
+          P.ncol[(size_t)y * (P.nx + 1) + x] = DIR == 0 ? sCol[hy][hx] : sCol[hx][hy];
+        if (li < TS && lj < TS && x < P.nx && y < P.ny)
+          P.ncen[(size_t)y * P.nx + x] = DIR == 0 ? sCen[hy][hx] : sCen[hx][hy];
+      }
+      if (tid == 0) {
+        P.has[tile] = 0;
+        cnt.add(C_TILES_EMPTY, 1u);
+      }
+      if (it + gridDim.x < ntile) prefetch(tileAt(it + gridDim.x));
+      continue;
     }
     if (tid == 0) cnt.add(C_TILES_SWEPT, 1u);
     // old segments of the halo cells (frame coordinates)
@@ -541,95 +589,102 @@ __global__ __launch_bounds__(256, 8) void k_sweep(SweepParams P) {
       const int la = k % NE, lb = k / NE;
       sSeg[lb][la] = segCodeOf(sCol[lb][la], sCol[lb][la + 1], sCol[lb + 1][la + 1], sCol[lb + 1][la], sCen[lb][la]);
     }
-    // --- advect the present markers of the halo (Eq. marker_dis) -------------
-    // Aligned edges (a,b): a in [a0-2, a0+17], b in [b0-2, b0+18]; unaligned
-    // edges (a,b): a in [a0-2, a0+18], b in [b0-2, b0+17]. The present ones
-    // are first listed in LDS, then each thread advects one listed marker, so
-    // all offsets and face velocities are fetched in a single round.
-    for (int k = tid; k < NH * NE; k += blockDim.x) {
-      int la, lb;
-      if (DIR == 0) { la = k % NE; lb = k / NE; }
-      else { lb = k % NH; la = k / NH; }
-      int a = a0 - HALO + la, b = b0 - HALO + lb;
-      if (a >= 0 && a < na && b >= 0 && b <= nb && sCol[lb][la] != sCol[lb][la + 1])
-        sAdv[atomicAdd(&sNAdv, 1u)] = (uint16_t)(lb * NE + la);
-      if (DIR == 0) { la = k % NH; lb = k / NH; }
-      else { lb = k % NE; la = k / NE; }
-      a = a0 - HALO + la;
-      b = b0 - HALO + lb;
-      if (a >= 0 && a <= na && b >= 0 && b < nb && sCol[lb][la] != sCol[lb + 1][la])
-        sAdv[atomicAdd(&sNAdv, 1u)] = (uint16_t)(0x8000u | (lb * NH + la));
-    }
-    __syncthreads();
-    {
-      const uint32_t nadv = sNAdv;
-      for (uint32_t w = tid; w < nadv; w += blockDim.x) {
-        const uint32_t code = sAdv[w];
-        if (!(code & 0x8000u)) {
-          const int la = code % NE, lb = code / NE;
-          const int a = a0 - HALO + la, b = b0 - HALO + lb;
-          const double s = alo[G.ale(a, b)];
-          const double ub = lerp(lerp(V(a, b - 1), V(a + 1, b - 1), s), lerp(V(a, b), V(a + 1, b), s), 0.5);
-          const double d = ub * lam;
-          const double spv = s + d;
-          sSp[lb][la] = spv;
-          const bool own = la >= HALO && la < HALO + TS && lb >= HALO && (lb < HALO + TS || b == nb);
-          if (own) {
-            cnt.add(C_MARKERS, 1u);
-            if (fabs(d) > 0.5) atomicOr(&sErr, ERRBIT_CFL);
-            if ((spv >= 1.0 && a + 1 >= na) || (spv < 0.0 && a == 0)) atomicOr(&sErr, ERRBIT_DOMAIN);
+    // --- advect the listed markers (Eq. marker_dis), flip crossed nodes ------
+    for (uint32_t w = tid; w < nadv; w += blockDim.x) {
+      const uint32_t code = sAdv[w];
+      if (!(code & 0x8000u)) {
+        const int la = code % NE, lb = code / NE;
+        const int a = a0 - HALO + la, b = b0 - HALO + lb;
+        const double s = alo[G.ale(a, b)];
+        const double ub = lerp(lerp(V(a, b - 1), V(a + 1, b - 1), s), lerp(V(a, b), V(a + 1, b), s), 0.5);
+        const double d = ub * lam;
+        const double spv = s + d;
+        sSp[lb][la] = spv;
+        const bool own = la >= HALO && la < HALO + TS && lb >= HALO && (lb < HALO + TS || b == nb);
+        if (own) {
+          cnt.add(C_MARKERS, 1u);
+          if (fabs(d) > 0.5) atomicOr(&sErr, ERRBIT_CFL);
+          if ((spv >= 1.0 && a + 1 >= na) || (spv < 0.0 && a == 0)) atomicOr(&sErr, ERRBIT_DOMAIN);
+        }
+        // the crossed node flips; the edge it lands on receives a lander
+        const int j = b - b0;
+        if (j >= 0 && j < NN) {
+          int flip = -1, t = a;
+          if (spv >= 1.0) {
+            if (a + 1 < na) flip = a + 1;
+            t = a + 1 < na ? a + 1 : -1;
+          } else if (spv < 0.0) {
+            if (a > 0) flip = a;
+            t = a > 0 ? a - 1 : -1;
           }
-        } else {
-          const uint32_t c = code & 0x7fffu;
-          const int la = c % NH, lb = c / NH;
-          const int a = a0 - HALO + la, b = b0 - HALO + lb;
-          const double t = uno[G.une(a, b)];
-          const double v0 = V(a, b - 1), v1 = V(a, b), v2 = V(a, b + 1);
-          const double ub = t < 0.5 ? lerp(v0, v1, t + 0.5) : lerp(v1, v2, t - 0.5);
-          const double d = ub * lam;
-          const bool wall = a == 0 || a == na;
-          sT[lb][la] = t;
-          sD[lb][la] = wall ? 0.0 : d;
-          const bool own = la >= HALO && (la < HALO + TS || a == na) && lb >= HALO && lb < HALO + TS;
-          if (own) {
-            cnt.add(C_MARKERS, 1u);
-            if (fabs(d) > 0.5) atomicOr(&sErr, ERRBIT_CFL);
-            if (wall && d != 0.0) cnt.add(C_WALL_VIOLATION, 1u);
-          }
+          if (flip >= a0 && flip <= a0 + TS) atomicXor(&sNRow[j], 1u << (flip - a0));
+          if (t >= a0 && t < a0 + TS) atomicOr(&sRecv[j], 1u << (t - a0));
+        }
+      } else {
+        const uint32_t c = code & 0x7fffu;
+        const int la = c % NH, lb = c / NH;
+        const int a = a0 - HALO + la, b = b0 - HALO + lb;
+        const double t = uno[G.une(a, b)];
+        const double v0 = V(a, b - 1), v1 = V(a, b), v2 = V(a, b + 1);
+        const double ub = t < 0.5 ? lerp(v0, v1, t + 0.5) : lerp(v1, v2, t - 0.5);
+        const double d = ub * lam;
+        const bool wall = a == 0 || a == na;
+        sT[lb][la] = t;
+        sD[lb][la] = wall ? 0.0 : d;
+        const bool own = la >= HALO && (la < HALO + TS || a == na) && lb >= HALO && lb < HALO + TS;
+        if (own) {
+          cnt.add(C_MARKERS, 1u);
+          if (fabs(d) > 0.5) atomicOr(&sErr, ERRBIT_CFL);
+          if (wall && d != 0.0) cnt.add(C_WALL_VIOLATION, 1u);
         }
       }
     }
-    __syncthreads();
-    // --- new corner colours of nodes [a0, a0+16] x [b0, b0+16] ---------------
-    for (int k = tid; k < NN * NN; k += blockDim.x) {
-      const int hx = k % NN, hy = k / NN;
-      const int la = DIR == 0 ? hx : hy, lb = DIR == 0 ? hy : hx;
-      const int a = a0 + la, b = b0 + lb;
-      int c = 0;
-      if (a <= na && b <= nb) {
-        c = T.computeNewC(a, b);
-        const bool own = (la < TS || a == na) && (lb < TS || b == nb);
-        if (own) P.ncol[G.node(a, b)] = (uint8_t)c;
-      }
-      sNcol[lb][la] = (uint8_t)c;
+    // result slots of the new unaligned edges start empty
+    for (int k = tid; k < TS * NN; k += blockDim.x) {
+      (&sRight[0][0])[k] = -1;
+      (&sLeft[0][0])[k] = -1;
     }
+    // the next tile's colours are fetched while this one computes
+    if (it + gridDim.x < ntile) prefetch(tileAt(it + gridDim.x));
     __syncthreads();
-    uint32_t hasm = 0;
-    // --- new aligned edges (landers): kept sources for t in [a0-1, a0+16] ----
+    // kept sources of new aligned edges (t,b), t in [a0-1, a0+16], b in [b0, b0+16]
     for (int k = tid; k < (TS + 2) * NN; k += blockDim.x) {
-      int lt, lb;
-      if (DIR == 0) { lt = k % (TS + 2); lb = k / (TS + 2); }
-      else { lb = k % NN; lt = k / NN; }
+      const int lt = k % (TS + 2), lb = k / (TS + 2);
       const int a = a0 - 1 + lt, b = b0 + lb;
       int8_t kr = -2;
       if (a >= 0 && a < na && b <= nb) {
         int keep;
-        const int n = T.landers(a, b, &keep);
+        T.landers(a, b, &keep);
         if (keep >= 0) kr = (int8_t)(keep - a);
-        if (lt >= 1 && lt <= TS && (lb < TS || b == nb)) {
+      }
+      sKeep[lb][lt] = kr;
+    }
+    uint32_t hasm = 0;
+    // --- new node colours out; new aligned edges; unaligned work list --------
+    for (int k = tid; k < NN * NN; k += blockDim.x) {
+      const int hx = k % NN, hy = k / NN;
+      const int la = DIR == 0 ? hx : hy, lb = DIR == 0 ? hy : hx;
+      const int a = a0 + la, b = b0 + lb;
+      if (a <= na && b <= nb && (la < TS || a == na) && (lb < TS || b == nb))
+        P.ncol[G.node(a, b)] = (uint8_t)((sNRow[lb] >> la) & 1u);
+    }
+    if (tid < NN) {
+      // new aligned edges (a,b), a in [a0, a0+15], on row b = b0+tid
+      const int j = tid, b = b0 + j;
+      const uint32_t valid = (1u << min(TS, max(0, na - a0))) - 1u;
+      if (b <= nb && (j < TS || b == nb)) {
+        const uint32_t nr = sNRow[j];
+        const uint32_t pres = (nr ^ (nr >> 1)) & valid;
+        uint32_t m = pres | (sRecv[j] & valid);
+        while (m) {
+          const int i = __ffs(m) - 1;
+          m &= m - 1;
+          const int a = a0 + i;
+          int keep;
+          const int n = T.landers(a, b, &keep);
           if (n == 3) cnt.add(C_THREE_LANDERS, 1u);
-          cnt.add(C_ANNIHILATED, (uint32_t)((uint32_t)(n - (n & 1))));
-          const bool newpres = T.newC(a, b) != T.newC(a + 1, b);
+          cnt.add(C_ANNIHILATED, (uint32_t)(n - (n & 1)));
+          const bool newpres = (pres >> i) & 1u;
           if ((int)newpres != (n & 1)) cnt.add(C_INVARIANT_FAIL, 1u);
           double o = 0.0;
           if (keep >= 0) {
@@ -643,29 +698,26 @@ __global__ __launch_bounds__(256, 8) void k_sweep(SweepParams P) {
           }
         }
       }
-      sKeep[lb][lt] = kr;
-    }
-    // --- the unaligned work list ---------------------------------------------
-    for (int k = tid; k < TS * NN; k += blockDim.x) {
-      // unaligned edge on line a in [a0, a0+16], row b in [b0, b0+15]
-      {
-        int la, lb;
-        if (DIR == 0) { la = k % NN; lb = k / NN; }
-        else { lb = k % TS; la = k / TS; }
-        const int a = a0 + la, b = b0 + lb;
-        sRight[lb][la] = -1;
-        sLeft[lb][la] = -1;
-        if (a <= na && b < nb) {
-          const bool own = la < TS || a == na;
+    } else if (tid >= 64 && tid < 64 + TS) {
+      // new unaligned edges on lines a in [a0, a0+16], row b = b0+j
+      const int j = tid - 64, b = b0 + j;
+      if (b < nb) {
+        const uint32_t lines = (1u << min(NN, max(0, na + 1 - a0))) - 1u;
+        uint32_t m = (sNRow[j] ^ sNRow[j + 1]) & lines;
+        while (m) {
+          const int i = __ffs(m) - 1;
+          m &= m - 1;
+          const int a = a0 + i;
+          const bool own = i < TS || a == na;
           if (a == 0 || a == na) {
             // walls hold their markers (wall nodes never change colour)
-            if (own && T.presU(a, b)) {
+            if (own) {
               unn[G.une(a, b)] = T.tU(a, b);
               hasm |= DIR == 0 ? maskV(a, b, x0, y0) : maskH(b, a, x0, y0);
             }
-          } else if (T.newC(a, b) != T.newC(a, b + 1)) {
+          } else {
             const uint32_t w = atomicAdd(&sNWork, 1u);
-            sWork[w] = (uint16_t)(lb * NN + la);
+            sWork[w] = (uint16_t)(j * NN + i);
           }
         }
       }
@@ -704,8 +756,9 @@ __global__ __launch_bounds__(256, 8) void k_sweep(SweepParams P) {
         cc = right;
         cnt.add(C_CV_SET, 1u);
       } else {
-        const int k0 = T.newC(a, b), k1 = T.newC(a + 1, b), k2 = T.newC(a + 1, b + 1), k3 = T.newC(a, b + 1);
-        if ((k0 != k1) + (k1 != k2) + (k3 != k2) + (k0 != k3) == 4) cnt.add(C_CV_UNRESOLVED, 1u);
+        const uint32_t r0 = sNRow[lb] >> la, r1 = sNRow[lb + 1] >> la;
+        const uint32_t k0 = r0 & 1u, k1 = (r0 >> 1) & 1u, k3 = r1 & 1u, k2 = (r1 >> 1) & 1u;
+        if (k0 != k1 && k1 != k2 && k3 != k2 && k0 != k3) cnt.add(C_CV_UNRESOLVED, 1u);
       }
       P.ncen[G.cell(a, b)] = (uint8_t)cc;
     }
@@ -1079,6 +1132,22 @@ __global__ __launch_bounds__(256) void k_frac_curv(FracParams P) {
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+// Workgroups of a kernel that are resident on one CU at once (persistent
+// grids are sized to exactly fill the GPU, so the static tile shares of all
+// workgroups run concurrently).
+int resident_blocks(int which) {
+  int n = 0;
+  hipError_t e = hipErrorInvalidValue;
+  switch (which) {
+    case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_sweep<0>, 256, 0); break;
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_sweep<1>, 256, 0); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_frac_curv<1>, 256, 0); break;
+    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_frac_curv<2>, 256, 0); break;
+    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_frac_curv<3>, 256, 0); break;
+  }
+  return (e == hipSuccess && n > 0) ? n : 1;
+}
+
 hipError_t launch_sweep(int dir, const SweepParams &p, int grid, hipStream_t s) {
   if (dir == 0) hipLaunchKernelGGL(k_sweep<0>, dim3(grid), dim3(256), 0, s, p);
   else hipLaunchKernelGGL(k_sweep<1>, dim3(grid), dim3(256), 0, s, p);

@@ -18,8 +18,9 @@ struct ebit_handle {
   ebit_grid g;
   hipStream_t stream;
   int ntx, nty, ntiles;
-  int nblocks;  // persistent grid for tile kernels
-  int fracTileBlocks;  // of which the fraction pass gives to near tiles
+  int sweepBlocks[2];  // persistent grids: x and y sweeps
+  int fracBlocks[3];   // fraction modes 1, 2, 3
+  int fracTileBlocks[3];  // of which the fraction pass gives to near tiles
   // state copies [0], [1]
   uint8_t *col[2], *cen[2];
   double *hoff[2], *voff[2];
@@ -173,12 +174,12 @@ int sweep(ebit_handle *h, int dir, const double *u, const double *v, double dt) 
   p.has = h->has;
   p.err = h->err;
   p.ctr = h->ctr;
-  HIPCHK(launch_sweep(dir, p, h->nblocks, h->stream));
+  HIPCHK(launch_sweep(dir, p, h->sweepBlocks[dir], h->stream));
   h->cur = nxt;
   return compact(h);
 }
 
-FracParams frac_params(ebit_handle *h, const double *Cin, double *Cout, double *Kout) {
+FracParams frac_params(ebit_handle *h, int mode, const double *Cin, double *Cout, double *Kout) {
   FracParams p;
   p.nx = h->g.nx;
   p.ny = h->g.ny;
@@ -196,7 +197,7 @@ FracParams frac_params(ebit_handle *h, const double *Cin, double *Cout, double *
   p.list = h->nearList;
   p.count = h->counts + 2 * h->slot + 1;
   p.ctr = h->ctr;
-  p.tileBlocks = h->fracTileBlocks;
+  p.tileBlocks = h->fracTileBlocks[mode - 1];
   p.work = h->fracWork + 2 * h->fracParity;
   p.workNext = h->fracWork + 2 * (h->fracParity ^ 1);
   h->fracParity ^= 1;
@@ -240,15 +241,18 @@ int ebit_create(const ebit_grid *grid, const ebit_state *init, void *ws_dev, siz
   carve(h, (char *)ws_dev, &tot);
   int dev = 0, cus = 256;
   if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 256;
-  h->nblocks = cus * 8;
+  for (int d = 0; d < 2; d++) h->sweepBlocks[d] = cus * resident_blocks(d);
   {
     double share = 0.5;
     const char *e = getenv("EBIT_FRAC_TILE_SHARE");
     if (e) share = atof(e);
     if (!(share > 0.0)) share = 0.5;
     if (share > 0.95) share = 0.95;
-    h->fracTileBlocks = (int)(h->nblocks * share);
-    if (h->fracTileBlocks < 1) h->fracTileBlocks = 1;
+    for (int m = 0; m < 3; m++) {
+      h->fracBlocks[m] = cus * resident_blocks(2 + m);
+      h->fracTileBlocks[m] = (int)(h->fracBlocks[m] * share);
+      if (h->fracTileBlocks[m] < 1) h->fracTileBlocks[m] = 1;
+    }
   }
   rc = upload(h, init);
   if (rc) {
@@ -271,8 +275,8 @@ int ebit_advect(ebit_handle *h, const double *u_dev, const double *v_dev, double
 
 int ebit_fraction(ebit_handle *h, double *C_dev) {
   if (!h || !C_dev) return EBIT_ERR_ARG;
-  FracParams p = frac_params(h, nullptr, C_dev, nullptr);
-  HIPCHK(launch_frac_curv(1, p, h->nblocks, h->stream));
+  FracParams p = frac_params(h, 1, nullptr, C_dev, nullptr);
+  HIPCHK(launch_frac_curv(1, p, h->fracBlocks[0], h->stream));
   h->fracEpoch = h->epoch;
   return EBIT_OK;
 }
@@ -280,15 +284,15 @@ int ebit_fraction(ebit_handle *h, double *C_dev) {
 int ebit_curvature(ebit_handle *h, const double *C_dev, double *K_dev) {
   if (!h || !C_dev || !K_dev) return EBIT_ERR_ARG;
   if (h->fracEpoch != h->epoch) return EBIT_ERR_STATE;
-  FracParams p = frac_params(h, C_dev, nullptr, K_dev);
-  HIPCHK(launch_frac_curv(2, p, h->nblocks, h->stream));
+  FracParams p = frac_params(h, 2, C_dev, nullptr, K_dev);
+  HIPCHK(launch_frac_curv(2, p, h->fracBlocks[1], h->stream));
   return EBIT_OK;
 }
 
 int ebit_fraction_curvature(ebit_handle *h, double *C_dev, double *K_dev) {
   if (!h || !C_dev || !K_dev) return EBIT_ERR_ARG;
-  FracParams p = frac_params(h, nullptr, C_dev, K_dev);
-  HIPCHK(launch_frac_curv(3, p, h->nblocks, h->stream));
+  FracParams p = frac_params(h, 3, nullptr, C_dev, K_dev);
+  HIPCHK(launch_frac_curv(3, p, h->fracBlocks[2], h->stream));
   h->fracEpoch = h->epoch;
   return EBIT_OK;
 }
