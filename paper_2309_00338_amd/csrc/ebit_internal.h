@@ -51,7 +51,29 @@ struct SweepParams {
   const uint32_t *list;
   const uint32_t *count;
   uint16_t *has;  // per tile: where its markers sit (any / near a side / near a corner)
+  double *sp;     // advected aligned offsets s' of present edges (aligned-edge layout)
+  double *dd;     // displacements of present unaligned markers (unaligned-edge layout)
+  uint32_t *jobs; // new unaligned markers for the fit kernel (unaligned-edge index)
+  uint32_t *njobs;
   uint32_t *err;
+  unsigned long long *ctr;
+};
+
+struct FitParams {
+  int nx, ny;
+  const uint8_t *col;   // old node colours
+  const uint8_t *cen;   // old centre colours
+  const uint8_t *ncol;  // new node colours
+  const double *sp;
+  const double *dd;
+  const double *hoff;   // old offsets
+  const double *voff;
+  double *nhoff;        // new offsets
+  double *nvoff;
+  uint8_t *ncen;        // new centre colours
+  uint8_t *zr;          // per unaligned edge: centre-CV results of its fit
+  const uint32_t *jobs;
+  const uint32_t *njobs;
   unsigned long long *ctr;
 };
 
@@ -76,9 +98,12 @@ struct FracParams {
 };
 
 // launchers (defined with the kernels)
-// resident workgroups per CU of: 0/1 the x/y sweep, 2/3/4 fraction modes 1/2/3
+// resident workgroups per CU of: 0/1 the x/y sweep, 2/3/4 fraction modes 1/2/3,
+// 5/6 the x/y fit, 7 the centre kernel
 int resident_blocks(int which);
 hipError_t launch_sweep(int dir, const SweepParams &p, int grid, hipStream_t s);
+hipError_t launch_fit(int dir, const FitParams &p, int grid, hipStream_t s);
+hipError_t launch_centre(int dir, const FitParams &p, int grid, hipStream_t s);
 hipError_t launch_init_has(const uint8_t *col, int nx, int ny, int ntx, int nty, uint16_t *has, uint8_t *nearPrev,
                            hipStream_t s);
 hipError_t launch_compact(const uint16_t *has, uint8_t *nearPrev, uint8_t *tinfo, const uint8_t *col, int nx, int ntx,

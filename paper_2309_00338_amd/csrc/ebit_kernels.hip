@@ -114,8 +114,6 @@ struct Tile {
   const double (*dd)[NH];     // unaligned (a,b): d ; a in [a0-2,a0+18], b in [b0-2,b0+17]
   const double (*tt)[NH];     // unaligned (a,b): t
   const uint32_t *nrow;       // new node colours, row b-b0 in [0,16], bit a-a0 in [0,16]
-  const uint16_t (*seg)[NE];  // old cell segments [b][a], a in [a0-2, a0+17], b in [b0-2, b0+17]
-  const int8_t (*keep)[NN + 1];  // kept source - t on new aligned edge (t,b), t in [a0-1,a0+16], b in [b0,b0+16]
 
   __device__ int C(int a, int b) const { return col[b - b0 + HALO][a - a0 + HALO]; }
   __device__ bool presA(int a, int b) const { return C(a, b) != C(a + 1, b); }
@@ -124,11 +122,57 @@ struct Tile {
   __device__ double dU(int a, int b) const { return dd[b - b0 + HALO][a - a0 + HALO]; }
   __device__ double tU(int a, int b) const { return tt[b - b0 + HALO][a - a0 + HALO]; }
   __device__ int cenv(int p, int q) const { return cen[q - b0 + HALO][p - a0 + HALO]; }
-  __device__ uint16_t segc(int p, int q) const { return seg[q - b0 + HALO][p - a0 + HALO]; }
   __device__ int newC(int a, int b) const { return (nrow[b - b0] >> (a - a0)) & 1; }
 
   // aligned markers landing on edge (a,b): their number and the kept source
   // (-1 when none): one lander is kept, of three the middle source
+  __device__ int landers(int a, int b, int *keepSrc) const {
+    int n = 0, first = -1, second = -1;
+    if (a >= 1 && presA(a - 1, b) && spv(a - 1, b) >= 1.0) { first = a - 1; n++; }
+    if (presA(a, b)) {
+      const double s = spv(a, b);
+      if (s >= 0.0 && s < 1.0) {
+        if (n == 0) first = a;
+        else second = a;
+        n++;
+      }
+    }
+    if (a + 1 < na && presA(a + 1, b) && spv(a + 1, b) < 0.0) {
+      if (n == 0) first = a + 1;
+      else if (n == 1) second = a + 1;
+      n++;
+    }
+    *keepSrc = n == 1 ? first : (n == 3 ? second : -1);
+    return n;
+  }
+};
+
+// The same view over global memory (old state, advected offsets and
+// displacements written by the sweep, new colours): used by the fit kernel,
+// where one lane handles one new unaligned marker.
+template <int DIR>
+struct GView {
+  GMap<DIR> G;
+  int na, nb;
+  const uint8_t *__restrict__ col;   // old node colours
+  const uint8_t *__restrict__ cen;   // old centre colours
+  const uint8_t *__restrict__ ncol;  // new node colours
+  const double *__restrict__ sp;     // aligned: s' (present edges)
+  const double *__restrict__ dd;     // unaligned: d (present edges)
+  const double *__restrict__ uno;    // unaligned: old offsets t
+  __device__ GView(const FitParams &P, const double *uno_)
+      : G(P.nx, P.ny), na(G.na), nb(G.nb), col(P.col), cen(P.cen), ncol(P.ncol), sp(P.sp), dd(P.dd), uno(uno_) {}
+  __device__ int C(int a, int b) const { return col[G.node(a, b)]; }
+  __device__ bool presA(int a, int b) const { return C(a, b) != C(a + 1, b); }
+  __device__ bool presU(int a, int b) const { return C(a, b) != C(a, b + 1); }
+  __device__ double spv(int a, int b) const { return sp[G.ale(a, b)]; }
+  __device__ double dU(int a, int b) const { return dd[G.une(a, b)]; }
+  __device__ double tU(int a, int b) const { return uno[G.une(a, b)]; }
+  __device__ int cenv(int p, int q) const { return cen[G.cell(p, q)]; }
+  __device__ uint16_t segc(int p, int q) const {
+    return segCodeOf(C(p, q), C(p + 1, q), C(p + 1, q + 1), C(p, q + 1), cenv(p, q));
+  }
+  __device__ int newC(int a, int b) const { return ncol[G.node(a, b)]; }
   __device__ int landers(int a, int b, int *keepSrc) const {
     int n = 0, first = -1, second = -1;
     if (a >= 1 && presA(a - 1, b) && spv(a - 1, b) >= 1.0) { first = a - 1; n++; }
@@ -153,11 +197,11 @@ struct Tile {
     const int t = s >= 1.0 ? p + 1 : (s < 0.0 ? p - 1 : p);
     return (t < 0 || t >= na) ? -1 : t;
   }
-  // the aligned marker of old edge (p,q) is the one kept on new edge target
-  // (target in [a0-1, a0+16], q in [b0, b0+16])
   __device__ bool keptOn(int p, int q, int target) const {
     if (landTarget(p, q) != target) return false;
-    return keep[q - b0][target - a0 + 1] == p - target;
+    int keep;
+    landers(target, q, &keep);
+    return keep == p;
   }
 };
 
@@ -177,7 +221,8 @@ __device__ __forceinline__ MRef edgeMarker(int p, int q, int e) {
 
 // advected marker in the frame of node (a0,b0): aligned markers move along
 // their line (blue points), unaligned ones off it (gray points)
-__device__ __forceinline__ void advPoint(const Tile &T, MRef m, int a0, int b0, double *X, double *Y) {
+template <class View>
+__device__ __forceinline__ void advPoint(const View &T, MRef m, int a0, int b0, double *X, double *Y) {
   if (m.kind == 0) {
     *X = (double)(m.a - a0) + T.spv(m.a, m.b);
     *Y = (double)(m.b - b0);
@@ -188,14 +233,16 @@ __device__ __forceinline__ void advPoint(const Tile &T, MRef m, int a0, int b0, 
 }
 
 // "left of line a = a0" iff x < a0, decided exactly on the offset
-__device__ __forceinline__ bool leftOf(const Tile &T, MRef m, int a0) {
+template <class View>
+__device__ __forceinline__ bool leftOf(const View &T, MRef m, int a0) {
   if (m.kind == 0) return T.spv(m.a, m.b) < (double)(a0 - m.a);
   return T.dU(m.a, m.b) < (double)(a0 - m.a);
 }
 
 // chain neighbour of the marker on edge e of old cell (p,q), away from it:
 // its partner in the cell across edge e
-__device__ bool chainNb(const Tile &T, int p, int q, int e, MRef *out) {
+template <class View>
+__device__ bool chainNb(const View &T, int p, int q, int e, MRef *out) {
   int pp = p, qq = q;
   if (e == 0) qq = q - 1;
   else if (e == 1) pp = p + 1;
@@ -280,7 +327,8 @@ struct Counts {
 // New unaligned marker on interior line a, row b (present by the new
 // colours): its offset, and the centre-CV results for the cell right of the
 // line (cell a) and left of it (cell a-1): -1 or the new centre colour.
-__device__ double newUnaligned(const Tile &T, int a, int b, int *resRight, int *resLeft, const Counts &cnt, bool count) {
+template <class View>
+__device__ double newUnaligned(const View &T, int a, int b, int *resRight, int *resLeft, const Counts &cnt, bool count) {
   *resRight = -1;
   *resLeft = -1;
   uint32_t lties = 0, lrej = 0;
@@ -407,14 +455,10 @@ __global__ __launch_bounds__(256, 8) void k_sweep(SweepParams P) {
   __shared__ uint32_t sRow[NH];     // old colours, bit la of frame row lb
   __shared__ uint32_t sNRow[NN];    // new colours, bit a-a0 of row b-b0
   __shared__ uint32_t sRecv[NN];    // new aligned edges (a,b) that receive a lander, bit a-a0
-  __shared__ uint16_t sSeg[NE][NE];
-  __shared__ int8_t sKeep[NN][NN + 1];
   __shared__ uint32_t sTiles[64];   // this workgroup's first tiles
-  __shared__ int8_t sRight[TS][NN];  // [lb][la]: result for the cell right of line a
-  __shared__ int8_t sLeft[TS][NN];   // result for the cell left of line a
   __shared__ uint16_t sAdv[2 * NH * NE];
   __shared__ uint16_t sWork[TS * NN];
-  __shared__ uint32_t sNAdv, sNWork, sHas;
+  __shared__ uint32_t sNAdv, sNWork, sHas, sJobBase;
   __shared__ uint32_t sCnt[NCOUNTERS];
   __shared__ uint32_t sErr;
 
@@ -445,8 +489,6 @@ __global__ __launch_bounds__(256, 8) void k_sweep(SweepParams P) {
   T.dd = sD;
   T.tt = sT;
   T.nrow = sNRow;
-  T.seg = sSeg;
-  T.keep = sKeep;
 
   // Staging of colours and centre colours: each thread owns two node slots
   // and two cell slots of the halo (memory order). The next tile's bytes are
@@ -584,11 +626,6 @@ __global__ __launch_bounds__(256, 8) void k_sweep(SweepParams P) {
       continue;
     }
     if (tid == 0) cnt.add(C_TILES_SWEPT, 1u);
-    // old segments of the halo cells (frame coordinates)
-    for (int k = tid; k < NE * NE; k += blockDim.x) {
-      const int la = k % NE, lb = k / NE;
-      sSeg[lb][la] = segCodeOf(sCol[lb][la], sCol[lb][la + 1], sCol[lb + 1][la + 1], sCol[lb + 1][la], sCen[lb][la]);
-    }
     // --- advect the listed markers (Eq. marker_dis), flip crossed nodes ------
     for (uint32_t w = tid; w < nadv; w += blockDim.x) {
       const uint32_t code = sAdv[w];
@@ -602,6 +639,7 @@ __global__ __launch_bounds__(256, 8) void k_sweep(SweepParams P) {
         sSp[lb][la] = spv;
         const bool own = la >= HALO && la < HALO + TS && lb >= HALO && (lb < HALO + TS || b == nb);
         if (own) {
+          P.sp[G.ale(a, b)] = spv;
           cnt.add(C_MARKERS, 1u);
           if (fabs(d) > 0.5) atomicOr(&sErr, ERRBIT_CFL);
           if ((spv >= 1.0 && a + 1 >= na) || (spv < 0.0 && a == 0)) atomicOr(&sErr, ERRBIT_DOMAIN);
@@ -633,32 +671,16 @@ __global__ __launch_bounds__(256, 8) void k_sweep(SweepParams P) {
         sD[lb][la] = wall ? 0.0 : d;
         const bool own = la >= HALO && (la < HALO + TS || a == na) && lb >= HALO && lb < HALO + TS;
         if (own) {
+          P.dd[G.une(a, b)] = wall ? 0.0 : d;
           cnt.add(C_MARKERS, 1u);
           if (fabs(d) > 0.5) atomicOr(&sErr, ERRBIT_CFL);
           if (wall && d != 0.0) cnt.add(C_WALL_VIOLATION, 1u);
         }
       }
     }
-    // result slots of the new unaligned edges start empty
-    for (int k = tid; k < TS * NN; k += blockDim.x) {
-      (&sRight[0][0])[k] = -1;
-      (&sLeft[0][0])[k] = -1;
-    }
     // the next tile's colours are fetched while this one computes
     if (it + gridDim.x < ntile) prefetch(tileAt(it + gridDim.x));
     __syncthreads();
-    // kept sources of new aligned edges (t,b), t in [a0-1, a0+16], b in [b0, b0+16]
-    for (int k = tid; k < (TS + 2) * NN; k += blockDim.x) {
-      const int lt = k % (TS + 2), lb = k / (TS + 2);
-      const int a = a0 - 1 + lt, b = b0 + lb;
-      int8_t kr = -2;
-      if (a >= 0 && a < na && b <= nb) {
-        int keep;
-        T.landers(a, b, &keep);
-        if (keep >= 0) kr = (int8_t)(keep - a);
-      }
-      sKeep[lb][lt] = kr;
-    }
     uint32_t hasm = 0;
     // --- new node colours out; new aligned edges; unaligned work list --------
     for (int k = tid; k < NN * NN; k += blockDim.x) {
@@ -715,52 +737,29 @@ __global__ __launch_bounds__(256, 8) void k_sweep(SweepParams P) {
               unn[G.une(a, b)] = T.tU(a, b);
               hasm |= DIR == 0 ? maskV(a, b, x0, y0) : maskH(b, a, x0, y0);
             }
-          } else {
+          } else if (own) {
+            // interior line owned by this tile: one fit job
             const uint32_t w = atomicAdd(&sNWork, 1u);
             sWork[w] = (uint16_t)(j * NN + i);
+            hasm |= DIR == 0 ? maskV(a, b, x0, y0) : maskH(b, a, x0, y0);
           }
         }
       }
     }
     __syncthreads();
-    // --- circle fits for the present new unaligned edges ---------------------
+    // --- hand the new unaligned markers to the fit kernel ---------------------
     const uint32_t nwork = sNWork;
-    for (uint32_t w = tid; w < nwork; w += blockDim.x) {
-      const int la = sWork[w] % NN, lb = sWork[w] / NN;
-      const int a = a0 + la, b = b0 + lb;
-      const bool own = la < TS || a == na;
-      int rR, rL;
-      const double y = newUnaligned(T, a, b, &rR, &rL, cnt, own);
-      sRight[lb][la] = (int8_t)rR;
-      sLeft[lb][la] = (int8_t)rL;
-      if (own) {
-        unn[G.une(a, b)] = y;
-        hasm |= DIR == 0 ? maskV(a, b, x0, y0) : maskH(b, a, x0, y0);
-      }
-    }
-    __syncthreads();
-    // --- centre colours of the tile's cells (Sec. 2.3, rules (1)-(5)) --------
+    if (tid == 0) sJobBase = nwork ? atomicAdd(P.njobs, nwork) : 0u;
+    // centre colours carry over; the centre kernel applies rules (1)-(5)
     for (int k = tid; k < TS * TS; k += blockDim.x) {
       const int hx = k % TS, hy = k / TS;
-      const int la = DIR == 0 ? hx : hy, lb = DIR == 0 ? hy : hx;
-      const int a = a0 + la, b = b0 + lb;
-      if (a >= na || b >= nb) continue;
-      const int left = sRight[lb][la];      // line a, cell to its right
-      const int right = sLeft[lb][la + 1];  // line a+1, cell to its left
-      int cc = T.cenv(a, b);
-      if (left >= 0) {
-        cc = left;
-        cnt.add(C_CV_SET, 1u);
-        if (right >= 0 && right != left) cnt.add(C_CV_CONFLICT, 1u);
-      } else if (right >= 0) {
-        cc = right;
-        cnt.add(C_CV_SET, 1u);
-      } else {
-        const uint32_t r0 = sNRow[lb] >> la, r1 = sNRow[lb + 1] >> la;
-        const uint32_t k0 = r0 & 1u, k1 = (r0 >> 1) & 1u, k3 = r1 & 1u, k2 = (r1 >> 1) & 1u;
-        if (k0 != k1 && k1 != k2 && k3 != k2 && k0 != k3) cnt.add(C_CV_UNRESOLVED, 1u);
-      }
-      P.ncen[G.cell(a, b)] = (uint8_t)cc;
+      const int x = x0 + hx, y = y0 + hy;
+      if (x < P.nx && y < P.ny) P.ncen[(size_t)y * P.nx + x] = DIR == 0 ? sCen[hy + HALO][hx + HALO] : sCen[hx + HALO][hy + HALO];
+    }
+    __syncthreads();
+    for (uint32_t w = tid; w < nwork; w += blockDim.x) {
+      const int la = sWork[w] % NN, lb = sWork[w] / NN;
+      P.jobs[sJobBase + w] = (uint32_t)G.une(a0 + la, b0 + lb);
     }
     if (hasm) atomicOr(&sHas, hasm);
     __syncthreads();
@@ -769,6 +768,87 @@ __global__ __launch_bounds__(256, 8) void k_sweep(SweepParams P) {
   __syncthreads();
   if (tid < NCOUNTERS && sCnt[tid]) atomicAdd(&P.ctr[tid], (unsigned long long)sCnt[tid]);
   if (tid == 0 && sErr) atomicOr(P.err, sErr);
+}
+
+// ---------------------------------------------------------------------------
+// Fit kernel: one lane per new unaligned marker of the sweep (the job list),
+// so the circle fits of all tiles share full wavefronts. Reads the old state,
+// the advected offsets and displacements the sweep wrote and the new colours;
+// writes the marker's offset and, per edge, the centre-CV results for the cell
+// right of the line (bits 0-1, value + 1) and the cell left of it (bits 2-3).
+// ---------------------------------------------------------------------------
+template <int DIR>
+__global__ __launch_bounds__(256) void k_fit(FitParams P) {
+  __shared__ uint32_t sCnt[NCOUNTERS];
+  const int tid = threadIdx.x;
+  if (tid < NCOUNTERS) sCnt[tid] = 0;
+  __syncthreads();
+  const Counts cnt{sCnt};
+  const GView<DIR> V(P, DIR == 0 ? P.voff : P.hoff);
+  double *__restrict__ unn = DIR == 0 ? P.nvoff : P.nhoff;
+  const uint32_t nj = *P.njobs;
+  for (uint32_t w = blockIdx.x * blockDim.x + tid; w < nj; w += gridDim.x * blockDim.x) {
+    const uint32_t e = P.jobs[w];
+    int a, b;
+    if (DIR == 0) { b = (int)(e / (uint32_t)(P.nx + 1)); a = (int)(e % (uint32_t)(P.nx + 1)); }
+    else { a = (int)(e / (uint32_t)P.nx); b = (int)(e % (uint32_t)P.nx); }
+    int rR, rL;
+    const double y = newUnaligned(V, a, b, &rR, &rL, cnt, true);
+    unn[e] = y;
+    P.zr[e] = (uint8_t)((rR + 1) | ((rL + 1) << 2));
+  }
+  __syncthreads();
+  if (tid < NCOUNTERS && sCnt[tid]) atomicAdd(&P.ctr[tid], (unsigned long long)sCnt[tid]);
+}
+
+// Centre kernel: rules (1)-(5) of Sec. 2.3 for the cells next to new
+// unaligned markers. A cell takes the result of the marker on its left edge,
+// else of the one on its right edge, else keeps its centre colour (already
+// carried over by the sweep). The job on line a settles cell a and, when line
+// a-1 holds no job, cell a-1.
+template <int DIR>
+__global__ __launch_bounds__(256) void k_centre(FitParams P) {
+  __shared__ uint32_t sCnt[NCOUNTERS];
+  const int tid = threadIdx.x;
+  if (tid < NCOUNTERS) sCnt[tid] = 0;
+  __syncthreads();
+  const Counts cnt{sCnt};
+  const GMap<DIR> G(P.nx, P.ny);
+  const int na = G.na;
+  auto newC = [&](int a, int b) -> int { return P.ncol[G.node(a, b)]; };
+  const uint32_t nj = *P.njobs;
+  for (uint32_t w = blockIdx.x * blockDim.x + tid; w < nj; w += gridDim.x * blockDim.x) {
+    const uint32_t e = P.jobs[w];
+    int a, b;
+    if (DIR == 0) { b = (int)(e / (uint32_t)(P.nx + 1)); a = (int)(e % (uint32_t)(P.nx + 1)); }
+    else { a = (int)(e / (uint32_t)P.nx); b = (int)(e % (uint32_t)P.nx); }
+    auto isJob = [&](int l) -> bool { return l > 0 && l < na && newC(l, b) != newC(l, b + 1); };
+    auto settle = [&](int c, int left, int right) {
+      int cc = -1;
+      if (left >= 0) {
+        cc = left;
+        cnt.add(C_CV_SET, 1u);
+        if (right >= 0 && right != left) cnt.add(C_CV_CONFLICT, 1u);
+      } else if (right >= 0) {
+        cc = right;
+        cnt.add(C_CV_SET, 1u);
+      } else {
+        const int k0 = newC(c, b), k1 = newC(c + 1, b), k2 = newC(c + 1, b + 1), k3 = newC(c, b + 1);
+        if (k0 != k1 && k1 != k2 && k3 != k2 && k0 != k3) cnt.add(C_CV_UNRESOLVED, 1u);
+      }
+      if (cc >= 0) P.ncen[G.cell(c, b)] = (uint8_t)cc;
+    };
+    const uint32_t z = P.zr[e];
+    // cell a, right of line a
+    {
+      const int right = isJob(a + 1) ? (int)((P.zr[G.une(a + 1, b)] >> 2) & 3u) - 1 : -1;
+      settle(a, (int)(z & 3u) - 1, right);
+    }
+    // cell a-1, left of line a, when its own left line holds no job
+    if (!isJob(a - 1)) settle(a - 1, -1, (int)((z >> 2) & 3u) - 1);
+  }
+  __syncthreads();
+  if (tid < NCOUNTERS && sCnt[tid]) atomicAdd(&P.ctr[tid], (unsigned long long)sCnt[tid]);
 }
 
 // ---------------------------------------------------------------------------
@@ -825,9 +905,11 @@ __global__ __launch_bounds__(256) void k_compact(const uint16_t *__restrict__ ha
   const int ntiles = ntx * nty;
   const int tid = threadIdx.x;
   if (blockIdx.x == 0 && tid == 0) {
-    // clear the other slot for the next compaction (nothing reads it now)
-    counts[2 * (slot ^ 1)] = 0;
-    counts[2 * (slot ^ 1) + 1] = 0;
+    // clear the other slot (active, near, jobs) for the next compaction;
+    // nothing reads it now
+    counts[3 * (slot ^ 1)] = 0;
+    counts[3 * (slot ^ 1) + 1] = 0;
+    counts[3 * (slot ^ 1) + 2] = 0;
   }
   const int base = (blockIdx.x * blockDim.x + tid) * CPT;
   uint32_t actBits = 0, nearBits = 0;
@@ -855,8 +937,8 @@ __global__ __launch_bounds__(256) void k_compact(const uint16_t *__restrict__ ha
     __syncthreads();
   }
   if (tid == 255) {
-    sBaseA = sA[255] ? atomicAdd(&counts[2 * slot], sA[255]) : 0;
-    sBaseN = sN[255] ? atomicAdd(&counts[2 * slot + 1], sN[255]) : 0;
+    sBaseA = sA[255] ? atomicAdd(&counts[3 * slot], sA[255]) : 0;
+    sBaseN = sN[255] ? atomicAdd(&counts[3 * slot + 1], sN[255]) : 0;
   }
   __syncthreads();
   uint32_t pa = sBaseA + sA[tid] - ca, pn = sBaseN + sN[tid] - cn;
@@ -1141,6 +1223,9 @@ int resident_blocks(int which) {
   switch (which) {
     case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_sweep<0>, 256, 0); break;
     case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_sweep<1>, 256, 0); break;
+    case 5: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fit<0>, 256, 0); break;
+    case 6: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fit<1>, 256, 0); break;
+    case 7: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_centre<0>, 256, 0); break;
     case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_frac_curv<1>, 256, 0); break;
     case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_frac_curv<2>, 256, 0); break;
     default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_frac_curv<3>, 256, 0); break;
@@ -1151,6 +1236,18 @@ int resident_blocks(int which) {
 hipError_t launch_sweep(int dir, const SweepParams &p, int grid, hipStream_t s) {
   if (dir == 0) hipLaunchKernelGGL(k_sweep<0>, dim3(grid), dim3(256), 0, s, p);
   else hipLaunchKernelGGL(k_sweep<1>, dim3(grid), dim3(256), 0, s, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_fit(int dir, const FitParams &p, int grid, hipStream_t s) {
+  if (dir == 0) hipLaunchKernelGGL(k_fit<0>, dim3(grid), dim3(256), 0, s, p);
+  else hipLaunchKernelGGL(k_fit<1>, dim3(grid), dim3(256), 0, s, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_centre(int dir, const FitParams &p, int grid, hipStream_t s) {
+  if (dir == 0) hipLaunchKernelGGL(k_centre<0>, dim3(grid), dim3(256), 0, s, p);
+  else hipLaunchKernelGGL(k_centre<1>, dim3(grid), dim3(256), 0, s, p);
   return hipGetLastError();
 }
 

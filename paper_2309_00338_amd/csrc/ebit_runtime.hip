@@ -28,7 +28,11 @@ struct ebit_handle {
   // tile tables
   uint16_t *has;
   uint8_t *nearPrev, *tinfo;
-  uint32_t *actList, *nearList, *counts;  // counts: [act0, near0, act1, near1]
+  uint32_t *actList, *nearList, *counts;  // counts: [act, near, jobs] x 2 slots
+  double *sp, *dd;     // advected offsets / displacements of the current sweep
+  uint8_t *zr;         // per unaligned edge: centre-CV results of its fit
+  uint32_t *jobs;      // new unaligned markers of the current sweep
+  int fitBlocks[2], centreBlocks;
   int slot;                               // counts slot written by the last compaction
   uint32_t *fracWork;  // claim counters of the fraction pass: two launches x [tiles, rows]
   int fracParity;
@@ -71,7 +75,11 @@ void carve(ebit_handle *h, char *base, size_t *total) {
   h->tinfo = c.take<uint8_t>(base, h->ntiles);
   h->actList = c.take<uint32_t>(base, h->ntiles);
   h->nearList = c.take<uint32_t>(base, h->ntiles);
-  h->counts = c.take<uint32_t>(base, 4);
+  h->counts = c.take<uint32_t>(base, 6);
+  h->sp = c.take<double>(base, (nx + 1) * (ny + 1));
+  h->dd = c.take<double>(base, (nx + 1) * (ny + 1));
+  h->zr = c.take<uint8_t>(base, (nx + 1) * (ny + 1));
+  h->jobs = c.take<uint32_t>(base, (nx + 1) * (ny + 1));
   h->fracWork = c.take<uint32_t>(base, 4);
   h->err = c.take<uint32_t>(base, 1);
   h->ctr = c.take<unsigned long long>(base, NCOUNTERS);
@@ -129,7 +137,7 @@ int upload(ebit_handle *h, const ebit_state *s) {
     HIPCHK(hipMemcpyAsync(h->voff[k], s->voff, nv * sizeof(double), hipMemcpyHostToDevice, h->stream));
   }
   h->cur = 0;
-  HIPCHK(hipMemsetAsync(h->counts, 0, 4 * sizeof(uint32_t), h->stream));
+  HIPCHK(hipMemsetAsync(h->counts, 0, 6 * sizeof(uint32_t), h->stream));
   HIPCHK(hipMemsetAsync(h->fracWork, 0, 4 * sizeof(uint32_t), h->stream));
   h->fracParity = 0;
   HIPCHK(hipMemsetAsync(h->err, 0, sizeof(uint32_t), h->stream));
@@ -170,11 +178,34 @@ int sweep(ebit_handle *h, int dir, const double *u, const double *v, double dt) 
   p.nhoff = h->hoff[nxt];
   p.nvoff = h->voff[nxt];
   p.list = h->actList;
-  p.count = h->counts + 2 * h->slot;
+  p.count = h->counts + 3 * h->slot;
   p.has = h->has;
   p.err = h->err;
   p.ctr = h->ctr;
+  p.sp = h->sp;
+  p.dd = h->dd;
+  p.jobs = h->jobs;
+  p.njobs = h->counts + 3 * h->slot + 2;
   HIPCHK(launch_sweep(dir, p, h->sweepBlocks[dir], h->stream));
+  FitParams f;
+  f.nx = h->g.nx;
+  f.ny = h->g.ny;
+  f.col = h->col[h->cur];
+  f.cen = h->cen[h->cur];
+  f.ncol = h->col[nxt];
+  f.sp = h->sp;
+  f.dd = h->dd;
+  f.hoff = h->hoff[h->cur];
+  f.voff = h->voff[h->cur];
+  f.nhoff = h->hoff[nxt];
+  f.nvoff = h->voff[nxt];
+  f.ncen = h->cen[nxt];
+  f.zr = h->zr;
+  f.jobs = h->jobs;
+  f.njobs = p.njobs;
+  f.ctr = h->ctr;
+  HIPCHK(launch_fit(dir, f, h->fitBlocks[dir], h->stream));
+  HIPCHK(launch_centre(dir, f, h->centreBlocks, h->stream));
   h->cur = nxt;
   return compact(h);
 }
@@ -195,7 +226,7 @@ FracParams frac_params(ebit_handle *h, int mode, const double *Cin, double *Cout
   p.Kout = Kout;
   p.tinfo = h->tinfo;
   p.list = h->nearList;
-  p.count = h->counts + 2 * h->slot + 1;
+  p.count = h->counts + 3 * h->slot + 1;
   p.ctr = h->ctr;
   p.tileBlocks = h->fracTileBlocks[mode - 1];
   p.work = h->fracWork + 2 * h->fracParity;
@@ -241,7 +272,11 @@ int ebit_create(const ebit_grid *grid, const ebit_state *init, void *ws_dev, siz
   carve(h, (char *)ws_dev, &tot);
   int dev = 0, cus = 256;
   if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 256;
-  for (int d = 0; d < 2; d++) h->sweepBlocks[d] = cus * resident_blocks(d);
+  for (int d = 0; d < 2; d++) {
+    h->sweepBlocks[d] = cus * resident_blocks(d);
+    h->fitBlocks[d] = cus * resident_blocks(5 + d);
+  }
+  h->centreBlocks = cus * resident_blocks(7);
   {
     double share = 0.5;
     const char *e = getenv("EBIT_FRAC_TILE_SHARE");
