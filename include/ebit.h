@@ -68,7 +68,7 @@ enum {
 enum { EBIT_SWEEP_ALTERNATE = 0u, EBIT_SWEEP_XY = 1u };
 
 typedef struct {
-  int32_t nx, ny;  /* cells along x and y, each >= 4 */
+  int32_t nx, ny;  /* cells along x and y, each in [4, 65535] */
   double h;        /* physical cell size, > 0 */
   uint32_t flags;  /* EBIT_SWEEP_* */
 } ebit_grid;

@@ -32,6 +32,7 @@ constexpr int HALO = 2;
 constexpr int NH = TS + 2 * HALO + 1;  // staged nodes per side (21)
 constexpr int NE = NH - 1;             // staged cells / edges per side (20)
 constexpr int NN = TS + 1;             // new nodes per side (17)
+constexpr int JOBCAP = 1024;           // queued fit jobs per sweep workgroup (>= one tile's 256)
 
 // marker-position mask bits of a tile
 enum : uint16_t {
@@ -457,8 +458,8 @@ __global__ __launch_bounds__(256, 8) void k_sweep(SweepParams P) {
   __shared__ uint32_t sRecv[NN];    // new aligned edges (a,b) that receive a lander, bit a-a0
   __shared__ uint32_t sTiles[64];   // this workgroup's first tiles
   __shared__ uint16_t sAdv[2 * NH * NE];
-  __shared__ uint16_t sWork[TS * NN];
-  __shared__ uint32_t sNAdv, sNWork, sHas, sJobBase;
+  __shared__ uint32_t sJob[JOBCAP];  // new interior unaligned markers of this workgroup's tiles
+  __shared__ uint32_t sNAdv, sNJob, sHas, sJobBase;
   __shared__ uint32_t sCnt[NCOUNTERS];
   __shared__ uint32_t sErr;
 
@@ -477,8 +478,21 @@ __global__ __launch_bounds__(256, 8) void k_sweep(SweepParams P) {
 
   const int tid = threadIdx.x;
   if (tid < NCOUNTERS) sCnt[tid] = 0;
-  if (tid == 0) sErr = 0;
+  if (tid == 0) {
+    sErr = 0;
+    sNJob = 0;
+  }
+  if (tid < NH) sRow[tid] = 0;
   const Counts cnt{sCnt};
+  // the queued jobs go to the fit kernel's list with one reservation
+  auto flushJobs = [&]() {
+    const uint32_t n = sNJob;
+    if (tid == 0) sJobBase = atomicAdd(P.njobs, n);
+    __syncthreads();
+    for (uint32_t w = tid; w < n; w += blockDim.x) P.jobs[sJobBase + w] = sJob[w];
+    __syncthreads();
+    if (tid == 0) sNJob = 0;
+  };
 
   Tile T;
   T.na = na;
@@ -531,11 +545,9 @@ __global__ __launch_bounds__(256, 8) void k_sweep(SweepParams P) {
     T.b0 = b0;
     __syncthreads();  // the previous tile is done with LDS
     if (tid == 0) {
-      sNWork = 0;
       sNAdv = 0;
       sHas = 0;
     }
-    if (tid < NH) sRow[tid] = 0;
     if (tid < NN) sRecv[tid] = 0;
     // --- stage old colours and centre colours --------------------------------
     {
@@ -556,8 +568,8 @@ __global__ __launch_bounds__(256, 8) void k_sweep(SweepParams P) {
       putCell(tid, pe0);
       putCell(tid + 256, pe1);
     }
-    __syncthreads();
-    // colour-1 nodes set their bit in the frame-row masks
+    // colour-1 nodes set their bit in the frame-row masks (zero since the
+    // previous tile)
     {
       auto bitNode = [&](int k, uint8_t c) {
         if (k >= NH * NH || !c) return;
@@ -622,6 +634,7 @@ __global__ __launch_bounds__(256, 8) void k_sweep(SweepParams P) {
         P.has[tile] = 0;
         cnt.add(C_TILES_EMPTY, 1u);
       }
+      if (tid < NH) sRow[tid] = 0;
       if (it + gridDim.x < ntile) prefetch(tileAt(it + gridDim.x));
       continue;
     }
@@ -682,6 +695,7 @@ __global__ __launch_bounds__(256, 8) void k_sweep(SweepParams P) {
     if (it + gridDim.x < ntile) prefetch(tileAt(it + gridDim.x));
     __syncthreads();
     uint32_t hasm = 0;
+    if (tid < NH) sRow[tid] = 0;  // read last by the edge list; ready for the next tile
     // --- new node colours out; new aligned edges; unaligned work list --------
     for (int k = tid; k < NN * NN; k += blockDim.x) {
       const int hx = k % NN, hy = k / NN;
@@ -739,33 +753,26 @@ __global__ __launch_bounds__(256, 8) void k_sweep(SweepParams P) {
             }
           } else if (own) {
             // interior line owned by this tile: one fit job
-            const uint32_t w = atomicAdd(&sNWork, 1u);
-            sWork[w] = (uint16_t)(j * NN + i);
+            sJob[atomicAdd(&sNJob, 1u)] = (uint32_t)G.une(a, b);
             hasm |= DIR == 0 ? maskV(a, b, x0, y0) : maskH(b, a, x0, y0);
           }
         }
       }
     }
-    __syncthreads();
-    // --- hand the new unaligned markers to the fit kernel ---------------------
-    const uint32_t nwork = sNWork;
-    if (tid == 0) sJobBase = nwork ? atomicAdd(P.njobs, nwork) : 0u;
     // centre colours carry over; the centre kernel applies rules (1)-(5)
     for (int k = tid; k < TS * TS; k += blockDim.x) {
       const int hx = k % TS, hy = k / TS;
       const int x = x0 + hx, y = y0 + hy;
       if (x < P.nx && y < P.ny) P.ncen[(size_t)y * P.nx + x] = DIR == 0 ? sCen[hy + HALO][hx + HALO] : sCen[hx + HALO][hy + HALO];
     }
-    __syncthreads();
-    for (uint32_t w = tid; w < nwork; w += blockDim.x) {
-      const int la = sWork[w] % NN, lb = sWork[w] / NN;
-      P.jobs[sJobBase + w] = (uint32_t)G.une(a0 + la, b0 + lb);
-    }
     if (hasm) atomicOr(&sHas, hasm);
     __syncthreads();
     if (tid == 0) P.has[tile] = (uint16_t)sHas;
+    // keep room for a full tile of jobs
+    if (sNJob > JOBCAP - TS * TS) flushJobs();
   }
   __syncthreads();
+  if (sNJob) flushJobs();
   if (tid < NCOUNTERS && sCnt[tid]) atomicAdd(&P.ctr[tid], (unsigned long long)sCnt[tid]);
   if (tid == 0 && sErr) atomicOr(P.err, sErr);
 }

@@ -56,7 +56,7 @@ struct Carve {
 };
 
 bool grid_ok(const ebit_grid *g) {
-  return g && g->nx >= 4 && g->ny >= 4 && g->nx <= (1 << 20) && g->ny <= (1 << 20) && isfinite(g->h) && g->h > 0.0 &&
+  return g && g->nx >= 4 && g->ny >= 4 && g->nx <= 65535 && g->ny <= 65535 && isfinite(g->h) && g->h > 0.0 &&
          (g->flags & ~1u) == 0;
 }
 
