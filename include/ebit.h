@@ -109,7 +109,7 @@ typedef struct {
 typedef struct ebit_handle ebit_handle;
 
 /* Bytes of device workspace a grid needs (both state buffers, tile tables,
- * lists, counters). Returns EBIT_ERR_ARG for an invalid grid. */
+ * lists, counters, sweep scratch). Returns EBIT_ERR_ARG for an invalid grid. */
 int ebit_workspace_bytes(const ebit_grid *grid, size_t *bytes);
 
 /* Validate the host state `init`, upload it into the caller's device
@@ -165,6 +165,93 @@ int ebit_sync(ebit_handle *h);
 int ebit_destroy(ebit_handle *h);
 
 const char *ebit_strerror(int code);
+
+/* After EBIT_ERR_DEVICE: the HIP error name and the runtime call that failed,
+ * as a NUL-terminated string owned by the library (per calling thread); "" if
+ * no HIP call has failed on this thread. */
+const char *ebit_device_error(void);
+
+/* ===========================================================================
+ * Batched form: a fixed set of independent grids advanced together, one
+ * kernel launch per phase for all of them (the tiles of all grids share one
+ * work list). Each grid behaves exactly as it would under its own handle; all
+ * grids take their steps together, so step n of every grid uses the same
+ * sweep order (EBIT_SWEEP_ALTERNATE counts the batch's steps).
+ *
+ * Packed buffers. Grid k's u, v, C and K sit in shared device buffers at the
+ * element offsets ebit_batch_layout reports (each start 256-byte aligned,
+ * per-grid layout as in the header comment); totals[0..2] are the element
+ * counts of the u, v and C/K buffers. dt is per grid, in device memory.
+ * =========================================================================== */
+typedef struct ebit_batch ebit_batch;
+
+/* Workspace bytes for n grids (grids[0..n-1] as in ebit_workspace_bytes). */
+int ebit_batch_workspace_bytes(int n, const ebit_grid *grids, size_t *bytes);
+
+/* Validate and upload n initial states (inits[k] for grids[k]); synchronous
+ * with respect to the host buffers. Errors as ebit_create. */
+int ebit_batch_create(int n, const ebit_grid *grids, const ebit_state *inits, void *ws_dev, size_t ws_bytes,
+                      void *hip_stream, ebit_batch **out);
+
+/* Element offsets of each grid's u, v and C/K in the packed buffers (any
+ * pointer may be NULL; arrays of n entries) and the buffer totals (3). */
+int ebit_batch_layout(const ebit_batch *b, size_t *u_off, size_t *v_off, size_t *c_off, size_t *totals);
+
+/* One step of every grid (as ebit_advect), grid k with dt_dev[k]. */
+int ebit_batch_advect(ebit_batch *b, const double *u_packed, const double *v_packed, const double *dt_dev);
+
+/* Fraction and curvature of every grid (as ebit_fraction_curvature). */
+int ebit_batch_fraction_curvature(ebit_batch *b, double *C_packed, double *K_packed);
+
+/* Grid k's current state to host buffers (any may be NULL); waits. */
+int ebit_batch_get_state(ebit_batch *b, int k, uint8_t *node_color, uint8_t *cell_color, double *hoff, double *voff,
+                         int64_t *step);
+
+/* Counters summed over the grids; waits. */
+int ebit_batch_stats(ebit_batch *b, ebit_counters *out);
+
+/* Waits; status[k] (n entries, may be NULL) is grid k's latched device error;
+ * returns the first nonzero one. A grid in error leaves the others valid. */
+int ebit_batch_sync(ebit_batch *b, int *status);
+int ebit_batch_destroy(ebit_batch *b);
+
+/* ===========================================================================
+ * Served form: a pool that admits grids between steps, advances every admitted
+ * grid by one step per ebit_pool_step (advection, then fraction and curvature
+ * into the grid's own C and K), and retires them on request. Each grid keeps
+ * its own steady face velocities and dt (uploaded at admission) and its own
+ * step count (its sweep order starts from step 0 at admission). The workspace
+ * holds tables for max_grids grids and max_tiles 16x16-cell tiles, then an
+ * arena for the per-grid arrays; ebit_pool_grid_bytes gives one grid's arena
+ * bytes and tiles, for admission control.
+ * =========================================================================== */
+typedef struct ebit_pool ebit_pool;
+
+int ebit_pool_workspace_bytes(int max_grids, uint32_t max_tiles, size_t arena_bytes, size_t *bytes);
+int ebit_pool_grid_bytes(const ebit_grid *grid, size_t *bytes, uint32_t *tiles);
+int ebit_pool_create(int max_grids, uint32_t max_tiles, void *ws_dev, size_t ws_bytes, void *hip_stream,
+                     ebit_pool **out);
+
+/* Admit a grid: validate and upload its state, u_host and v_host (host,
+ * layout above) and dt; synchronous with respect to the host buffers. Returns
+ * its slot. EBIT_ERR_NOMEM when no slot, tile range or arena space is free
+ * (nothing changes; admit again after a retire). */
+int ebit_pool_admit(ebit_pool *p, const ebit_grid *grid, const ebit_state *init, const double *u_host,
+                    const double *v_host, double dt, int *slot_out);
+
+/* One step of every admitted grid, then its C and K. Asynchronous. */
+int ebit_pool_step(ebit_pool *p);
+
+/* Waits; copies the grid's latest C and K (either may be NULL) to the host,
+ * with the steps it has taken and its latched device error. */
+int ebit_pool_read(ebit_pool *p, int slot, double *C_host, double *K_host, int64_t *steps, int *status);
+int ebit_pool_get_state(ebit_pool *p, int slot, uint8_t *node_color, uint8_t *cell_color, double *hoff,
+                        double *voff);
+
+/* Release the slot, its tiles and its arena space (asynchronous). */
+int ebit_pool_retire(ebit_pool *p, int slot);
+int ebit_pool_stats(ebit_pool *p, ebit_counters *out);
+int ebit_pool_destroy(ebit_pool *p);
 
 #ifdef __cplusplus
 }

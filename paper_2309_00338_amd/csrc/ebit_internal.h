@@ -1,4 +1,11 @@
 // Internal definitions shared by the gfx950 kernels and the host runtime.
+//
+// One engine advances any number of independent grids ("instances") with one
+// launch per phase. Every grid is cut into 16x16-cell tiles and the tiles of
+// all grids share one global index space: grid k owns tiles
+// [tile0, tile0 + ntx*nty). Kernels map a global tile (or a fit job) to its
+// grid through a per-tile instance table and read the grid's geometry and
+// buffers from a device array of descriptors.
 #ifndef EBIT_INTERNAL_H
 #define EBIT_INTERNAL_H
 
@@ -10,8 +17,9 @@ namespace ebit {
 
 constexpr int TS = 16;             // tile edge in cells
 constexpr double TIE_EPS = 1e-12;  // near-degenerate decision threshold
+constexpr uint32_t NO_INST = 0xffffffffu;  // tile owned by no grid
 
-// counter slots (same order as the public ebit_stats fields)
+// counter slots (same order as the public ebit_counters fields)
 enum {
   C_MARKERS = 0,
   C_ANNIHILATED,
@@ -35,80 +43,151 @@ enum {
 };
 
 enum : uint32_t { ERRBIT_CFL = 1u, ERRBIT_DOMAIN = 2u };
+enum : uint32_t { INST_XY = 1u };  // sweeps x then y every step
 
-struct SweepParams {
-  int nx, ny, ntx, nty;
-  double lam;
-  const uint8_t *col;
-  const uint8_t *cen;
-  const double *hoff;
-  const double *voff;
-  const double *vel;
-  uint8_t *ncol;
-  uint8_t *ncen;
-  double *nhoff;
-  double *nvoff;
-  const uint32_t *list;
-  const uint32_t *count;
-  uint16_t *has;  // per tile: where its markers sit (any / near a side / near a corner)
-  double *sp;     // advected aligned offsets s' of present edges (aligned-edge layout)
-  double *dd;     // displacements of present unaligned markers (unaligned-edge layout)
-  uint32_t *jobs; // new unaligned markers for the fit kernel (unaligned-edge index)
-  uint32_t *njobs;
-  uint32_t *err;
-  unsigned long long *ctr;
-};
+// tile info bits written by the compaction, read by the fraction pass
+enum : uint8_t { TI_NEAR = 1, TI_COLOUR = 2, TI_DEAD = 4 };
 
-struct FitParams {
-  int nx, ny;
-  const uint8_t *col;   // old node colours
-  const uint8_t *cen;   // old centre colours
-  const uint8_t *ncol;  // new node colours
-  const double *sp;
-  const double *dd;
-  const double *hoff;   // old offsets
-  const double *voff;
-  double *nhoff;        // new offsets
-  double *nvoff;
-  uint8_t *ncen;        // new centre colours
-  uint8_t *zr;          // per unaligned edge: centre-CV results of its fit
-  const uint32_t *jobs;
-  const uint32_t *njobs;
-  unsigned long long *ctr;
-};
-
-struct FracParams {
-  int nx, ny, ntx, nty;
+// One grid: geometry, both state copies, per-sweep scratch, and where its
+// velocities and output fields sit relative to the base pointers of a call.
+struct Inst {
+  int32_t nx, ny, ntx, nty;
+  uint32_t tile0;       // first global tile
+  uint32_t stepPar;     // parity of the engine step at which the grid's step 0 ran
+  uint32_t flags;       // INST_XY
+  uint32_t pad;
   double h;
-  const uint8_t *col;
-  const uint8_t *cen;
-  const double *hoff;
-  const double *voff;
-  const double *Cin;
-  double *Cout;
-  double *Kout;
-  const uint8_t *tinfo;  // per tile: bit 0 near, bit 1 uniform colour
-  int vec;               // rows may use 16-byte stores (even nx, aligned C/K)
-  int tileBlocks;        // workgroups [0, tileBlocks) claim near tiles before rows
-  uint32_t *work;        // this launch's claim counters: [tiles, rows]
-  uint32_t *workNext;    // the next launch's, cleared by this one
-  const uint32_t *list;
-  const uint32_t *count;
-  unsigned long long *ctr;
+  uint64_t uoff, voffv;  // element offsets of u and v in the call's velocity buffers
+  uint64_t coff, koff;   // element offsets of C and kappa in the call's field buffers
+  uint8_t *col[2];       // node colours, (ny+1) x (nx+1), both copies
+  uint8_t *cen[2];       // centre colours, ny x nx
+  double *hoff[2];       // H-edge offsets, (ny+1) x nx
+  double *voff[2];       // V-edge offsets, ny x (nx+1)
+  double *sp;            // advected aligned offsets s' of the current sweep
+  double *dd;            // displacements of the unaligned markers of the current sweep
+  uint8_t *zr;           // per unaligned edge: centre-CV results of its fit
+  uint32_t *err;         // error bits of this grid
 };
 
-// launchers (defined with the kernels)
-// resident workgroups per CU of: 0/1 the x/y sweep, 2/3/4 fraction modes 1/2/3,
-// 5/6 the x/y fit, 7 the centre kernel
+// One grid as one sweep sees it: the copies it reads and writes, its
+// velocity for the sweep direction and lambda = dt / h. Built on the host per
+// launch when an engine holds one grid, on the device per tile otherwise.
+struct SweepView {
+  int32_t nx, ny, ntx, pad;
+  uint32_t tile0;
+  double lam;
+  const uint8_t *col, *cen;   // state before the sweep
+  const double *hoff, *voff;
+  uint8_t *ncol, *ncen;       // state after the sweep
+  double *nhoff, *nvoff;
+  const double *vel;          // u for the x sweep, v for the y sweep
+  double *sp, *dd;
+  uint8_t *zr;
+  uint32_t *err;
+};
+
+__host__ __device__ inline SweepView sweep_view(const Inst &I, uint32_t cur, int dir, const double *u, const double *v,
+                                                double lam) {
+  SweepView w;
+  w.nx = I.nx;
+  w.ny = I.ny;
+  w.ntx = I.ntx;
+  w.pad = 0;
+  w.tile0 = I.tile0;
+  w.lam = lam;
+  w.col = I.col[cur];
+  w.cen = I.cen[cur];
+  w.hoff = I.hoff[cur];
+  w.voff = I.voff[cur];
+  w.ncol = I.col[cur ^ 1u];
+  w.ncen = I.cen[cur ^ 1u];
+  w.nhoff = I.hoff[cur ^ 1u];
+  w.nvoff = I.voff[cur ^ 1u];
+  w.vel = dir == 0 ? u + I.uoff : v + I.voffv;
+  w.sp = I.sp;
+  w.dd = I.dd;
+  w.zr = I.zr;
+  w.err = I.err;
+  return w;
+}
+
+// counts per compaction slot: active tiles of x-sweeping grids, of
+// y-sweeping grids, near tiles, fit jobs of the x and y sweeps
+constexpr int NSLOT = 8;
+enum { CNT_ACT_X = 0, CNT_ACT_Y = 1, CNT_NEAR = 2, CNT_JOBS_X = 3, CNT_JOBS_Y = 4 };
+
+// Arguments of the kernels of one sweep direction (sweep, fit, centre). The
+// x direction reads the active list and the job list from the front, the y
+// direction from the back.
+struct SweepArgs {
+  const Inst *inst;
+  const uint32_t *tileInst;  // global tile -> grid
+  const double *u, *v;       // velocity base pointers of the call
+  const double *dts;         // per-grid dt (device) or null: dt for every grid
+  double dt;
+  uint32_t cur;              // copy holding the state before this sweep (0/1)
+  uint32_t ntiles;           // global tiles (length of the active list)
+  const uint2 *list;         // active tiles: (global tile, grid)
+  const uint32_t *count;     // active tiles of this direction
+  uint16_t *has;             // per tile: where its markers sit
+  uint2 *jobs;               // fit jobs: (grid, unaligned-edge index)
+  uint32_t jobCap;           // length of the job list
+  uint32_t *njobs;           // fit jobs of this direction
+  unsigned long long *ctr;
+  SweepView one;             // the grid's view when the engine holds one grid
+};
+
+struct CompactArgs {
+  const Inst *inst;
+  const uint32_t *tileInst;
+  uint32_t ntiles;
+  uint32_t cur;              // copy holding the current state
+  uint32_t stepNo;           // engine step and phase of the next sweep
+  int phase;
+  int afterSweep;            // 1 after a sweep, 0 after grids were added or removed
+  int slot;
+  const uint16_t *has;
+  uint8_t *nearPrev, *tinfo;
+  uint2 *actList, *nearList;  // (global tile, grid)
+  uint32_t *counts;
+  Inst one;                  // the descriptor itself when the engine holds one grid
+};
+
+struct FracArgs {
+  const Inst *inst;
+  const uint32_t *tileInst;
+  uint32_t ntiles;           // global tiles
+  uint32_t cur;              // copy holding the current state
+  const double *Cin;         // base pointers of the call (C read by curvature-only)
+  double *Cout, *Kout;
+  const uint8_t *tinfo;
+  const uint2 *list;         // near tiles: (global tile, grid)
+  const uint32_t *count;
+  int nearBlocks;            // workgroups [0, nearBlocks) work the near tiles
+  unsigned long long *ctr;
+  Inst one;                  // the descriptor itself when the engine holds one grid
+};
+
+__host__ __device__ inline int sweep_dir(const Inst &I, uint32_t stepNo, int phase) {
+  if (I.flags & INST_XY) return phase;
+  return (int)((stepNo + I.stepPar) & 1u) ^ phase;
+}
+
+// launchers (defined with the kernels); resident_blocks(which): resident
+// workgroups per CU of 0 the sweep, 1 the fit, 2 the centre kernel, 3/4/5 the
+// fraction modes 1/2/3 (the y-direction kernels use the same resources)
 int resident_blocks(int which);
-hipError_t launch_sweep(int dir, const SweepParams &p, int grid, hipStream_t s);
-hipError_t launch_fit(int dir, const FitParams &p, int grid, hipStream_t s);
-hipError_t launch_centre(int dir, const FitParams &p, int grid, hipStream_t s);
-hipError_t launch_init_has(const uint8_t *col, int nx, int ny, int ntx, int nty, uint16_t *has, uint8_t *nearPrev,
-                           hipStream_t s);
-hipError_t launch_compact(const uint16_t *has, uint8_t *nearPrev, uint8_t *tinfo, const uint8_t *col, int nx, int ntx,
-                          int nty, uint32_t *actList, uint32_t *nearList, uint32_t *counts, int slot, hipStream_t s);
-hipError_t launch_frac_curv(int mode, const FracParams &p, int grid, hipStream_t s);
+// one: the engine holds a single grid (index 0)
+hipError_t launch_sweep(int dir, bool one, const SweepArgs &a, int grid, hipStream_t s);
+hipError_t launch_fit(int dir, bool one, const SweepArgs &a, int grid, hipStream_t s);
+hipError_t launch_centre(int dir, bool one, const SweepArgs &a, int grid, hipStream_t s);
+hipError_t launch_init_tiles(const Inst *inst, uint32_t kinst, uint32_t ntiles, uint32_t cur, uint32_t *tileInst,
+                             uint16_t *has, uint8_t *nearPrev, hipStream_t s);
+hipError_t launch_clear_tiles(uint32_t *tileInst, uint16_t *has, uint8_t *nearPrev, uint8_t *tinfo, uint32_t tile0,
+                              uint32_t ntiles, hipStream_t s);
+hipError_t launch_compact(bool one, const CompactArgs &a, hipStream_t s);
+hipError_t launch_frac_curv(int mode, bool one, const FracArgs &a, int grid, hipStream_t s);
+int frac_fill_blocks(uint32_t ntiles);
 
 }  // namespace ebit
 

@@ -1,24 +1,27 @@
 // EBIT interface step: gfx950 kernels.
 //
-// Layout in HBM (one grid): node colours and centre colours as bytes, marker
+// Layout in HBM (per grid): node colours and centre colours as bytes, marker
 // offsets as FP64 structure-of-arrays (hoff, voff), each twice (ping-pong: a
-// sweep reads one copy and writes the other). The grid is cut into 16x16-cell
-// tiles. Each tile keeps a small mask of where its own markers sit (anywhere,
-// within 3 cells of each side, of each corner); a tile is "near" the
-// interface when it holds markers or a neighbour holds markers close to their
-// shared side or corner. Only tiles that are near in this sweep or were near in
-// the previous one (so both copies stay coherent) are swept; only near tiles
-// do polygon and height-function work; every other cell gets its tile's
-// uniform colour as C and 0 as curvature in a pure write stream.
+// sweep reads one copy and writes the other). Every grid is cut into
+// 16x16-cell tiles; the tiles of all grids an engine holds share one global
+// index space, so one launch per phase serves any number of grids. Each tile
+// keeps a small mask of where its own markers sit (anywhere, within 3 cells
+// of each side, of each corner); a tile is "near" the interface when it holds
+// markers or a neighbour holds markers close to their shared side or corner.
+// Only tiles that are near in this sweep or were near in the previous one (so
+// both copies stay coherent) are swept; only near tiles do polygon and
+// height-function work; every other cell gets its tile's uniform colour as C
+// and 0 as curvature in a pure write stream.
 //
 // A sweep is a gather: each output (node colour, edge offset, centre colour)
 // is a function of the old state within two cells, so there are no atomics on
 // state and no ordering between tiles. A workgroup stages its tile plus a
 // 2-cell halo in LDS (colours, centre colours, advected aligned offsets,
-// unaligned displacements), computes new colours and lander choices, gathers
-// the present new unaligned edges into an LDS work list (so circle fits run on
-// consecutive lanes), then sets the centre colours. Every FP64 expression is
-// written in one fixed order and the file is built with -ffp-contract=off.
+// unaligned displacements), computes new colours and lander choices and
+// queues the present new unaligned edges; the fit kernel then places them one
+// per lane and the centre kernel sets the centre colours. Every FP64
+// expression is written in one fixed order and the file is built with
+// -ffp-contract=off.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -28,11 +31,20 @@ namespace ebit {
 
 __device__ __forceinline__ double lerp(double a, double b, double t) { return a + t * (b - a); }
 
+// Pointers read from a grid descriptor are generic; accesses through them
+// would be flat instructions, which also count against the LDS wait counter.
+// Every per-grid array lives in device global memory, so kernels cast them.
+#define GL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ GL T *gp(T *p) {
+  return (GL T *)p;
+}
+
 constexpr int HALO = 2;
 constexpr int NH = TS + 2 * HALO + 1;  // staged nodes per side (21)
 constexpr int NE = NH - 1;             // staged cells / edges per side (20)
 constexpr int NN = TS + 1;             // new nodes per side (17)
-constexpr int JOBCAP = 1024;           // queued fit jobs per sweep workgroup (>= one tile's 256)
+constexpr int JOBCAP = 512;            // queued fit jobs per sweep workgroup (>= one tile's 256)
 
 // marker-position mask bits of a tile
 enum : uint16_t {
@@ -155,14 +167,16 @@ template <int DIR>
 struct GView {
   GMap<DIR> G;
   int na, nb;
-  const uint8_t *__restrict__ col;   // old node colours
-  const uint8_t *__restrict__ cen;   // old centre colours
-  const uint8_t *__restrict__ ncol;  // new node colours
-  const double *__restrict__ sp;     // aligned: s' (present edges)
-  const double *__restrict__ dd;     // unaligned: d (present edges)
-  const double *__restrict__ uno;    // unaligned: old offsets t
-  __device__ GView(const FitParams &P, const double *uno_)
-      : G(P.nx, P.ny), na(G.na), nb(G.nb), col(P.col), cen(P.cen), ncol(P.ncol), sp(P.sp), dd(P.dd), uno(uno_) {}
+  const GL uint8_t *__restrict__ col;   // old node colours
+  const GL uint8_t *__restrict__ cen;   // old centre colours
+  const GL uint8_t *__restrict__ ncol;  // new node colours
+  const GL double *__restrict__ sp;     // aligned: s' (present edges)
+  const GL double *__restrict__ dd;     // unaligned: d (present edges)
+  const GL double *__restrict__ uno;    // unaligned: old offsets t
+  __device__ GView(int nx, int ny, const uint8_t *col_, const uint8_t *cen_, const uint8_t *ncol_, const double *sp_,
+                   const double *dd_, const double *uno_)
+      : G(nx, ny), na(G.na), nb(G.nb), col(gp(col_)), cen(gp(cen_)), ncol(gp(ncol_)), sp(gp(sp_)), dd(gp(dd_)),
+        uno(gp(uno_)) {}
   __device__ int C(int a, int b) const { return col[G.node(a, b)]; }
   __device__ bool presA(int a, int b) const { return C(a, b) != C(a + 1, b); }
   __device__ bool presU(int a, int b) const { return C(a, b) != C(a, b + 1); }
@@ -440,14 +454,22 @@ __device__ double newUnaligned(const View &T, int a, int b, int *resRight, int *
 }
 
 // ---------------------------------------------------------------------------
-// Sweep kernel: one workgroup per active tile (persistent over the list).
-// Frame coordinates: halo slot (la, lb) is node (a0-2+la, b0-2+lb). Colours
-// are also kept as one bit mask per frame row, so present edges, new edges
-// and 4-marker cells are found with a few word operations per row and only
-// the edges that carry markers are visited one by one.
+// Sweep kernel: one workgroup per active tile (persistent over the list of
+// active tiles of all grids). Frame coordinates: halo slot (la, lb) is node
+// (a0-2+la, b0-2+lb). Colours are also kept as one bit mask per frame row, so
+// present edges, new edges and 4-marker cells are found with a few word
+// operations per row and only the edges that carry markers are visited one by
+// one. The sweep direction is a property of the tile's grid (its step
+// parity): the compaction lists the tiles of x-sweeping grids from the front
+// of the active list and those of y-sweeping grids from its back, and each
+// direction has its own launch.
 // ---------------------------------------------------------------------------
-template <int DIR>
-__global__ __launch_bounds__(256, 8) void k_sweep(SweepParams P) {
+__device__ __forceinline__ uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+
+// ONE: the engine holds a single grid, whose descriptor comes with the kernel
+// arguments (loop-invariant, no descriptor loads per tile).
+template <int DIR, bool ONE>
+__global__ __launch_bounds__(256, 8) void k_sweep(SweepArgs A, const Inst *__restrict__ inst) {
   __shared__ uint8_t sCol[NH][NH];
   __shared__ uint8_t sCen[NE][NE];
   __shared__ double sSp[NH][NE];
@@ -456,70 +478,57 @@ __global__ __launch_bounds__(256, 8) void k_sweep(SweepParams P) {
   __shared__ uint32_t sRow[NH];     // old colours, bit la of frame row lb
   __shared__ uint32_t sNRow[NN];    // new colours, bit a-a0 of row b-b0
   __shared__ uint32_t sRecv[NN];    // new aligned edges (a,b) that receive a lander, bit a-a0
-  __shared__ uint32_t sTiles[64];   // this workgroup's first tiles
+  __shared__ uint2 sTiles[64];      // this workgroup's first (tile, grid) entries
   __shared__ uint16_t sAdv[2 * NH * NE];
-  __shared__ uint32_t sJob[JOBCAP];  // new interior unaligned markers of this workgroup's tiles
+  __shared__ uint2 sJob[JOBCAP];    // new interior unaligned markers of this workgroup's tiles
   __shared__ uint32_t sNAdv, sNJob, sHas, sJobBase;
   __shared__ uint32_t sCnt[NCOUNTERS];
-  __shared__ uint32_t sErr;
-
-  const GMap<DIR> G(P.nx, P.ny);
-  const int na = G.na, nb = G.nb;
-  const double lam = P.lam;
-  const double *__restrict__ alo = DIR == 0 ? P.hoff : P.voff;
-  const double *__restrict__ uno = DIR == 0 ? P.voff : P.hoff;
-  double *__restrict__ aln = DIR == 0 ? P.nhoff : P.nvoff;
-  double *__restrict__ unn = DIR == 0 ? P.nvoff : P.nhoff;
-  const double *__restrict__ vel = P.vel;
-  auto V = [&](int a, int r) -> double {
-    r = r < 0 ? 0 : (r > nb - 1 ? nb - 1 : r);
-    return vel[G.une(a, r)];
-  };
 
   const int tid = threadIdx.x;
+  const uint32_t cur = A.cur, nxt = cur ^ 1u;
   if (tid < NCOUNTERS) sCnt[tid] = 0;
-  if (tid == 0) {
-    sErr = 0;
-    sNJob = 0;
-  }
+  if (tid == 0) sNJob = 0;
   if (tid < NH) sRow[tid] = 0;
   const Counts cnt{sCnt};
   // the queued jobs go to the fit kernel's list with one reservation
   auto flushJobs = [&]() {
     const uint32_t n = sNJob;
-    if (tid == 0) sJobBase = atomicAdd(P.njobs, n);
+    if (tid == 0) sJobBase = atomicAdd(A.njobs, n);
     __syncthreads();
-    for (uint32_t w = tid; w < n; w += blockDim.x) P.jobs[sJobBase + w] = sJob[w];
+    for (uint32_t w = tid; w < n; w += blockDim.x) A.jobs[DIR == 0 ? sJobBase + w : A.jobCap - 1u - (sJobBase + w)] = sJob[w];
     __syncthreads();
     if (tid == 0) sNJob = 0;
   };
-
-  Tile T;
-  T.na = na;
-  T.nb = nb;
-  T.col = sCol;
-  T.cen = sCen;
-  T.sp = sSp;
-  T.dd = sD;
-  T.tt = sT;
-  T.nrow = sNRow;
 
   // Staging of colours and centre colours: each thread owns two node slots
   // and two cell slots of the halo (memory order). The next tile's bytes are
   // fetched into registers while the current tile computes.
   static_assert(NH * NH <= 512 && NE * NE <= 512, "two staging slots per thread");
   uint8_t pc0 = 0, pc1 = 0, pe0 = 0, pe1 = 0;
-  auto prefetch = [&](uint32_t tl) {
-    const int px0 = (int)(tl % (uint32_t)P.ntx) * TS, py0 = (int)(tl / (uint32_t)P.ntx) * TS;
+  auto prefetch = [&](uint2 te) {
+    const uint32_t gt = te.x;
+    int nx, ny, ntx;
+    uint32_t tile0;
+    const GL uint8_t *col, *cen;
+    if (ONE) {
+      nx = A.one.nx, ny = A.one.ny, ntx = A.one.ntx, tile0 = A.one.tile0;
+      col = gp(A.one.col), cen = gp(A.one.cen);
+    } else {
+      const Inst &I = inst[te.y];
+      nx = I.nx, ny = I.ny, ntx = I.ntx, tile0 = I.tile0;
+      col = gp(I.col[cur]), cen = gp(I.cen[cur]);
+    }
+    const uint32_t lt = gt - tile0;
+    const int px0 = (int)(lt % (uint32_t)ntx) * TS, py0 = (int)(lt / (uint32_t)ntx) * TS;
     auto node = [&](int k) -> uint8_t {
       if (k >= NH * NH) return 0;
       const int x = px0 - HALO + k % NH, y = py0 - HALO + k / NH;
-      return (x >= 0 && y >= 0 && x <= P.nx && y <= P.ny) ? P.col[(size_t)y * (P.nx + 1) + x] : (uint8_t)0;
+      return (x >= 0 && y >= 0 && x <= nx && y <= ny) ? col[(size_t)y * (nx + 1) + x] : (uint8_t)0;
     };
     auto cell = [&](int k) -> uint8_t {
       if (k >= NE * NE) return 0;
       const int x = px0 - HALO + k % NE, y = py0 - HALO + k / NE;
-      return (x >= 0 && y >= 0 && x < P.nx && y < P.ny) ? P.cen[(size_t)y * P.nx + x] : (uint8_t)0;
+      return (x >= 0 && y >= 0 && x < nx && y < ny) ? cen[(size_t)y * nx + x] : (uint8_t)0;
     };
     pc0 = node(tid);
     pc1 = node(tid + 256);
@@ -527,20 +536,55 @@ __global__ __launch_bounds__(256, 8) void k_sweep(SweepParams P) {
     pe1 = cell(tid + 256);
   };
 
-  const uint32_t ntile = *P.count;
+  const uint32_t ntile = *A.count;
   // this workgroup's tile indices, so no index load waits in the loop
-  if (tid < 64 && blockIdx.x + tid * gridDim.x < ntile) sTiles[tid] = P.list[blockIdx.x + tid * gridDim.x];
+  auto entry = [&](uint32_t it) -> uint2 { return A.list[DIR == 0 ? it : A.ntiles - 1u - it]; };
+  if (tid < 64 && blockIdx.x + tid * gridDim.x < ntile) sTiles[tid] = entry(blockIdx.x + tid * gridDim.x);
   __syncthreads();
-  auto tileAt = [&](uint32_t it) -> uint32_t {
+  auto tileAt = [&](uint32_t it) -> uint2 {
     const uint32_t k = (it - blockIdx.x) / gridDim.x;
-    return k < 64 ? sTiles[k] : P.list[it];
+    const uint2 e = k < 64 ? sTiles[k] : entry(it);
+    return make_uint2(uni(e.x), uni(e.y));
   };
   if (blockIdx.x < ntile) prefetch(tileAt(blockIdx.x));
+
   for (uint32_t it = blockIdx.x; it < ntile; it += gridDim.x) {
-    const uint32_t tile = tileAt(it);
-    const int tx = (int)(tile % (uint32_t)P.ntx), ty = (int)(tile / (uint32_t)P.ntx);
+    const uint2 te = tileAt(it);
+    const uint32_t gt = te.x, kinst = ONE ? 0u : te.y;
+    const SweepView W = ONE ? A.one
+                            : sweep_view(inst[kinst], cur, DIR, A.u, A.v,
+                                         (A.dts ? A.dts[kinst] : A.dt) / inst[kinst].h);
+    const int nx = W.nx, ny = W.ny;
+    const GMap<DIR> G(nx, ny);
+    const int na = G.na, nb = G.nb;
+    const double lam = W.lam;
+    const GL double *__restrict__ alo = gp(DIR == 0 ? W.hoff : W.voff);
+    const GL double *__restrict__ uno = gp(DIR == 0 ? W.voff : W.hoff);
+    GL double *__restrict__ aln = gp(DIR == 0 ? W.nhoff : W.nvoff);
+    GL double *__restrict__ unn = gp(DIR == 0 ? W.nvoff : W.nhoff);
+    const GL double *__restrict__ vel = gp(W.vel);
+    GL uint8_t *__restrict__ ncol = gp(W.ncol);
+    GL uint8_t *__restrict__ ncen = gp(W.ncen);
+    GL double *__restrict__ spg = gp(W.sp);
+    GL double *__restrict__ ddg = gp(W.dd);
+    uint32_t *errg = W.err;  // written only on an error
+    auto V = [&](int a, int r) -> double {
+      r = r < 0 ? 0 : (r > nb - 1 ? nb - 1 : r);
+      return vel[G.une(a, r)];
+    };
+    const uint32_t lt = gt - W.tile0;
+    const int tx = (int)(lt % (uint32_t)W.ntx), ty = (int)(lt / (uint32_t)W.ntx);
     const int x0 = tx * TS, y0 = ty * TS;
     const int a0 = DIR == 0 ? x0 : y0, b0 = DIR == 0 ? y0 : x0;
+    Tile T;
+    T.na = na;
+    T.nb = nb;
+    T.col = sCol;
+    T.cen = sCen;
+    T.sp = sSp;
+    T.dd = sD;
+    T.tt = sT;
+    T.nrow = sNRow;
     T.a0 = a0;
     T.b0 = b0;
     __syncthreads();  // the previous tile is done with LDS
@@ -623,15 +667,15 @@ __global__ __launch_bounds__(256, 8) void k_sweep(SweepParams P) {
       for (int k = tid; k < NN * NN; k += blockDim.x) {
         const int li = k % NN, lj = k / NN;
         const int x = x0 + li, y = y0 + lj;
-        if (x > P.nx || y > P.ny) continue;
+        if (x > nx || y > ny) continue;
         const int hx = li + HALO, hy = lj + HALO;
-        if ((li < TS || x == P.nx) && (lj < TS || y == P.ny))
-          P.ncol[(size_t)y * (P.nx + 1) + x] = DIR == 0 ? sCol[hy][hx] : sCol[hx][hy];
-        if (li < TS && lj < TS && x < P.nx && y < P.ny)
-          P.ncen[(size_t)y * P.nx + x] = DIR == 0 ? sCen[hy][hx] : sCen[hx][hy];
+        if ((li < TS || x == nx) && (lj < TS || y == ny))
+          ncol[(size_t)y * (nx + 1) + x] = DIR == 0 ? sCol[hy][hx] : sCol[hx][hy];
+        if (li < TS && lj < TS && x < nx && y < ny)
+          ncen[(size_t)y * nx + x] = DIR == 0 ? sCen[hy][hx] : sCen[hx][hy];
       }
       if (tid == 0) {
-        P.has[tile] = 0;
+        A.has[gt] = 0;
         cnt.add(C_TILES_EMPTY, 1u);
       }
       if (tid < NH) sRow[tid] = 0;
@@ -652,10 +696,10 @@ __global__ __launch_bounds__(256, 8) void k_sweep(SweepParams P) {
         sSp[lb][la] = spv;
         const bool own = la >= HALO && la < HALO + TS && lb >= HALO && (lb < HALO + TS || b == nb);
         if (own) {
-          P.sp[G.ale(a, b)] = spv;
+          spg[G.ale(a, b)] = spv;
           cnt.add(C_MARKERS, 1u);
-          if (fabs(d) > 0.5) atomicOr(&sErr, ERRBIT_CFL);
-          if ((spv >= 1.0 && a + 1 >= na) || (spv < 0.0 && a == 0)) atomicOr(&sErr, ERRBIT_DOMAIN);
+          if (fabs(d) > 0.5) atomicOr(errg, ERRBIT_CFL);
+          if ((spv >= 1.0 && a + 1 >= na) || (spv < 0.0 && a == 0)) atomicOr(errg, ERRBIT_DOMAIN);
         }
         // the crossed node flips; the edge it lands on receives a lander
         const int j = b - b0;
@@ -684,9 +728,9 @@ __global__ __launch_bounds__(256, 8) void k_sweep(SweepParams P) {
         sD[lb][la] = wall ? 0.0 : d;
         const bool own = la >= HALO && (la < HALO + TS || a == na) && lb >= HALO && lb < HALO + TS;
         if (own) {
-          P.dd[G.une(a, b)] = wall ? 0.0 : d;
+          ddg[G.une(a, b)] = wall ? 0.0 : d;
           cnt.add(C_MARKERS, 1u);
-          if (fabs(d) > 0.5) atomicOr(&sErr, ERRBIT_CFL);
+          if (fabs(d) > 0.5) atomicOr(errg, ERRBIT_CFL);
           if (wall && d != 0.0) cnt.add(C_WALL_VIOLATION, 1u);
         }
       }
@@ -702,7 +746,7 @@ __global__ __launch_bounds__(256, 8) void k_sweep(SweepParams P) {
       const int la = DIR == 0 ? hx : hy, lb = DIR == 0 ? hy : hx;
       const int a = a0 + la, b = b0 + lb;
       if (a <= na && b <= nb && (la < TS || a == na) && (lb < TS || b == nb))
-        P.ncol[G.node(a, b)] = (uint8_t)((sNRow[lb] >> la) & 1u);
+        ncol[G.node(a, b)] = (uint8_t)((sNRow[lb] >> la) & 1u);
     }
     if (tid < NN) {
       // new aligned edges (a,b), a in [a0, a0+15], on row b = b0+tid
@@ -753,7 +797,7 @@ __global__ __launch_bounds__(256, 8) void k_sweep(SweepParams P) {
             }
           } else if (own) {
             // interior line owned by this tile: one fit job
-            sJob[atomicAdd(&sNJob, 1u)] = (uint32_t)G.une(a, b);
+            sJob[atomicAdd(&sNJob, 1u)] = make_uint2(kinst, (uint32_t)G.une(a, b));
             hasm |= DIR == 0 ? maskV(a, b, x0, y0) : maskH(b, a, x0, y0);
           }
         }
@@ -763,18 +807,17 @@ __global__ __launch_bounds__(256, 8) void k_sweep(SweepParams P) {
     for (int k = tid; k < TS * TS; k += blockDim.x) {
       const int hx = k % TS, hy = k / TS;
       const int x = x0 + hx, y = y0 + hy;
-      if (x < P.nx && y < P.ny) P.ncen[(size_t)y * P.nx + x] = DIR == 0 ? sCen[hy + HALO][hx + HALO] : sCen[hx + HALO][hy + HALO];
+      if (x < nx && y < ny) ncen[(size_t)y * nx + x] = DIR == 0 ? sCen[hy + HALO][hx + HALO] : sCen[hx + HALO][hy + HALO];
     }
     if (hasm) atomicOr(&sHas, hasm);
     __syncthreads();
-    if (tid == 0) P.has[tile] = (uint16_t)sHas;
+    if (tid == 0) A.has[gt] = (uint16_t)sHas;
     // keep room for a full tile of jobs
     if (sNJob > JOBCAP - TS * TS) flushJobs();
   }
   __syncthreads();
   if (sNJob) flushJobs();
-  if (tid < NCOUNTERS && sCnt[tid]) atomicAdd(&P.ctr[tid], (unsigned long long)sCnt[tid]);
-  if (tid == 0 && sErr) atomicOr(P.err, sErr);
+  if (tid < NCOUNTERS && sCnt[tid]) atomicAdd(&A.ctr[tid], (unsigned long long)sCnt[tid]);
 }
 
 // ---------------------------------------------------------------------------
@@ -784,28 +827,56 @@ __global__ __launch_bounds__(256, 8) void k_sweep(SweepParams P) {
 // writes the marker's offset and, per edge, the centre-CV results for the cell
 // right of the line (bits 0-1, value + 1) and the cell left of it (bits 2-3).
 // ---------------------------------------------------------------------------
+// Runs f(k) on the lanes whose grid is k, one grid of the wavefront at a time
+// (taken from the first lane still pending), so k is wave-uniform and the
+// grid's descriptor stays in scalar registers. Lanes with k == NO_INST idle.
+template <class F>
+__device__ __forceinline__ void eachGrid(uint32_t k, F f) {
+  bool pending = k != NO_INST;
+  for (;;) {
+    const uint64_t m = __ballot(pending);
+    if (m == 0) break;
+    const uint32_t k0 = (uint32_t)__builtin_amdgcn_readlane((int)k, (int)(__ffsll((unsigned long long)m) - 1));
+    if (pending && k == k0) {
+      f(k0);
+      pending = false;
+    }
+  }
+}
+
 template <int DIR>
-__global__ __launch_bounds__(256) void k_fit(FitParams P) {
+__device__ __forceinline__ void fitJob(const SweepView &W, uint32_t e, const Counts &cnt) {
+  const GView<DIR> V(W.nx, W.ny, W.col, W.cen, W.ncol, W.sp, W.dd, DIR == 0 ? W.voff : W.hoff);
+  GL double *__restrict__ unn = gp(DIR == 0 ? W.nvoff : W.nhoff);
+  int a, b;
+  if (DIR == 0) { b = (int)(e / (uint32_t)(W.nx + 1)); a = (int)(e % (uint32_t)(W.nx + 1)); }
+  else { a = (int)(e / (uint32_t)W.nx); b = (int)(e % (uint32_t)W.nx); }
+  int rR, rL;
+  const double y = newUnaligned(V, a, b, &rR, &rL, cnt, true);
+  unn[e] = y;
+  gp(W.zr)[e] = (uint8_t)((rR + 1) | ((rL + 1) << 2));
+}
+
+template <int DIR, bool ONE>
+__global__ __launch_bounds__(256) void k_fit(SweepArgs A, const Inst *__restrict__ inst) {
   __shared__ uint32_t sCnt[NCOUNTERS];
   const int tid = threadIdx.x;
   if (tid < NCOUNTERS) sCnt[tid] = 0;
   __syncthreads();
   const Counts cnt{sCnt};
-  const GView<DIR> V(P, DIR == 0 ? P.voff : P.hoff);
-  double *__restrict__ unn = DIR == 0 ? P.nvoff : P.nhoff;
-  const uint32_t nj = *P.njobs;
-  for (uint32_t w = blockIdx.x * blockDim.x + tid; w < nj; w += gridDim.x * blockDim.x) {
-    const uint32_t e = P.jobs[w];
-    int a, b;
-    if (DIR == 0) { b = (int)(e / (uint32_t)(P.nx + 1)); a = (int)(e % (uint32_t)(P.nx + 1)); }
-    else { a = (int)(e / (uint32_t)P.nx); b = (int)(e % (uint32_t)P.nx); }
-    int rR, rL;
-    const double y = newUnaligned(V, a, b, &rR, &rL, cnt, true);
-    unn[e] = y;
-    P.zr[e] = (uint8_t)((rR + 1) | ((rL + 1) << 2));
+  const uint32_t nj = *A.njobs;
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t w0 = blockIdx.x * blockDim.x; w0 < nj; w0 += stride) {
+    const uint32_t w = w0 + tid;
+    const uint2 jb = w < nj ? A.jobs[DIR == 0 ? w : A.jobCap - 1u - w] : make_uint2(NO_INST, 0u);
+    if (ONE) {
+      if (w < nj) fitJob<DIR>(A.one, jb.y, cnt);
+    } else {
+      eachGrid(jb.x, [&](uint32_t k) { fitJob<DIR>(sweep_view(inst[k], A.cur, DIR, A.u, A.v, 0.0), jb.y, cnt); });
+    }
   }
   __syncthreads();
-  if (tid < NCOUNTERS && sCnt[tid]) atomicAdd(&P.ctr[tid], (unsigned long long)sCnt[tid]);
+  if (tid < NCOUNTERS && sCnt[tid]) atomicAdd(&A.ctr[tid], (unsigned long long)sCnt[tid]);
 }
 
 // Centre kernel: rules (1)-(5) of Sec. 2.3 for the cells next to new
@@ -814,62 +885,80 @@ __global__ __launch_bounds__(256) void k_fit(FitParams P) {
 // carried over by the sweep). The job on line a settles cell a and, when line
 // a-1 holds no job, cell a-1.
 template <int DIR>
-__global__ __launch_bounds__(256) void k_centre(FitParams P) {
+__device__ __forceinline__ void centreJob(const SweepView &W, uint32_t e, const Counts &cnt) {
+  const GMap<DIR> G(W.nx, W.ny);
+  const int na = G.na;
+  const GL uint8_t *__restrict__ ncol = gp(W.ncol);
+  GL uint8_t *__restrict__ ncen = gp(W.ncen);
+  const GL uint8_t *__restrict__ zr = gp(W.zr);
+  auto newC = [&](int a, int b) -> int { return ncol[G.node(a, b)]; };
+  int a, b;
+  if (DIR == 0) { b = (int)(e / (uint32_t)(W.nx + 1)); a = (int)(e % (uint32_t)(W.nx + 1)); }
+  else { a = (int)(e / (uint32_t)W.nx); b = (int)(e % (uint32_t)W.nx); }
+  auto isJob = [&](int l) -> bool { return l > 0 && l < na && newC(l, b) != newC(l, b + 1); };
+  auto settle = [&](int c, int left, int right) {
+    int cc = -1;
+    if (left >= 0) {
+      cc = left;
+      cnt.add(C_CV_SET, 1u);
+      if (right >= 0 && right != left) cnt.add(C_CV_CONFLICT, 1u);
+    } else if (right >= 0) {
+      cc = right;
+      cnt.add(C_CV_SET, 1u);
+    } else {
+      const int k0 = newC(c, b), k1 = newC(c + 1, b), k2 = newC(c + 1, b + 1), k3 = newC(c, b + 1);
+      if (k0 != k1 && k1 != k2 && k3 != k2 && k0 != k3) cnt.add(C_CV_UNRESOLVED, 1u);
+    }
+    if (cc >= 0) ncen[G.cell(c, b)] = (uint8_t)cc;
+  };
+  const uint32_t z = zr[e];
+  // cell a, right of line a
+  {
+    const int right = isJob(a + 1) ? (int)((zr[G.une(a + 1, b)] >> 2) & 3u) - 1 : -1;
+    settle(a, (int)(z & 3u) - 1, right);
+  }
+  // cell a-1, left of line a, when its own left line holds no job
+  if (!isJob(a - 1)) settle(a - 1, -1, (int)((z >> 2) & 3u) - 1);
+}
+
+template <int DIR, bool ONE>
+__global__ __launch_bounds__(256) void k_centre(SweepArgs A, const Inst *__restrict__ inst) {
   __shared__ uint32_t sCnt[NCOUNTERS];
   const int tid = threadIdx.x;
   if (tid < NCOUNTERS) sCnt[tid] = 0;
   __syncthreads();
   const Counts cnt{sCnt};
-  const GMap<DIR> G(P.nx, P.ny);
-  const int na = G.na;
-  auto newC = [&](int a, int b) -> int { return P.ncol[G.node(a, b)]; };
-  const uint32_t nj = *P.njobs;
-  for (uint32_t w = blockIdx.x * blockDim.x + tid; w < nj; w += gridDim.x * blockDim.x) {
-    const uint32_t e = P.jobs[w];
-    int a, b;
-    if (DIR == 0) { b = (int)(e / (uint32_t)(P.nx + 1)); a = (int)(e % (uint32_t)(P.nx + 1)); }
-    else { a = (int)(e / (uint32_t)P.nx); b = (int)(e % (uint32_t)P.nx); }
-    auto isJob = [&](int l) -> bool { return l > 0 && l < na && newC(l, b) != newC(l, b + 1); };
-    auto settle = [&](int c, int left, int right) {
-      int cc = -1;
-      if (left >= 0) {
-        cc = left;
-        cnt.add(C_CV_SET, 1u);
-        if (right >= 0 && right != left) cnt.add(C_CV_CONFLICT, 1u);
-      } else if (right >= 0) {
-        cc = right;
-        cnt.add(C_CV_SET, 1u);
-      } else {
-        const int k0 = newC(c, b), k1 = newC(c + 1, b), k2 = newC(c + 1, b + 1), k3 = newC(c, b + 1);
-        if (k0 != k1 && k1 != k2 && k3 != k2 && k0 != k3) cnt.add(C_CV_UNRESOLVED, 1u);
-      }
-      if (cc >= 0) P.ncen[G.cell(c, b)] = (uint8_t)cc;
-    };
-    const uint32_t z = P.zr[e];
-    // cell a, right of line a
-    {
-      const int right = isJob(a + 1) ? (int)((P.zr[G.une(a + 1, b)] >> 2) & 3u) - 1 : -1;
-      settle(a, (int)(z & 3u) - 1, right);
+  const uint32_t nj = *A.njobs;
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t w0 = blockIdx.x * blockDim.x; w0 < nj; w0 += stride) {
+    const uint32_t w = w0 + tid;
+    const uint2 jb = w < nj ? A.jobs[DIR == 0 ? w : A.jobCap - 1u - w] : make_uint2(NO_INST, 0u);
+    if (ONE) {
+      if (w < nj) centreJob<DIR>(A.one, jb.y, cnt);
+    } else {
+      eachGrid(jb.x, [&](uint32_t k) { centreJob<DIR>(sweep_view(inst[k], A.cur, DIR, A.u, A.v, 0.0), jb.y, cnt); });
     }
-    // cell a-1, left of line a, when its own left line holds no job
-    if (!isJob(a - 1)) settle(a - 1, -1, (int)((z >> 2) & 3u) - 1);
   }
   __syncthreads();
-  if (tid < NCOUNTERS && sCnt[tid]) atomicAdd(&P.ctr[tid], (unsigned long long)sCnt[tid]);
+  if (tid < NCOUNTERS && sCnt[tid]) atomicAdd(&A.ctr[tid], (unsigned long long)sCnt[tid]);
 }
 
 // ---------------------------------------------------------------------------
-// Tile bookkeeping: marker masks of an uploaded state, then per-sweep
-// compaction into the active list (near now or near last sweep) and the near
-// list. Each workgroup scans 1024 tiles and reserves its list slots with one
+// Tile bookkeeping: tiles of a newly placed grid (owner, marker masks), tiles
+// of a removed grid, and the per-sweep compaction into the active list (near
+// now or near before the previous compaction) and the near list. Each
+// compaction workgroup scans 1024 tiles and reserves its list slots with one
 // atomic per list.
 // ---------------------------------------------------------------------------
-__global__ void k_init_has(const uint8_t *__restrict__ col, int nx, int ny, int ntx, int nty, uint16_t *has,
-                           uint8_t *nearPrev) {
-  const int tile = blockIdx.x;
-  if (tile >= ntx * nty) return;
-  const int tx = tile % ntx, ty = tile / ntx;
+__global__ void k_init_tiles(const Inst *__restrict__ inst, uint32_t kinst, uint32_t cur, uint32_t *tileInst,
+                             uint16_t *has, uint8_t *nearPrev) {
+  const Inst &I = inst[kinst];
+  const uint32_t lt = blockIdx.x;
+  if (lt >= (uint32_t)(I.ntx * I.nty)) return;
+  const int nx = I.nx, ny = I.ny;
+  const int tx = (int)(lt % (uint32_t)I.ntx), ty = (int)(lt / (uint32_t)I.ntx);
   const int x0 = tx * TS, y0 = ty * TS;
+  const GL uint8_t *__restrict__ col = gp(I.col[cur]);
   __shared__ uint32_t sh;
   if (threadIdx.x == 0) sh = 0;
   __syncthreads();
@@ -887,9 +976,21 @@ __global__ void k_init_has(const uint8_t *__restrict__ col, int nx, int ny, int 
   if (m) atomicOr(&sh, m);
   __syncthreads();
   if (threadIdx.x == 0) {
-    has[tile] = (uint16_t)sh;
-    nearPrev[tile] = 0;
+    const uint32_t gt = I.tile0 + lt;
+    has[gt] = (uint16_t)sh;
+    nearPrev[gt] = 0;
+    tileInst[gt] = kinst;
   }
+}
+
+__global__ void k_clear_tiles(uint32_t *tileInst, uint16_t *has, uint8_t *nearPrev, uint8_t *tinfo, uint32_t tile0,
+                              uint32_t n) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  tileInst[tile0 + t] = NO_INST;
+  has[tile0 + t] = 0;
+  nearPrev[tile0 + t] = 0;
+  tinfo[tile0 + t] = TI_DEAD;
 }
 
 __device__ __forceinline__ bool nearOf(const uint16_t *__restrict__ has, int tx, int ty, int ntx, int nty) {
@@ -903,55 +1004,73 @@ __device__ __forceinline__ bool nearOf(const uint16_t *__restrict__ has, int tx,
 
 constexpr int CPT = 4;  // tiles per thread in the compaction
 
-__global__ __launch_bounds__(256) void k_compact(const uint16_t *__restrict__ has, uint8_t *__restrict__ nearPrev,
-                                                 uint8_t *__restrict__ tinfo, const uint8_t *__restrict__ col, int nx,
-                                                 int ntx, int nty, uint32_t *actList, uint32_t *nearList,
-                                                 uint32_t *counts, int slot) {
-  __shared__ uint32_t sA[256], sN[256];
-  __shared__ uint32_t sBaseA, sBaseN;
-  const int ntiles = ntx * nty;
+// nearPrev bits: 0 near at the latest compaction, 1 near at the one before.
+// After a sweep the latest becomes the one before; a compaction without a
+// sweep in between (grids added or removed) keeps it. Active tiles of grids
+// whose next sweep runs along x go to the front of the active list, the others
+// to its back.
+template <bool ONE>
+__global__ __launch_bounds__(256) void k_compact(CompactArgs C) {
+  __shared__ uint32_t sA[256], sB[256], sN[256];
+  __shared__ uint32_t sBaseA, sBaseB, sBaseN;
   const int tid = threadIdx.x;
-  if (blockIdx.x == 0 && tid == 0) {
-    // clear the other slot (active, near, jobs) for the next compaction;
-    // nothing reads it now
-    counts[3 * (slot ^ 1)] = 0;
-    counts[3 * (slot ^ 1) + 1] = 0;
-    counts[3 * (slot ^ 1) + 2] = 0;
+  if (blockIdx.x == 0 && tid < NSLOT) {
+    // clear the other slot for the next compaction; nothing reads it now
+    C.counts[NSLOT * (C.slot ^ 1) + tid] = 0;
   }
-  const int base = (blockIdx.x * blockDim.x + tid) * CPT;
-  uint32_t actBits = 0, nearBits = 0;
+  const uint32_t base = (blockIdx.x * blockDim.x + tid) * CPT;
+  uint32_t actBits = 0, dirBits = 0, nearBits = 0;
+  uint32_t kq[CPT];
   for (int q = 0; q < CPT; q++) {
-    const int t = base + q;
-    if (t >= ntiles) break;
-    const int tx = t % ntx, ty = t / ntx;
-    const bool nr = nearOf(has, tx, ty, ntx, nty);
-    const bool act = nr || nearPrev[t] != 0;
-    nearPrev[t] = (uint8_t)nr;
-    tinfo[t] = (uint8_t)((nr ? 1 : 0) | (col[(size_t)(ty * TS) * (nx + 1) + tx * TS] << 1));
+    const uint32_t t = base + q;
+    kq[q] = 0;
+    if (t >= C.ntiles) break;
+    const uint32_t k = ONE ? 0u : C.tileInst[t];
+    kq[q] = k;
+    if (k == NO_INST) continue;
+    const Inst &I = ONE ? C.one : C.inst[k];
+    const uint32_t lt = t - I.tile0;
+    const int tx = (int)(lt % (uint32_t)I.ntx), ty = (int)(lt / (uint32_t)I.ntx);
+    const bool nr = nearOf(C.has + I.tile0, tx, ty, I.ntx, I.nty);
+    const uint32_t pv = C.nearPrev[t];
+    const uint32_t prev = C.afterSweep ? (pv & 1u) : ((pv >> 1) & 1u);
+    const bool act = nr || prev;
+    C.nearPrev[t] = (uint8_t)((nr ? 1u : 0u) | (prev << 1));
+    C.tinfo[t] = (uint8_t)((nr ? TI_NEAR : 0) |
+                           (gp(I.col[C.cur])[(size_t)(ty * TS) * (I.nx + 1) + tx * TS] ? TI_COLOUR : 0));
     actBits |= (uint32_t)act << q;
+    dirBits |= (uint32_t)(act && sweep_dir(I, C.stepNo, C.phase) == 1) << q;
     nearBits |= (uint32_t)nr << q;
   }
   // exclusive block scan of the per-thread counts
-  const uint32_t ca = __popc(actBits), cn = __popc(nearBits);
+  const uint32_t cb = __popc(dirBits), ca = __popc(actBits) - cb, cn = __popc(nearBits);
   sA[tid] = ca;
+  sB[tid] = cb;
   sN[tid] = cn;
   __syncthreads();
   for (int off = 1; off < 256; off <<= 1) {
-    const uint32_t xa = tid >= off ? sA[tid - off] : 0, xn = tid >= off ? sN[tid - off] : 0;
+    const uint32_t xa = tid >= off ? sA[tid - off] : 0, xb = tid >= off ? sB[tid - off] : 0,
+                   xn = tid >= off ? sN[tid - off] : 0;
     __syncthreads();
     sA[tid] += xa;
+    sB[tid] += xb;
     sN[tid] += xn;
     __syncthreads();
   }
+  uint32_t *cs = C.counts + NSLOT * C.slot;
   if (tid == 255) {
-    sBaseA = sA[255] ? atomicAdd(&counts[3 * slot], sA[255]) : 0;
-    sBaseN = sN[255] ? atomicAdd(&counts[3 * slot + 1], sN[255]) : 0;
+    sBaseA = sA[255] ? atomicAdd(&cs[CNT_ACT_X], sA[255]) : 0;
+    sBaseB = sB[255] ? atomicAdd(&cs[CNT_ACT_Y], sB[255]) : 0;
+    sBaseN = sN[255] ? atomicAdd(&cs[CNT_NEAR], sN[255]) : 0;
   }
   __syncthreads();
-  uint32_t pa = sBaseA + sA[tid] - ca, pn = sBaseN + sN[tid] - cn;
+  uint32_t pa = sBaseA + sA[tid] - ca, pb = sBaseB + sB[tid] - cb, pn = sBaseN + sN[tid] - cn;
   for (int q = 0; q < CPT; q++) {
-    if (actBits >> q & 1) actList[pa++] = (uint32_t)(base + q);
-    if (nearBits >> q & 1) nearList[pn++] = (uint32_t)(base + q);
+    if (actBits >> q & 1) {
+      if (dirBits >> q & 1) C.actList[C.ntiles - 1u - pb++] = make_uint2(base + q, kq[q]);
+      else C.actList[pa++] = make_uint2(base + q, kq[q]);
+    }
+    if (nearBits >> q & 1) C.nearList[pn++] = make_uint2(base + q, kq[q]);
   }
 }
 
@@ -967,8 +1086,16 @@ __device__ __forceinline__ int haloCell(int k, int n) {
   return k < 0 ? 0 : (k >= n ? n - 1 : k);
 }
 
+struct FracCtx {
+  int nx, ny;
+  const GL uint8_t *__restrict__ col;
+  const GL uint8_t *__restrict__ cen;
+  const GL double *__restrict__ hoff;
+  const GL double *__restrict__ voff;
+};
+
 // area of colour 1 in cell (i,j) from its corner colours (BL, BR, TR, TL)
-__device__ double cellFraction(const FracParams &P, int i, int j, int kBL, int kBR, int kTR, int kTL) {
+__device__ double cellFraction(const FracCtx &P, int i, int j, int kBL, int kBR, int kTR, int kTL) {
   const size_t W1 = (size_t)P.nx + 1;
   const bool pb = kBL != kBR, pr = kBR != kTR, pt = kTL != kTR, pl = kBL != kTL;
   const int n = (int)pb + (int)pr + (int)pt + (int)pl;
@@ -1014,50 +1141,6 @@ __device__ double cellFraction(const FracParams &P, int i, int j, int kBL, int k
   return cen ? 1.0 - s : s;
 }
 
-// Dense write of one grid row for the cells of uniform (not near) tiles:
-// C = the tile's colour, K = 0. Two cells per thread; rows of even length use
-// 16-byte non-temporal stores when the buffers allow it.
-typedef double v2d __attribute__((ext_vector_type(2)));
-
-template <int MODE>
-__device__ __forceinline__ void fillPair(const FracParams &P, const uint8_t *trow, size_t rowoff, int i) {
-  const int nx = P.nx;
-  const uint8_t t0 = trow[i / TS];
-  const bool two = i + 1 < nx;
-  const uint8_t t1 = two ? trow[(i + 1) / TS] : (uint8_t)1;
-  if (P.vec && !(t0 & 1) && !(t1 & 1)) {
-    if (MODE & 1) {
-      v2d c = {(double)(t0 >> 1), (double)(t1 >> 1)};
-      __builtin_nontemporal_store(c, (v2d *)&P.Cout[rowoff + i]);
-    }
-    if (MODE & 2) {
-      v2d z = {0.0, 0.0};
-      __builtin_nontemporal_store(z, (v2d *)&P.Kout[rowoff + i]);
-    }
-    return;
-  }
-  if (!(t0 & 1)) {
-    if (MODE & 1) P.Cout[rowoff + i] = (double)(t0 >> 1);
-    if (MODE & 2) P.Kout[rowoff + i] = 0.0;
-  }
-  if (two && !(t1 & 1)) {
-    if (MODE & 1) P.Cout[rowoff + i + 1] = (double)(t1 >> 1);
-    if (MODE & 2) P.Kout[rowoff + i + 1] = 0.0;
-  }
-}
-
-template <int MODE>
-__device__ __forceinline__ void fillRow(const FracParams &P, int j) {
-  const uint8_t *trow = P.tinfo + (size_t)(j / TS) * P.ntx;
-  const size_t rowoff = (size_t)j * P.nx;
-  const int step = 2 * (int)blockDim.x;
-  for (int i = 2 * (int)threadIdx.x; i < P.nx; i += 4 * step) {
-#pragma unroll
-    for (int u = 0; u < 4; u++)
-      if (i + u * step < P.nx) fillPair<MODE>(P, trow, rowoff, i + u * step);
-  }
-}
-
 // Heights along columns (rows == 0) or rows (rows == 1) around cell (i,j);
 // returns 1 and kappa on success.
 template <class GetC, class GetN, class GetB>
@@ -1090,49 +1173,89 @@ __device__ bool hfTry(int i, int j, int rows, double h, GetC getC, GetN getN, Ge
   return true;
 }
 
-// Fraction and/or curvature of the whole grid in one persistent launch.
-// First the near tiles from the list: node colours of the tile plus halo in
-// LDS; C, marker count and BL colour of every halo cell (mirrored across
-// walls), polygons only where markers are; then C and/or kappa of the tile's
-// cells. Then the dense rows, where uniform tiles get their colour and zero
-// curvature. MODE 1: C only; 2: kappa from the caller's C; 3: both.
-template <int MODE>
-__global__ __launch_bounds__(256) void k_frac_curv(FracParams P) {
+// Fraction and/or curvature of every grid in one launch. Workgroups
+// [0, nearBlocks) take the near tiles of the list (static stride): node
+// colours of the tile plus halo in LDS; C, marker count and BL colour of every
+// halo cell (mirrored across walls), polygons only where markers are; then C
+// and/or kappa of the tile's cells. Every later workgroup fills 16 consecutive
+// global tiles: cells of tiles that are neither near nor unowned get their
+// tile's colour as C and zero curvature, one 8-byte store per lane and row,
+// lanes along a grid row. MODE 1: C only; 2: kappa from the caller's C; 3: both.
+constexpr int FILL_TILES = 16;
+
+template <int MODE, bool ONE>
+__global__ __launch_bounds__(256) void k_frac_curv(FracArgs A, const Inst *__restrict__ inst,
+                                                   const uint32_t *__restrict__ tileInst) {
   constexpr int W = TS + 6;  // halo cells per side
   constexpr int WN = W + 1;  // halo nodes per side
+  const int tid = threadIdx.x;
+  if ((int)blockIdx.x >= A.nearBlocks) {
+    // --- dense fill ----------------------------------------------------------
+    const uint32_t t = (blockIdx.x - (uint32_t)A.nearBlocks) * FILL_TILES + (uint32_t)tid / TS;
+    if (t >= A.ntiles) return;
+    const uint8_t ti = A.tinfo[t];
+    if (ti & (TI_NEAR | TI_DEAD)) return;
+    const Inst &I = ONE ? A.one : inst[tileInst[t]];
+    const uint32_t lt = t - I.tile0;
+    const int tx = (int)(lt % (uint32_t)I.ntx), ty = (int)(lt / (uint32_t)I.ntx);
+    const int x = tx * TS + tid % TS;
+    if (x >= I.nx) return;
+    const int nx = I.nx, rows = min(TS, I.ny - ty * TS);
+    const double c = (ti & TI_COLOUR) ? 1.0 : 0.0;
+    double *Cp = (MODE & 1) ? A.Cout + I.coff + (size_t)(ty * TS) * nx + x : nullptr;
+    double *Kp = (MODE & 2) ? A.Kout + I.koff + (size_t)(ty * TS) * nx + x : nullptr;
+#pragma unroll 4
+    for (int r = 0; r < rows; r++) {
+      if (MODE & 1) Cp[(size_t)r * nx] = c;
+      if (MODE & 2) Kp[(size_t)r * nx] = 0.0;
+    }
+    return;
+  }
   __shared__ uint8_t sNode[WN][WN];
   __shared__ double sC[W][W];
   __shared__ uint8_t sN[W][W];
   __shared__ uint8_t sB[W][W];
   __shared__ uint32_t sCnt[2];
-  const int tid = threadIdx.x;
   if (tid < 2) sCnt[tid] = 0;
   uint32_t interf = 0, hffail = 0;
-  const int nx = P.nx, ny = P.ny;
-  // The first tileBlocks workgroups take a static share of the near tiles;
-  // every workgroup then claims uniform rows in chunks, so the row stream
-  // starts at once and absorbs the tile workers as they finish.
-  __shared__ uint32_t sClaim;
-  if (blockIdx.x == 0 && tid == 0) {
-    // the other launch's counters, for the next launch (nothing reads them now)
-    P.workNext[0] = 0;
-    P.workNext[1] = 0;
-  }
-  const bool tileBlock = (int)blockIdx.x < P.tileBlocks;
-  const uint32_t ntile = tileBlock ? *P.count : 0u;
+  const uint32_t ntile = *A.count;
   uint32_t ntiles_done = 0;
-  for (uint32_t it = blockIdx.x; it < ntile; it += (uint32_t)P.tileBlocks) {
+  // node colours of the tile plus halo: three slots per thread, fetched for
+  // the next tile while this one computes
+  static_assert(WN * WN <= 3 * 256, "three node slots per thread");
+  uint8_t pn[3] = {0, 0, 0};
+  auto entry = [&](uint32_t it) -> uint2 {
+    const uint2 e = A.list[it];
+    return make_uint2(uni(e.x), uni(e.y));
+  };
+  auto prefetch = [&](uint2 te) {
+    const Inst &I = ONE ? A.one : inst[te.y];
+    const int nx = I.nx, ny = I.ny;
+    const uint32_t lt = te.x - I.tile0;
+    const int x0 = (int)(lt % (uint32_t)I.ntx) * TS, y0 = (int)(lt / (uint32_t)I.ntx) * TS;
+    const GL uint8_t *col = gp(I.col[A.cur]);
+#pragma unroll
+    for (int q = 0; q < 3; q++) {
+      const int k = tid + 256 * q;
+      const int gx = x0 - 3 + k % WN, gy = y0 - 3 + k / WN;
+      pn[q] = (k < WN * WN && gx >= 0 && gy >= 0 && gx <= nx && gy <= ny) ? col[(size_t)gy * (nx + 1) + gx] : 0;
+    }
+  };
+  if (blockIdx.x < ntile) prefetch(entry(blockIdx.x));
+  for (uint32_t it = blockIdx.x; it < ntile; it += (uint32_t)A.nearBlocks) {
     __syncthreads();
-    const uint32_t tile = P.list[it];
-    const int tx = (int)(tile % (uint32_t)P.ntx), ty = (int)(tile / (uint32_t)P.ntx);
+    const uint2 te = entry(it);
+    const Inst &I = ONE ? A.one : inst[te.y];
+    const int nx = I.nx, ny = I.ny;
+    const FracCtx P{nx, ny, gp(I.col[A.cur]), gp(I.cen[A.cur]), gp(I.hoff[A.cur]), gp(I.voff[A.cur])};
+    const uint32_t lt = te.x - I.tile0;
+    const int tx = (int)(lt % (uint32_t)I.ntx), ty = (int)(lt / (uint32_t)I.ntx);
     const int x0 = tx * TS, y0 = ty * TS;
     ntiles_done++;
-    for (int k = tid; k < WN * WN; k += blockDim.x) {
-      const int li = k % WN, lj = k / WN;
-      const int gx = x0 - 3 + li, gy = y0 - 3 + lj;
-      uint8_t c = 0;
-      if (gx >= 0 && gy >= 0 && gx <= nx && gy <= ny) c = P.col[(size_t)gy * (nx + 1) + gx];
-      sNode[lj][li] = c;
+#pragma unroll
+    for (int q = 0; q < 3; q++) {
+      const int k = tid + 256 * q;
+      if (k < WN * WN) sNode[k / WN][k % WN] = pn[q];
     }
     __syncthreads();
     for (int k = tid; k < W * W; k += blockDim.x) {
@@ -1158,19 +1281,21 @@ __global__ __launch_bounds__(256) void k_frac_curv(FracParams P) {
       }
       const int nm = (kBL != kBR) + (kBR != kTR) + (kTL != kTR) + (kBL != kTL);
       double c;
-      if (MODE == 2) c = P.Cin[(size_t)gj * nx + gi];
+      if (MODE == 2) c = A.Cin[I.coff + (size_t)gj * nx + gi];
       else c = cellFraction(P, gi, gj, kBL, kBR, kTR, kTL);
       sC[lj][li] = c;
       sN[lj][li] = (uint8_t)nm;
       sB[lj][li] = (uint8_t)kBL;
     }
+    // the next tile's colours are fetched while this one's heights run
+    if (it + (uint32_t)A.nearBlocks < ntile) prefetch(entry(it + (uint32_t)A.nearBlocks));
     __syncthreads();
     for (int k = tid; k < TS * TS; k += blockDim.x) {
       const int li = k % TS, lj = k / TS;
       const int i = x0 + li, j = y0 + lj;
       if (i >= nx || j >= ny) continue;
       const size_t id = (size_t)j * nx + i;
-      if (MODE & 1) P.Cout[id] = sC[lj + 3][li + 3];
+      if (MODE & 1) A.Cout[I.coff + id] = sC[lj + 3][li + 3];
       if (MODE & 2) {
         double kap = 0.0;
         if (sN[lj + 3][li + 3] >= 2) {
@@ -1187,33 +1312,24 @@ __global__ __launch_bounds__(256) void k_frac_curv(FracParams P) {
           auto getC = [&](int a, int b) -> double { return sC[b - y0 + 3][a - x0 + 3]; };
           auto getN = [&](int a, int b) -> int { return sN[b - y0 + 3][a - x0 + 3]; };
           auto getB = [&](int a, int b) -> int { return sB[b - y0 + 3][a - x0 + 3]; };
-          if (!hfTry(i, j, firstRows, P.h, getC, getN, getB, &kap) &&
-              !hfTry(i, j, 1 - firstRows, P.h, getC, getN, getB, &kap)) {
+          if (!hfTry(i, j, firstRows, I.h, getC, getN, getB, &kap) &&
+              !hfTry(i, j, 1 - firstRows, I.h, getC, getN, getB, &kap)) {
             kap = __builtin_nan("");
             hffail++;
           }
         }
-        P.Kout[id] = kap;
+        A.Kout[I.koff + id] = kap;
       }
     }
-  }
-  constexpr uint32_t ROWS = 8;
-  for (;;) {
-    __syncthreads();
-    if (tid == 0) sClaim = atomicAdd(&P.work[1], ROWS);
-    __syncthreads();
-    const uint32_t j0 = sClaim;
-    if (j0 >= (uint32_t)ny) break;
-    for (uint32_t j = j0; j < j0 + ROWS && j < (uint32_t)ny; j++) fillRow<MODE>(P, (int)j);
   }
   if (MODE & 2) {
     if (interf) atomicAdd(&sCnt[0], interf);
     if (hffail) atomicAdd(&sCnt[1], hffail);
     __syncthreads();
     if (tid == 0) {
-      if (sCnt[0]) atomicAdd(&P.ctr[C_INTERFACIAL], (unsigned long long)sCnt[0]);
-      if (sCnt[1]) atomicAdd(&P.ctr[C_HF_FAIL], (unsigned long long)sCnt[1]);
-      if (ntiles_done) atomicAdd(&P.ctr[C_TILES_NEAR], (unsigned long long)ntiles_done);
+      if (sCnt[0]) atomicAdd(&A.ctr[C_INTERFACIAL], (unsigned long long)sCnt[0]);
+      if (sCnt[1]) atomicAdd(&A.ctr[C_HF_FAIL], (unsigned long long)sCnt[1]);
+      if (ntiles_done) atomicAdd(&A.ctr[C_TILES_NEAR], (unsigned long long)ntiles_done);
     }
   }
 }
@@ -1228,55 +1344,90 @@ int resident_blocks(int which) {
   int n = 0;
   hipError_t e = hipErrorInvalidValue;
   switch (which) {
-    case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_sweep<0>, 256, 0); break;
-    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_sweep<1>, 256, 0); break;
-    case 5: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fit<0>, 256, 0); break;
-    case 6: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fit<1>, 256, 0); break;
-    case 7: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_centre<0>, 256, 0); break;
-    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_frac_curv<1>, 256, 0); break;
-    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_frac_curv<2>, 256, 0); break;
-    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_frac_curv<3>, 256, 0); break;
+    case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_sweep<0, true>, 256, 0); break;
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fit<0, false>, 256, 0); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_centre<0, false>, 256, 0); break;
+    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_frac_curv<1, false>, 256, 0); break;
+    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_frac_curv<2, false>, 256, 0); break;
+    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_frac_curv<3, false>, 256, 0); break;
   }
+  if (e != hipSuccess) (void)hipGetLastError();  // a failed query must not surface at the next launch
   return (e == hipSuccess && n > 0) ? n : 1;
 }
 
-hipError_t launch_sweep(int dir, const SweepParams &p, int grid, hipStream_t s) {
-  if (dir == 0) hipLaunchKernelGGL(k_sweep<0>, dim3(grid), dim3(256), 0, s, p);
-  else hipLaunchKernelGGL(k_sweep<1>, dim3(grid), dim3(256), 0, s, p);
+#define EBIT_LAUNCH(K, grid, s, ...) \
+  do {                               \
+    hipLaunchKernelGGL(K, dim3(grid), dim3(256), 0, s, __VA_ARGS__); \
+  } while (0)
+
+hipError_t launch_sweep(int dir, bool one, const SweepArgs &a, int grid, hipStream_t s) {
+  if (dir == 0) {
+    if (one) EBIT_LAUNCH((k_sweep<0, true>), grid, s, a, a.inst);
+    else EBIT_LAUNCH((k_sweep<0, false>), grid, s, a, a.inst);
+  } else {
+    if (one) EBIT_LAUNCH((k_sweep<1, true>), grid, s, a, a.inst);
+    else EBIT_LAUNCH((k_sweep<1, false>), grid, s, a, a.inst);
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_fit(int dir, const FitParams &p, int grid, hipStream_t s) {
-  if (dir == 0) hipLaunchKernelGGL(k_fit<0>, dim3(grid), dim3(256), 0, s, p);
-  else hipLaunchKernelGGL(k_fit<1>, dim3(grid), dim3(256), 0, s, p);
+hipError_t launch_fit(int dir, bool one, const SweepArgs &a, int grid, hipStream_t s) {
+  if (dir == 0) {
+    if (one) EBIT_LAUNCH((k_fit<0, true>), grid, s, a, a.inst);
+    else EBIT_LAUNCH((k_fit<0, false>), grid, s, a, a.inst);
+  } else {
+    if (one) EBIT_LAUNCH((k_fit<1, true>), grid, s, a, a.inst);
+    else EBIT_LAUNCH((k_fit<1, false>), grid, s, a, a.inst);
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_centre(int dir, const FitParams &p, int grid, hipStream_t s) {
-  if (dir == 0) hipLaunchKernelGGL(k_centre<0>, dim3(grid), dim3(256), 0, s, p);
-  else hipLaunchKernelGGL(k_centre<1>, dim3(grid), dim3(256), 0, s, p);
+hipError_t launch_centre(int dir, bool one, const SweepArgs &a, int grid, hipStream_t s) {
+  if (dir == 0) {
+    if (one) EBIT_LAUNCH((k_centre<0, true>), grid, s, a, a.inst);
+    else EBIT_LAUNCH((k_centre<0, false>), grid, s, a, a.inst);
+  } else {
+    if (one) EBIT_LAUNCH((k_centre<1, true>), grid, s, a, a.inst);
+    else EBIT_LAUNCH((k_centre<1, false>), grid, s, a, a.inst);
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_init_has(const uint8_t *col, int nx, int ny, int ntx, int nty, uint16_t *has, uint8_t *nearPrev,
-                           hipStream_t s) {
-  hipLaunchKernelGGL(k_init_has, dim3(ntx * nty), dim3(256), 0, s, col, nx, ny, ntx, nty, has, nearPrev);
+hipError_t launch_init_tiles(const Inst *inst, uint32_t kinst, uint32_t ntiles, uint32_t cur, uint32_t *tileInst,
+                             uint16_t *has, uint8_t *nearPrev, hipStream_t s) {
+  if (ntiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_init_tiles, dim3(ntiles), dim3(256), 0, s, inst, kinst, cur, tileInst, has, nearPrev);
   return hipGetLastError();
 }
 
-hipError_t launch_compact(const uint16_t *has, uint8_t *nearPrev, uint8_t *tinfo, const uint8_t *col, int nx, int ntx,
-                          int nty, uint32_t *actList, uint32_t *nearList, uint32_t *counts, int slot, hipStream_t s) {
-  const int n = ntx * nty;
-  const int per = 256 * CPT;
-  hipLaunchKernelGGL(k_compact, dim3((n + per - 1) / per), dim3(256), 0, s, has, nearPrev, tinfo, col, nx, ntx, nty,
-                     actList, nearList, counts, slot);
+hipError_t launch_clear_tiles(uint32_t *tileInst, uint16_t *has, uint8_t *nearPrev, uint8_t *tinfo, uint32_t tile0,
+                              uint32_t ntiles, hipStream_t s) {
+  if (ntiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_clear_tiles, dim3((ntiles + 255) / 256), dim3(256), 0, s, tileInst, has, nearPrev, tinfo,
+                     tile0, ntiles);
   return hipGetLastError();
 }
 
-hipError_t launch_frac_curv(int mode, const FracParams &p, int grid, hipStream_t s) {
-  if (mode == 1) hipLaunchKernelGGL(k_frac_curv<1>, dim3(grid), dim3(256), 0, s, p);
-  else if (mode == 2) hipLaunchKernelGGL(k_frac_curv<2>, dim3(grid), dim3(256), 0, s, p);
-  else hipLaunchKernelGGL(k_frac_curv<3>, dim3(grid), dim3(256), 0, s, p);
+hipError_t launch_compact(bool one, const CompactArgs &a, hipStream_t s) {
+  const uint32_t per = 256 * CPT;
+  const uint32_t blocks = a.ntiles ? (a.ntiles + per - 1) / per : 1;
+  if (one) EBIT_LAUNCH(k_compact<true>, blocks, s, a);
+  else EBIT_LAUNCH(k_compact<false>, blocks, s, a);
+  return hipGetLastError();
+}
+
+int frac_fill_blocks(uint32_t ntiles) { return (int)((ntiles + FILL_TILES - 1) / FILL_TILES); }
+
+hipError_t launch_frac_curv(int mode, bool one, const FracArgs &a, int grid, hipStream_t s) {
+  if (one) {
+    if (mode == 1) EBIT_LAUNCH((k_frac_curv<1, true>), grid, s, a, a.inst, a.tileInst);
+    else if (mode == 2) EBIT_LAUNCH((k_frac_curv<2, true>), grid, s, a, a.inst, a.tileInst);
+    else EBIT_LAUNCH((k_frac_curv<3, true>), grid, s, a, a.inst, a.tileInst);
+  } else {
+    if (mode == 1) EBIT_LAUNCH((k_frac_curv<1, false>), grid, s, a, a.inst, a.tileInst);
+    else if (mode == 2) EBIT_LAUNCH((k_frac_curv<2, false>), grid, s, a, a.inst, a.tileInst);
+    else EBIT_LAUNCH((k_frac_curv<3, false>), grid, s, a, a.inst, a.tileInst);
+  }
   return hipGetLastError();
 }
 

@@ -1,54 +1,52 @@
 // EBIT interface step: host runtime behind the C-ABI in include/ebit.h.
 //
-// The handle carves the caller's device workspace into both copies of the
-// state (colours and FP64 offsets), the per-tile tables and lists, the error
-// word and the counters, and enqueues the kernels on the caller's stream.
-// Nothing here allocates device memory.
+// An engine holds any number of grids in one device workspace: the shared
+// tile tables, lists and counters, a descriptor per grid, and per grid both
+// copies of the state and the sweep scratch. One launch per phase serves all
+// grids. The single-grid handle is an engine with one grid; the batch holds a
+// fixed set of grids whose velocities and output fields the caller packs into
+// shared buffers; the pool admits and retires grids between steps and keeps
+// each grid's velocities and fields in its own arena. Nothing here allocates
+// device memory: every byte comes from the caller's workspace.
 #include <hip/hip_runtime.h>
 #include <math.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+
+#include <map>
+#include <new>
+#include <vector>
 
 #include "ebit.h"
 #include "ebit_internal.h"
 
 using namespace ebit;
 
-struct ebit_handle {
-  ebit_grid g;
-  hipStream_t stream;
-  int ntx, nty, ntiles;
-  int sweepBlocks[2];  // persistent grids: x and y sweeps
-  int fracBlocks[3];   // fraction modes 1, 2, 3
-  int fracTileBlocks[3];  // of which the fraction pass gives to near tiles
-  // state copies [0], [1]
-  uint8_t *col[2], *cen[2];
-  double *hoff[2], *voff[2];
-  int cur;  // copy holding the current state
-  // tile tables
-  uint16_t *has;
-  uint8_t *nearPrev, *tinfo;
-  uint32_t *actList, *nearList, *counts;  // counts: [act, near, jobs] x 2 slots
-  double *sp, *dd;     // advected offsets / displacements of the current sweep
-  uint8_t *zr;         // per unaligned edge: centre-CV results of its fit
-  uint32_t *jobs;      // new unaligned markers of the current sweep
-  int fitBlocks[2], centreBlocks;
-  int slot;                               // counts slot written by the last compaction
-  uint32_t *fracWork;  // claim counters of the fraction pass: two launches x [tiles, rows]
-  int fracParity;
-  uint32_t *err;
-  unsigned long long *ctr;
-  int64_t step;
-  int64_t epoch, fracEpoch;
-};
-
 namespace {
+
+// the last failed HIP call of this thread, for ebit_device_error()
+thread_local char g_devErr[256] = "";
+
+int device_failed(hipError_t err, const char *what, int line) {
+  snprintf(g_devErr, sizeof g_devErr, "%s (%d) from %.160s at runtime line %d", hipGetErrorName(err), (int)err, what,
+           line);
+  return EBIT_ERR_DEVICE;
+}
+
+#define HIPCHK(x)                                                    \
+  do {                                                               \
+    const hipError_t err_ = (x);                                     \
+    if (err_ != hipSuccess) return device_failed(err_, #x, __LINE__); \
+  } while (0)
+
+size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
 
 struct Carve {
   size_t off = 0;
   template <class T>
   T *take(char *base, size_t n) {
-    off = (off + 255) & ~(size_t)255;
+    off = align256(off);
     T *p = base ? (T *)(base + off) : nullptr;
     off += n * sizeof(T);
     return p;
@@ -60,35 +58,61 @@ bool grid_ok(const ebit_grid *g) {
          (g->flags & ~1u) == 0;
 }
 
-void carve(ebit_handle *h, char *base, size_t *total) {
-  const size_t nx = h->g.nx, ny = h->g.ny;
+uint32_t tiles_of(const ebit_grid &g) { return (uint32_t)(((g.nx + TS - 1) / TS) * ((g.ny + TS - 1) / TS)); }
+size_t jobs_of(const ebit_grid &g) { return (size_t)(g.nx + 1) * (g.ny + 1); }
+
+constexpr uint32_t MAX_POOL_TILES = (1u << 24) - 1u;  // keeps the job list within 32-bit indices
+constexpr uint32_t JOBS_PER_TILE = TS * TS;            // interior unaligned edges a tile owns, at most
+
+}  // namespace
+
+// One grid's host-side descriptor copy lives here; the device copy is what
+// the kernels read.
+struct Engine {
+  hipStream_t stream = nullptr;
+  uint32_t ntiles = 0;  // global tile space
+  uint32_t maxGrids = 0;
+  uint32_t jobCap = 0;
+  int sweepBlocks = 0, fitBlocks = 0, centreBlocks = 0, nearBlocks[3] = {0, 0, 0};
+  // device tables
+  Inst *dinst = nullptr;
+  uint32_t *tileInst = nullptr, *counts = nullptr, *errs = nullptr;
+  uint2 *actList = nullptr, *nearList = nullptr;  // (global tile, grid)
+  uint16_t *has = nullptr;
+  uint8_t *nearPrev = nullptr, *tinfo = nullptr;
+  uint2 *jobs = nullptr;
+  unsigned long long *ctr = nullptr;
+  // host mirror
+  std::vector<Inst> hinst;
+  std::vector<uint8_t> live;
+  std::vector<ebit_grid> grids;
+  uint32_t cur = 0, stepNo = 0;
+  int slot = 1;
+  int64_t epoch = 0, fracEpoch = -1;
+};
+
+namespace {
+
+// per-grid device arrays: both state copies and the sweep scratch
+void carve_grid(Inst *I, const ebit_grid &g, char *base, Carve &c) {
+  const size_t nx = g.nx, ny = g.ny;
   const size_t nn = (nx + 1) * (ny + 1), nc = nx * ny, nh = nx * (ny + 1), nv = (nx + 1) * ny;
-  Carve c;
   for (int k = 0; k < 2; k++) {
-    h->col[k] = c.take<uint8_t>(base, nn);
-    h->cen[k] = c.take<uint8_t>(base, nc);
-    h->hoff[k] = c.take<double>(base, nh);
-    h->voff[k] = c.take<double>(base, nv);
+    I->col[k] = c.take<uint8_t>(base, nn);
+    I->cen[k] = c.take<uint8_t>(base, nc);
+    I->hoff[k] = c.take<double>(base, nh);
+    I->voff[k] = c.take<double>(base, nv);
   }
-  h->has = c.take<uint16_t>(base, h->ntiles);
-  h->nearPrev = c.take<uint8_t>(base, h->ntiles);
-  h->tinfo = c.take<uint8_t>(base, h->ntiles);
-  h->actList = c.take<uint32_t>(base, h->ntiles);
-  h->nearList = c.take<uint32_t>(base, h->ntiles);
-  h->counts = c.take<uint32_t>(base, 6);
-  h->sp = c.take<double>(base, (nx + 1) * (ny + 1));
-  h->dd = c.take<double>(base, (nx + 1) * (ny + 1));
-  h->zr = c.take<uint8_t>(base, (nx + 1) * (ny + 1));
-  h->jobs = c.take<uint32_t>(base, (nx + 1) * (ny + 1));
-  h->fracWork = c.take<uint32_t>(base, 4);
-  h->err = c.take<uint32_t>(base, 1);
-  h->ctr = c.take<unsigned long long>(base, NCOUNTERS);
-  *total = (c.off + 255) & ~(size_t)255;
+  I->sp = c.take<double>(base, nn);
+  I->dd = c.take<double>(base, nn);
+  I->zr = c.take<uint8_t>(base, nn);
 }
 
-void tiles_of(const ebit_grid *g, int *ntx, int *nty) {
-  *ntx = (g->nx + TS - 1) / TS;
-  *nty = (g->ny + TS - 1) / TS;
+size_t grid_bytes(const ebit_grid &g) {
+  Inst tmp;
+  Carve c;
+  carve_grid(&tmp, g, nullptr, c);
+  return align256(c.off);
 }
 
 int validate_state(const ebit_grid *g, const ebit_state *s) {
@@ -114,140 +138,366 @@ int validate_state(const ebit_grid *g, const ebit_state *s) {
   return EBIT_OK;
 }
 
-#define HIPCHK(x)                          \
-  do {                                     \
-    if ((x) != hipSuccess) return EBIT_ERR_DEVICE; \
-  } while (0)
-
-// compaction of the current state: marker flags -> active and near lists
-int compact(ebit_handle *h) {
-  h->slot ^= 1;
-  HIPCHK(launch_compact(h->has, h->nearPrev, h->tinfo, h->col[h->cur], h->g.nx, h->ntx, h->nty, h->actList,
-                        h->nearList, h->counts, h->slot, h->stream));
-  return EBIT_OK;
-}
-
-int upload(ebit_handle *h, const ebit_state *s) {
-  const size_t nx = h->g.nx, ny = h->g.ny;
-  const size_t nn = (nx + 1) * (ny + 1), nc = nx * ny, nh = nx * (ny + 1), nv = (nx + 1) * ny;
-  for (int k = 0; k < 2; k++) {
-    HIPCHK(hipMemcpyAsync(h->col[k], s->node_color, nn, hipMemcpyHostToDevice, h->stream));
-    HIPCHK(hipMemcpyAsync(h->cen[k], s->cell_color, nc, hipMemcpyHostToDevice, h->stream));
-    HIPCHK(hipMemcpyAsync(h->hoff[k], s->hoff, nh * sizeof(double), hipMemcpyHostToDevice, h->stream));
-    HIPCHK(hipMemcpyAsync(h->voff[k], s->voff, nv * sizeof(double), hipMemcpyHostToDevice, h->stream));
+// First-fit allocator over [0, cap): tile ranges and arena bytes of the pool.
+struct RangeAlloc {
+  std::map<size_t, size_t> freeRuns;  // start -> length
+  void init(size_t cap) {
+    freeRuns.clear();
+    if (cap) freeRuns[0] = cap;
   }
-  h->cur = 0;
-  HIPCHK(hipMemsetAsync(h->counts, 0, 6 * sizeof(uint32_t), h->stream));
-  HIPCHK(hipMemsetAsync(h->fracWork, 0, 4 * sizeof(uint32_t), h->stream));
-  h->fracParity = 0;
-  HIPCHK(hipMemsetAsync(h->err, 0, sizeof(uint32_t), h->stream));
-  HIPCHK(hipMemsetAsync(h->ctr, 0, NCOUNTERS * sizeof(unsigned long long), h->stream));
-  h->slot = 1;
-  HIPCHK(launch_init_has(h->col[0], h->g.nx, h->g.ny, h->ntx, h->nty, h->has, h->nearPrev, h->stream));
-  int rc = compact(h);
+  bool take(size_t n, size_t align, size_t *start) {
+    for (auto it = freeRuns.begin(); it != freeRuns.end(); ++it) {
+      const size_t s0 = it->first, len = it->second;
+      const size_t s = (s0 + align - 1) / align * align;
+      if (s - s0 + n > len) continue;
+      freeRuns.erase(it);
+      if (s > s0) freeRuns[s0] = s - s0;
+      if (s0 + len > s + n) freeRuns[s + n] = s0 + len - (s + n);
+      *start = s;
+      return true;
+    }
+    return false;
+  }
+  void give(size_t s, size_t n) {
+    auto it = freeRuns.emplace(s, n).first;
+    auto nx = std::next(it);
+    if (nx != freeRuns.end() && s + n == nx->first) {
+      it->second += nx->second;
+      freeRuns.erase(nx);
+    }
+    if (it != freeRuns.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        freeRuns.erase(it);
+      }
+    }
+  }
+};
+
+void carve_engine(Engine *e, char *base, Carve &c) {
+  e->dinst = c.take<Inst>(base, e->maxGrids);
+  e->errs = c.take<uint32_t>(base, e->maxGrids);
+  e->tileInst = c.take<uint32_t>(base, e->ntiles);
+  e->has = c.take<uint16_t>(base, e->ntiles);
+  e->nearPrev = c.take<uint8_t>(base, e->ntiles);
+  e->tinfo = c.take<uint8_t>(base, e->ntiles);
+  e->actList = c.take<uint2>(base, e->ntiles);
+  e->nearList = c.take<uint2>(base, e->ntiles);
+  e->counts = c.take<uint32_t>(base, 2 * NSLOT);
+  e->jobs = c.take<uint2>(base, e->jobCap);
+  e->ctr = c.take<unsigned long long>(base, NCOUNTERS);
+}
+
+// engine tables for ntiles tiles, maxGrids grids and jobCap fit jobs
+size_t engine_bytes(uint32_t ntiles, uint32_t maxGrids, uint32_t jobCap) {
+  Engine tmp;
+  tmp.ntiles = ntiles;
+  tmp.maxGrids = maxGrids;
+  tmp.jobCap = jobCap;
+  Carve c;
+  carve_engine(&tmp, nullptr, c);
+  return align256(c.off);
+}
+
+void engine_launch_config(Engine *e) {
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    cus = 256;
+  e->sweepBlocks = cus * resident_blocks(0);
+  e->fitBlocks = cus * resident_blocks(1);
+  e->centreBlocks = cus * resident_blocks(2);
+  double perCU = 6.0;  // near-tile workgroups per CU of the fraction pass
+  if (const char *v = getenv("EBIT_FRAC_NEAR_BLOCKS_PER_CU")) perCU = atof(v);
+  if (!(perCU > 0.0)) perCU = 6.0;
+  for (int m = 0; m < 3; m++) {
+    int nb = (int)(cus * perCU);
+    const int cap = cus * resident_blocks(3 + m);
+    if (nb > cap) nb = cap;
+    e->nearBlocks[m] = nb < 1 ? 1 : nb;
+  }
+}
+
+// clears every table; all tiles start unowned
+int engine_reset(Engine *e) {
+  HIPCHK(hipMemsetAsync(e->counts, 0, 2 * NSLOT * sizeof(uint32_t), e->stream));
+  HIPCHK(hipMemsetAsync(e->ctr, 0, NCOUNTERS * sizeof(unsigned long long), e->stream));
+  HIPCHK(hipMemsetAsync(e->errs, 0, e->maxGrids * sizeof(uint32_t), e->stream));
+  HIPCHK(launch_clear_tiles(e->tileInst, e->has, e->nearPrev, e->tinfo, 0, e->ntiles, e->stream));
+  e->slot = 1;
+  return EBIT_OK;
+}
+
+int engine_compact(Engine *e, int afterSweep, uint32_t nextStep, int nextPhase) {
+  e->slot ^= 1;
+  CompactArgs a;
+  a.inst = e->dinst;
+  a.tileInst = e->tileInst;
+  a.ntiles = e->ntiles;
+  a.cur = e->cur;
+  a.stepNo = nextStep;
+  a.phase = nextPhase;
+  a.afterSweep = afterSweep;
+  a.slot = e->slot;
+  a.has = e->has;
+  a.nearPrev = e->nearPrev;
+  a.tinfo = e->tinfo;
+  a.actList = e->actList;
+  a.nearList = e->nearList;
+  a.counts = e->counts;
+  a.one = e->hinst[0];
+  HIPCHK(launch_compact(e->maxGrids == 1, a, e->stream));
+  return EBIT_OK;
+}
+
+// writes grid k's descriptor, uploads its state into both copies and marks
+// its tiles; the caller lists the tiles afterwards
+int engine_place(Engine *e, uint32_t k, const ebit_state *s) {
+  const Inst &I = e->hinst[k];
+  const size_t nx = I.nx, ny = I.ny;
+  const size_t nn = (nx + 1) * (ny + 1), nc = nx * ny, nh = nx * (ny + 1), nv = (nx + 1) * ny;
+  HIPCHK(hipMemcpyAsync(e->dinst + k, &e->hinst[k], sizeof(Inst), hipMemcpyHostToDevice, e->stream));
+  for (int c = 0; c < 2; c++) {
+    HIPCHK(hipMemcpyAsync(I.col[c], s->node_color, nn, hipMemcpyHostToDevice, e->stream));
+    HIPCHK(hipMemcpyAsync(I.cen[c], s->cell_color, nc, hipMemcpyHostToDevice, e->stream));
+    HIPCHK(hipMemcpyAsync(I.hoff[c], s->hoff, nh * sizeof(double), hipMemcpyHostToDevice, e->stream));
+    HIPCHK(hipMemcpyAsync(I.voff[c], s->voff, nv * sizeof(double), hipMemcpyHostToDevice, e->stream));
+  }
+  HIPCHK(hipMemsetAsync(e->errs + k, 0, sizeof(uint32_t), e->stream));
+  HIPCHK(launch_init_tiles(e->dinst, k, (uint32_t)(I.ntx * I.nty), e->cur, e->tileInst, e->has, e->nearPrev,
+                           e->stream));
+  // the uploads read host memory the caller may reuse after return
+  HIPCHK(hipStreamSynchronize(e->stream));
+  return EBIT_OK;
+}
+
+int engine_sweep(Engine *e, int phase, const double *u, const double *v, const double *dts, double dt) {
+  bool dirs[2] = {false, false};
+  for (uint32_t k = 0; k < e->maxGrids; k++)
+    if (e->live[k]) dirs[sweep_dir(e->hinst[k], e->stepNo, phase)] = true;
+  SweepArgs a;
+  a.inst = e->dinst;
+  a.tileInst = e->tileInst;
+  a.u = u;
+  a.v = v;
+  a.dts = dts;
+  a.dt = dt;
+  a.cur = e->cur;
+  a.ntiles = e->ntiles;
+  a.list = e->actList;
+  a.has = e->has;
+  a.jobs = e->jobs;
+  a.jobCap = e->jobCap;
+  a.ctr = e->ctr;
+  uint32_t *cs = e->counts + NSLOT * e->slot;
+  for (int d = 0; d < 2; d++) {
+    if (!dirs[d]) continue;
+    a.count = cs + (d == 0 ? CNT_ACT_X : CNT_ACT_Y);
+    a.njobs = cs + (d == 0 ? CNT_JOBS_X : CNT_JOBS_Y);
+    // the single grid's view, resolved here (the kernels read it from their arguments)
+    a.one = sweep_view(e->hinst[0], e->cur, d, u, v, dts ? 0.0 : dt / e->hinst[0].h);
+    HIPCHK(launch_sweep(d, e->maxGrids == 1, a, e->sweepBlocks, e->stream));
+    HIPCHK(launch_fit(d, e->maxGrids == 1, a, e->fitBlocks, e->stream));
+    HIPCHK(launch_centre(d, e->maxGrids == 1, a, e->centreBlocks, e->stream));
+  }
+  e->cur ^= 1u;
+  const uint32_t nextStep = phase == 0 ? e->stepNo : e->stepNo + 1;
+  return engine_compact(e, 1, nextStep, phase == 0 ? 1 : 0);
+}
+
+int engine_advect(Engine *e, const double *u, const double *v, const double *dts, double dt) {
+  int rc = engine_sweep(e, 0, u, v, dts, dt);
+  if (!rc) rc = engine_sweep(e, 1, u, v, dts, dt);
+  e->stepNo++;
+  e->epoch++;
+  return rc;
+}
+
+int engine_frac(Engine *e, int mode, const double *Cin, double *Cout, double *Kout) {
+  FracArgs a;
+  a.inst = e->dinst;
+  a.tileInst = e->tileInst;
+  a.ntiles = e->ntiles;
+  a.cur = e->cur;
+  a.Cin = Cin;
+  a.Cout = Cout;
+  a.Kout = Kout;
+  a.tinfo = e->tinfo;
+  a.list = e->nearList;
+  a.count = e->counts + NSLOT * e->slot + CNT_NEAR;
+  a.nearBlocks = e->nearBlocks[mode - 1];
+  a.ctr = e->ctr;
+  a.one = e->hinst[0];
+  HIPCHK(launch_frac_curv(mode, e->maxGrids == 1, a, a.nearBlocks + frac_fill_blocks(e->ntiles), e->stream));
+  return EBIT_OK;
+}
+
+int status_of(uint32_t bits) {
+  if (bits & ERRBIT_CFL) return EBIT_ERR_CFL;
+  if (bits & ERRBIT_DOMAIN) return EBIT_ERR_DOMAIN;
+  return EBIT_OK;
+}
+
+// waits for the stream; per-grid status (optional) and the first error
+int engine_errors(Engine *e, int *status) {
+  std::vector<uint32_t> bits(e->maxGrids, 0);
+  HIPCHK(hipMemcpyAsync(bits.data(), e->errs, e->maxGrids * sizeof(uint32_t), hipMemcpyDeviceToHost, e->stream));
+  HIPCHK(hipStreamSynchronize(e->stream));
+  int first = EBIT_OK;
+  for (uint32_t k = 0; k < e->maxGrids; k++) {
+    const int st = e->live[k] ? status_of(bits[k]) : EBIT_OK;
+    if (status) status[k] = st;
+    if (st && !first) first = st;
+  }
+  return first;
+}
+
+int engine_counters(Engine *e, ebit_counters *out) {
+  unsigned long long v[NCOUNTERS];
+  HIPCHK(hipMemcpyAsync(v, e->ctr, sizeof v, hipMemcpyDeviceToHost, e->stream));
+  HIPCHK(hipStreamSynchronize(e->stream));
+  int64_t *dst = (int64_t *)out;
+  for (int k = 0; k < NCOUNTERS; k++) dst[k] = (int64_t)v[k];
+  return EBIT_OK;
+}
+
+int engine_get_state(Engine *e, uint32_t k, uint8_t *node_color, uint8_t *cell_color, double *hoff, double *voff) {
+  const Inst &I = e->hinst[k];
+  const size_t nx = I.nx, ny = I.ny;
+  const uint32_t c = e->cur;
+  if (node_color) HIPCHK(hipMemcpyAsync(node_color, I.col[c], (nx + 1) * (ny + 1), hipMemcpyDeviceToHost, e->stream));
+  if (cell_color) HIPCHK(hipMemcpyAsync(cell_color, I.cen[c], nx * ny, hipMemcpyDeviceToHost, e->stream));
+  if (hoff) HIPCHK(hipMemcpyAsync(hoff, I.hoff[c], nx * (ny + 1) * sizeof(double), hipMemcpyDeviceToHost, e->stream));
+  if (voff) HIPCHK(hipMemcpyAsync(voff, I.voff[c], (nx + 1) * ny * sizeof(double), hipMemcpyDeviceToHost, e->stream));
+  HIPCHK(hipStreamSynchronize(e->stream));
+  return EBIT_OK;
+}
+
+void fill_inst(Inst *I, const ebit_grid &g, uint32_t tile0, uint32_t stepPar, uint32_t *err) {
+  I->nx = g.nx;
+  I->ny = g.ny;
+  I->ntx = (g.nx + TS - 1) / TS;
+  I->nty = (g.ny + TS - 1) / TS;
+  I->tile0 = tile0;
+  I->stepPar = stepPar;
+  I->flags = (g.flags & EBIT_SWEEP_XY) ? INST_XY : 0u;
+  I->pad = 0;
+  I->h = g.h;
+  I->uoff = I->voffv = I->coff = I->koff = 0;
+  I->err = err;
+}
+
+int batch_sizes(int n, const ebit_grid *grids, uint32_t *ntiles, uint32_t *jobCap, size_t *gridBytes) {
+  if (n < 1 || !grids) return EBIT_ERR_ARG;
+  size_t nt = 0, nj = 0, gb = 0;
+  for (int k = 0; k < n; k++) {
+    if (!grid_ok(&grids[k])) return EBIT_ERR_ARG;
+    nt += tiles_of(grids[k]);
+    nj += jobs_of(grids[k]);
+    gb += grid_bytes(grids[k]);
+  }
+  if (nt >= 0xffffffffull || nj >= 0xffffffffull) return EBIT_ERR_ARG;
+  *ntiles = (uint32_t)nt;
+  *jobCap = (uint32_t)nj;
+  *gridBytes = gb;
+  return EBIT_OK;
+}
+
+// lays out and fills an engine with n fixed grids (tiles in grid order)
+int engine_create_fixed(Engine *e, int n, const ebit_grid *grids, const ebit_state *inits, void *ws, size_t bytes,
+                        void *stream) {
+  uint32_t ntiles, jobCap;
+  size_t gb;
+  int rc = batch_sizes(n, grids, &ntiles, &jobCap, &gb);
   if (rc) return rc;
-  HIPCHK(hipStreamSynchronize(h->stream));
-  h->epoch++;
+  if (!ws || ((uintptr_t)ws & 255) != 0 || !inits) return EBIT_ERR_ARG;
+  for (int k = 0; k < n; k++) {
+    rc = validate_state(&grids[k], &inits[k]);
+    if (rc) return rc;
+  }
+  e->ntiles = ntiles;
+  e->maxGrids = (uint32_t)n;
+  e->jobCap = jobCap;
+  if (bytes < engine_bytes(ntiles, (uint32_t)n, jobCap) + gb) return EBIT_ERR_NOMEM;
+  e->stream = (hipStream_t)stream;
+  Carve c;
+  carve_engine(e, (char *)ws, c);
+  e->hinst.assign(n, Inst());
+  e->live.assign(n, 1);
+  e->grids.assign(grids, grids + n);
+  engine_launch_config(e);
+  rc = engine_reset(e);
+  if (rc) return rc;
+  uint32_t t0 = 0;
+  for (int k = 0; k < n; k++) {
+    fill_inst(&e->hinst[k], grids[k], t0, 0, e->errs + k);
+    carve_grid(&e->hinst[k], grids[k], (char *)ws, c);
+    t0 += tiles_of(grids[k]);
+  }
+  for (int k = 0; k < n; k++) {
+    rc = engine_place(e, (uint32_t)k, &inits[k]);
+    if (rc) return rc;
+  }
+  rc = engine_compact(e, 0, e->stepNo, 0);
+  if (rc) return rc;
+  HIPCHK(hipStreamSynchronize(e->stream));
+  e->epoch++;
   return EBIT_OK;
-}
-
-int read_err(ebit_handle *h) {
-  uint32_t e = 0;
-  HIPCHK(hipMemcpyAsync(&e, h->err, sizeof e, hipMemcpyDeviceToHost, h->stream));
-  HIPCHK(hipStreamSynchronize(h->stream));
-  if (e & ERRBIT_CFL) return EBIT_ERR_CFL;
-  if (e & ERRBIT_DOMAIN) return EBIT_ERR_DOMAIN;
-  return EBIT_OK;
-}
-
-int sweep(ebit_handle *h, int dir, const double *u, const double *v, double dt) {
-  SweepParams p;
-  const int nxt = h->cur ^ 1;
-  p.nx = h->g.nx;
-  p.ny = h->g.ny;
-  p.ntx = h->ntx;
-  p.nty = h->nty;
-  p.lam = dt / h->g.h;
-  p.col = h->col[h->cur];
-  p.cen = h->cen[h->cur];
-  p.hoff = h->hoff[h->cur];
-  p.voff = h->voff[h->cur];
-  p.vel = dir == 0 ? u : v;
-  p.ncol = h->col[nxt];
-  p.ncen = h->cen[nxt];
-  p.nhoff = h->hoff[nxt];
-  p.nvoff = h->voff[nxt];
-  p.list = h->actList;
-  p.count = h->counts + 3 * h->slot;
-  p.has = h->has;
-  p.err = h->err;
-  p.ctr = h->ctr;
-  p.sp = h->sp;
-  p.dd = h->dd;
-  p.jobs = h->jobs;
-  p.njobs = h->counts + 3 * h->slot + 2;
-  HIPCHK(launch_sweep(dir, p, h->sweepBlocks[dir], h->stream));
-  FitParams f;
-  f.nx = h->g.nx;
-  f.ny = h->g.ny;
-  f.col = h->col[h->cur];
-  f.cen = h->cen[h->cur];
-  f.ncol = h->col[nxt];
-  f.sp = h->sp;
-  f.dd = h->dd;
-  f.hoff = h->hoff[h->cur];
-  f.voff = h->voff[h->cur];
-  f.nhoff = h->hoff[nxt];
-  f.nvoff = h->voff[nxt];
-  f.ncen = h->cen[nxt];
-  f.zr = h->zr;
-  f.jobs = h->jobs;
-  f.njobs = p.njobs;
-  f.ctr = h->ctr;
-  HIPCHK(launch_fit(dir, f, h->fitBlocks[dir], h->stream));
-  HIPCHK(launch_centre(dir, f, h->centreBlocks, h->stream));
-  h->cur = nxt;
-  return compact(h);
-}
-
-FracParams frac_params(ebit_handle *h, int mode, const double *Cin, double *Cout, double *Kout) {
-  FracParams p;
-  p.nx = h->g.nx;
-  p.ny = h->g.ny;
-  p.ntx = h->ntx;
-  p.nty = h->nty;
-  p.h = h->g.h;
-  p.col = h->col[h->cur];
-  p.cen = h->cen[h->cur];
-  p.hoff = h->hoff[h->cur];
-  p.voff = h->voff[h->cur];
-  p.Cin = Cin;
-  p.Cout = Cout;
-  p.Kout = Kout;
-  p.tinfo = h->tinfo;
-  p.list = h->nearList;
-  p.count = h->counts + 3 * h->slot + 1;
-  p.ctr = h->ctr;
-  p.tileBlocks = h->fracTileBlocks[mode - 1];
-  p.work = h->fracWork + 2 * h->fracParity;
-  p.workNext = h->fracWork + 2 * (h->fracParity ^ 1);
-  h->fracParity ^= 1;
-  p.vec = (h->g.nx % 2 == 0) && ((uintptr_t)Cout % 16 == 0) && ((uintptr_t)Kout % 16 == 0);
-  return p;
 }
 
 }  // namespace
 
+// single grid: an engine with one grid and the grid's own step count
+struct ebit_handle {
+  Engine e;
+  int64_t step = 0;
+};
+
+// batch: fixed grids, velocities and fields packed by the caller
+struct ebit_batch {
+  Engine e;
+  int n = 0;
+  std::vector<size_t> uoff, voff, coff;
+  size_t utot = 0, vtot = 0, ctot = 0;
+};
+
+// pool: grids come and go between steps
+struct PoolGrid {
+  size_t arenaOff = 0, arenaLen = 0, tile0 = 0;
+  int64_t steps = 0;
+};
+
+struct ebit_pool {
+  Engine e;
+  char *arena = nullptr;
+  size_t arenaBytes = 0;
+  RangeAlloc tileAlloc, arenaAlloc;
+  std::vector<PoolGrid> pg;
+  double *dts = nullptr;  // device, per slot
+  std::vector<double> hdts;
+  bool dirty = false;  // grids added or removed since the last listing
+};
+
+namespace {
+// per-grid arena bytes: state copies and scratch, then u, v, C, K
+size_t pool_grid_bytes(const ebit_grid &g) {
+  const size_t nx = g.nx, ny = g.ny;
+  return grid_bytes(g) + align256(ny * (nx + 1) * 8) + align256((ny + 1) * nx * 8) + 2 * align256(nx * ny * 8) + 256;
+}
+size_t pool_table_bytes(int max_grids, uint32_t max_tiles) {
+  return engine_bytes(max_tiles, (uint32_t)max_grids, max_tiles * JOBS_PER_TILE) +
+         align256((size_t)max_grids * sizeof(double));
+}
+}  // namespace
+
 extern "C" {
 
+// ---------------------------------------------------------------------------
+// single grid
+// ---------------------------------------------------------------------------
 int ebit_workspace_bytes(const ebit_grid *grid, size_t *bytes) {
   if (!grid_ok(grid) || !bytes) return EBIT_ERR_ARG;
-  ebit_handle tmp;
-  memset(&tmp, 0, sizeof tmp);
-  tmp.g = *grid;
-  tiles_of(grid, &tmp.ntx, &tmp.nty);
-  tmp.ntiles = tmp.ntx * tmp.nty;
-  carve(&tmp, nullptr, bytes);
+  *bytes = engine_bytes(tiles_of(*grid), 1, (uint32_t)jobs_of(*grid)) + grid_bytes(*grid);
   return EBIT_OK;
 }
 
@@ -262,36 +512,11 @@ int ebit_create(const ebit_grid *grid, const ebit_state *init, void *ws_dev, siz
   size_t need = 0;
   ebit_workspace_bytes(grid, &need);
   if (ws_bytes < need) return EBIT_ERR_NOMEM;
-  ebit_handle *h = (ebit_handle *)calloc(1, sizeof(ebit_handle));
+  ebit_handle *h = new (std::nothrow) ebit_handle();
   if (!h) return EBIT_ERR_NOMEM;
-  h->g = *grid;
-  h->stream = (hipStream_t)hip_stream;
-  tiles_of(grid, &h->ntx, &h->nty);
-  h->ntiles = h->ntx * h->nty;
-  size_t tot;
-  carve(h, (char *)ws_dev, &tot);
-  int dev = 0, cus = 256;
-  if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 256;
-  for (int d = 0; d < 2; d++) {
-    h->sweepBlocks[d] = cus * resident_blocks(d);
-    h->fitBlocks[d] = cus * resident_blocks(5 + d);
-  }
-  h->centreBlocks = cus * resident_blocks(7);
-  {
-    double share = 0.5;
-    const char *e = getenv("EBIT_FRAC_TILE_SHARE");
-    if (e) share = atof(e);
-    if (!(share > 0.0)) share = 0.5;
-    if (share > 0.95) share = 0.95;
-    for (int m = 0; m < 3; m++) {
-      h->fracBlocks[m] = cus * resident_blocks(2 + m);
-      h->fracTileBlocks[m] = (int)(h->fracBlocks[m] * share);
-      if (h->fracTileBlocks[m] < 1) h->fracTileBlocks[m] = 1;
-    }
-  }
-  rc = upload(h, init);
+  rc = engine_create_fixed(&h->e, 1, grid, init, ws_dev, ws_bytes, hip_stream);
   if (rc) {
-    free(h);
+    delete h;
     return rc;
   }
   *out = h;
@@ -300,84 +525,388 @@ int ebit_create(const ebit_grid *grid, const ebit_state *init, void *ws_dev, siz
 
 int ebit_advect(ebit_handle *h, const double *u_dev, const double *v_dev, double dt) {
   if (!h || !u_dev || !v_dev || !isfinite(dt)) return EBIT_ERR_ARG;
-  const int first = ((h->g.flags & EBIT_SWEEP_XY) || (h->step % 2) == 0) ? 0 : 1;
-  int rc = sweep(h, first, u_dev, v_dev, dt);
-  if (!rc) rc = sweep(h, 1 - first, u_dev, v_dev, dt);
+  h->e.stepNo = (uint32_t)(h->step & 1);  // the sweep order follows the grid's own step count
+  const int rc = engine_advect(&h->e, u_dev, v_dev, nullptr, dt);
   h->step++;
-  h->epoch++;
   return rc;
 }
 
 int ebit_fraction(ebit_handle *h, double *C_dev) {
   if (!h || !C_dev) return EBIT_ERR_ARG;
-  FracParams p = frac_params(h, 1, nullptr, C_dev, nullptr);
-  HIPCHK(launch_frac_curv(1, p, h->fracBlocks[0], h->stream));
-  h->fracEpoch = h->epoch;
-  return EBIT_OK;
+  const int rc = engine_frac(&h->e, 1, nullptr, C_dev, nullptr);
+  h->e.fracEpoch = h->e.epoch;
+  return rc;
 }
 
 int ebit_curvature(ebit_handle *h, const double *C_dev, double *K_dev) {
   if (!h || !C_dev || !K_dev) return EBIT_ERR_ARG;
-  if (h->fracEpoch != h->epoch) return EBIT_ERR_STATE;
-  FracParams p = frac_params(h, 2, C_dev, nullptr, K_dev);
-  HIPCHK(launch_frac_curv(2, p, h->fracBlocks[1], h->stream));
-  return EBIT_OK;
+  if (h->e.fracEpoch != h->e.epoch) return EBIT_ERR_STATE;
+  return engine_frac(&h->e, 2, C_dev, nullptr, K_dev);
 }
 
 int ebit_fraction_curvature(ebit_handle *h, double *C_dev, double *K_dev) {
   if (!h || !C_dev || !K_dev) return EBIT_ERR_ARG;
-  FracParams p = frac_params(h, 3, nullptr, C_dev, K_dev);
-  HIPCHK(launch_frac_curv(3, p, h->fracBlocks[2], h->stream));
-  h->fracEpoch = h->epoch;
-  return EBIT_OK;
+  const int rc = engine_frac(&h->e, 3, nullptr, C_dev, K_dev);
+  h->e.fracEpoch = h->e.epoch;
+  return rc;
 }
 
 int ebit_get_state(ebit_handle *h, uint8_t *node_color, uint8_t *cell_color, double *hoff, double *voff,
                    int64_t *step) {
   if (!h) return EBIT_ERR_ARG;
-  const size_t nx = h->g.nx, ny = h->g.ny;
-  if (node_color) HIPCHK(hipMemcpyAsync(node_color, h->col[h->cur], (nx + 1) * (ny + 1), hipMemcpyDeviceToHost, h->stream));
-  if (cell_color) HIPCHK(hipMemcpyAsync(cell_color, h->cen[h->cur], nx * ny, hipMemcpyDeviceToHost, h->stream));
-  if (hoff) HIPCHK(hipMemcpyAsync(hoff, h->hoff[h->cur], nx * (ny + 1) * sizeof(double), hipMemcpyDeviceToHost, h->stream));
-  if (voff) HIPCHK(hipMemcpyAsync(voff, h->voff[h->cur], (nx + 1) * ny * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  int rc = engine_get_state(&h->e, 0, node_color, cell_color, hoff, voff);
+  if (rc) return rc;
   if (step) *step = h->step;
-  return read_err(h);
+  return engine_errors(&h->e, nullptr);
 }
 
 int ebit_set_state(ebit_handle *h, const ebit_state *state, int64_t step) {
   if (!h || step < 0) return EBIT_ERR_ARG;
-  int rc = validate_state(&h->g, state);
+  int rc = validate_state(&h->e.grids[0], state);
   if (rc) return rc;
   h->step = step;
-  return upload(h, state);
+  h->e.stepNo = (uint32_t)(step & 1);
+  rc = engine_place(&h->e, 0, state);  // clears the marker history of every tile of the grid
+  if (rc) return rc;
+  HIPCHK(hipMemsetAsync(h->e.ctr, 0, NCOUNTERS * sizeof(unsigned long long), h->e.stream));
+  rc = engine_compact(&h->e, 0, h->e.stepNo, 0);
+  if (rc) return rc;
+  h->e.epoch++;
+  return EBIT_OK;
 }
 
 int ebit_stats(ebit_handle *h, ebit_counters *out) {
   if (!h || !out) return EBIT_ERR_ARG;
-  unsigned long long v[NCOUNTERS];
-  HIPCHK(hipMemcpyAsync(v, h->ctr, sizeof v, hipMemcpyDeviceToHost, h->stream));
-  int rc = read_err(h);
-  int64_t *dst = (int64_t *)out;
-  for (int k = 0; k < NCOUNTERS; k++) dst[k] = (int64_t)v[k];
-  return rc;
+  int rc = engine_counters(&h->e, out);
+  if (rc) return rc;
+  return engine_errors(&h->e, nullptr);
 }
 
 int ebit_stats_reset(ebit_handle *h) {
   if (!h) return EBIT_ERR_ARG;
-  HIPCHK(hipMemsetAsync(h->ctr, 0, NCOUNTERS * sizeof(unsigned long long), h->stream));
+  HIPCHK(hipMemsetAsync(h->e.ctr, 0, NCOUNTERS * sizeof(unsigned long long), h->e.stream));
   return EBIT_OK;
 }
 
 int ebit_sync(ebit_handle *h) {
   if (!h) return EBIT_ERR_ARG;
-  return read_err(h);
+  return engine_errors(&h->e, nullptr);
 }
 
 int ebit_destroy(ebit_handle *h) {
   if (!h) return EBIT_ERR_ARG;
-  free(h);
+  delete h;
   return EBIT_OK;
 }
+
+// ---------------------------------------------------------------------------
+// batch
+// ---------------------------------------------------------------------------
+int ebit_batch_workspace_bytes(int n, const ebit_grid *grids, size_t *bytes) {
+  if (!bytes) return EBIT_ERR_ARG;
+  uint32_t ntiles, jobCap;
+  size_t gb;
+  int rc = batch_sizes(n, grids, &ntiles, &jobCap, &gb);
+  if (rc) return rc;
+  *bytes = engine_bytes(ntiles, (uint32_t)n, jobCap) + gb;
+  return EBIT_OK;
+}
+
+int ebit_batch_create(int n, const ebit_grid *grids, const ebit_state *inits, void *ws_dev, size_t ws_bytes,
+                      void *hip_stream, ebit_batch **out) {
+  if (!out) return EBIT_ERR_ARG;
+  *out = nullptr;
+  if (n < 1 || !grids || !inits) return EBIT_ERR_ARG;
+  ebit_batch *b = new (std::nothrow) ebit_batch();
+  if (!b) return EBIT_ERR_NOMEM;
+  int rc = engine_create_fixed(&b->e, n, grids, inits, ws_dev, ws_bytes, hip_stream);
+  if (rc) {
+    delete b;
+    return rc;
+  }
+  b->n = n;
+  b->uoff.resize(n);
+  b->voff.resize(n);
+  b->coff.resize(n);
+  size_t u = 0, v = 0, c = 0;
+  auto up = [](size_t x) { return (x + 31) & ~(size_t)31; };  // 256-byte aligned starts
+  for (int k = 0; k < n; k++) {
+    const size_t nx = grids[k].nx, ny = grids[k].ny;
+    b->uoff[k] = u;
+    b->voff[k] = v;
+    b->coff[k] = c;
+    u = up(u + ny * (nx + 1));
+    v = up(v + (ny + 1) * nx);
+    c = up(c + ny * nx);
+    Inst &I = b->e.hinst[k];
+    I.uoff = b->uoff[k];
+    I.voffv = b->voff[k];
+    I.coff = I.koff = b->coff[k];
+    const hipError_t err = hipMemcpyAsync(b->e.dinst + k, &I, sizeof(Inst), hipMemcpyHostToDevice, b->e.stream);
+    if (err != hipSuccess) {
+      delete b;
+      return device_failed(err, "descriptor upload", __LINE__);
+    }
+  }
+  b->utot = u;
+  b->vtot = v;
+  b->ctot = c;
+  const hipError_t serr = hipStreamSynchronize(b->e.stream);
+  if (serr != hipSuccess) {
+    delete b;
+    return device_failed(serr, "hipStreamSynchronize", __LINE__);
+  }
+  *out = b;
+  return EBIT_OK;
+}
+
+int ebit_batch_layout(const ebit_batch *b, size_t *u_off, size_t *v_off, size_t *c_off, size_t *totals) {
+  if (!b) return EBIT_ERR_ARG;
+  for (int k = 0; k < b->n; k++) {
+    if (u_off) u_off[k] = b->uoff[k];
+    if (v_off) v_off[k] = b->voff[k];
+    if (c_off) c_off[k] = b->coff[k];
+  }
+  if (totals) {
+    totals[0] = b->utot;
+    totals[1] = b->vtot;
+    totals[2] = b->ctot;
+  }
+  return EBIT_OK;
+}
+
+int ebit_batch_advect(ebit_batch *b, const double *u_packed, const double *v_packed, const double *dt_dev) {
+  if (!b || !u_packed || !v_packed || !dt_dev) return EBIT_ERR_ARG;
+  return engine_advect(&b->e, u_packed, v_packed, dt_dev, 0.0);
+}
+
+int ebit_batch_fraction_curvature(ebit_batch *b, double *C_packed, double *K_packed) {
+  if (!b || !C_packed || !K_packed) return EBIT_ERR_ARG;
+  const int rc = engine_frac(&b->e, 3, nullptr, C_packed, K_packed);
+  b->e.fracEpoch = b->e.epoch;
+  return rc;
+}
+
+int ebit_batch_get_state(ebit_batch *b, int k, uint8_t *node_color, uint8_t *cell_color, double *hoff, double *voff,
+                         int64_t *step) {
+  if (!b || k < 0 || k >= b->n) return EBIT_ERR_ARG;
+  int rc = engine_get_state(&b->e, (uint32_t)k, node_color, cell_color, hoff, voff);
+  if (rc) return rc;
+  if (step) *step = b->e.stepNo;
+  return EBIT_OK;
+}
+
+int ebit_batch_stats(ebit_batch *b, ebit_counters *out) {
+  if (!b || !out) return EBIT_ERR_ARG;
+  return engine_counters(&b->e, out);
+}
+
+int ebit_batch_sync(ebit_batch *b, int *status) {
+  if (!b) return EBIT_ERR_ARG;
+  return engine_errors(&b->e, status);
+}
+
+int ebit_batch_destroy(ebit_batch *b) {
+  if (!b) return EBIT_ERR_ARG;
+  delete b;
+  return EBIT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// pool (served form)
+// ---------------------------------------------------------------------------
+int ebit_pool_workspace_bytes(int max_grids, uint32_t max_tiles, size_t arena_bytes, size_t *bytes) {
+  if (!bytes || max_grids < 1 || max_tiles < 1 || max_tiles > MAX_POOL_TILES) return EBIT_ERR_ARG;
+  *bytes = pool_table_bytes(max_grids, max_tiles) + align256(arena_bytes);
+  return EBIT_OK;
+}
+
+int ebit_pool_grid_bytes(const ebit_grid *grid, size_t *bytes, uint32_t *tiles) {
+  if (!grid_ok(grid)) return EBIT_ERR_ARG;
+  if (bytes) *bytes = pool_grid_bytes(*grid);
+  if (tiles) *tiles = tiles_of(*grid);
+  return EBIT_OK;
+}
+
+int ebit_pool_create(int max_grids, uint32_t max_tiles, void *ws_dev, size_t ws_bytes, void *hip_stream,
+                     ebit_pool **out) {
+  if (!out) return EBIT_ERR_ARG;
+  *out = nullptr;
+  if (max_grids < 1 || max_tiles < 1 || max_tiles > MAX_POOL_TILES || !ws_dev || ((uintptr_t)ws_dev & 255) != 0)
+    return EBIT_ERR_ARG;
+  const size_t tb = pool_table_bytes(max_grids, max_tiles);
+  if (ws_bytes < tb) return EBIT_ERR_NOMEM;
+  ebit_pool *p = new (std::nothrow) ebit_pool();
+  if (!p) return EBIT_ERR_NOMEM;
+  Engine *e = &p->e;
+  e->ntiles = max_tiles;
+  e->maxGrids = (uint32_t)max_grids;
+  e->jobCap = max_tiles * JOBS_PER_TILE;
+  e->stream = (hipStream_t)hip_stream;
+  Carve c;
+  carve_engine(e, (char *)ws_dev, c);
+  p->dts = c.take<double>((char *)ws_dev, max_grids);
+  p->arena = (char *)ws_dev + tb;
+  p->arenaBytes = ws_bytes - tb;
+  e->hinst.assign(max_grids, Inst());
+  e->live.assign(max_grids, 0);
+  e->grids.assign(max_grids, ebit_grid());
+  p->pg.assign(max_grids, PoolGrid());
+  p->hdts.assign(max_grids, 0.0);
+  p->tileAlloc.init(max_tiles);
+  p->arenaAlloc.init(p->arenaBytes);
+  engine_launch_config(e);
+  int rc = engine_reset(e);
+  if (!rc) {
+    const hipError_t err = hipMemsetAsync(p->dts, 0, max_grids * sizeof(double), e->stream);
+    if (err != hipSuccess) rc = device_failed(err, "hipMemsetAsync(dts)", __LINE__);
+  }
+  if (!rc) rc = engine_compact(e, 0, 0, 0);
+  if (!rc) {
+    const hipError_t err = hipStreamSynchronize(e->stream);
+    if (err != hipSuccess) rc = device_failed(err, "hipStreamSynchronize", __LINE__);
+  }
+  if (rc) {
+    delete p;
+    return rc;
+  }
+  *out = p;
+  return EBIT_OK;
+}
+
+int ebit_pool_admit(ebit_pool *p, const ebit_grid *grid, const ebit_state *init, const double *u_host,
+                    const double *v_host, double dt, int *slot_out) {
+  if (!p || !slot_out || !grid_ok(grid) || !u_host || !v_host || !isfinite(dt)) return EBIT_ERR_ARG;
+  int rc = validate_state(grid, init);
+  if (rc) return rc;
+  Engine *e = &p->e;
+  int k = -1;
+  for (uint32_t s = 0; s < e->maxGrids; s++)
+    if (!e->live[s]) {
+      k = (int)s;
+      break;
+    }
+  if (k < 0) return EBIT_ERR_NOMEM;
+  const uint32_t nt = tiles_of(*grid);
+  const size_t gb = pool_grid_bytes(*grid);
+  size_t t0 = 0, a0 = 0;
+  if (!p->tileAlloc.take(nt, 1, &t0)) return EBIT_ERR_NOMEM;
+  if (!p->arenaAlloc.take(gb, 256, &a0)) {
+    p->tileAlloc.give(t0, nt);
+    return EBIT_ERR_NOMEM;
+  }
+  PoolGrid &g = p->pg[k];
+  g.arenaOff = a0;
+  g.arenaLen = gb;
+  g.tile0 = t0;
+  g.steps = 0;
+  Inst &I = e->hinst[k];
+  // the grid's step 0 runs at the engine's current step
+  fill_inst(&I, *grid, (uint32_t)t0, e->stepNo & 1u, e->errs + k);
+  Carve c;
+  c.off = a0;
+  carve_grid(&I, *grid, p->arena, c);
+  const size_t nx = grid->nx, ny = grid->ny;
+  double *u = c.take<double>(p->arena, ny * (nx + 1));
+  double *v = c.take<double>(p->arena, (ny + 1) * nx);
+  double *C = c.take<double>(p->arena, nx * ny);
+  double *K = c.take<double>(p->arena, nx * ny);
+  const double *base = (const double *)p->arena;
+  I.uoff = (size_t)(u - base);
+  I.voffv = (size_t)(v - base);
+  I.coff = (size_t)(C - base);
+  I.koff = (size_t)(K - base);
+  e->grids[k] = *grid;
+  p->hdts[k] = dt;
+  {
+    hipError_t err = hipMemcpyAsync(u, u_host, ny * (nx + 1) * sizeof(double), hipMemcpyHostToDevice, e->stream);
+    if (err == hipSuccess)
+      err = hipMemcpyAsync(v, v_host, (ny + 1) * nx * sizeof(double), hipMemcpyHostToDevice, e->stream);
+    if (err == hipSuccess) err = hipMemcpyAsync(p->dts + k, &p->hdts[k], sizeof(double), hipMemcpyHostToDevice, e->stream);
+    if (err != hipSuccess) rc = device_failed(err, "velocity upload", __LINE__);
+  }
+  if (!rc) rc = engine_place(e, (uint32_t)k, init);
+  if (rc) {
+    p->tileAlloc.give(t0, nt);
+    p->arenaAlloc.give(a0, gb);
+    return rc;
+  }
+  e->live[k] = 1;
+  p->dirty = true;
+  *slot_out = k;
+  return EBIT_OK;
+}
+
+int ebit_pool_retire(ebit_pool *p, int slot) {
+  if (!p || slot < 0 || (uint32_t)slot >= p->e.maxGrids || !p->e.live[slot]) return EBIT_ERR_ARG;
+  Engine *e = &p->e;
+  PoolGrid &g = p->pg[slot];
+  const uint32_t nt = tiles_of(e->grids[slot]);
+  HIPCHK(launch_clear_tiles(e->tileInst, e->has, e->nearPrev, e->tinfo, (uint32_t)g.tile0, nt, e->stream));
+  // the tile range and arena bytes are reused only by later admissions,
+  // whose uploads follow on the same stream
+  p->tileAlloc.give(g.tile0, nt);
+  p->arenaAlloc.give(g.arenaOff, g.arenaLen);
+  e->live[slot] = 0;
+  p->dirty = true;
+  return EBIT_OK;
+}
+
+int ebit_pool_step(ebit_pool *p) {
+  if (!p) return EBIT_ERR_ARG;
+  Engine *e = &p->e;
+  bool any = false;
+  for (uint32_t k = 0; k < e->maxGrids; k++) any = any || e->live[k];
+  if (p->dirty) {
+    int rc = engine_compact(e, 0, e->stepNo, 0);
+    if (rc) return rc;
+    p->dirty = false;
+  }
+  if (!any) return EBIT_OK;
+  const double *base = (const double *)p->arena;
+  int rc = engine_advect(e, base, base, p->dts, 0.0);
+  if (rc) return rc;
+  rc = engine_frac(e, 3, nullptr, (double *)p->arena, (double *)p->arena);
+  e->fracEpoch = e->epoch;
+  for (uint32_t k = 0; k < e->maxGrids; k++)
+    if (e->live[k]) p->pg[k].steps++;
+  return rc;
+}
+
+int ebit_pool_read(ebit_pool *p, int slot, double *C_host, double *K_host, int64_t *steps, int *status) {
+  if (!p || slot < 0 || (uint32_t)slot >= p->e.maxGrids || !p->e.live[slot]) return EBIT_ERR_ARG;
+  Engine *e = &p->e;
+  const Inst &I = e->hinst[slot];
+  const size_t n = (size_t)I.nx * I.ny;
+  const double *base = (const double *)p->arena;
+  if (C_host) HIPCHK(hipMemcpyAsync(C_host, base + I.coff, n * sizeof(double), hipMemcpyDeviceToHost, e->stream));
+  if (K_host) HIPCHK(hipMemcpyAsync(K_host, base + I.koff, n * sizeof(double), hipMemcpyDeviceToHost, e->stream));
+  uint32_t bits = 0;
+  HIPCHK(hipMemcpyAsync(&bits, e->errs + slot, sizeof bits, hipMemcpyDeviceToHost, e->stream));
+  HIPCHK(hipStreamSynchronize(e->stream));
+  if (steps) *steps = p->pg[slot].steps;
+  if (status) *status = status_of(bits);
+  return EBIT_OK;
+}
+
+int ebit_pool_get_state(ebit_pool *p, int slot, uint8_t *node_color, uint8_t *cell_color, double *hoff,
+                        double *voff) {
+  if (!p || slot < 0 || (uint32_t)slot >= p->e.maxGrids || !p->e.live[slot]) return EBIT_ERR_ARG;
+  return engine_get_state(&p->e, (uint32_t)slot, node_color, cell_color, hoff, voff);
+}
+
+int ebit_pool_stats(ebit_pool *p, ebit_counters *out) {
+  if (!p || !out) return EBIT_ERR_ARG;
+  return engine_counters(&p->e, out);
+}
+
+int ebit_pool_destroy(ebit_pool *p) {
+  if (!p) return EBIT_ERR_ARG;
+  delete p;
+  return EBIT_OK;
+}
+
+const char *ebit_device_error(void) { return g_devErr; }
 
 const char *ebit_strerror(int code) {
   switch (code) {
@@ -387,7 +916,7 @@ const char *ebit_strerror(int code) {
     case EBIT_ERR_CFL: return "a marker moved more than half a cell in one sweep";
     case EBIT_ERR_DOMAIN: return "a marker would leave the grid";
     case EBIT_ERR_DEVICE: return "HIP runtime error";
-    case EBIT_ERR_NOMEM: return "workspace too small or host allocation failed";
+    case EBIT_ERR_NOMEM: return "workspace too small, or no free slot, tiles or arena space";
     default: return "unknown error";
   }
 }

@@ -47,12 +47,19 @@ class ebit_counters(ctypes.Structure):
 class EbitError(RuntimeError):
     def __init__(self, code: int, where: str):
         self.code = code
-        super().__init__(f"{where}: {strerror(code)} (code {code})")
+        detail = ""
+        if code == EBIT_ERR_DEVICE:
+            detail = ": " + _lib.ebit_device_error().decode()
+        super().__init__(f"{where}: {strerror(code)} (code {code}){detail}")
 
 
 def _load() -> ctypes.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"libebit.so is not built ({LIB_PATH}); run __graft_entry__.build()")
+    # torch first: it brings its own HIP and HSA runtimes, and the library must
+    # bind to those (one HSA runtime per process) rather than load a second copy
+    import torch  # noqa: F401
+
     lib = ctypes.CDLL(LIB_PATH)
     vp, sz = ctypes.c_void_p, ctypes.c_size_t
     G, S = ctypes.POINTER(ebit_grid), ctypes.POINTER(ebit_state)
@@ -70,12 +77,37 @@ def _load() -> ctypes.CDLL:
         "ebit_sync": [vp],
         "ebit_destroy": [vp],
     }
+    B, P = vp, vp
+    i32, u32, szp = ctypes.c_int, ctypes.c_uint32, ctypes.POINTER(sz)
+    sigs.update({
+        "ebit_batch_workspace_bytes": [i32, G, szp],
+        "ebit_batch_create": [i32, G, S, vp, sz, vp, ctypes.POINTER(vp)],
+        "ebit_batch_layout": [B, szp, szp, szp, szp],
+        "ebit_batch_advect": [B, vp, vp, vp],
+        "ebit_batch_fraction_curvature": [B, vp, vp],
+        "ebit_batch_get_state": [B, i32, vp, vp, vp, vp, ctypes.POINTER(ctypes.c_int64)],
+        "ebit_batch_stats": [B, ctypes.POINTER(ebit_counters)],
+        "ebit_batch_sync": [B, ctypes.POINTER(ctypes.c_int)],
+        "ebit_batch_destroy": [B],
+        "ebit_pool_workspace_bytes": [i32, u32, sz, szp],
+        "ebit_pool_grid_bytes": [G, szp, ctypes.POINTER(u32)],
+        "ebit_pool_create": [i32, u32, vp, sz, vp, ctypes.POINTER(vp)],
+        "ebit_pool_admit": [P, G, S, vp, vp, ctypes.c_double, ctypes.POINTER(ctypes.c_int)],
+        "ebit_pool_step": [P],
+        "ebit_pool_read": [P, i32, vp, vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int)],
+        "ebit_pool_get_state": [P, i32, vp, vp, vp, vp],
+        "ebit_pool_retire": [P, i32],
+        "ebit_pool_stats": [P, ctypes.POINTER(ebit_counters)],
+        "ebit_pool_destroy": [P],
+    })
     for name, args in sigs.items():
         f = getattr(lib, name)
         f.argtypes = args
         f.restype = ctypes.c_int
     lib.ebit_strerror.argtypes = [ctypes.c_int]
     lib.ebit_strerror.restype = ctypes.c_char_p
+    lib.ebit_device_error.argtypes = []
+    lib.ebit_device_error.restype = ctypes.c_char_p
     return lib
 
 
@@ -197,6 +229,206 @@ class EbitGrid:
     def close(self):
         if getattr(self, "_h", None):
             _lib.ebit_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _empty_state(nx: int, ny: int, h: float, step: int = 0) -> State:
+    return State(nx, ny, h, np.empty((ny + 1, nx + 1), np.uint8), np.empty((ny, nx), np.uint8),
+                 np.empty((ny + 1, nx), np.float64), np.empty((ny, nx + 1), np.float64), step)
+
+
+class EbitBatch:
+    """A fixed set of independent grids advanced together (one launch per
+    phase for all of them). Velocities, C and K live in packed device buffers;
+    grid k's arrays start at the element offsets of the layout."""
+
+    def __init__(self, states, flags: int = EBIT_SWEEP_ALTERNATE, device: str = "cuda:0", stream=None):
+        import torch
+
+        self.torch = torch
+        self.device = torch.device(device)
+        self.n = n = len(states)
+        if n < 1:
+            raise ValueError("a batch needs at least one grid")
+        self.shapes = [(st.nx, st.ny, st.h) for st in states]
+        grids = (ebit_grid * n)(*[ebit_grid(st.nx, st.ny, st.h, flags) for st in states])
+        hs, keep = [], []
+        for st in states:
+            s, k = _host_state(st)
+            hs.append(s)
+            keep.append(k)
+        inits = (ebit_state * n)(*hs)
+        nbytes = ctypes.c_size_t(0)
+        _chk(_lib.ebit_batch_workspace_bytes(n, grids, ctypes.byref(nbytes)), "ebit_batch_workspace_bytes")
+        self.ws = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        handle = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _chk(_lib.ebit_batch_create(n, grids, inits, self.ws.data_ptr(), nbytes.value, self.stream.cuda_stream,
+                                        ctypes.byref(handle)), "ebit_batch_create")
+        self._h = handle
+        uo, vo, co, tot = ((ctypes.c_size_t * n)(), (ctypes.c_size_t * n)(), (ctypes.c_size_t * n)(),
+                           (ctypes.c_size_t * 3)())
+        _chk(_lib.ebit_batch_layout(self._h, uo, vo, co, tot), "ebit_batch_layout")
+        self.u_off, self.v_off, self.c_off = list(uo), list(vo), list(co)
+        self.totals = tuple(tot)
+        self.step = 0
+
+    def pack_velocities(self, us, vs):
+        """Device buffers holding grid k's u and v (host arrays) at the layout's offsets."""
+        torch = self.torch
+        U = np.zeros(self.totals[0], np.float64)
+        V = np.zeros(self.totals[1], np.float64)
+        for k, (u, v) in enumerate(zip(us, vs)):
+            nx, ny, _ = self.shapes[k]
+            assert u.shape == (ny, nx + 1) and v.shape == (ny + 1, nx)
+            U[self.u_off[k]:self.u_off[k] + u.size] = u.ravel()
+            V[self.v_off[k]:self.v_off[k] + v.size] = v.ravel()
+        return torch.from_numpy(U).to(self.device), torch.from_numpy(V).to(self.device)
+
+    def new_fields(self):
+        t = self.torch
+        return (t.empty(self.totals[2], dtype=t.float64, device=self.device),
+                t.empty(self.totals[2], dtype=t.float64, device=self.device))
+
+    def field(self, F, k):
+        nx, ny, _ = self.shapes[k]
+        return F[self.c_off[k]:self.c_off[k] + nx * ny].view(ny, nx)
+
+    def _buf(self, t, n, name):
+        torch = self.torch
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or t.device != self.device:
+            raise TypeError(f"{name} must be a float64 tensor on {self.device}")
+        if t.numel() < n or not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous with at least {n} elements")
+        return t.data_ptr()
+
+    def advect(self, U, V, dts):
+        pu = self._buf(U, self.totals[0], "u")
+        pv = self._buf(V, self.totals[1], "v")
+        pd = self._buf(dts, self.n, "dts")
+        _chk(_lib.ebit_batch_advect(self._h, pu, pv, pd), "ebit_batch_advect")
+        self.step += 1
+
+    def fraction_curvature(self, C, K):
+        _chk(_lib.ebit_batch_fraction_curvature(self._h, self._buf(C, self.totals[2], "C"),
+                                                self._buf(K, self.totals[2], "K")), "ebit_batch_fraction_curvature")
+        return C, K
+
+    def get_state(self, k) -> State:
+        nx, ny, h = self.shapes[k]
+        st = _empty_state(nx, ny, h)
+        step = ctypes.c_int64(0)
+        _chk(_lib.ebit_batch_get_state(self._h, k, st.c.ctypes.data, st.cc.ctypes.data, st.hoff.ctypes.data,
+                                       st.voff.ctypes.data, ctypes.byref(step)), "ebit_batch_get_state")
+        st.step = int(step.value)
+        return st
+
+    def stats(self) -> dict:
+        out = ebit_counters()
+        _chk(_lib.ebit_batch_stats(self._h, ctypes.byref(out)), "ebit_batch_stats")
+        return {k: int(getattr(out, k)) for k in COUNTERS}
+
+    def sync(self):
+        """Per-grid status codes (0 = ok)."""
+        st = (ctypes.c_int * self.n)()
+        _lib.ebit_batch_sync(self._h, st)
+        return list(st)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.ebit_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class EbitPool:
+    """Served form: grids admitted and retired between steps; every admitted
+    grid takes one step (advection, fraction, curvature) per step() call."""
+
+    def __init__(self, max_grids: int, max_tiles: int, arena_bytes: int, device: str = "cuda:0", stream=None):
+        import torch
+
+        self.torch = torch
+        self.device = torch.device(device)
+        nbytes = ctypes.c_size_t(0)
+        _chk(_lib.ebit_pool_workspace_bytes(max_grids, max_tiles, arena_bytes, ctypes.byref(nbytes)),
+             "ebit_pool_workspace_bytes")
+        self.ws = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        handle = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _chk(_lib.ebit_pool_create(max_grids, max_tiles, self.ws.data_ptr(), nbytes.value,
+                                       self.stream.cuda_stream, ctypes.byref(handle)), "ebit_pool_create")
+        self._h = handle
+        self.shapes = {}
+
+    @staticmethod
+    def grid_bytes(nx: int, ny: int, h: float):
+        g = ebit_grid(nx, ny, h, 0)
+        b, t = ctypes.c_size_t(0), ctypes.c_uint32(0)
+        _chk(_lib.ebit_pool_grid_bytes(ctypes.byref(g), ctypes.byref(b), ctypes.byref(t)), "ebit_pool_grid_bytes")
+        return b.value, t.value
+
+    def admit(self, state: State, u, v, dt: float, flags: int = EBIT_SWEEP_ALTERNATE):
+        """Slot of the admitted grid, or None when the pool is full."""
+        g = ebit_grid(state.nx, state.ny, state.h, flags)
+        s, keep = _host_state(state)
+        u = np.ascontiguousarray(u, np.float64)
+        v = np.ascontiguousarray(v, np.float64)
+        if u.shape != (state.ny, state.nx + 1) or v.shape != (state.ny + 1, state.nx):
+            raise ValueError("u, v shapes do not match the grid")
+        slot = ctypes.c_int(-1)
+        rc = _lib.ebit_pool_admit(self._h, ctypes.byref(g), ctypes.byref(s), u.ctypes.data, v.ctypes.data,
+                                  float(dt), ctypes.byref(slot))
+        if rc == EBIT_ERR_NOMEM:
+            return None
+        _chk(rc, "ebit_pool_admit")
+        self.shapes[slot.value] = (state.nx, state.ny, state.h)
+        return slot.value
+
+    def step(self):
+        _chk(_lib.ebit_pool_step(self._h), "ebit_pool_step")
+
+    def read(self, slot: int, fields: bool = True):
+        nx, ny, _ = self.shapes[slot]
+        C = np.empty((ny, nx), np.float64) if fields else None
+        K = np.empty((ny, nx), np.float64) if fields else None
+        steps, status = ctypes.c_int64(0), ctypes.c_int(0)
+        _chk(_lib.ebit_pool_read(self._h, slot, C.ctypes.data if fields else None, K.ctypes.data if fields else None,
+                                 ctypes.byref(steps), ctypes.byref(status)), "ebit_pool_read")
+        return C, K, int(steps.value), int(status.value)
+
+    def get_state(self, slot: int) -> State:
+        nx, ny, h = self.shapes[slot]
+        st = _empty_state(nx, ny, h)
+        _chk(_lib.ebit_pool_get_state(self._h, slot, st.c.ctypes.data, st.cc.ctypes.data, st.hoff.ctypes.data,
+                                      st.voff.ctypes.data), "ebit_pool_get_state")
+        return st
+
+    def retire(self, slot: int):
+        _chk(_lib.ebit_pool_retire(self._h, slot), "ebit_pool_retire")
+        self.shapes.pop(slot, None)
+
+    def stats(self) -> dict:
+        out = ebit_counters()
+        _chk(_lib.ebit_pool_stats(self._h, ctypes.byref(out)), "ebit_pool_stats")
+        return {k: int(getattr(out, k)) for k in COUNTERS}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.ebit_pool_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -418,3 +418,65 @@ def random_instance(rng, n: int, nshapes: int, ellipses: bool = True, period: fl
         period = rng.uniform(1.0, 8.0)
     dt = cfl / n
     return st, u, v, vortex_dt_schedule(dt, period, steps)
+
+
+def batched_instances(count: int = 256, nmin: int = 64, nmax: int = 1024, steps: int = 100, seed: int = 1004,
+                      max_shapes: int = 20):
+    """Many independent grids for the batched form: N log-uniform in
+    [nmin, nmax], 1..max_shapes circles or ellipses each (semi-major axis 3-12 %
+    of the side, axis ratio 1-3, semi-minor >= 3 cells, non-overlapping
+    bounding circles), single vortex with its own period T ~ U[1, 8], CFL 0.5
+    with the time factor folded into each grid's dt. Returns a list of
+    (state, u, v, dts)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for _ in range(count):
+        n = int(round(math.exp(rng.uniform(math.log(nmin), math.log(nmax)))))
+        k = int(rng.integers(1, max_shapes + 1))
+        out.append(random_instance(rng, n, k, ellipses=True, steps=steps))
+    return out
+
+
+def served_requests(count: int, rate: float = 200.0, nmin: int = 128, nmax: int = 2048, seed: int = 1005,
+                    smin: int = 16, smax: int = 256, max_circles: int = 50, modes: int = 4):
+    """Request stream for the served form: Poisson arrivals at `rate` per second;
+    each request is a grid with N log-uniform in [nmin, nmax], 1..max_circles
+    non-overlapping circles of radius U[max(3h, 0.01), 0.08], a steady
+    divergence-free field psi = sum_m a_m sin(k_m pi x) sin(l_m pi y) with
+    a_m ~ N(0, 0.1) and k_m, l_m in 1..4, dt = 0.5 h / max|face velocity|, and
+    U{smin..smax} steps. Yields dicts with the arrival time and the instance,
+    built lazily so a long stream never sits in memory at once."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    t = 0.0
+    for r in range(count):
+        t += rng.exponential(1.0 / rate)
+        n = int(round(math.exp(rng.uniform(math.log(nmin), math.log(nmax)))))
+        ncirc = int(rng.integers(1, max_circles + 1))
+        steps = int(rng.integers(smin, smax + 1))
+        amps = rng.normal(0.0, 0.1, modes)
+        ks = rng.integers(1, 5, modes)
+        ls = rng.integers(1, 5, modes)
+        circ_seed = int(rng.integers(0, 2**63 - 1))
+        yield {"id": r, "arrival": t, "n": n, "circles": ncirc, "steps": steps, "amps": amps, "ks": ks, "ls": ls,
+               "seed": circ_seed}
+
+
+def served_instance(req):
+    """The grid, velocities and dt of one served request (see served_requests)."""
+    n = req["n"]
+    h = 1.0 / n
+    rng = np.random.Generator(np.random.PCG64(req["seed"]))
+    rmin = max(3.0 * h, 0.01) * n
+    rmax = max(0.08 * n, rmin)
+    circles = _place_circles(rng, n, req["circles"], rmin, rmax, gap=2.0, wall=2.0, max_tries=20000)
+    st = init_state(n, n, [Circle(*c) for c in circles])
+    x = np.arange(n + 1) / n
+    psi = np.zeros((n + 1, n + 1))
+    for a, k, l in zip(req["amps"], req["ks"], req["ls"]):
+        psi += a * np.sin(k * np.pi * x)[None, :] * np.sin(l * np.pi * x)[:, None]
+    psi[0, :] = psi[-1, :] = 0.0
+    psi[:, 0] = psi[:, -1] = 0.0
+    u, v = faces_from_psi(psi, h)
+    umax = max(float(np.abs(u).max()), float(np.abs(v).max()), 1e-30)
+    dt = 0.5 * h / umax
+    return st, u, v, dt

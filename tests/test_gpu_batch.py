@@ -1,0 +1,160 @@
+"""GPU parity of the batched and served forms: every grid of a batch or a pool
+against its own oracle run, step by step, through the C-ABI."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2309_00338_amd import ebit
+from paper_2309_00338_amd import inputs as I
+from tests.parity import compare_fields, compare_state
+
+pytestmark = pytest.mark.gpu
+
+
+def _instances():
+    """Grids of several sizes, ragged tails and one fixed sweep order."""
+    rng = np.random.Generator(np.random.PCG64(4242))
+    out = []
+    for n, k in ((20, 1), (33, 3), (48, 4), (64, 2), (71, 5), (96, 6)):
+        st, u, v, dts = I.random_instance(rng, n, k, ellipses=True, steps=16)
+        out.append((st, u, v, dts))
+    # a rectangular grid with a ragged tail in both directions
+    st = I.init_state(37, 53, [I.Ellipse(18.3, 26.1, 11.0, 7.0, 0.4)], h=1.0 / 53)
+    x = np.arange(38) / 37
+    y = np.arange(54) / 53
+    psi = (np.sin(np.pi * x)[None, :] ** 2) * (np.sin(np.pi * y)[:, None] ** 2) / np.pi
+    psi[0, :] = psi[-1, :] = 0.0
+    psi[:, 0] = psi[:, -1] = 0.0
+    u, v = I.faces_from_psi(psi, st.h)
+    umax = max(np.abs(u).max(), np.abs(v).max())
+    out.append((st, u, v, [0.45 * st.h / umax * (1 - 0.02 * k) for k in range(16)]))
+    return out
+
+
+def test_batch_matches_oracle_per_grid():
+    import torch
+
+    inst = _instances()
+    b = ebit.EbitBatch([s for s, _, _, _ in inst])
+    U, V = b.pack_velocities([u for _, u, _, _ in inst], [v for _, _, v, _ in inst])
+    nsteps = len(inst[0][3])
+    dts = torch.tensor([[d[k] for _, _, _, d in inst] for k in range(nsteps)], dtype=torch.float64, device="cuda:0")
+    C, K = b.new_fields()
+    orc = [s.copy() for s, _, _, _ in inst]
+    ocnt = oracle.new_counters()
+    for k in range(nsteps):
+        b.advect(U, V, dts[k])
+        for g, (st, u, v, d) in enumerate(inst):
+            rc, _ = oracle.step(orc[g], u, v, d[k], counters=ocnt)
+            assert rc == oracle.OK
+        if k % 3 == 2 or k == nsteps - 1:
+            b.fraction_curvature(C, K)
+            torch.cuda.synchronize()
+            for g in range(len(inst)):
+                gs = b.get_state(g)
+                compare_state(gs, orc[g], f"grid {g} step {k}")
+                Co = oracle.fraction(orc[g])
+                Ko, _ = oracle.curvature(orc[g], Co, counters=ocnt)
+                compare_fields(b.field(C, g).cpu().numpy(), b.field(K, g).cpu().numpy(), Co, Ko, orc[g].nx,
+                               orc[g].h, f"grid {g} step {k}")
+    assert b.sync() == [0] * len(inst)
+    gc = {k: v for k, v in b.stats().items() if k not in ebit.SCHEDULE_COUNTERS}
+    assert gc == oracle.counters_dict(ocnt)
+
+
+def test_batch_equals_single_handles():
+    """The batch gives bit-identical states to one handle per grid."""
+    import torch
+
+    inst = _instances()[:4]
+    b = ebit.EbitBatch([s for s, _, _, _ in inst])
+    U, V = b.pack_velocities([u for _, u, _, _ in inst], [v for _, _, v, _ in inst])
+    singles = [ebit.EbitGrid(s) for s, _, _, _ in inst]
+    us = [(torch.from_numpy(u).cuda(), torch.from_numpy(v).cuda()) for _, u, v, _ in inst]
+    for k in range(10):
+        dts = torch.tensor([d[k] for _, _, _, d in inst], dtype=torch.float64, device="cuda:0")
+        b.advect(U, V, dts)
+        for g, h in enumerate(singles):
+            h.advect(us[g][0], us[g][1], inst[g][3][k])
+    for g, h in enumerate(singles):
+        a, s = b.get_state(g), h.get_state()
+        assert np.array_equal(a.c, s.c) and np.array_equal(a.cc, s.cc)
+        assert np.array_equal(a.hoff * a.h_present(), s.hoff * s.h_present())
+        assert np.array_equal(a.voff * a.v_present(), s.voff * s.v_present())
+
+
+def test_batch_error_is_per_grid():
+    """A CFL violation in one grid latches only that grid's status."""
+    import torch
+
+    inst = _instances()[:3]
+    b = ebit.EbitBatch([s for s, _, _, _ in inst])
+    U, V = b.pack_velocities([u for _, u, _, _ in inst], [v for _, _, v, _ in inst])
+    dts = torch.tensor([inst[0][3][0], 3.0 / inst[1][0].nx, inst[2][3][0]], dtype=torch.float64, device="cuda:0")
+    b.advect(U, V, dts)
+    st = b.sync()
+    assert st[0] == 0 and st[2] == 0 and st[1] == ebit.EBIT_ERR_CFL
+
+
+class _Ref:
+    """One grid of the pool and its oracle twin."""
+
+    def __init__(self, st, u, v, dt):
+        self.o = st.copy()
+        self.o.step = 0
+        self.u, self.v, self.dt = u, v, dt
+
+    def step(self, ocnt):
+        rc, _ = oracle.step(self.o, self.u, self.v, self.dt, counters=ocnt)
+        assert rc == oracle.OK
+
+
+def _pool_instance(n, k, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    st, u, v, dts = I.random_instance(rng, n, k, ellipses=True, steps=1, period=1e9)
+    return st, u, v, dts[0]
+
+
+def test_pool_admit_step_retire_matches_oracle():
+    pool = ebit.EbitPool(max_grids=3, max_tiles=64, arena_bytes=64 << 20)
+    ocnt = oracle.new_counters()
+    live = {}
+
+    def admit(n, k, seed):
+        st, u, v, dt = _pool_instance(n, k, seed)
+        slot = pool.admit(st, u, v, dt)
+        if slot is not None:
+            live[slot] = _Ref(st, u, v, dt)
+        return slot
+
+    def step_and_check(tag):
+        pool.step()
+        for s, r in live.items():
+            r.step(ocnt)
+        for s, r in live.items():
+            C, K, steps, status = pool.read(s)
+            assert status == 0 and steps == r.o.step
+            compare_state(pool.get_state(s), r.o, f"{tag} slot {s}")
+            Co = oracle.fraction(r.o)
+            Ko, _ = oracle.curvature(r.o, Co, counters=ocnt)
+            compare_fields(C, K, Co, Ko, r.o.nx, r.o.h, f"{tag} slot {s}")
+
+    a = admit(48, 3, 11)
+    for k in range(3):
+        step_and_check(f"A{k}")
+    b = admit(40, 2, 12)  # its step 0 runs at an odd pool step: both sweep orders in one phase
+    for k in range(2):
+        step_and_check(f"AB{k}")
+    c = admit(33, 2, 13)
+    assert admit(20, 1, 14) is None  # no free slot
+    step_and_check("ABC")
+    pool.retire(a)
+    live.pop(a)
+    d = admit(44, 4, 15)  # reuses the freed slot, tiles and arena space
+    assert d == a
+    for k in range(4):
+        step_and_check(f"BCD{k}")
+    pool.retire(b)
+    live.pop(b)
+    step_and_check("CD")
+    assert c is not None
