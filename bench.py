@@ -1,15 +1,23 @@
 """Benchmark of the EBIT interface step on one MI355X.
 
-Workload: 8192 x 8192 FP64 grid, 2000 seeded non-overlapping circles (radii
-uniform in [4, 32] cells), single-vortex face velocity with period T = 4 at
-CFL 0.5 (dt = h/2, time factor cos(pi t / T) folded into dt). One step is the
-whole hot path: ebit_advect (x and y sweeps with circle fit, Color Vertex
-update and topology change) followed by ebit_fraction_curvature.
+Default workload (the headline line): 8192 x 8192 FP64 grid, 2000 seeded
+non-overlapping circles (radii uniform in [4, 32] cells), single-vortex face
+velocity with period T = 4 at CFL 0.5 (dt = h/2, time factor cos(pi t / T)
+folded into dt). One step is the whole hot path: ebit_advect (x and y sweeps
+with circle fit, Color Vertex update and topology change) followed by
+ebit_fraction_curvature.
 
 Prints one JSON line: throughput in cell-steps/s over the timed steps (state
 and velocities already resident in HBM), the roofline of the dominant kernel
 (fraction + curvature, timed live with events on its stream), the whole-step
 algorithmic-bytes roofline, and the CPU oracle timed on a bounded sample.
+
+--workload batched: 256 independent grids (N log-uniform in [64, 1024], 1-20
+circles or ellipses, own vortex period each) advanced by the batched entry
+points, against a loop of per-grid handles on one stream.
+--workload served: a pool serving a Poisson stream of requests (200/s, N
+log-uniform in [128, 2048], steady random fields, 16-256 steps each); reports
+cell-steps/s and the arrival-to-result latency percentiles.
 """
 import argparse
 import json
@@ -73,6 +81,11 @@ def main():
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--circles", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=("single", "batched", "served"), default="single")
+    ap.add_argument("--grids", type=int, default=256, help="batched: number of grids")
+    ap.add_argument("--served-seconds", type=float, default=4.0, help="served: seconds of arrivals")
+    ap.add_argument("--rate", type=float, default=200.0, help="served: arrivals per second")
+    ap.add_argument("--pool-tiles", type=int, default=1 << 18, help="served: tile capacity of the pool")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized device buffer 5 times (a plain copy kernel of known size, "
                          "the reference for scaling hardware byte counters), then exit")
@@ -92,6 +105,11 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
+
+    if args.workload == "batched":
+        return bench_batched(args)
+    if args.workload == "served":
+        return bench_served(args)
 
     import torch
 
@@ -181,6 +199,182 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on one step of the same grid")
         out["cpu_baseline"] = cpu_baseline(w, 1)
+    print(json.dumps(out), flush=True)
+
+
+def bench_batched(args):
+    """Batched form against a loop of per-grid handles, same grids and steps."""
+    import torch
+
+    from paper_2309_00338_amd import ebit
+    from paper_2309_00338_amd import inputs as I
+
+    t0 = time.perf_counter()
+    nsteps = args.warmup + args.steps
+    inst = I.batched_instances(count=args.grids, steps=nsteps)
+    cells = sum(st.nx * st.ny for st, _, _, _ in inst)
+    log(f"[bench] generated {len(inst)} grids, {cells:.3e} cells in {time.perf_counter() - t0:.1f}s")
+    dev = torch.device("cuda:0")
+    b = ebit.EbitBatch([st for st, _, _, _ in inst], device=dev)
+    U, V = b.pack_velocities([u for _, u, _, _ in inst], [v for _, _, v, _ in inst])
+    dts = torch.tensor([[d[k] for _, _, _, d in inst] for k in range(nsteps)], dtype=torch.float64, device=dev)
+    C, K = b.new_fields()
+    stream = b.stream
+
+    def timed(step_fn):
+        for k in range(args.warmup):
+            step_fn(k)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for k in range(args.warmup, nsteps):
+            step_fn(k)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / args.steps
+
+    def batched_step(k):
+        b.advect(U, V, dts[k])
+        b.fraction_curvature(C, K)
+
+    ms_b = timed(batched_step)
+    st_b = b.sync()
+    if any(st_b):
+        raise RuntimeError(f"batched run reported device errors: {sorted(set(st_b))}")
+    log(f"[bench] batched: {ms_b * 1e3:.1f} us/step")
+    del b, U, V, C, K
+    torch.cuda.empty_cache()
+
+    grids = [ebit.EbitGrid(st, device=dev) for st, _, _, _ in inst]
+    vel = [(torch.from_numpy(u).to(dev), torch.from_numpy(v).to(dev)) for _, u, v, _ in inst]
+    fields = [g.new_field() for g in grids]
+    kfields = [g.new_field() for g in grids]
+
+    def plain_step(k):
+        for g, (u, v), (_, _, _, d), c, kk in zip(grids, vel, inst, fields, kfields):
+            g.advect(u, v, d[k])
+            g.fraction_curvature(c, kk)
+
+    ms_p = timed(plain_step)
+    for g in grids:
+        g.sync()
+    log(f"[bench] plain loop: {ms_p * 1e3:.1f} us/step")
+    out = {
+        "metric": METRIC, "value": cells / (ms_b * 1e-3), "unit": "cell-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_b, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"batched: {len(inst)} grids, N log-uniform in [64,1024], 1-20 circles/ellipses, "
+                               f"single vortex T~U[1,8], CFL 0.5", "grids": len(inst), "cells": cells, "seed": 1004},
+        "plain": {"value": cells / (ms_p * 1e-3), "ms_per_step": ms_p,
+                  "what": "one ebit_advect + ebit_fraction_curvature per grid per step, one stream"},
+        "batched_vs_plain": ms_p / ms_b,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_served(args):
+    """Pool serving a Poisson request stream. The clock is wall time minus the
+    client's time spent building requests; a request's latency runs from its
+    arrival to the end of the GPU step that completes it."""
+    import collections
+
+    import numpy as np
+    import torch
+
+    from paper_2309_00338_amd import ebit
+    from paper_2309_00338_amd import inputs as I
+
+    count = max(1, int(round(args.served_seconds * args.rate)))
+    reqs = I.served_requests(count, rate=args.rate)
+    dev = torch.device("cuda:0")
+    free, total = torch.cuda.mem_get_info(dev)
+    arena = int(min(free * 0.6, 96 << 30))
+    pool = ebit.EbitPool(max_grids=256, max_tiles=args.pool_tiles, arena_bytes=arena, device=dev)
+    stream = pool.stream
+    gen_time = 0.0
+    wall0 = time.perf_counter()
+
+    def clock():
+        return time.perf_counter() - wall0 - gen_time
+
+    pending = collections.deque()
+    nxt = None
+    exhausted = False
+    live = {}  # slot -> (request, cells)
+    lat, cell_steps, steps_run = [], 0, 0
+    offered, last_arrival = 0, 0.0
+    skip = 0.0  # idle time skipped when nothing is live and the next arrival is in the future
+    done_all = False
+    while not done_all:
+        # bring in every request that has arrived
+        while True:
+            if nxt is None and not exhausted:
+                try:
+                    t = time.perf_counter()
+                    req = next(reqs)
+                    req["inst"] = I.served_instance(req)
+                    gen_time += time.perf_counter() - t
+                    nxt = req
+                except StopIteration:
+                    exhausted = True
+            if nxt is not None and nxt["arrival"] <= clock() + skip:
+                pending.append(nxt)
+                nxt = None
+                continue
+            break
+        # admit in arrival order while the pool has room
+        while pending:
+            req = pending[0]
+            st, u, v, dt = req["inst"]
+            slot = pool.admit(st, u, v, dt)
+            if slot is None:
+                break
+            pending.popleft()
+            live[slot] = (req, st.nx * st.ny)
+            offered += st.nx * st.ny * req["steps"]
+            last_arrival = req["arrival"]
+            req.pop("inst")
+        if not live:
+            if exhausted and not pending and nxt is None:
+                done_all = True
+                continue
+            if nxt is not None:
+                skip = max(skip, nxt["arrival"] - clock())
+            continue
+        pool.step()
+        torch.cuda.synchronize()
+        steps_run += 1
+        now = clock() + skip
+        for slot in list(live):
+            req, cells = live[slot]
+            cell_steps += cells
+            req["done"] = req.get("done", 0) + 1
+            if req["done"] >= req["steps"]:
+                _, _, _, status = pool.read(slot, fields=False)
+                if status:
+                    raise RuntimeError(f"request {req['id']} failed with status {status}")
+                lat.append(now - req["arrival"])
+                pool.retire(slot)
+                del live[slot]
+    elapsed = clock() + skip
+    busy = clock()
+    lat_ms = np.array(lat) * 1e3
+    out = {
+        "metric": METRIC, "value": cell_steps / elapsed, "unit": "cell-steps/s", "n_gpus": 1, "steps": steps_run,
+        "warmup": 0, "ms_per_step": busy / max(steps_run, 1) * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"served: Poisson {args.rate:g}/s for {args.served_seconds:g} s, N log-uniform in "
+                               f"[128,2048], 1-50 circles, steady 4-mode fields, 16-256 steps", "requests": count,
+                   "seed": 1005},
+        "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99)),
+                       "max": float(lat_ms.max())},
+        "served": {"requests": len(lat), "cell_steps": cell_steps, "pool_steps": steps_run,
+                   "offered_cell_steps_per_s": offered / max(last_arrival, 1e-9),
+                   "busy_cell_steps_per_s": cell_steps / busy, "span_s": elapsed, "busy_s": busy,
+                   "client_generation_s": gen_time,
+                   "what": "value = cell-steps delivered / span (arrival clock); busy rate excludes idle gaps; "
+                           "latency = arrival to the end of the step completing the request, fields in HBM"},
+    }
     print(json.dumps(out), flush=True)
 
 
