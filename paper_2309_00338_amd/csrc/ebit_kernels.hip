@@ -539,16 +539,30 @@ __global__ __launch_bounds__(256, 8) void k_sweep(SweepArgs A, const Inst *__res
   const uint32_t ntile = *A.count;
   // this workgroup's tile indices, so no index load waits in the loop
   auto entry = [&](uint32_t it) -> uint2 { return A.list[DIR == 0 ? it : A.ntiles - 1u - it]; };
-  if (tid < 64 && blockIdx.x + tid * gridDim.x < ntile) sTiles[tid] = entry(blockIdx.x + tid * gridDim.x);
+  // this workgroup's tiles: a stride of the list for one grid, a contiguous
+  // chunk of it for many (consecutive entries mostly share a grid, and so do
+  // the fit jobs the workgroup queues, which keeps fit wavefronts on one grid)
+  uint32_t itBeg, itEnd, itStep;
+  if (ONE) {
+    itBeg = blockIdx.x;
+    itEnd = ntile;
+    itStep = gridDim.x;
+  } else {
+    const uint32_t chunk = (ntile + gridDim.x - 1) / gridDim.x;
+    itBeg = min(ntile, blockIdx.x * chunk);
+    itEnd = min(ntile, itBeg + chunk);
+    itStep = 1;
+  }
+  if (tid < 64 && itBeg + tid * itStep < itEnd) sTiles[tid] = entry(itBeg + tid * itStep);
   __syncthreads();
   auto tileAt = [&](uint32_t it) -> uint2 {
-    const uint32_t k = (it - blockIdx.x) / gridDim.x;
+    const uint32_t k = (it - itBeg) / itStep;
     const uint2 e = k < 64 ? sTiles[k] : entry(it);
     return make_uint2(uni(e.x), uni(e.y));
   };
-  if (blockIdx.x < ntile) prefetch(tileAt(blockIdx.x));
+  if (itBeg < itEnd) prefetch(tileAt(itBeg));
 
-  for (uint32_t it = blockIdx.x; it < ntile; it += gridDim.x) {
+  for (uint32_t it = itBeg; it < itEnd; it += itStep) {
     const uint2 te = tileAt(it);
     const uint32_t gt = te.x, kinst = ONE ? 0u : te.y;
     const SweepView W = ONE ? A.one
@@ -679,7 +693,7 @@ __global__ __launch_bounds__(256, 8) void k_sweep(SweepArgs A, const Inst *__res
         cnt.add(C_TILES_EMPTY, 1u);
       }
       if (tid < NH) sRow[tid] = 0;
-      if (it + gridDim.x < ntile) prefetch(tileAt(it + gridDim.x));
+      if (it + itStep < itEnd) prefetch(tileAt(it + itStep));
       continue;
     }
     if (tid == 0) cnt.add(C_TILES_SWEPT, 1u);
@@ -736,7 +750,7 @@ __global__ __launch_bounds__(256, 8) void k_sweep(SweepArgs A, const Inst *__res
       }
     }
     // the next tile's colours are fetched while this one computes
-    if (it + gridDim.x < ntile) prefetch(tileAt(it + gridDim.x));
+    if (it + itStep < itEnd) prefetch(tileAt(it + itStep));
     __syncthreads();
     uint32_t hasm = 0;
     if (tid < NH) sRow[tid] = 0;  // read last by the edge list; ready for the next tile

@@ -257,12 +257,16 @@ int engine_place(Engine *e, uint32_t k, const ebit_state *s) {
   const size_t nx = I.nx, ny = I.ny;
   const size_t nn = (nx + 1) * (ny + 1), nc = nx * ny, nh = nx * (ny + 1), nv = (nx + 1) * ny;
   HIPCHK(hipMemcpyAsync(e->dinst + k, &e->hinst[k], sizeof(Inst), hipMemcpyHostToDevice, e->stream));
-  for (int c = 0; c < 2; c++) {
-    HIPCHK(hipMemcpyAsync(I.col[c], s->node_color, nn, hipMemcpyHostToDevice, e->stream));
-    HIPCHK(hipMemcpyAsync(I.cen[c], s->cell_color, nc, hipMemcpyHostToDevice, e->stream));
-    HIPCHK(hipMemcpyAsync(I.hoff[c], s->hoff, nh * sizeof(double), hipMemcpyHostToDevice, e->stream));
-    HIPCHK(hipMemcpyAsync(I.voff[c], s->voff, nv * sizeof(double), hipMemcpyHostToDevice, e->stream));
-  }
+  // the current copy from the host, the other one on the device
+  const uint32_t c = e->cur, o = e->cur ^ 1u;
+  HIPCHK(hipMemcpyAsync(I.col[c], s->node_color, nn, hipMemcpyHostToDevice, e->stream));
+  HIPCHK(hipMemcpyAsync(I.cen[c], s->cell_color, nc, hipMemcpyHostToDevice, e->stream));
+  HIPCHK(hipMemcpyAsync(I.hoff[c], s->hoff, nh * sizeof(double), hipMemcpyHostToDevice, e->stream));
+  HIPCHK(hipMemcpyAsync(I.voff[c], s->voff, nv * sizeof(double), hipMemcpyHostToDevice, e->stream));
+  HIPCHK(hipMemcpyAsync(I.col[o], I.col[c], nn, hipMemcpyDeviceToDevice, e->stream));
+  HIPCHK(hipMemcpyAsync(I.cen[o], I.cen[c], nc, hipMemcpyDeviceToDevice, e->stream));
+  HIPCHK(hipMemcpyAsync(I.hoff[o], I.hoff[c], nh * sizeof(double), hipMemcpyDeviceToDevice, e->stream));
+  HIPCHK(hipMemcpyAsync(I.voff[o], I.voff[c], nv * sizeof(double), hipMemcpyDeviceToDevice, e->stream));
   HIPCHK(hipMemsetAsync(e->errs + k, 0, sizeof(uint32_t), e->stream));
   HIPCHK(launch_init_tiles(e->dinst, k, (uint32_t)(I.ntx * I.nty), e->cur, e->tileInst, e->has, e->nearPrev,
                            e->stream));
