@@ -64,13 +64,17 @@ enum {
 
 /* Sweep order (Sec. 2.1 splits each step into an x and a y sweep; the paper
  * does not fix their order). ALTERNATE: step n runs x then y when n is even,
- * y then x when n is odd. XY: always x then y. */
-enum { EBIT_SWEEP_ALTERNATE = 0u, EBIT_SWEEP_XY = 1u };
+ * y then x when n is odd. XY: always x then y.
+ * FIT_LINE: place each new unaligned marker where the straight segment between
+ * the two advected points that straddle the grid line crosses it, instead of
+ * by the circle fit of Sec. 2.2 (the method's first version, the EBIT-SL rows
+ * of Tables 1, 3, 4 and 5). */
+enum { EBIT_SWEEP_ALTERNATE = 0u, EBIT_SWEEP_XY = 1u, EBIT_FIT_LINE = 2u };
 
 typedef struct {
   int32_t nx, ny;  /* cells along x and y, each in [4, 65535] */
   double h;        /* physical cell size, > 0 */
-  uint32_t flags;  /* EBIT_SWEEP_* */
+  uint32_t flags;  /* EBIT_SWEEP_* | EBIT_FIT_LINE */
 } ebit_grid;
 
 /* Host-side state (Sec. 2.1-2.3): corner colours, centre colours and marker

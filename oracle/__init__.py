@@ -39,7 +39,7 @@ def _load():
             build_oracle()
         lib = ctypes.CDLL(LIB)
         lib.or_sweep.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _u8p, _u8p, _f64p, _f64p, _f64p,
-                                 _f64p, ctypes.c_double, ctypes.c_int, _i64p]
+                                 _f64p, ctypes.c_double, ctypes.c_int, ctypes.c_int, _i64p]
         lib.or_step.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _u8p, _u8p, _f64p, _f64p, _f64p,
                                 _f64p, ctypes.c_double, ctypes.c_int64, ctypes.c_int, _i64p]
         lib.or_fraction.argtypes = [ctypes.c_int, ctypes.c_int, _u8p, _u8p, _f64p, _f64p, _f64p]
@@ -71,27 +71,28 @@ def counters_dict(arr):
     return {k: int(v) for k, v in zip(COUNTERS, arr)}
 
 
-def sweep(st, u, v, dt, direction, counters=None):
-    """One 1D sweep in place (direction 0 = x with u, 1 = y with v)."""
+def sweep(st, u, v, dt, direction, counters=None, line=False):
+    """One 1D sweep in place (direction 0 = x with u, 1 = y with v); line:
+    EBIT-SL placement of the new unaligned markers instead of the circle fit."""
     _check(st)
     cnt = new_counters() if counters is None else counters
     u = np.ascontiguousarray(u, np.float64)
     v = np.ascontiguousarray(v, np.float64)
     rc = _load().or_sweep(st.nx, st.ny, st.h, _p(st.c, _u8p), _p(st.cc, _u8p), _p(st.hoff, _f64p),
                           _p(st.voff, _f64p), _p(u, _f64p), _p(v, _f64p), float(dt), int(direction),
-                          _p(cnt, _i64p))
+                          2 if line else 0, _p(cnt, _i64p))
     return rc, cnt
 
 
-def step(st, u, v, dt, xy_only=False, counters=None):
-    """One time step (two sweeps) in place; advances st.step."""
+def step(st, u, v, dt, xy_only=False, counters=None, line=False):
+    """One time step (two sweeps) in place; advances st.step. line: EBIT-SL."""
     _check(st)
     cnt = new_counters() if counters is None else counters
     u = np.ascontiguousarray(u, np.float64)
     v = np.ascontiguousarray(v, np.float64)
     rc = _load().or_step(st.nx, st.ny, st.h, _p(st.c, _u8p), _p(st.cc, _u8p), _p(st.hoff, _f64p),
                          _p(st.voff, _f64p), _p(u, _f64p), _p(v, _f64p), float(dt), int(st.step),
-                         1 if xy_only else 0, _p(cnt, _i64p))
+                         (1 if xy_only else 0) | (2 if line else 0), _p(cnt, _i64p))
     st.step += 1
     return rc, cnt
 

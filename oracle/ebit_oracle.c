@@ -80,6 +80,7 @@ typedef struct {
   const double *un;   /* nb x (na+1)   unaligned-edge offsets */
   const double *vel;  /* nb x (na+1)   face velocity along the sweep */
   double lam;         /* dt / h */
+  int line;           /* place new unaligned markers by the straight line (EBIT-SL) */
 } frame;
 
 #define NODE(F, a, b) ((size_t)(b) * (size_t)((F)->na + 1) + (size_t)(a))
@@ -448,6 +449,11 @@ static int sweep_frame(const frame *F, uint8_t *ncol_out, uint8_t *ncen, double 
       double y;
       if (X3 == 0.0) {
         y = Y3;
+      } else if (F->line) {
+        /* EBIT-SL, the method's first version (Sec. 2.2 and the SL rows of
+         * Tables 1, 3, 4, 5): the new marker is where the straight segment
+         * P2P3 crosses the grid line */
+        y = ysl[pick];
       } else {
         double X1 = 0, Y1 = 0, X4 = 0, Y4 = 0, rA = 0, rB = 0;
         int okA = 0, okB = 0;
@@ -559,16 +565,16 @@ static void transpose_f64(const double *src, double *dst, int rows, int cols) {
     for (int c = 0; c < cols; c++) dst[(size_t)c * rows + r] = src[(size_t)r * cols + c];
 }
 
-/* dir 0: sweep along x with u; dir 1: along y with v. */
+/* dir 0: sweep along x with u; dir 1: along y with v. flags bit 1: EBIT-SL. */
 int or_sweep(int nx, int ny, double h, uint8_t *c, uint8_t *cc, double *hoff, double *voff, const double *u,
-             const double *v, double dt, int dir, int64_t *st) {
+             const double *v, double dt, int dir, int flags, int64_t *st) {
   if (nx < 4 || ny < 4 || !(h > 0.0)) return OR_ERR_ARG;
   const size_t n_nodes = (size_t)(nx + 1) * (ny + 1), n_cells = (size_t)nx * ny;
   const size_t n_h = (size_t)nx * (ny + 1), n_v = (size_t)(nx + 1) * ny;
   double lam = dt / h;
   int rc;
   if (dir == 0) {
-    frame F = {nx, ny, c, cc, hoff, voff, u, lam};
+    frame F = {nx, ny, c, cc, hoff, voff, u, lam, (flags >> 1) & 1};
     uint8_t *nc = malloc(n_nodes), *ncc = malloc(n_cells);
     double *nh = calloc(n_h, sizeof(double)), *nv = calloc(n_v, sizeof(double));
     if (!nc || !ncc || !nh || !nv) { free(nc); free(ncc); free(nh); free(nv); return OR_ERR_NOMEM; }
@@ -595,7 +601,7 @@ int or_sweep(int nx, int ny, double h, uint8_t *c, uint8_t *cc, double *hoff, do
   transpose_f64(hoff, tun, ny + 1, nx); /* H edges are unaligned */
   transpose_f64(v, tvel, ny + 1, nx);
   {
-    frame F = {ny, nx, tc, tcc, tal, tun, tvel, lam};
+    frame F = {ny, nx, tc, tcc, tal, tun, tvel, lam, (flags >> 1) & 1};
     rc = sweep_frame(&F, nc, ncc, nal, nun, st);
   }
   transpose_u8(nc, c, nx + 1, ny + 1);
@@ -608,12 +614,13 @@ out:
 }
 
 /* One time step = two sweeps (Sec. 2.1). reading: step n runs x then y when n
- * is even and y then x when n is odd, unless xy_only is set. */
+ * is even and y then x when n is odd, unless flags bit 0 (x then y always) is
+ * set. flags bit 1: EBIT-SL placement of new unaligned markers. */
 int or_step(int nx, int ny, double h, uint8_t *c, uint8_t *cc, double *hoff, double *voff, const double *u,
-            const double *v, double dt, int64_t step, int xy_only, int64_t *st) {
-  int first = (xy_only || (step % 2) == 0) ? 0 : 1;
-  int rc1 = or_sweep(nx, ny, h, c, cc, hoff, voff, u, v, dt, first, st);
-  int rc2 = or_sweep(nx, ny, h, c, cc, hoff, voff, u, v, dt, 1 - first, st);
+            const double *v, double dt, int64_t step, int flags, int64_t *st) {
+  int first = ((flags & 1) || (step % 2) == 0) ? 0 : 1;
+  int rc1 = or_sweep(nx, ny, h, c, cc, hoff, voff, u, v, dt, first, flags, st);
+  int rc2 = or_sweep(nx, ny, h, c, cc, hoff, voff, u, v, dt, 1 - first, flags, st);
   return rc1 ? rc1 : rc2;
 }
 

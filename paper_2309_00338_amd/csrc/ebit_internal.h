@@ -43,7 +43,7 @@ enum {
 };
 
 enum : uint32_t { ERRBIT_CFL = 1u, ERRBIT_DOMAIN = 2u };
-enum : uint32_t { INST_XY = 1u };  // sweeps x then y every step
+enum : uint32_t { INST_XY = 1u, INST_LINE = 2u };  // x then y every step; straight-line placement
 
 // tile info bits written by the compaction, read by the fraction pass
 enum : uint8_t { TI_NEAR = 1, TI_COLOUR = 2, TI_DEAD = 4 };
@@ -84,6 +84,8 @@ struct SweepView {
   double *sp, *dd;
   uint8_t *zr;
   uint32_t *err;
+  uint32_t line;              // straight-line placement of new unaligned markers
+  uint32_t pad2;
 };
 
 __host__ __device__ inline SweepView sweep_view(const Inst &I, uint32_t cur, int dir, const double *u, const double *v,
@@ -108,6 +110,8 @@ __host__ __device__ inline SweepView sweep_view(const Inst &I, uint32_t cur, int
   w.dd = I.dd;
   w.zr = I.zr;
   w.err = I.err;
+  w.line = (I.flags & INST_LINE) ? 1u : 0u;
+  w.pad2 = 0;
   return w;
 }
 

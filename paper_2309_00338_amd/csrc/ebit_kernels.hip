@@ -343,7 +343,8 @@ struct Counts {
 // colours): its offset, and the centre-CV results for the cell right of the
 // line (cell a) and left of it (cell a-1): -1 or the new centre colour.
 template <class View>
-__device__ double newUnaligned(const View &T, int a, int b, int *resRight, int *resLeft, const Counts &cnt, bool count) {
+__device__ double newUnaligned(const View &T, int a, int b, int *resRight, int *resLeft, const Counts &cnt, bool count,
+                               bool line) {
   *resRight = -1;
   *resLeft = -1;
   uint32_t lties = 0, lrej = 0;
@@ -405,6 +406,9 @@ __device__ double newUnaligned(const View &T, int a, int b, int *resRight, int *
   uint32_t fb = 0;
   if (X3 == 0.0) {
     y = Y3;
+  } else if (line) {
+    // straight-line placement: where segment P2P3 crosses the line
+    y = ysl;
   } else {
     double rA = 0, rB = 0;
     bool okA = false, okB = false;
@@ -866,7 +870,7 @@ __device__ __forceinline__ void fitJob(const SweepView &W, uint32_t e, const Cou
   if (DIR == 0) { b = (int)(e / (uint32_t)(W.nx + 1)); a = (int)(e % (uint32_t)(W.nx + 1)); }
   else { a = (int)(e / (uint32_t)W.nx); b = (int)(e % (uint32_t)W.nx); }
   int rR, rL;
-  const double y = newUnaligned(V, a, b, &rR, &rL, cnt, true);
+  const double y = newUnaligned(V, a, b, &rR, &rL, cnt, true, W.line != 0);
   unn[e] = y;
   gp(W.zr)[e] = (uint8_t)((rR + 1) | ((rL + 1) << 2));
 }

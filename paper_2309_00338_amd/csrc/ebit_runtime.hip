@@ -55,7 +55,7 @@ struct Carve {
 
 bool grid_ok(const ebit_grid *g) {
   return g && g->nx >= 4 && g->ny >= 4 && g->nx <= 65535 && g->ny <= 65535 && isfinite(g->h) && g->h > 0.0 &&
-         (g->flags & ~1u) == 0;
+         (g->flags & ~3u) == 0;
 }
 
 uint32_t tiles_of(const ebit_grid &g) { return (uint32_t)(((g.nx + TS - 1) / TS) * ((g.ny + TS - 1) / TS)); }
@@ -384,7 +384,7 @@ void fill_inst(Inst *I, const ebit_grid &g, uint32_t tile0, uint32_t stepPar, ui
   I->nty = (g.ny + TS - 1) / TS;
   I->tile0 = tile0;
   I->stepPar = stepPar;
-  I->flags = (g.flags & EBIT_SWEEP_XY) ? INST_XY : 0u;
+  I->flags = ((g.flags & EBIT_SWEEP_XY) ? INST_XY : 0u) | ((g.flags & EBIT_FIT_LINE) ? INST_LINE : 0u);
   I->pad = 0;
   I->h = g.h;
   I->uoff = I->voffv = I->coff = I->koff = 0;

@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "_build", "libebit.so")
 
 EBIT_OK, EBIT_ERR_ARG, EBIT_ERR_STATE, EBIT_ERR_CFL, EBIT_ERR_DOMAIN, EBIT_ERR_DEVICE, EBIT_ERR_NOMEM = range(7)
-EBIT_SWEEP_ALTERNATE, EBIT_SWEEP_XY = 0, 1
+EBIT_SWEEP_ALTERNATE, EBIT_SWEEP_XY, EBIT_FIT_LINE = 0, 1, 2
 
 COUNTERS = (
     "markers", "annihilated", "three_landers", "ties", "fit_fallback", "fit_reject",
@@ -248,7 +248,8 @@ class EbitBatch:
     phase for all of them). Velocities, C and K live in packed device buffers;
     grid k's arrays start at the element offsets of the layout."""
 
-    def __init__(self, states, flags: int = EBIT_SWEEP_ALTERNATE, device: str = "cuda:0", stream=None):
+    def __init__(self, states, flags=EBIT_SWEEP_ALTERNATE, device: str = "cuda:0", stream=None):
+        """flags: one value for every grid or one per grid."""
         import torch
 
         self.torch = torch
@@ -257,7 +258,10 @@ class EbitBatch:
         if n < 1:
             raise ValueError("a batch needs at least one grid")
         self.shapes = [(st.nx, st.ny, st.h) for st in states]
-        grids = (ebit_grid * n)(*[ebit_grid(st.nx, st.ny, st.h, flags) for st in states])
+        fl = list(flags) if hasattr(flags, "__len__") else [flags] * n
+        if len(fl) != n:
+            raise ValueError("one flags value per grid")
+        grids = (ebit_grid * n)(*[ebit_grid(st.nx, st.ny, st.h, int(f)) for st, f in zip(states, fl)])
         hs, keep = [], []
         for st in states:
             s, k = _host_state(st)

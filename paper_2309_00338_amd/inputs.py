@@ -84,6 +84,46 @@ class Circle:
 
 
 @dataclasses.dataclass
+class NotchedDisk:
+    """Zalesak's disk (Sec. 3.4): a disk with a rectangular slot of width w and
+    length l cut from its bottom, centred on the disk's vertical axis (reading:
+    the notch opens towards the rotation centre below the disk). Crossings by
+    bisection on the inside test."""
+    cx: float
+    cy: float
+    r: float
+    w: float
+    l: float
+
+    def bbox(self):
+        return self.cx - self.r, self.cx + self.r, self.cy - self.r, self.cy + self.r
+
+    def inside(self, X, Y):
+        dx = X - self.cx
+        dy = Y - self.cy
+        disk = dx * dx + dy * dy < self.r * self.r
+        slot = (np.abs(dx) < 0.5 * self.w) & (Y < self.cy - self.r + self.l)
+        return disk & ~slot
+
+    def _bisect(self, lo, hi, fixed, along_x, lo_inside):
+        lo = np.array(lo, np.float64)
+        hi = np.array(hi, np.float64)
+        for _ in range(64):
+            mid = 0.5 * (lo + hi)
+            m = self.inside(mid, fixed) if along_x else self.inside(fixed, mid)
+            same = m == lo_inside
+            lo = np.where(same, mid, lo)
+            hi = np.where(same, hi, mid)
+        return 0.5 * (lo + hi)
+
+    def cross_h(self, i, j, left_inside):
+        return self._bisect(i, i + 1.0, j, True, left_inside)
+
+    def cross_v(self, i, j, low_inside):
+        return self._bisect(j, j + 1.0, i, False, low_inside)
+
+
+@dataclasses.dataclass
 class Ellipse:
     cx: float
     cy: float
@@ -278,6 +318,39 @@ def single_vortex(n: int = 64, period: float = 2.0, cfl: float = 0.5, radius: fl
     nsteps = int(round(period / dt))
     return Workload(f"vortex{n}_T{period:g}", st, u, v, vortex_dt_schedule(dt, period, nsteps),
                     {"period": period, "cfl": cfl, "radius": radius, "centre": centre})
+
+
+def rotation_faces(n: int) -> Tuple[np.ndarray, np.ndarray]:
+    """Rigid rotation about the domain centre (Sec. 3.4): u = 2 pi (0.5 - y),
+    v = 2 pi (x - 0.5) on the MAC faces (discretely divergence-free)."""
+    h = 1.0 / n
+    yc = (np.arange(n) + 0.5) * h
+    xc = (np.arange(n) + 0.5) * h
+    u = np.repeat((2.0 * np.pi * (0.5 - yc))[:, None], n + 1, axis=1)
+    v = np.repeat((2.0 * np.pi * (xc - 0.5))[None, :], n + 1, axis=0)
+    return np.ascontiguousarray(u), np.ascontiguousarray(v)
+
+
+def zalesak(n: int = 64, cfl: float = math.pi / 16) -> Workload:
+    """Zalesak's disk (Sec. 3.4): R = 0.15 at (0.5, 0.75), slot 0.05 x 0.25, one
+    revolution (T = 1) at CFL = u_max dt / h with u_max = pi at t = 0."""
+    st = init_state(n, n, [NotchedDisk(0.5 * n, 0.75 * n, 0.15 * n, 0.05 * n, 0.25 * n)])
+    u, v = rotation_faces(n)
+    h = 1.0 / n
+    dt = cfl * h / math.pi
+    nsteps = int(round(1.0 / dt))
+    return Workload(f"zalesak{n}", st, u, v, [dt] * nsteps, {"cfl": cfl})
+
+
+def translation(n: int = 64, cfl: float = 0.125):
+    """Translation with uniform velocity (Sec. 3.2): R = 0.15 at (0.25, 0.75),
+    u = -v = 1 until t = 0.5, then reversed; returns the workload of the first
+    half and the reversed faces for the second."""
+    st = init_state(n, n, [Circle(0.25 * n, 0.75 * n, 0.15 * n)])
+    u, v = uniform_faces(n, n, 1.0, -1.0)
+    dt = cfl / n
+    nsteps = int(round(1.0 / dt))
+    return Workload(f"translation{n}", st, u, v, [dt] * nsteps, {"cfl": cfl, "reverse_at": nsteps // 2})
 
 
 def _place_circles(rng, n, count, rmin, rmax, gap, wall, max_tries=200000):

@@ -59,12 +59,13 @@ class Lockstep:
         self.u = torch.from_numpy(np.ascontiguousarray(u)).to("cuda:0")
         self.v = torch.from_numpy(np.ascontiguousarray(v)).to("cuda:0")
         self.xy_only = bool(flags & 1)
+        self.line = bool(flags & 2)
         self.ocnt = oracle.new_counters()
         self.worst = {"off": 0.0, "C": 0.0, "K": 0.0}
 
     def step(self, dt, check_state=True, check_fields=True, where=""):
         self.g.advect(self.u, self.v, dt)
-        rc, _ = oracle.step(self.o, self.u_h, self.v_h, dt, xy_only=self.xy_only, counters=self.ocnt)
+        rc, _ = oracle.step(self.o, self.u_h, self.v_h, dt, xy_only=self.xy_only, counters=self.ocnt, line=self.line)
         assert rc == oracle.OK, f"{where}: oracle rc {rc}"
         if check_state:
             gs = self.g.get_state()

@@ -158,3 +158,23 @@ def test_pool_admit_step_retire_matches_oracle():
     live.pop(b)
     step_and_check("CD")
     assert c is not None
+
+
+def test_batch_with_mixed_flags():
+    """Grids with the circle fit, the straight line and the fixed x-then-y order
+    in one batch, each against its own oracle run."""
+    import torch
+
+    inst = _instances()[:3]
+    flags = [0, ebit.EBIT_FIT_LINE, ebit.EBIT_SWEEP_XY | ebit.EBIT_FIT_LINE]
+    b = ebit.EbitBatch([s for s, _, _, _ in inst], flags=flags)
+    U, V = b.pack_velocities([u for _, u, _, _ in inst], [v for _, _, v, _ in inst])
+    orc = [s.copy() for s, _, _, _ in inst]
+    for k in range(12):
+        dts = torch.tensor([d[k] for _, _, _, d in inst], dtype=torch.float64, device="cuda:0")
+        b.advect(U, V, dts)
+        for g, (st, u, v, d) in enumerate(inst):
+            rc, _ = oracle.step(orc[g], u, v, d[k], xy_only=bool(flags[g] & 1), line=bool(flags[g] & 2))
+            assert rc == oracle.OK
+        for g in range(3):
+            compare_state(b.get_state(g), orc[g], f"grid {g} step {k}")

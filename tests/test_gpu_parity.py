@@ -181,3 +181,24 @@ def test_cfl_and_domain_errors_latch():
             code = ex.code
             break
     assert code == ebit.EBIT_ERR_DOMAIN
+
+
+def test_straight_line_mode_config1():
+    """EBIT-SL (flag EBIT_FIT_LINE) on the config-1 vortex, all 256 steps."""
+    from paper_2309_00338_amd import ebit
+
+    w = I.single_vortex(64, period=2.0, cfl=0.5)
+    ls = Lockstep(w.state, w.u, w.v, flags=ebit.EBIT_FIT_LINE)
+    cnt = _run(ls, w.dts, every=2, fields_every=4)
+    assert cnt["fit_reject"] == 0 and cnt["fit_fallback"] == 0
+    print("worst", ls.worst, cnt)
+
+
+@pytest.mark.parametrize("line", [False, True])
+def test_zalesak_disk_64(line):
+    """Zalesak's disk (Sec. 3.4), one full revolution (1024 steps), both modes."""
+    from paper_2309_00338_amd import ebit
+
+    w = I.zalesak(64)
+    ls = Lockstep(w.state, w.u, w.v, flags=ebit.EBIT_FIT_LINE if line else 0)
+    _run(ls, w.dts, every=32, fields_every=128)
