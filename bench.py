@@ -196,6 +196,26 @@ def main():
                           "frac": step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "counters": st,
     }
+    # consumers of C and kappa (not part of the step): rho, mu and the face forces
+    rho, mu = g.new_field(), g.new_field()
+    fx = torch.empty((n, n + 1), dtype=torch.float64, device=dev)
+    fy = torch.empty((n + 1, n), dtype=torch.float64, device=dev)
+    fl = (1000.0, 1.2, 1e-3, 1.8e-5, 0.07)
+    g.ns_fields(C, K, *fl, rho=rho, mu=mu, fx=fx, fy=fy)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(8):
+        g.ns_fields(C, K, *fl, rho=rho, mu=mu, fx=fx, fy=fy)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ns_us = e0.elapsed_time(e1) / 8 * 1e3
+    # algorithmic bytes: four dense outputs (2 cell fields, 2 face fields) + C and kappa of the band
+    ns_bytes = 8.0 * (2 * ncell + 2 * n * (n + 1)) + 16.0 * I_step
+    out["ns_fields"] = {"us_per_launch": ns_us, "alg_bytes_per_launch": ns_bytes,
+                        "achieved_GBs": ns_bytes / (ns_us * 1e-6) / 1e9,
+                        "frac": ns_bytes / (ns_us * 1e-6) / 1e9 / HBM_PEAK_GBS}
+    log(f"[bench] ns_fields: {ns_us:.1f} us/launch")
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on one step of the same grid")
         out["cpu_baseline"] = cpu_baseline(w, 1)

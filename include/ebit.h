@@ -149,6 +149,27 @@ int ebit_curvature(ebit_handle *h, const double *C_dev, double *K_dev);
 /* ebit_fraction followed by ebit_curvature in one pass (same results). */
 int ebit_fraction_curvature(ebit_handle *h, double *C_dev, double *K_dev);
 
+/* Two-fluid properties and surface tension of the one-fluid Navier-Stokes
+ * equations (Sec. 2.5): Eq. (physical) with the Heaviside function
+ * approximated by C, and the surface-tension term sigma kappa n delta_S as a
+ * continuum force on the MAC faces, sigma * kappa_f * (C_right - C_left) / h,
+ * where kappa_f is the curvature of the face's two cells that carry one (two
+ * or more markers and a finite kappa): their mean, the one that does, or 0.
+ * Wall faces carry no force. */
+typedef struct {
+  double rho1, rho2;  /* density of colour 1 (the reference phase) and colour 0 */
+  double mu1, mu2;    /* viscosity of colour 1 and colour 0 */
+  double sigma;       /* surface tension coefficient */
+} ebit_fluid;
+
+/* rho_dev, mu_dev: ny x nx per cell; fx_dev: ny x (nx+1) on the x-faces (the
+ * layout of u); fy_dev: (ny+1) x nx on the y-faces (the layout of v); any
+ * output may be NULL. C_dev and K_dev must be the fraction and curvature of
+ * the current state (EBIT_ERR_STATE if the state advanced since the last
+ * ebit_fraction or ebit_fraction_curvature). Fully written. */
+int ebit_ns_fields(ebit_handle *h, const double *C_dev, const double *K_dev, const ebit_fluid *fluid, double *rho_dev,
+                   double *mu_dev, double *fx_dev, double *fy_dev);
+
 /* Copy the current state to host buffers (any may be NULL) and the step
  * counter; waits on the stream and returns a latched device error. */
 int ebit_get_state(ebit_handle *h, uint8_t *node_color, uint8_t *cell_color, double *hoff, double *voff,
@@ -206,6 +227,11 @@ int ebit_batch_advect(ebit_batch *b, const double *u_packed, const double *v_pac
 
 /* Fraction and curvature of every grid (as ebit_fraction_curvature). */
 int ebit_batch_fraction_curvature(ebit_batch *b, double *C_packed, double *K_packed);
+
+/* As ebit_ns_fields for every grid: rho and mu in the C/K layout, fx in the
+ * u layout and fy in the v layout of ebit_batch_layout. */
+int ebit_batch_ns_fields(ebit_batch *b, const double *C_packed, const double *K_packed, const ebit_fluid *fluid,
+                         double *rho_packed, double *mu_packed, double *fx_packed, double *fy_packed);
 
 /* Grid k's current state to host buffers (any may be NULL); waits. */
 int ebit_batch_get_state(ebit_batch *b, int k, uint8_t *node_color, uint8_t *cell_color, double *hoff, double *voff,

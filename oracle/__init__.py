@@ -44,7 +44,10 @@ def _load():
                                 _f64p, ctypes.c_double, ctypes.c_int64, ctypes.c_int, _i64p]
         lib.or_fraction.argtypes = [ctypes.c_int, ctypes.c_int, _u8p, _u8p, _f64p, _f64p, _f64p]
         lib.or_curvature.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _u8p, _f64p, _f64p, _i64p]
-        for f in (lib.or_sweep, lib.or_step, lib.or_fraction, lib.or_curvature):
+        d = ctypes.c_double
+        lib.or_ns_fields.argtypes = [ctypes.c_int, ctypes.c_int, d, _u8p, _f64p, _f64p, d, d, d, d, d, _f64p,
+                                     _f64p, _f64p, _f64p]
+        for f in (lib.or_sweep, lib.or_step, lib.or_fraction, lib.or_curvature, lib.or_ns_fields):
             f.restype = ctypes.c_int
         assert lib.or_counter_count() == len(COUNTERS)
         _lib = lib
@@ -112,3 +115,19 @@ def curvature(st, C, counters=None):
     K = np.empty((st.ny, st.nx), np.float64)
     _load().or_curvature(st.nx, st.ny, st.h, _p(st.c, _u8p), _p(C, _f64p), _p(K, _f64p), _p(cnt, _i64p))
     return K, cnt
+
+
+def ns_fields(st, C, K, rho1, rho2, mu1, mu2, sigma):
+    """Density and viscosity per cell (Eq. physical with H = C) and the
+    surface-tension face forces sigma kappa_f grad C on the x- and y-faces."""
+    _check(st)
+    C = np.ascontiguousarray(C, np.float64)
+    K = np.ascontiguousarray(K, np.float64)
+    rho = np.empty((st.ny, st.nx))
+    mu = np.empty((st.ny, st.nx))
+    fx = np.empty((st.ny, st.nx + 1))
+    fy = np.empty((st.ny + 1, st.nx))
+    rc = _load().or_ns_fields(st.nx, st.ny, st.h, _p(st.c, _u8p), _p(C, _f64p), _p(K, _f64p), rho1, rho2, mu1, mu2,
+                              sigma, _p(rho, _f64p), _p(mu, _f64p), _p(fx, _f64p), _p(fy, _f64p))
+    assert rc == OK
+    return rho, mu, fx, fy

@@ -773,4 +773,62 @@ int or_curvature(int nx, int ny, double h, const uint8_t *c, const double *C, do
   return OR_OK;
 }
 
+/* ------------------------------------------------------------------------- */
+/* Consumers of the interface on the same grid (Sec. 2.5, Eq. physical and    */
+/* the surface-tension term of Eq. NS).                                        */
+/* ------------------------------------------------------------------------- */
+/* Eq. (physical) with the Heaviside function approximated by C:
+ * rho = C rho1 + (1 - C) rho2 and mu = C mu1 + (1 - C) mu2 in every cell.
+ * Surface tension as a continuum face force sigma kappa_f grad C (the delta
+ * function times the normal approximated by the gradient of C across the
+ * face): on the x-face between cells (i-1,j) and (i,j),
+ *   fx = sigma * kf * (C(i,j) - C(i-1,j)) / h,
+ * reading: kf is the curvature of the face's two cells that carry it (two or
+ * more markers and a finite value), their mean when both do, else 0; wall
+ * faces carry no force. fy likewise on the y-faces. Any output may be NULL. */
+static int curv_defined(int nx, const uint8_t *c, const double *K, int i, int j) {
+  return cell_markers(nx, c, i, j) >= 2 && isfinite(K[(size_t)j * nx + i]);
+}
+
+static double face_kappa(int nx, const uint8_t *c, const double *K, int ia, int ja, int ib, int jb) {
+  int da = curv_defined(nx, c, K, ia, ja), db = curv_defined(nx, c, K, ib, jb);
+  double ka = K[(size_t)ja * nx + ia], kb = K[(size_t)jb * nx + ib];
+  if (da && db) return (ka + kb) * 0.5;
+  if (da) return ka;
+  if (db) return kb;
+  return 0.0;
+}
+
+int or_ns_fields(int nx, int ny, double h, const uint8_t *c, const double *C, const double *K, double rho1,
+                 double rho2, double mu1, double mu2, double sigma, double *rho, double *mu, double *fx, double *fy) {
+  if (nx < 4 || ny < 4 || !(h > 0.0)) return OR_ERR_ARG;
+  for (int j = 0; j < ny; j++)
+    for (int i = 0; i < nx; i++) {
+      size_t id = (size_t)j * nx + i;
+      if (rho) rho[id] = C[id] * rho1 + (1.0 - C[id]) * rho2;
+      if (mu) mu[id] = C[id] * mu1 + (1.0 - C[id]) * mu2;
+    }
+  if (fx)
+    for (int j = 0; j < ny; j++)
+      for (int i = 0; i <= nx; i++) {
+        double f = 0.0;
+        if (i > 0 && i < nx) {
+          double cl = C[(size_t)j * nx + i - 1], cr = C[(size_t)j * nx + i];
+          if (cl != cr) f = sigma * face_kappa(nx, c, K, i - 1, j, i, j) * (cr - cl) / h;
+        }
+        fx[(size_t)j * (nx + 1) + i] = f;
+      }
+  if (fy)
+    for (int j = 0; j <= ny; j++)
+      for (int i = 0; i < nx; i++) {
+        double f = 0.0;
+        if (j > 0 && j < ny) {
+          double cb = C[(size_t)(j - 1) * nx + i], ct = C[(size_t)j * nx + i];
+          if (cb != ct) f = sigma * face_kappa(nx, c, K, i, j - 1, i, j) * (ct - cb) / h;
+        }
+        fy[(size_t)j * nx + i] = f;
+      }
+  return OR_OK;
+}
+
 int or_counter_count(void) { return S_COUNT; }

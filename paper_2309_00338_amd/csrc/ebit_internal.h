@@ -172,6 +172,23 @@ struct FracArgs {
   Inst one;                  // the descriptor itself when the engine holds one grid
 };
 
+// Consumers of C and kappa on the same grid: density, viscosity, surface
+// tension face forces (one launch for every grid of the engine).
+struct NsArgs {
+  const Inst *inst;
+  const uint32_t *tileInst;
+  uint32_t ntiles;
+  uint32_t cur;
+  const double *C, *K;        // cell fields, at each grid's coff / koff
+  double *rho, *mu;           // cell outputs at coff (either may be null)
+  double *fx, *fy;            // face outputs at uoff / voffv (either may be null)
+  double rho1, rho2, mu1, mu2, sigma;
+  const uint8_t *tinfo;
+  const uint2 *list;          // near tiles
+  const uint32_t *count;
+  int nearBlocks;
+};
+
 __host__ __device__ inline int sweep_dir(const Inst &I, uint32_t stepNo, int phase) {
   if (I.flags & INST_XY) return phase;
   return (int)((stepNo + I.stepPar) & 1u) ^ phase;
@@ -192,6 +209,7 @@ hipError_t launch_clear_tiles(uint32_t *tileInst, uint16_t *has, uint8_t *nearPr
 hipError_t launch_compact(bool one, const CompactArgs &a, hipStream_t s);
 hipError_t launch_frac_curv(int mode, bool one, const FracArgs &a, int grid, hipStream_t s);
 int frac_fill_blocks(uint32_t ntiles);
+hipError_t launch_ns(const NsArgs &a, int grid, hipStream_t s);
 
 }  // namespace ebit
 

@@ -1353,6 +1353,121 @@ __global__ __launch_bounds__(256) void k_frac_curv(FracArgs A, const Inst *__res
 }
 
 // ---------------------------------------------------------------------------
+// Consumers of the interface (Sec. 2.5, Eq. physical and the surface-tension
+// term of Eq. NS): rho and mu from C per cell, and the face force
+// sigma * kappa_f * (C_right - C_left) / h, kappa_f the curvature of the
+// face's cells that carry one (two or more markers, finite), their mean when
+// both do, else 0. Near tiles stage the tile plus one cell on the left and
+// bottom (colours, C, kappa) in LDS; every other tile is uniform up to and
+// including its border faces, so it gets constant rho, mu and zero forces.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double mixOf(double c, double a, double b) { return c * a + (1.0 - c) * b; }
+
+__global__ __launch_bounds__(256) void k_ns(NsArgs A, const Inst *__restrict__ inst,
+                                            const uint32_t *__restrict__ tileInst) {
+  constexpr int WC = TS + 1;  // cells per side with the left / bottom halo
+  const int tid = threadIdx.x;
+  if ((int)blockIdx.x >= A.nearBlocks) {
+    // --- uniform tiles: 16 consecutive global tiles, lanes along grid rows ---
+    const uint32_t t = (blockIdx.x - (uint32_t)A.nearBlocks) * FILL_TILES + (uint32_t)tid / TS;
+    if (t >= A.ntiles) return;
+    const uint8_t ti = A.tinfo[t];
+    if (ti & (TI_NEAR | TI_DEAD)) return;
+    const Inst &I = inst[tileInst[t]];
+    const uint32_t lt = t - I.tile0;
+    const int tx = (int)(lt % (uint32_t)I.ntx), ty = (int)(lt / (uint32_t)I.ntx);
+    const int x = tx * TS + tid % TS;
+    if (x >= I.nx) return;
+    const int nx = I.nx, ny = I.ny, y0 = ty * TS, rows = min(TS, ny - y0);
+    const double c = (ti & TI_COLOUR) ? 1.0 : 0.0;
+    const double r = mixOf(c, A.rho1, A.rho2), m = mixOf(c, A.mu1, A.mu2);
+    for (int q = 0; q < rows; q++) {
+      const int y = y0 + q;
+      if (A.rho) A.rho[I.coff + (size_t)y * nx + x] = r;
+      if (A.mu) A.mu[I.coff + (size_t)y * nx + x] = m;
+      if (A.fx) {
+        A.fx[I.uoff + (size_t)y * (nx + 1) + x] = 0.0;
+        if (x == nx - 1) A.fx[I.uoff + (size_t)y * (nx + 1) + nx] = 0.0;
+      }
+      if (A.fy) A.fy[I.voffv + (size_t)y * nx + x] = 0.0;
+    }
+    if (A.fy && y0 + rows == ny) A.fy[I.voffv + (size_t)ny * nx + x] = 0.0;
+    return;
+  }
+  __shared__ uint8_t sNode[WC + 1][WC + 1];
+  __shared__ double sC[WC][WC], sK[WC][WC];
+  __shared__ uint8_t sDef[WC][WC];
+  const uint32_t ntile = *A.count;
+  for (uint32_t it = blockIdx.x; it < ntile; it += (uint32_t)A.nearBlocks) {
+    __syncthreads();
+    const uint2 te = make_uint2(uni(A.list[it].x), uni(A.list[it].y));
+    const Inst &I = inst[te.y];
+    const int nx = I.nx, ny = I.ny;
+    const uint32_t lt = te.x - I.tile0;
+    const int x0 = (int)(lt % (uint32_t)I.ntx) * TS, y0 = (int)(lt / (uint32_t)I.ntx) * TS;
+    const GL uint8_t *col = gp(I.col[A.cur]);
+    const GL double *Cg = gp(A.C + I.coff);
+    const GL double *Kg = gp(A.K + I.koff);
+    // nodes x0-1 .. x0+16, cells x0-1 .. x0+15 (and the same in y)
+    for (int k = tid; k < (WC + 1) * (WC + 1); k += blockDim.x) {
+      const int li = k % (WC + 1), lj = k / (WC + 1);
+      const int gx = x0 - 1 + li, gy = y0 - 1 + lj;
+      sNode[lj][li] = (gx >= 0 && gy >= 0 && gx <= nx && gy <= ny) ? col[(size_t)gy * (nx + 1) + gx] : (uint8_t)0;
+    }
+    for (int k = tid; k < WC * WC; k += blockDim.x) {
+      const int li = k % WC, lj = k / WC;
+      const int gx = x0 - 1 + li, gy = y0 - 1 + lj;
+      const bool in = gx >= 0 && gy >= 0 && gx < nx && gy < ny;
+      sC[lj][li] = in ? Cg[(size_t)gy * nx + gx] : 0.0;
+      sK[lj][li] = in ? Kg[(size_t)gy * nx + gx] : 0.0;
+    }
+    __syncthreads();
+    for (int k = tid; k < WC * WC; k += blockDim.x) {
+      const int li = k % WC, lj = k / WC;
+      const int bl = sNode[lj][li], br = sNode[lj][li + 1], tr = sNode[lj + 1][li + 1], tl = sNode[lj + 1][li];
+      const int nm = (bl != br) + (br != tr) + (tl != tr) + (bl != tl);
+      sDef[lj][li] = (uint8_t)(nm >= 2 && isfinite(sK[lj][li]));
+    }
+    __syncthreads();
+    auto faceK = [&](int la, int ja, int lb, int jb) -> double {
+      const bool da = sDef[ja][la], db = sDef[jb][lb];
+      if (da && db) return (sK[ja][la] + sK[jb][lb]) * 0.5;
+      if (da) return sK[ja][la];
+      if (db) return sK[jb][lb];
+      return 0.0;
+    };
+    for (int k = tid; k < TS * TS; k += blockDim.x) {
+      const int li = k % TS, lj = k / TS;
+      const int x = x0 + li, y = y0 + lj;
+      if (x >= nx || y >= ny) continue;
+      const int ci = li + 1, cj = lj + 1;  // LDS slot of cell (x, y)
+      const double c = sC[cj][ci];
+      if (A.rho) A.rho[I.coff + (size_t)y * nx + x] = mixOf(c, A.rho1, A.rho2);
+      if (A.mu) A.mu[I.coff + (size_t)y * nx + x] = mixOf(c, A.mu1, A.mu2);
+      if (A.fx) {
+        // x-face x (left side of the cell); the wall face x = nx by the last column
+        double f = 0.0;
+        if (x > 0) {
+          const double cl = sC[cj][ci - 1];
+          if (cl != c) f = A.sigma * faceK(ci - 1, cj, ci, cj) * (c - cl) / I.h;
+        }
+        A.fx[I.uoff + (size_t)y * (nx + 1) + x] = f;
+        if (x == nx - 1) A.fx[I.uoff + (size_t)y * (nx + 1) + nx] = 0.0;
+      }
+      if (A.fy) {
+        double f = 0.0;
+        if (y > 0) {
+          const double cb = sC[cj - 1][ci];
+          if (cb != c) f = A.sigma * faceK(ci, cj - 1, ci, cj) * (c - cb) / I.h;
+        }
+        A.fy[I.voffv + (size_t)y * nx + x] = f;
+        if (y == ny - 1) A.fy[I.voffv + (size_t)ny * nx + x] = 0.0;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 // Workgroups of a kernel that are resident on one CU at once (persistent
@@ -1435,6 +1550,11 @@ hipError_t launch_compact(bool one, const CompactArgs &a, hipStream_t s) {
 }
 
 int frac_fill_blocks(uint32_t ntiles) { return (int)((ntiles + FILL_TILES - 1) / FILL_TILES); }
+
+hipError_t launch_ns(const NsArgs &a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_ns, dim3(grid), dim3(256), 0, s, a, a.inst, a.tileInst);
+  return hipGetLastError();
+}
 
 hipError_t launch_frac_curv(int mode, bool one, const FracArgs &a, int grid, hipStream_t s) {
   if (one) {

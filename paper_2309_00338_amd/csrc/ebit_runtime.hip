@@ -336,6 +336,36 @@ int engine_frac(Engine *e, int mode, const double *Cin, double *Cout, double *Ko
   return EBIT_OK;
 }
 
+int engine_ns(Engine *e, const double *C, const double *K, const ebit_fluid *f, double *rho, double *mu, double *fx,
+              double *fy) {
+  if (!C || !K || !f) return EBIT_ERR_ARG;
+  if (!isfinite(f->rho1) || !isfinite(f->rho2) || !isfinite(f->mu1) || !isfinite(f->mu2) || !isfinite(f->sigma))
+    return EBIT_ERR_ARG;
+  if (e->fracEpoch != e->epoch) return EBIT_ERR_STATE;
+  NsArgs a;
+  a.inst = e->dinst;
+  a.tileInst = e->tileInst;
+  a.ntiles = e->ntiles;
+  a.cur = e->cur;
+  a.C = C;
+  a.K = K;
+  a.rho = rho;
+  a.mu = mu;
+  a.fx = fx;
+  a.fy = fy;
+  a.rho1 = f->rho1;
+  a.rho2 = f->rho2;
+  a.mu1 = f->mu1;
+  a.mu2 = f->mu2;
+  a.sigma = f->sigma;
+  a.tinfo = e->tinfo;
+  a.list = e->nearList;
+  a.count = e->counts + NSLOT * e->slot + CNT_NEAR;
+  a.nearBlocks = e->nearBlocks[2];
+  HIPCHK(launch_ns(a, a.nearBlocks + frac_fill_blocks(e->ntiles), e->stream));
+  return EBIT_OK;
+}
+
 int status_of(uint32_t bits) {
   if (bits & ERRBIT_CFL) return EBIT_ERR_CFL;
   if (bits & ERRBIT_DOMAIN) return EBIT_ERR_DOMAIN;
@@ -555,6 +585,12 @@ int ebit_fraction_curvature(ebit_handle *h, double *C_dev, double *K_dev) {
   return rc;
 }
 
+int ebit_ns_fields(ebit_handle *h, const double *C_dev, const double *K_dev, const ebit_fluid *fluid, double *rho_dev,
+                   double *mu_dev, double *fx_dev, double *fy_dev) {
+  if (!h) return EBIT_ERR_ARG;
+  return engine_ns(&h->e, C_dev, K_dev, fluid, rho_dev, mu_dev, fx_dev, fy_dev);
+}
+
 int ebit_get_state(ebit_handle *h, uint8_t *node_color, uint8_t *cell_color, double *hoff, double *voff,
                    int64_t *step) {
   if (!h) return EBIT_ERR_ARG;
@@ -689,6 +725,12 @@ int ebit_batch_fraction_curvature(ebit_batch *b, double *C_packed, double *K_pac
   const int rc = engine_frac(&b->e, 3, nullptr, C_packed, K_packed);
   b->e.fracEpoch = b->e.epoch;
   return rc;
+}
+
+int ebit_batch_ns_fields(ebit_batch *b, const double *C_packed, const double *K_packed, const ebit_fluid *fluid,
+                         double *rho_packed, double *mu_packed, double *fx_packed, double *fy_packed) {
+  if (!b) return EBIT_ERR_ARG;
+  return engine_ns(&b->e, C_packed, K_packed, fluid, rho_packed, mu_packed, fx_packed, fy_packed);
 }
 
 int ebit_batch_get_state(ebit_batch *b, int k, uint8_t *node_color, uint8_t *cell_color, double *hoff, double *voff,

@@ -40,6 +40,11 @@ class ebit_state(ctypes.Structure):
                 ("voff", ctypes.c_void_p)]
 
 
+class ebit_fluid(ctypes.Structure):
+    _fields_ = [("rho1", ctypes.c_double), ("rho2", ctypes.c_double), ("mu1", ctypes.c_double),
+                ("mu2", ctypes.c_double), ("sigma", ctypes.c_double)]
+
+
 class ebit_counters(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in COUNTERS]
 
@@ -70,6 +75,7 @@ def _load() -> ctypes.CDLL:
         "ebit_fraction": [vp, vp],
         "ebit_curvature": [vp, vp, vp],
         "ebit_fraction_curvature": [vp, vp, vp],
+        "ebit_ns_fields": [vp, vp, vp, ctypes.POINTER(ebit_fluid), vp, vp, vp, vp],
         "ebit_get_state": [vp, vp, vp, vp, vp, ctypes.POINTER(ctypes.c_int64)],
         "ebit_set_state": [vp, S, ctypes.c_int64],
         "ebit_stats": [vp, ctypes.POINTER(ebit_counters)],
@@ -85,6 +91,7 @@ def _load() -> ctypes.CDLL:
         "ebit_batch_layout": [B, szp, szp, szp, szp],
         "ebit_batch_advect": [B, vp, vp, vp],
         "ebit_batch_fraction_curvature": [B, vp, vp],
+        "ebit_batch_ns_fields": [B, vp, vp, ctypes.POINTER(ebit_fluid), vp, vp, vp, vp],
         "ebit_batch_get_state": [B, i32, vp, vp, vp, vp, ctypes.POINTER(ctypes.c_int64)],
         "ebit_batch_stats": [B, ctypes.POINTER(ebit_counters)],
         "ebit_batch_sync": [B, ctypes.POINTER(ctypes.c_int)],
@@ -198,6 +205,21 @@ class EbitGrid:
         _chk(_lib.ebit_fraction_curvature(self._h, self._dev(C, (self.ny, self.nx), "C"),
                                           self._dev(K, (self.ny, self.nx), "K")), "ebit_fraction_curvature")
         return C, K
+
+    def ns_fields(self, C, K, rho1, rho2, mu1, mu2, sigma, rho=None, mu=None, fx=None, fy=None):
+        """Density, viscosity (per cell) and surface-tension face forces from the
+        current C and kappa; new tensors for any output not given."""
+        t = self.torch
+        rho = self.new_field() if rho is None else rho
+        mu = self.new_field() if mu is None else mu
+        fx = t.empty((self.ny, self.nx + 1), dtype=t.float64, device=self.device) if fx is None else fx
+        fy = t.empty((self.ny + 1, self.nx), dtype=t.float64, device=self.device) if fy is None else fy
+        fl = ebit_fluid(rho1, rho2, mu1, mu2, sigma)
+        _chk(_lib.ebit_ns_fields(self._h, self._dev(C, (self.ny, self.nx), "C"), self._dev(K, (self.ny, self.nx), "K"),
+                                 ctypes.byref(fl), self._dev(rho, (self.ny, self.nx), "rho"),
+                                 self._dev(mu, (self.ny, self.nx), "mu"), self._dev(fx, (self.ny, self.nx + 1), "fx"),
+                                 self._dev(fy, (self.ny + 1, self.nx), "fy")), "ebit_ns_fields")
+        return rho, mu, fx, fy
 
     # -- state, counters ---------------------------------------------------
     def get_state(self) -> State:
@@ -324,6 +346,19 @@ class EbitBatch:
         _chk(_lib.ebit_batch_fraction_curvature(self._h, self._buf(C, self.totals[2], "C"),
                                                 self._buf(K, self.totals[2], "K")), "ebit_batch_fraction_curvature")
         return C, K
+
+    def ns_fields(self, C, K, rho1, rho2, mu1, mu2, sigma):
+        """Packed rho, mu (C layout), fx (u layout), fy (v layout) of every grid."""
+        t = self.torch
+        rho = t.empty(self.totals[2], dtype=t.float64, device=self.device)
+        mu = t.empty(self.totals[2], dtype=t.float64, device=self.device)
+        fx = t.empty(self.totals[0], dtype=t.float64, device=self.device)
+        fy = t.empty(self.totals[1], dtype=t.float64, device=self.device)
+        fl = ebit_fluid(rho1, rho2, mu1, mu2, sigma)
+        _chk(_lib.ebit_batch_ns_fields(self._h, self._buf(C, self.totals[2], "C"), self._buf(K, self.totals[2], "K"),
+                                       ctypes.byref(fl), rho.data_ptr(), mu.data_ptr(), fx.data_ptr(), fy.data_ptr()),
+             "ebit_batch_ns_fields")
+        return rho, mu, fx, fy
 
     def get_state(self, k) -> State:
         nx, ny, h = self.shapes[k]

@@ -178,3 +178,32 @@ def test_batch_with_mixed_flags():
             assert rc == oracle.OK
         for g in range(3):
             compare_state(b.get_state(g), orc[g], f"grid {g} step {k}")
+
+
+def test_batch_ns_fields_per_grid():
+    import torch
+
+    inst = _instances()
+    b = ebit.EbitBatch([s for s, _, _, _ in inst])
+    U, V = b.pack_velocities([u for _, u, _, _ in inst], [v for _, _, v, _ in inst])
+    orc = [s.copy() for s, _, _, _ in inst]
+    for k in range(5):
+        dts = torch.tensor([d[k] for _, _, _, d in inst], dtype=torch.float64, device="cuda:0")
+        b.advect(U, V, dts)
+        for g, (st, u, v, d) in enumerate(inst):
+            assert oracle.step(orc[g], u, v, d[k])[0] == oracle.OK
+    C, K = b.new_fields()
+    b.fraction_curvature(C, K)
+    fl = (800.0, 2.0, 0.5, 0.01, 0.3)
+    rho, mu, fx, fy = b.ns_fields(C, K, *fl)
+    for g in range(len(inst)):
+        nx, ny, _ = b.shapes[g]
+        Co = oracle.fraction(orc[g])
+        Ko, _ = oracle.curvature(orc[g], Co)
+        want = oracle.ns_fields(orc[g], Co, Ko, *fl)
+        got = (b.field(rho, g), b.field(mu, g),
+               fx[b.u_off[g]:b.u_off[g] + ny * (nx + 1)].view(ny, nx + 1),
+               fy[b.v_off[g]:b.v_off[g] + (ny + 1) * nx].view(ny + 1, nx))
+        for name, gg, o in zip(("rho", "mu", "fx", "fy"), got, want):
+            d = np.abs(gg.cpu().numpy() - o) / np.maximum(np.abs(o), 1.0)
+            assert d.max(initial=0) <= 1e-12, (g, name, d.max())

@@ -536,3 +536,70 @@ def test_domain_exit_is_reported():
         if rc:
             break
     assert rc == oracle.ERR_DOMAIN
+
+
+# ---------------------------------------------------------------------------
+# consumers on the same grid (Sec. 2.5, Eq. physical, surface-tension term)
+# ---------------------------------------------------------------------------
+def test_ns_properties_are_the_linear_mix_of_eq_physical():
+    st = I.init_state(32, 32, [I.Circle(15.3, 16.1, 7.2)])
+    C = oracle.fraction(st)
+    K, _ = oracle.curvature(st, C)
+    rho, mu, fx, fy = oracle.ns_fields(st, C, K, 1000.0, 1.2, 1e-3, 1.8e-5, 0.07)
+    assert np.all(rho[C == 1.0] == 1000.0) and np.all(rho[C == 0.0] == 1.2)
+    assert np.all(mu[C == 1.0] == 1e-3) and np.all(mu[C == 0.0] == 1.8e-5)
+    frac = (C > 0) & (C < 1)
+    assert frac.any()
+    assert np.allclose(rho[frac], 1.2 + C[frac] * (1000.0 - 1.2), rtol=1e-14)
+    # forces only on faces where C jumps; none on the walls
+    assert np.all(fx[:, 0] == 0) and np.all(fx[:, -1] == 0) and np.all(fy[0] == 0) and np.all(fy[-1] == 0)
+    jump = np.zeros_like(fx, bool)
+    jump[:, 1:-1] = C[:, 1:] != C[:, :-1]
+    assert np.all(fx[~jump] == 0) and np.any(fx[jump] != 0)
+
+
+@pytest.mark.parametrize("R", [12.0, 20.0, 31.5])
+def test_csf_force_on_half_a_circle_is_laplace(R):
+    """With the exact curvature 1/R in every interfacial cell, the x-force on the
+    right half of a circle integrates to -2 sigma (the pressure jump sigma/R over
+    the projected length 2R, pointing inwards); the net force vanishes and each
+    row telescopes to zero."""
+    n = 128
+    st = I.init_state(n, n, [I.Circle(64.3, 63.8, R)])
+    C = oracle.fraction(st)
+    K, _ = oracle.curvature(st, C)
+    K0 = np.where((K != 0) | np.isnan(K), 1.0 / (R * st.h), 0.0)
+    sigma = 0.7
+    _, _, fx, fy = oracle.ns_fields(st, C, K0, 1.0, 1.0, 1.0, 1.0, sigma)
+    h2 = st.h * st.h
+    right = fx[:, np.arange(n + 1) > 64.3].sum() * h2
+    top = fy[np.arange(n + 1) > 63.8, :].sum() * h2
+    assert abs(right + 2 * sigma) < 2 * sigma * 2.0 / R
+    assert abs(top + 2 * sigma) < 2 * sigma * 2.0 / R
+    assert abs(fx.sum()) * h2 < 1e-12 and abs(fy.sum()) * h2 < 1e-12
+    assert np.abs(fx.sum(axis=1)).max() * h2 < 1e-12
+
+
+def test_csf_face_curvature_selection():
+    """kappa_f: mean of two defined cells, the defined one, else 0 (NaN and
+    marker-free cells do not count)."""
+    n = 16
+    st = I.init_state(n, n, [I.CosineBelow(n, 0.53, 0.0)])  # horizontal line y = 8.48, colour 1 below
+    C = oracle.fraction(st)
+    j = 8  # the interfacial row: every cell (i, 8) holds two markers
+    K = np.zeros_like(C)
+    # a flat line gives no jump in C along x; set C by hand in that row so the
+    # x-faces between interfacial cells carry forces
+    C2 = C.copy()
+    C2[j, 3], C2[j, 4], C2[j, 5] = 0.2, 0.5, 0.7
+    K[j, 3], K[j, 4], K[j, 5] = 2.0, np.nan, 6.0
+    _, _, fx, _ = oracle.ns_fields(st, C2, K, 1, 1, 1, 1, 1.0)
+    h = st.h
+    assert fx[j, 4] == pytest.approx((0.5 - 0.2) / h * 2.0, rel=1e-15)  # left cell only (right is NaN)
+    assert fx[j, 5] == pytest.approx((0.7 - 0.5) / h * 6.0, rel=1e-15)  # right cell only
+    C3 = C.copy()
+    C3[j, 10], C3[j, 11] = 0.3, 0.6
+    K3 = np.zeros_like(C)
+    K3[j, 10], K3[j, 11] = 1.0, 3.0
+    _, _, fx3, _ = oracle.ns_fields(st, C3, K3, 1, 1, 1, 1, 1.0)
+    assert fx3[j, 11] == pytest.approx((0.6 - 0.3) / h * 2.0, rel=1e-15)  # mean of both
