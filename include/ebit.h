@@ -104,6 +104,7 @@ typedef struct {
   int64_t invariant_fail;  /* lander parity differs from the colours */
   int64_t hf_fail;         /* interfacial cells with no valid height */
   int64_t interfacial;     /* cells with >= 2 markers seen by curvature */
+  int64_t ghf_fit;         /* of the hf_fail cells, those given kappa by the marker parabola */
   /* schedule diagnostics (GPU tiles of 16x16 cells) */
   int64_t tiles_swept;     /* tiles swept with markers in reach */
   int64_t tiles_empty;     /* tiles swept only to carry their state over */

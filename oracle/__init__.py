@@ -21,7 +21,7 @@ from .build import LIB, build_oracle
 COUNTERS = (
     "markers", "annihilated", "three_landers", "ties", "fit_fallback", "fit_reject",
     "parity_fallback", "three_crossings", "cv_set", "cv_conflict", "cv_unresolved",
-    "wall_violation", "invariant_fail", "hf_fail", "interfacial",
+    "wall_violation", "invariant_fail", "hf_fail", "interfacial", "ghf_fit",
 )
 
 OK, ERR_ARG, ERR_CFL, ERR_DOMAIN = 0, 1, 3, 4
@@ -43,11 +43,14 @@ def _load():
         lib.or_step.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _u8p, _u8p, _f64p, _f64p, _f64p,
                                 _f64p, ctypes.c_double, ctypes.c_int64, ctypes.c_int, _i64p]
         lib.or_fraction.argtypes = [ctypes.c_int, ctypes.c_int, _u8p, _u8p, _f64p, _f64p, _f64p]
-        lib.or_curvature.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _u8p, _f64p, _f64p, _i64p]
+        lib.or_curvature.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _u8p, _f64p, _f64p, _f64p, _f64p,
+                                     _i64p]
         d = ctypes.c_double
         lib.or_ns_fields.argtypes = [ctypes.c_int, ctypes.c_int, d, _u8p, _f64p, _f64p, d, d, d, d, d, _f64p,
                                      _f64p, _f64p, _f64p]
-        for f in (lib.or_sweep, lib.or_step, lib.or_fraction, lib.or_curvature, lib.or_ns_fields):
+        lib.or_parabola_fit.argtypes = [ctypes.c_int, _f64p, _f64p, d, d, ctypes.c_int, ctypes.c_int, d, _f64p]
+        for f in (lib.or_sweep, lib.or_step, lib.or_fraction, lib.or_curvature, lib.or_ns_fields,
+                  lib.or_parabola_fit):
             f.restype = ctypes.c_int
         assert lib.or_counter_count() == len(COUNTERS)
         _lib = lib
@@ -113,7 +116,8 @@ def curvature(st, C, counters=None):
     cnt = new_counters() if counters is None else counters
     C = np.ascontiguousarray(C, np.float64)
     K = np.empty((st.ny, st.nx), np.float64)
-    _load().or_curvature(st.nx, st.ny, st.h, _p(st.c, _u8p), _p(C, _f64p), _p(K, _f64p), _p(cnt, _i64p))
+    _load().or_curvature(st.nx, st.ny, st.h, _p(st.c, _u8p), _p(st.hoff, _f64p), _p(st.voff, _f64p), _p(C, _f64p),
+                         _p(K, _f64p), _p(cnt, _i64p))
     return K, cnt
 
 
@@ -131,3 +135,15 @@ def ns_fields(st, C, K, rho1, rho2, mu1, mu2, sigma):
                               sigma, _p(rho, _f64p), _p(mu, _f64p), _p(fx, _f64p), _p(fy, _f64p))
     assert rc == OK
     return rho, mu, fx, fy
+
+
+def parabola_fit(px, py, xc, yc, gx, gy, h):
+    """Curvature of the least-squares parabola through points (px, py) in the
+    frame of the normal (gx, gy) at (xc, yc), the curvature fallback; None when
+    the fit is not defined."""
+    px = np.ascontiguousarray(px, np.float64)
+    py = np.ascontiguousarray(py, np.float64)
+    k = np.zeros(1)
+    ok = _load().or_parabola_fit(len(px), _p(px, _f64p), _p(py, _f64p), float(xc), float(yc), int(gx), int(gy),
+                                 float(h), _p(k, _f64p))
+    return float(k[0]) if ok else None

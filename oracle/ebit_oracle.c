@@ -65,6 +65,7 @@ enum {
   S_INVARIANT_FAIL,   /* lander parity differs from the corner colours */
   S_HF_FAIL,          /* interfacial cells where both HF orientations fail */
   S_INTERFACIAL,      /* cells with two or more markers (curvature pass) */
+  S_GHF_FIT,          /* of the HF failures, cells given kappa by the marker parabola */
   S_COUNT
 };
 
@@ -741,7 +742,76 @@ static int hf_try(int nx, int ny, double h, const uint8_t *c, const double *C, i
   return 1;
 }
 
-int or_curvature(int nx, int ny, double h, const uint8_t *c, const double *C, double *K, int64_t *st) {
+/* Fallback where no height is valid: Sec. 2.5 computes kappa by the
+ * generalised height-function method, which fits a parabola to interface
+ * points, in a frame aligned with the interface normal, when heights are
+ * missing. reading: EBIT's markers are those points, and the normal is the
+ * integer node-colour gradient (gx, gy) used for the HF orientation, pointing
+ * into colour 1. All markers on the edges of the 5x5 cells around (i,j) that
+ * lie inside the grid, relative to the cell centre in index units, are
+ * projected on the tangent (X) and the normal (Y) and fitted by least squares
+ * with Y = a + b X + c X^2 (normal equations solved by Cramer's rule); kappa =
+ * 2c / (1 + b^2)^(3/2) / h, positive for convex colour 1. Fails with fewer
+ * than three points, a zero gradient or a degenerate system. The points are
+ * taken H edges first (rows y, then x), then V edges. */
+/* The fit itself on n points (px, py), exported for its pins. */
+int or_parabola_fit(int n, const double *px, const double *py, double xc, double yc, int gx, int gy, double h,
+                    double *kap) {
+  if (gx == 0 && gy == 0) return 0;
+  const double gl = sqrt((double)gx * (double)gx + (double)gy * (double)gy);
+  const double nX = (double)gx / gl, nY = (double)gy / gl; /* unit normal into colour 1 */
+  double S0 = 0.0, S1 = 0.0, S2 = 0.0, S3 = 0.0, S4 = 0.0, T0 = 0.0, T1 = 0.0, T2 = 0.0;
+  for (int k = 0; k < n; k++) {
+    const double dx = px[k] - xc, dy = py[k] - yc;
+    const double X = dx * (-nY) + dy * nX; /* along the tangent */
+    const double Y = dx * nX + dy * nY;    /* along the normal */
+    const double X2 = X * X;
+    S0 += 1.0;
+    S1 += X;
+    S2 += X2;
+    S3 += X2 * X;
+    S4 += X2 * X2;
+    T0 += Y;
+    T1 += X * Y;
+    T2 += X2 * Y;
+  }
+  if (S0 < 3.0) return 0;
+  const double det = S0 * (S2 * S4 - S3 * S3) - S1 * (S1 * S4 - S3 * S2) + S2 * (S1 * S3 - S2 * S2);
+  if (!(det > 1e-10 * (S0 * S2 * S4))) return 0;
+  const double db = S0 * (T1 * S4 - S3 * T2) - T0 * (S1 * S4 - S3 * S2) + S2 * (S1 * T2 - T1 * S2);
+  const double dc = S0 * (S2 * T2 - T1 * S3) - S1 * (S1 * T2 - T1 * S2) + T0 * (S1 * S3 - S2 * S2);
+  const double b = db / det, cc = dc / det;
+  const double g = 1.0 + b * b;
+  *kap = (2.0 * cc) / (h * g * sqrt(g));
+  return 1;
+}
+
+static int ghf_fit(int nx, int ny, double h, const uint8_t *c, const double *hoff, const double *voff, int i, int j,
+                   int gx, int gy, double *kap) {
+  const size_t W1 = (size_t)nx + 1;
+  double px[66], py[66];
+  int n = 0;
+  for (int pass = 0; pass < 2; pass++)
+    for (int y = j - 2; y <= j + 2 + (pass == 0); y++)
+      for (int x = i - 2; x <= i + 2 + (pass == 1); x++) {
+        if (pass == 0) { /* H(x,y) */
+          if (x < 0 || x >= nx || y < 0 || y > ny) continue;
+          if (c[(size_t)y * W1 + x] == c[(size_t)y * W1 + x + 1]) continue;
+          px[n] = x + hoff[(size_t)y * nx + x];
+          py[n] = y;
+        } else { /* V(x,y) */
+          if (x < 0 || x > nx || y < 0 || y >= ny) continue;
+          if (c[(size_t)y * W1 + x] == c[(size_t)(y + 1) * W1 + x]) continue;
+          px[n] = x;
+          py[n] = y + voff[(size_t)y * W1 + x];
+        }
+        n++;
+      }
+  return or_parabola_fit(n, px, py, i + 0.5, j + 0.5, gx, gy, h, kap);
+}
+
+int or_curvature(int nx, int ny, double h, const uint8_t *c, const double *hoff, const double *voff, const double *C,
+                 double *K, int64_t *st) {
   for (int j = 0; j < ny; j++)
     for (int i = 0; i < nx; i++) {
       size_t id = (size_t)j * nx + i;
@@ -766,8 +836,14 @@ int or_curvature(int nx, int ny, double h, const uint8_t *c, const double *C, do
       if (hf_try(nx, ny, h, c, C, i, j, first_rows, &kap) || hf_try(nx, ny, h, c, C, i, j, 1 - first_rows, &kap)) {
         K[id] = kap;
       } else {
-        K[id] = NAN;
         st[S_HF_FAIL]++;
+        /* the node sums point into colour 1 */
+        if (ghf_fit(nx, ny, h, c, hoff, voff, i, j, ncx, ncy, &kap)) {
+          K[id] = kap;
+          st[S_GHF_FIT]++;
+        } else {
+          K[id] = NAN;
+        }
       }
     }
   return OR_OK;

@@ -36,6 +36,7 @@ enum {
   C_INVARIANT_FAIL,
   C_HF_FAIL,
   C_INTERFACIAL,
+  C_GHF_FIT,
   C_TILES_SWEPT,   // diagnostics of the tiled schedule (no oracle counterpart)
   C_TILES_EMPTY,
   C_TILES_NEAR,

@@ -1191,6 +1191,60 @@ __device__ bool hfTry(int i, int j, int rows, double h, GetC getC, GetN getN, Ge
   return true;
 }
 
+// Where no height is valid: the least-squares parabola through the markers on
+// the edges of the 5x5 cells around (i,j), in the frame of the node-colour
+// gradient (gx, gy) (pointing into colour 1); kappa = 2c / (1 + b^2)^(3/2) / h.
+// Points are summed H edges first (rows y, then x), then V edges.
+template <class GetN>
+__device__ bool ghfFit(const FracCtx &P, double h, int i, int j, int gx, int gy, GetN node, double *kap) {
+  if (gx == 0 && gy == 0) return false;
+  const double gl = sqrt((double)gx * (double)gx + (double)gy * (double)gy);
+  const double nX = (double)gx / gl, nY = (double)gy / gl;
+  const double xc = i + 0.5, yc = j + 0.5;
+  double S0 = 0.0, S1 = 0.0, S2 = 0.0, S3 = 0.0, S4 = 0.0, T0 = 0.0, T1 = 0.0, T2 = 0.0;
+  auto add = [&](double px, double py) {
+    const double dx = px - xc, dy = py - yc;
+    const double X = dx * (-nY) + dy * nX;
+    const double Y = dx * nX + dy * nY;
+    const double X2 = X * X;
+    S0 += 1.0;
+    S1 += X;
+    S2 += X2;
+    S3 += X2 * X;
+    S4 += X2 * X2;
+    T0 += Y;
+    T1 += X * Y;
+    T2 += X2 * Y;
+  };
+  // rare path (cells where no height is valid): kept rolled so that it does
+  // not raise the register budget of the whole fraction pass
+#pragma unroll 1
+  for (int y = j - 2; y <= j + 3; y++)
+#pragma unroll 1
+    for (int x = i - 2; x <= i + 2; x++) {
+      if (x < 0 || x >= P.nx || y < 0 || y > P.ny) continue;
+      if (node(x, y) == node(x + 1, y)) continue;
+      add(x + P.hoff[(size_t)y * P.nx + x], (double)y);
+    }
+#pragma unroll 1
+  for (int y = j - 2; y <= j + 2; y++)
+#pragma unroll 1
+    for (int x = i - 2; x <= i + 3; x++) {
+      if (x < 0 || x > P.nx || y < 0 || y >= P.ny) continue;
+      if (node(x, y) == node(x, y + 1)) continue;
+      add((double)x, y + P.voff[(size_t)y * (P.nx + 1) + x]);
+    }
+  if (S0 < 3.0) return false;
+  const double det = S0 * (S2 * S4 - S3 * S3) - S1 * (S1 * S4 - S3 * S2) + S2 * (S1 * S3 - S2 * S2);
+  if (!(det > 1e-10 * (S0 * S2 * S4))) return false;
+  const double db = S0 * (T1 * S4 - S3 * T2) - T0 * (S1 * S4 - S3 * S2) + S2 * (S1 * T2 - T1 * S2);
+  const double dc = S0 * (S2 * T2 - T1 * S3) - S1 * (S1 * T2 - T1 * S2) + T0 * (S1 * S3 - S2 * S2);
+  const double b = db / det, cc = dc / det;
+  const double g = 1.0 + b * b;
+  *kap = (2.0 * cc) / (h * g * sqrt(g));
+  return true;
+}
+
 // Fraction and/or curvature of every grid in one launch. Workgroups
 // [0, nearBlocks) take the near tiles of the list (static stride): node
 // colours of the tile plus halo in LDS; C, marker count and BL colour of every
@@ -1233,9 +1287,9 @@ __global__ __launch_bounds__(256) void k_frac_curv(FracArgs A, const Inst *__res
   __shared__ double sC[W][W];
   __shared__ uint8_t sN[W][W];
   __shared__ uint8_t sB[W][W];
-  __shared__ uint32_t sCnt[2];
-  if (tid < 2) sCnt[tid] = 0;
-  uint32_t interf = 0, hffail = 0;
+  __shared__ uint32_t sCnt[3];
+  if (tid < 3) sCnt[tid] = 0;
+  uint32_t interf = 0, hffail = 0, ghf = 0;
   const uint32_t ntile = *A.count;
   uint32_t ntiles_done = 0;
   // node colours of the tile plus halo: three slots per thread, fetched for
@@ -1332,8 +1386,10 @@ __global__ __launch_bounds__(256) void k_frac_curv(FracArgs A, const Inst *__res
           auto getB = [&](int a, int b) -> int { return sB[b - y0 + 3][a - x0 + 3]; };
           if (!hfTry(i, j, firstRows, I.h, getC, getN, getB, &kap) &&
               !hfTry(i, j, 1 - firstRows, I.h, getC, getN, getB, &kap)) {
-            kap = __builtin_nan("");
             hffail++;
+            auto node = [&](int a, int b) -> int { return sNode[b - y0 + 3][a - x0 + 3]; };
+            if (ghfFit(P, I.h, i, j, ncx, ncy, node, &kap)) ghf++;
+            else kap = __builtin_nan("");
           }
         }
         A.Kout[I.koff + id] = kap;
@@ -1343,10 +1399,12 @@ __global__ __launch_bounds__(256) void k_frac_curv(FracArgs A, const Inst *__res
   if (MODE & 2) {
     if (interf) atomicAdd(&sCnt[0], interf);
     if (hffail) atomicAdd(&sCnt[1], hffail);
+    if (ghf) atomicAdd(&sCnt[2], ghf);
     __syncthreads();
     if (tid == 0) {
       if (sCnt[0]) atomicAdd(&A.ctr[C_INTERFACIAL], (unsigned long long)sCnt[0]);
       if (sCnt[1]) atomicAdd(&A.ctr[C_HF_FAIL], (unsigned long long)sCnt[1]);
+      if (sCnt[2]) atomicAdd(&A.ctr[C_GHF_FIT], (unsigned long long)sCnt[2]);
       if (ntiles_done) atomicAdd(&A.ctr[C_TILES_NEAR], (unsigned long long)ntiles_done);
     }
   }

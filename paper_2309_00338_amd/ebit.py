@@ -24,7 +24,7 @@ EBIT_SWEEP_ALTERNATE, EBIT_SWEEP_XY, EBIT_FIT_LINE = 0, 1, 2
 COUNTERS = (
     "markers", "annihilated", "three_landers", "ties", "fit_fallback", "fit_reject",
     "parity_fallback", "three_crossings", "cv_set", "cv_conflict", "cv_unresolved",
-    "wall_violation", "invariant_fail", "hf_fail", "interfacial",
+    "wall_violation", "invariant_fail", "hf_fail", "interfacial", "ghf_fit",
     "tiles_swept", "tiles_empty", "tiles_near",
 )
 # counters that describe the GPU schedule and have no oracle counterpart

@@ -603,3 +603,59 @@ def test_csf_face_curvature_selection():
     K3[j, 10], K3[j, 11] = 1.0, 3.0
     _, _, fx3, _ = oracle.ns_fields(st, C3, K3, 1, 1, 1, 1, 1.0)
     assert fx3[j, 11] == pytest.approx((0.6 - 0.3) / h * 2.0, rel=1e-15)  # mean of both
+
+
+# ---------------------------------------------------------------------------
+# curvature fallback (Sec. 2.5: generalised height function) where no height
+# is valid: least-squares parabola through the markers in the normal frame
+# ---------------------------------------------------------------------------
+def test_parabola_fit_is_exact_on_a_parabola_in_any_frame():
+    rng = np.random.Generator(np.random.PCG64(77))
+    for gx, gy in ((0, -3), (2, 2), (-1, 4), (5, -2)):
+        nrm = np.array([gx, gy], float) / np.hypot(gx, gy)
+        tan = np.array([-nrm[1], nrm[0]])
+        a, b, c = 0.1, 0.3, 0.2
+        X = rng.uniform(-2.5, 2.5, 9)
+        Y = a + b * X + c * X * X
+        P = np.outer(X, tan) + np.outer(Y, nrm) + np.array([4.5, 7.5])
+        k = oracle.parabola_fit(P[:, 0], P[:, 1], 4.5, 7.5, gx, gy, 0.01)
+        assert k == pytest.approx(2 * c / (1 + b * b) ** 1.5 / 0.01, rel=1e-11)
+
+
+def test_parabola_fit_equals_numpy_least_squares():
+    rng = np.random.Generator(np.random.PCG64(78))
+    for _ in range(20):
+        n = int(rng.integers(3, 30))
+        X = rng.uniform(-2.5, 2.5, n)
+        Y = rng.normal(0, 0.5, n)
+        gx, gy = 0, 1  # frame = grid axes: X along -x, Y along +y
+        k = oracle.parabola_fit(-X + 1.5, Y + 2.5, 1.5, 2.5, gx, gy, 1.0)
+        c2, c1, c0 = np.polyfit(X, Y, 2)
+        assert k == pytest.approx(2 * c2 / (1 + c1 * c1) ** 1.5, rel=1e-9, abs=1e-12)
+
+
+def test_parabola_fit_rejects_too_few_points_and_zero_normal():
+    assert oracle.parabola_fit([1.0, 2.0], [1.0, 1.5], 1.5, 1.2, 0, 1, 1.0) is None
+    assert oracle.parabola_fit([1.0, 2.0, 3.0], [1.0, 1.5, 1.2], 1.5, 1.2, 0, 0, 1.0) is None
+    assert oracle.parabola_fit([1.0, 1.0, 1.0], [1.0, 1.5, 1.2], 0.5, 1.2, 0, 1, 1.0) is None  # one abscissa
+
+
+@pytest.mark.parametrize("R", [4.1, 5.5, 7.0, 9.0, 14.0])
+def test_curvature_fallback_leaves_no_nan_on_small_circles(R):
+    """Every cell where both height orientations fail gets the parabola's
+    curvature; on circles of 4-14 cells all interfacial cells are within the
+    chord bias of 1/R (reading R12 bounds the heights' bias at ~13 %)."""
+    n = 64
+    fails = 0
+    for k in range(4):
+        st = I.init_state(n, n, [I.Circle(31.3 + 0.17 * k, 32.7 - 0.11 * k, R)])
+        C = oracle.fraction(st)
+        K, cnt = oracle.curvature(st, C)
+        d = oracle.counters_dict(cnt)
+        assert d["ghf_fit"] == d["hf_fail"]
+        fails += d["hf_fail"]
+        assert not np.isnan(K).any()
+        fin = K != 0
+        err = np.abs(K[fin] * st.h * R - 1.0)
+        assert err.max() < 0.2 and np.median(err) < 0.12, (R, err.max(), np.median(err))
+    assert fails > 0
