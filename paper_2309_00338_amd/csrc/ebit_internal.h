@@ -201,7 +201,9 @@ __host__ __device__ inline int sweep_dir(const Inst &I, uint32_t stepNo, int pha
 int resident_blocks(int which);
 // one: the engine holds a single grid (index 0)
 hipError_t launch_sweep(int dir, bool one, const SweepArgs &a, int grid, hipStream_t s);
-hipError_t launch_fit(int dir, bool one, const SweepArgs &a, int grid, hipStream_t s);
+// c: the compaction that follows the sweep, run by extra workgroups of the
+// fit launch (null: fits only)
+hipError_t launch_fit(int dir, bool one, const SweepArgs &a, int grid, const CompactArgs *c, hipStream_t s);
 hipError_t launch_centre(int dir, bool one, const SweepArgs &a, int grid, hipStream_t s);
 hipError_t launch_init_tiles(const Inst *inst, uint32_t kinst, uint32_t ntiles, uint32_t cur, uint32_t *tileInst,
                              uint16_t *has, uint8_t *nearPrev, hipStream_t s);

@@ -472,13 +472,14 @@ __device__ __forceinline__ uint32_t uni(uint32_t x) { return __builtin_amdgcn_re
 
 // ONE: the engine holds a single grid, whose descriptor comes with the kernel
 // arguments (loop-invariant, no descriptor loads per tile).
+constexpr int SWEEP_BS = 256;
+constexpr int STAGE_SLOTS = 2;  // halo nodes / cells staged per thread
+
 template <int DIR, bool ONE>
-__global__ __launch_bounds__(256, 8) void k_sweep(SweepArgs A, const Inst *__restrict__ inst) {
+__global__ __launch_bounds__(SWEEP_BS, 8) void k_sweep(SweepArgs A, const Inst *__restrict__ inst) {
   __shared__ uint8_t sCol[NH][NH];
   __shared__ uint8_t sCen[NE][NE];
   __shared__ double sSp[NH][NE];
-  __shared__ double sD[NE][NH];
-  __shared__ double sT[NE][NH];
   __shared__ uint32_t sRow[NH];     // old colours, bit la of frame row lb
   __shared__ uint32_t sNRow[NN];    // new colours, bit a-a0 of row b-b0
   __shared__ uint32_t sRecv[NN];    // new aligned edges (a,b) that receive a lander, bit a-a0
@@ -507,8 +508,10 @@ __global__ __launch_bounds__(256, 8) void k_sweep(SweepArgs A, const Inst *__res
   // Staging of colours and centre colours: each thread owns two node slots
   // and two cell slots of the halo (memory order). The next tile's bytes are
   // fetched into registers while the current tile computes.
-  static_assert(NH * NH <= 512 && NE * NE <= 512, "two staging slots per thread");
-  uint8_t pc0 = 0, pc1 = 0, pe0 = 0, pe1 = 0;
+  static_assert(NH * NH <= STAGE_SLOTS * SWEEP_BS && NE * NE <= STAGE_SLOTS * SWEEP_BS, "staging slots per thread");
+  uint8_t pc[STAGE_SLOTS], pe[STAGE_SLOTS];
+#pragma unroll
+  for (int q = 0; q < STAGE_SLOTS; q++) pc[q] = pe[q] = 0;
   auto prefetch = [&](uint2 te) {
     const uint32_t gt = te.x;
     int nx, ny, ntx;
@@ -534,10 +537,11 @@ __global__ __launch_bounds__(256, 8) void k_sweep(SweepArgs A, const Inst *__res
       const int x = px0 - HALO + k % NE, y = py0 - HALO + k / NE;
       return (x >= 0 && y >= 0 && x < nx && y < ny) ? cen[(size_t)y * nx + x] : (uint8_t)0;
     };
-    pc0 = node(tid);
-    pc1 = node(tid + 256);
-    pe0 = cell(tid);
-    pe1 = cell(tid + 256);
+#pragma unroll
+    for (int q = 0; q < STAGE_SLOTS; q++) {
+      pc[q] = node(tid + SWEEP_BS * q);
+      pe[q] = cell(tid + SWEEP_BS * q);
+    }
   };
 
   const uint32_t ntile = *A.count;
@@ -600,8 +604,8 @@ __global__ __launch_bounds__(256, 8) void k_sweep(SweepArgs A, const Inst *__res
     T.col = sCol;
     T.cen = sCen;
     T.sp = sSp;
-    T.dd = sD;
-    T.tt = sT;
+    T.dd = nullptr;  // displacements and old unaligned offsets are not staged:
+    T.tt = nullptr;  // the fit kernel reads them from the scratch and the state
     T.nrow = sNRow;
     T.a0 = a0;
     T.b0 = b0;
@@ -625,10 +629,11 @@ __global__ __launch_bounds__(256, 8) void k_sweep(SweepArgs A, const Inst *__res
         if (DIR == 0) sCen[hy][hx] = c;
         else sCen[hx][hy] = c;
       };
-      putNode(tid, pc0);
-      putNode(tid + 256, pc1);
-      putCell(tid, pe0);
-      putCell(tid + 256, pe1);
+#pragma unroll
+      for (int q = 0; q < STAGE_SLOTS; q++) {
+        putNode(tid + SWEEP_BS * q, pc[q]);
+        putCell(tid + SWEEP_BS * q, pe[q]);
+      }
     }
     // colour-1 nodes set their bit in the frame-row masks (zero since the
     // previous tile)
@@ -639,8 +644,8 @@ __global__ __launch_bounds__(256, 8) void k_sweep(SweepArgs A, const Inst *__res
         const int la = DIR == 0 ? hx : hy, lb = DIR == 0 ? hy : hx;
         atomicOr(&sRow[lb], 1u << la);
       };
-      bitNode(tid, pc0);
-      bitNode(tid + 256, pc1);
+#pragma unroll
+      for (int q = 0; q < STAGE_SLOTS; q++) bitNode(tid + SWEEP_BS * q, pc[q]);
     }
     __syncthreads();
     // --- list the present halo edges -----------------------------------------
@@ -742,11 +747,11 @@ __global__ __launch_bounds__(256, 8) void k_sweep(SweepArgs A, const Inst *__res
         const double ub = t < 0.5 ? lerp(v0, v1, t + 0.5) : lerp(v1, v2, t - 0.5);
         const double d = ub * lam;
         const bool wall = a == 0 || a == na;
-        sT[lb][la] = t;
-        sD[lb][la] = wall ? 0.0 : d;
         const bool own = la >= HALO && (la < HALO + TS || a == na) && lb >= HALO && lb < HALO + TS;
         if (own) {
           ddg[G.une(a, b)] = wall ? 0.0 : d;
+          // walls hold their markers (wall nodes never change colour)
+          if (wall) unn[G.une(a, b)] = t;
           cnt.add(C_MARKERS, 1u);
           if (fabs(d) > 0.5) atomicOr(errg, ERRBIT_CFL);
           if (wall && d != 0.0) cnt.add(C_WALL_VIOLATION, 1u);
@@ -808,11 +813,8 @@ __global__ __launch_bounds__(256, 8) void k_sweep(SweepArgs A, const Inst *__res
           const int a = a0 + i;
           const bool own = i < TS || a == na;
           if (a == 0 || a == na) {
-            // walls hold their markers (wall nodes never change colour)
-            if (own) {
-              unn[G.une(a, b)] = T.tU(a, b);
-              hasm |= DIR == 0 ? maskV(a, b, x0, y0) : maskH(b, a, x0, y0);
-            }
+            // a wall marker (its offset was copied while advecting)
+            if (own) hasm |= DIR == 0 ? maskV(a, b, x0, y0) : maskH(b, a, x0, y0);
           } else if (own) {
             // interior line owned by this tile: one fit job
             sJob[atomicAdd(&sNJob, 1u)] = make_uint2(kinst, (uint32_t)G.une(a, b));
@@ -875,16 +877,118 @@ __device__ __forceinline__ void fitJob(const SweepView &W, uint32_t e, const Cou
   gp(W.zr)[e] = (uint8_t)((rR + 1) | ((rL + 1) << 2));
 }
 
+__device__ __forceinline__ bool nearOf(const uint16_t *__restrict__ has, int tx, int ty, int ntx, int nty) {
+  auto H = [&](int x, int y) -> uint32_t {
+    return (x < 0 || y < 0 || x >= ntx || y >= nty) ? 0u : (uint32_t)has[y * ntx + x];
+  };
+  return (H(tx, ty) & M_ANY) || (H(tx - 1, ty) & M_R) || (H(tx + 1, ty) & M_L) || (H(tx, ty - 1) & M_T) ||
+         (H(tx, ty + 1) & M_B) || (H(tx - 1, ty - 1) & M_RT) || (H(tx + 1, ty - 1) & M_LT) ||
+         (H(tx - 1, ty + 1) & M_RB) || (H(tx + 1, ty + 1) & M_LB);
+}
+
+constexpr int CPT = 4;  // tiles per thread in the compaction
+
+// nearPrev bits: 0 near at the latest compaction, 1 near at the one before.
+// After a sweep the latest becomes the one before; a compaction without a
+// sweep in between (grids added or removed) keeps it. Active tiles of grids
+// whose next sweep runs along x go to the front of the active list, the others
+// to its back.
+template <bool ONE>
+__device__ void compactBlock(const CompactArgs &C, uint32_t blk) {
+  __shared__ uint32_t sA[256], sB[256], sN[256];
+  __shared__ uint32_t sBaseA, sBaseB, sBaseN;
+  const int tid = threadIdx.x;
+  if (blk == 0 && tid == 0) {
+    // the other slot's list counts start the next compaction from zero, and
+    // this slot's job counts the next sweep (the fits and centre colours of the
+    // sweep before still read the other slot's job counts)
+    uint32_t *other = C.counts + NSLOT * (C.slot ^ 1), *mine = C.counts + NSLOT * C.slot;
+    other[CNT_ACT_X] = 0;
+    other[CNT_ACT_Y] = 0;
+    other[CNT_NEAR] = 0;
+    mine[CNT_JOBS_X] = 0;
+    mine[CNT_JOBS_Y] = 0;
+  }
+  const uint32_t base = (blk * blockDim.x + tid) * CPT;
+  uint32_t actBits = 0, dirBits = 0, nearBits = 0;
+  uint32_t kq[CPT];
+  for (int q = 0; q < CPT; q++) {
+    const uint32_t t = base + q;
+    kq[q] = 0;
+    if (t >= C.ntiles) break;
+    const uint32_t k = ONE ? 0u : C.tileInst[t];
+    kq[q] = k;
+    if (k == NO_INST) continue;
+    const Inst &I = ONE ? C.one : C.inst[k];
+    const uint32_t lt = t - I.tile0;
+    const int tx = (int)(lt % (uint32_t)I.ntx), ty = (int)(lt / (uint32_t)I.ntx);
+    const bool nr = nearOf(C.has + I.tile0, tx, ty, I.ntx, I.nty);
+    const uint32_t pv = C.nearPrev[t];
+    const uint32_t prev = C.afterSweep ? (pv & 1u) : ((pv >> 1) & 1u);
+    const bool act = nr || prev;
+    C.nearPrev[t] = (uint8_t)((nr ? 1u : 0u) | (prev << 1));
+    C.tinfo[t] = (uint8_t)((nr ? TI_NEAR : 0) |
+                           (gp(I.col[C.cur])[(size_t)(ty * TS) * (I.nx + 1) + tx * TS] ? TI_COLOUR : 0));
+    actBits |= (uint32_t)act << q;
+    dirBits |= (uint32_t)(act && sweep_dir(I, C.stepNo, C.phase) == 1) << q;
+    nearBits |= (uint32_t)nr << q;
+  }
+  // exclusive block scan of the per-thread counts
+  const uint32_t cb = __popc(dirBits), ca = __popc(actBits) - cb, cn = __popc(nearBits);
+  sA[tid] = ca;
+  sB[tid] = cb;
+  sN[tid] = cn;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const uint32_t xa = tid >= off ? sA[tid - off] : 0, xb = tid >= off ? sB[tid - off] : 0,
+                   xn = tid >= off ? sN[tid - off] : 0;
+    __syncthreads();
+    sA[tid] += xa;
+    sB[tid] += xb;
+    sN[tid] += xn;
+    __syncthreads();
+  }
+  uint32_t *cs = C.counts + NSLOT * C.slot;
+  if (tid == 255) {
+    sBaseA = sA[255] ? atomicAdd(&cs[CNT_ACT_X], sA[255]) : 0;
+    sBaseB = sB[255] ? atomicAdd(&cs[CNT_ACT_Y], sB[255]) : 0;
+    sBaseN = sN[255] ? atomicAdd(&cs[CNT_NEAR], sN[255]) : 0;
+  }
+  __syncthreads();
+  uint32_t pa = sBaseA + sA[tid] - ca, pb = sBaseB + sB[tid] - cb, pn = sBaseN + sN[tid] - cn;
+  for (int q = 0; q < CPT; q++) {
+    if (actBits >> q & 1) {
+      if (dirBits >> q & 1) C.actList[C.ntiles - 1u - pb++] = make_uint2(base + q, kq[q]);
+      else C.actList[pa++] = make_uint2(base + q, kq[q]);
+    }
+    if (nearBits >> q & 1) C.nearList[pn++] = make_uint2(base + q, kq[q]);
+  }
+}
+
+template <bool ONE>
+__global__ __launch_bounds__(256) void k_compact(CompactArgs C) {
+  compactBlock<ONE>(C, blockIdx.x);
+}
+
+// The same launch also runs the compaction of the state this sweep produced
+// (it reads only what the sweep wrote): workgroups [0, compactBlocks) compact,
+// the others fit, so the compaction's latency hides under the fits.
 template <int DIR, bool ONE>
-__global__ __launch_bounds__(256) void k_fit(SweepArgs A, const Inst *__restrict__ inst) {
+__global__ __launch_bounds__(256) void k_fit(SweepArgs A, const Inst *__restrict__ inst, CompactArgs C,
+                                             uint32_t compactBlocks) {
+  if (blockIdx.x < compactBlocks) {
+    compactBlock<ONE>(C, blockIdx.x);
+    return;
+  }
   __shared__ uint32_t sCnt[NCOUNTERS];
   const int tid = threadIdx.x;
   if (tid < NCOUNTERS) sCnt[tid] = 0;
   __syncthreads();
   const Counts cnt{sCnt};
   const uint32_t nj = *A.njobs;
-  const uint32_t stride = gridDim.x * blockDim.x;
-  for (uint32_t w0 = blockIdx.x * blockDim.x; w0 < nj; w0 += stride) {
+  const uint32_t fb = blockIdx.x - compactBlocks;
+  const uint32_t stride = (gridDim.x - compactBlocks) * blockDim.x;
+  for (uint32_t w0 = fb * blockDim.x; w0 < nj; w0 += stride) {
     const uint32_t w = w0 + tid;
     const uint2 jb = w < nj ? A.jobs[DIR == 0 ? w : A.jobCap - 1u - w] : make_uint2(NO_INST, 0u);
     if (ONE) {
@@ -1009,87 +1113,6 @@ __global__ void k_clear_tiles(uint32_t *tileInst, uint16_t *has, uint8_t *nearPr
   has[tile0 + t] = 0;
   nearPrev[tile0 + t] = 0;
   tinfo[tile0 + t] = TI_DEAD;
-}
-
-__device__ __forceinline__ bool nearOf(const uint16_t *__restrict__ has, int tx, int ty, int ntx, int nty) {
-  auto H = [&](int x, int y) -> uint32_t {
-    return (x < 0 || y < 0 || x >= ntx || y >= nty) ? 0u : (uint32_t)has[y * ntx + x];
-  };
-  return (H(tx, ty) & M_ANY) || (H(tx - 1, ty) & M_R) || (H(tx + 1, ty) & M_L) || (H(tx, ty - 1) & M_T) ||
-         (H(tx, ty + 1) & M_B) || (H(tx - 1, ty - 1) & M_RT) || (H(tx + 1, ty - 1) & M_LT) ||
-         (H(tx - 1, ty + 1) & M_RB) || (H(tx + 1, ty + 1) & M_LB);
-}
-
-constexpr int CPT = 4;  // tiles per thread in the compaction
-
-// nearPrev bits: 0 near at the latest compaction, 1 near at the one before.
-// After a sweep the latest becomes the one before; a compaction without a
-// sweep in between (grids added or removed) keeps it. Active tiles of grids
-// whose next sweep runs along x go to the front of the active list, the others
-// to its back.
-template <bool ONE>
-__global__ __launch_bounds__(256) void k_compact(CompactArgs C) {
-  __shared__ uint32_t sA[256], sB[256], sN[256];
-  __shared__ uint32_t sBaseA, sBaseB, sBaseN;
-  const int tid = threadIdx.x;
-  if (blockIdx.x == 0 && tid < NSLOT) {
-    // clear the other slot for the next compaction; nothing reads it now
-    C.counts[NSLOT * (C.slot ^ 1) + tid] = 0;
-  }
-  const uint32_t base = (blockIdx.x * blockDim.x + tid) * CPT;
-  uint32_t actBits = 0, dirBits = 0, nearBits = 0;
-  uint32_t kq[CPT];
-  for (int q = 0; q < CPT; q++) {
-    const uint32_t t = base + q;
-    kq[q] = 0;
-    if (t >= C.ntiles) break;
-    const uint32_t k = ONE ? 0u : C.tileInst[t];
-    kq[q] = k;
-    if (k == NO_INST) continue;
-    const Inst &I = ONE ? C.one : C.inst[k];
-    const uint32_t lt = t - I.tile0;
-    const int tx = (int)(lt % (uint32_t)I.ntx), ty = (int)(lt / (uint32_t)I.ntx);
-    const bool nr = nearOf(C.has + I.tile0, tx, ty, I.ntx, I.nty);
-    const uint32_t pv = C.nearPrev[t];
-    const uint32_t prev = C.afterSweep ? (pv & 1u) : ((pv >> 1) & 1u);
-    const bool act = nr || prev;
-    C.nearPrev[t] = (uint8_t)((nr ? 1u : 0u) | (prev << 1));
-    C.tinfo[t] = (uint8_t)((nr ? TI_NEAR : 0) |
-                           (gp(I.col[C.cur])[(size_t)(ty * TS) * (I.nx + 1) + tx * TS] ? TI_COLOUR : 0));
-    actBits |= (uint32_t)act << q;
-    dirBits |= (uint32_t)(act && sweep_dir(I, C.stepNo, C.phase) == 1) << q;
-    nearBits |= (uint32_t)nr << q;
-  }
-  // exclusive block scan of the per-thread counts
-  const uint32_t cb = __popc(dirBits), ca = __popc(actBits) - cb, cn = __popc(nearBits);
-  sA[tid] = ca;
-  sB[tid] = cb;
-  sN[tid] = cn;
-  __syncthreads();
-  for (int off = 1; off < 256; off <<= 1) {
-    const uint32_t xa = tid >= off ? sA[tid - off] : 0, xb = tid >= off ? sB[tid - off] : 0,
-                   xn = tid >= off ? sN[tid - off] : 0;
-    __syncthreads();
-    sA[tid] += xa;
-    sB[tid] += xb;
-    sN[tid] += xn;
-    __syncthreads();
-  }
-  uint32_t *cs = C.counts + NSLOT * C.slot;
-  if (tid == 255) {
-    sBaseA = sA[255] ? atomicAdd(&cs[CNT_ACT_X], sA[255]) : 0;
-    sBaseB = sB[255] ? atomicAdd(&cs[CNT_ACT_Y], sB[255]) : 0;
-    sBaseN = sN[255] ? atomicAdd(&cs[CNT_NEAR], sN[255]) : 0;
-  }
-  __syncthreads();
-  uint32_t pa = sBaseA + sA[tid] - ca, pb = sBaseB + sB[tid] - cb, pn = sBaseN + sN[tid] - cn;
-  for (int q = 0; q < CPT; q++) {
-    if (actBits >> q & 1) {
-      if (dirBits >> q & 1) C.actList[C.ntiles - 1u - pb++] = make_uint2(base + q, kq[q]);
-      else C.actList[pa++] = make_uint2(base + q, kq[q]);
-    }
-    if (nearBits >> q & 1) C.nearList[pn++] = make_uint2(base + q, kq[q]);
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1535,8 +1558,8 @@ int resident_blocks(int which) {
   int n = 0;
   hipError_t e = hipErrorInvalidValue;
   switch (which) {
-    case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_sweep<0, true>, 256, 0); break;
-    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fit<0, false>, 256, 0); break;
+    case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_sweep<0, true>, SWEEP_BS, 0); break;
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fit<0, false>, 256, 0); break;  // fits only
     case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_centre<0, false>, 256, 0); break;
     case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_frac_curv<1, false>, 256, 0); break;
     case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_frac_curv<2, false>, 256, 0); break;
@@ -1553,22 +1576,31 @@ int resident_blocks(int which) {
 
 hipError_t launch_sweep(int dir, bool one, const SweepArgs &a, int grid, hipStream_t s) {
   if (dir == 0) {
-    if (one) EBIT_LAUNCH((k_sweep<0, true>), grid, s, a, a.inst);
-    else EBIT_LAUNCH((k_sweep<0, false>), grid, s, a, a.inst);
+    if (one) hipLaunchKernelGGL((k_sweep<0, true>), dim3(grid), dim3(SWEEP_BS), 0, s, a, a.inst);
+    else hipLaunchKernelGGL((k_sweep<0, false>), dim3(grid), dim3(SWEEP_BS), 0, s, a, a.inst);
   } else {
-    if (one) EBIT_LAUNCH((k_sweep<1, true>), grid, s, a, a.inst);
-    else EBIT_LAUNCH((k_sweep<1, false>), grid, s, a, a.inst);
+    if (one) hipLaunchKernelGGL((k_sweep<1, true>), dim3(grid), dim3(SWEEP_BS), 0, s, a, a.inst);
+    else hipLaunchKernelGGL((k_sweep<1, false>), dim3(grid), dim3(SWEEP_BS), 0, s, a, a.inst);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_fit(int dir, bool one, const SweepArgs &a, int grid, hipStream_t s) {
+uint32_t compact_blocks(uint32_t ntiles) {
+  const uint32_t per = 256 * CPT;
+  return ntiles ? (ntiles + per - 1) / per : 1;
+}
+
+hipError_t launch_fit(int dir, bool one, const SweepArgs &a, int grid, const CompactArgs *c, hipStream_t s) {
+  CompactArgs none{};
+  const uint32_t cb = c ? compact_blocks(c->ntiles) : 0u;
+  const CompactArgs &ca = c ? *c : none;
+  const int g = grid + (int)cb;
   if (dir == 0) {
-    if (one) EBIT_LAUNCH((k_fit<0, true>), grid, s, a, a.inst);
-    else EBIT_LAUNCH((k_fit<0, false>), grid, s, a, a.inst);
+    if (one) EBIT_LAUNCH((k_fit<0, true>), g, s, a, a.inst, ca, cb);
+    else EBIT_LAUNCH((k_fit<0, false>), g, s, a, a.inst, ca, cb);
   } else {
-    if (one) EBIT_LAUNCH((k_fit<1, true>), grid, s, a, a.inst);
-    else EBIT_LAUNCH((k_fit<1, false>), grid, s, a, a.inst);
+    if (one) EBIT_LAUNCH((k_fit<1, true>), g, s, a, a.inst, ca, cb);
+    else EBIT_LAUNCH((k_fit<1, false>), g, s, a, a.inst, ca, cb);
   }
   return hipGetLastError();
 }
@@ -1600,8 +1632,7 @@ hipError_t launch_clear_tiles(uint32_t *tileInst, uint16_t *has, uint8_t *nearPr
 }
 
 hipError_t launch_compact(bool one, const CompactArgs &a, hipStream_t s) {
-  const uint32_t per = 256 * CPT;
-  const uint32_t blocks = a.ntiles ? (a.ntiles + per - 1) / per : 1;
+  const uint32_t blocks = compact_blocks(a.ntiles);
   if (one) EBIT_LAUNCH(k_compact<true>, blocks, s, a);
   else EBIT_LAUNCH(k_compact<false>, blocks, s, a);
   return hipGetLastError();

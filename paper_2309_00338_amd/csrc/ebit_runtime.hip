@@ -228,8 +228,7 @@ int engine_reset(Engine *e) {
   return EBIT_OK;
 }
 
-int engine_compact(Engine *e, int afterSweep, uint32_t nextStep, int nextPhase) {
-  e->slot ^= 1;
+CompactArgs compact_args(Engine *e, int afterSweep, uint32_t nextStep, int nextPhase) {
   CompactArgs a;
   a.inst = e->dinst;
   a.tileInst = e->tileInst;
@@ -246,6 +245,12 @@ int engine_compact(Engine *e, int afterSweep, uint32_t nextStep, int nextPhase) 
   a.nearList = e->nearList;
   a.counts = e->counts;
   a.one = e->hinst[0];
+  return a;
+}
+
+int engine_compact(Engine *e, int afterSweep, uint32_t nextStep, int nextPhase) {
+  e->slot ^= 1;
+  const CompactArgs a = compact_args(e, afterSweep, nextStep, nextPhase);
   HIPCHK(launch_compact(e->maxGrids == 1, a, e->stream));
   return EBIT_OK;
 }
@@ -294,6 +299,18 @@ int engine_sweep(Engine *e, int phase, const double *u, const double *v, const d
   a.jobCap = e->jobCap;
   a.ctr = e->ctr;
   uint32_t *cs = e->counts + NSLOT * e->slot;
+  const uint32_t nextStep = phase == 0 ? e->stepNo : e->stepNo + 1;
+  if (!dirs[0] && !dirs[1]) {
+    e->cur ^= 1u;
+    return engine_compact(e, 1, nextStep, phase == 0 ? 1 : 0);
+  }
+  // the compaction of the swept state rides with the last fit launch
+  const int last = dirs[1] ? 1 : 0;
+  e->cur ^= 1u;
+  e->slot ^= 1;
+  const CompactArgs c = compact_args(e, 1, nextStep, phase == 0 ? 1 : 0);
+  e->cur ^= 1u;
+  e->slot ^= 1;
   for (int d = 0; d < 2; d++) {
     if (!dirs[d]) continue;
     a.count = cs + (d == 0 ? CNT_ACT_X : CNT_ACT_Y);
@@ -301,12 +318,12 @@ int engine_sweep(Engine *e, int phase, const double *u, const double *v, const d
     // the single grid's view, resolved here (the kernels read it from their arguments)
     a.one = sweep_view(e->hinst[0], e->cur, d, u, v, dts ? 0.0 : dt / e->hinst[0].h);
     HIPCHK(launch_sweep(d, e->maxGrids == 1, a, e->sweepBlocks, e->stream));
-    HIPCHK(launch_fit(d, e->maxGrids == 1, a, e->fitBlocks, e->stream));
+    HIPCHK(launch_fit(d, e->maxGrids == 1, a, e->fitBlocks, d == last ? &c : nullptr, e->stream));
     HIPCHK(launch_centre(d, e->maxGrids == 1, a, e->centreBlocks, e->stream));
   }
   e->cur ^= 1u;
-  const uint32_t nextStep = phase == 0 ? e->stepNo : e->stepNo + 1;
-  return engine_compact(e, 1, nextStep, phase == 0 ? 1 : 0);
+  e->slot ^= 1;
+  return EBIT_OK;
 }
 
 int engine_advect(Engine *e, const double *u, const double *v, const double *dts, double dt) {
