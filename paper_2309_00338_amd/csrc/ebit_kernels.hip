@@ -648,13 +648,15 @@ __global__ __launch_bounds__(SWEEP_BS, 8) void k_sweep(SweepArgs A, const Inst *
       for (int q = 0; q < STAGE_SLOTS; q++) bitNode(tid + SWEEP_BS * q, pc[q]);
     }
     __syncthreads();
-    // --- list the present halo edges -----------------------------------------
-    // aligned (a,b): la in [0,20) with a in [0,na), b = b0-2+lb in [0,nb];
-    // unaligned (a,b): lb in [0,20) with b in [0,nb), la in [0,21) with a in [0,na]
+    // --- list the present edges -----------------------------------------------
+    // aligned (a,b), halo included (their advected offsets feed the landers):
+    // la in [0,20) with a in [0,na), b = b0-2+lb in [0,nb];
+    // unaligned (a,b), only those of this tile (nothing reads the others):
+    // lb in [2,18) with b < nb, la in [2,18) or the wall a = na
     const int laMinA = max(0, HALO - a0), laMaxA = min(NE - 1, na - 1 - a0 + HALO);
-    const int laMaxU = min(NH - 1, na - a0 + HALO);
+    const int laMaxU = min(HALO + TS - 1 + (na - a0 == TS ? 1 : 0), na - a0 + HALO);
     const uint32_t maskA = laMaxA >= laMinA ? ((2u << laMaxA) - 1u) & ~((1u << laMinA) - 1u) : 0u;
-    const uint32_t maskU = laMaxU >= laMinA ? ((2u << laMaxU) - 1u) & ~((1u << laMinA) - 1u) : 0u;
+    const uint32_t maskU = ((2u << laMaxU) - 1u) & ~((1u << HALO) - 1u);
     if (tid < NH) {
       const int lb = tid, b = b0 - HALO + lb;
       const uint32_t r = sRow[lb];
@@ -669,7 +671,7 @@ __global__ __launch_bounds__(SWEEP_BS, 8) void k_sweep(SweepArgs A, const Inst *
           }
         }
       }
-      if (lb < NE && b >= 0 && b < nb) {
+      if (lb >= HALO && lb < HALO + TS && b < nb) {
         uint32_t m = (r ^ sRow[lb + 1]) & maskU;
         if (m) {
           uint32_t w = atomicAdd(&sNAdv, (uint32_t)__popc(m));
@@ -747,15 +749,13 @@ __global__ __launch_bounds__(SWEEP_BS, 8) void k_sweep(SweepArgs A, const Inst *
         const double ub = t < 0.5 ? lerp(v0, v1, t + 0.5) : lerp(v1, v2, t - 0.5);
         const double d = ub * lam;
         const bool wall = a == 0 || a == na;
-        const bool own = la >= HALO && (la < HALO + TS || a == na) && lb >= HALO && lb < HALO + TS;
-        if (own) {
-          ddg[G.une(a, b)] = wall ? 0.0 : d;
-          // walls hold their markers (wall nodes never change colour)
-          if (wall) unn[G.une(a, b)] = t;
-          cnt.add(C_MARKERS, 1u);
-          if (fabs(d) > 0.5) atomicOr(errg, ERRBIT_CFL);
-          if (wall && d != 0.0) cnt.add(C_WALL_VIOLATION, 1u);
-        }
+        // every listed unaligned marker belongs to this tile
+        ddg[G.une(a, b)] = wall ? 0.0 : d;
+        // walls hold their markers (wall nodes never change colour)
+        if (wall) unn[G.une(a, b)] = t;
+        cnt.add(C_MARKERS, 1u);
+        if (fabs(d) > 0.5) atomicOr(errg, ERRBIT_CFL);
+        if (wall && d != 0.0) cnt.add(C_WALL_VIOLATION, 1u);
       }
     }
     // the next tile's colours are fetched while this one computes
