@@ -43,6 +43,14 @@ enum {
   NCOUNTERS
 };
 
+// Counters live in CTR_PARTS partitions of CTR_STRIDE 64-bit slots (one
+// 256-byte line each); a workgroup adds into partition blockIdx % CTR_PARTS,
+// so that the adds of thousands of workgroups do not queue on one line. The
+// host sums the partitions.
+constexpr int CTR_PARTS = 64;
+constexpr int CTR_STRIDE = 32;
+static_assert(NCOUNTERS <= CTR_STRIDE, "counters fit one partition");
+
 enum : uint32_t { ERRBIT_CFL = 1u, ERRBIT_DOMAIN = 2u };
 enum : uint32_t { INST_XY = 1u, INST_LINE = 2u };  // x then y every step; straight-line placement
 
@@ -158,6 +166,14 @@ struct CompactArgs {
   Inst one;                  // the descriptor itself when the engine holds one grid
 };
 
+// A wavefront's cells (64 consecutive cells of a near tile) whose heights
+// failed in both directions, left for the parabola fit of k_ghf: the tile,
+// grid * 4 + the wavefront's index in the tile, and one bit per cell.
+struct GhfEntry {
+  uint32_t tile, gridWave;
+  unsigned long long mask;
+};
+
 struct FracArgs {
   const Inst *inst;
   const uint32_t *tileInst;
@@ -170,6 +186,9 @@ struct FracArgs {
   const uint32_t *count;
   int nearBlocks;            // workgroups [0, nearBlocks) work the near tiles
   unsigned long long *ctr;
+  GhfEntry *ghf;             // cells left for the parabola fit (4 entries per tile at most)
+  uint32_t *ghfCount;        // entries of this launch (zero on entry)
+  uint32_t *ghfClear;        // the other launch parity's count, zeroed by this launch
   Inst one;                  // the descriptor itself when the engine holds one grid
 };
 
@@ -197,7 +216,8 @@ __host__ __device__ inline int sweep_dir(const Inst &I, uint32_t stepNo, int pha
 
 // launchers (defined with the kernels); resident_blocks(which): resident
 // workgroups per CU of 0 the sweep, 1 the fit, 2 the centre kernel, 3/4/5 the
-// fraction modes 1/2/3 (the y-direction kernels use the same resources)
+// fraction modes 1/2/3 (the y-direction kernels use the same resources; the
+// fraction workgroups are half the size of the others)
 int resident_blocks(int which);
 // one: the engine holds a single grid (index 0)
 hipError_t launch_sweep(int dir, bool one, const SweepArgs &a, int grid, hipStream_t s);
@@ -212,6 +232,9 @@ hipError_t launch_clear_tiles(uint32_t *tileInst, uint16_t *has, uint8_t *nearPr
 hipError_t launch_compact(bool one, const CompactArgs &a, hipStream_t s);
 hipError_t launch_frac_curv(int mode, bool one, const FracArgs &a, int grid, hipStream_t s);
 int frac_fill_blocks(uint32_t ntiles);
+int ns_fill_blocks(uint32_t ntiles);
+// the parabola fit of the cells a curvature launch left (same FracArgs)
+hipError_t launch_ghf(bool one, const FracArgs &a, int grid, hipStream_t s);
 hipError_t launch_ns(const NsArgs &a, int grid, hipStream_t s);
 
 }  // namespace ebit

@@ -332,6 +332,11 @@ __device__ __forceinline__ double chordY(double X2, double Y2, double X3, double
 }
 
 // Counters of one workgroup, in LDS (events are rare next to the work).
+// this workgroup's counter partition
+__device__ __forceinline__ unsigned long long *ctrPart(unsigned long long *ctr) {
+  return ctr + (blockIdx.x % (uint32_t)CTR_PARTS) * CTR_STRIDE;
+}
+
 struct Counts {
   uint32_t *s;
   __device__ void add(int k, uint32_t v) const {
@@ -837,7 +842,7 @@ __global__ __launch_bounds__(SWEEP_BS, 8) void k_sweep(SweepArgs A, const Inst *
   }
   __syncthreads();
   if (sNJob) flushJobs();
-  if (tid < NCOUNTERS && sCnt[tid]) atomicAdd(&A.ctr[tid], (unsigned long long)sCnt[tid]);
+  if (tid < NCOUNTERS && sCnt[tid]) atomicAdd(&ctrPart(A.ctr)[tid], (unsigned long long)sCnt[tid]);
 }
 
 // ---------------------------------------------------------------------------
@@ -998,7 +1003,7 @@ __global__ __launch_bounds__(256) void k_fit(SweepArgs A, const Inst *__restrict
     }
   }
   __syncthreads();
-  if (tid < NCOUNTERS && sCnt[tid]) atomicAdd(&A.ctr[tid], (unsigned long long)sCnt[tid]);
+  if (tid < NCOUNTERS && sCnt[tid]) atomicAdd(&ctrPart(A.ctr)[tid], (unsigned long long)sCnt[tid]);
 }
 
 // Centre kernel: rules (1)-(5) of Sec. 2.3 for the cells next to new
@@ -1062,7 +1067,7 @@ __global__ __launch_bounds__(256) void k_centre(SweepArgs A, const Inst *__restr
     }
   }
   __syncthreads();
-  if (tid < NCOUNTERS && sCnt[tid]) atomicAdd(&A.ctr[tid], (unsigned long long)sCnt[tid]);
+  if (tid < NCOUNTERS && sCnt[tid]) atomicAdd(&ctrPart(A.ctr)[tid], (unsigned long long)sCnt[tid]);
 }
 
 // ---------------------------------------------------------------------------
@@ -1214,23 +1219,42 @@ __device__ bool hfTry(int i, int j, int rows, double h, GetC getC, GetN getN, Ge
   return true;
 }
 
+// Integer node-colour gradient around cell (i,j) over the 4x4 nodes
+// i-1..i+2, j-1..j+2 (mirrored across walls); points into colour 1.
+template <class NodeAt>
+__device__ __forceinline__ void nodeGradient(int i, int j, int nx, int ny, NodeAt nodeAt, int *gx, int *gy) {
+  auto nodeC = [&](int a, int b) -> int { return nodeAt(mirrorNode(a, nx), mirrorNode(b, ny)); };
+  int ncx = 0, ncy = 0;
+  for (int m = j - 1; m <= j + 2; m++) ncx += nodeC(i + 2, m) + nodeC(i + 1, m) - nodeC(i, m) - nodeC(i - 1, m);
+  for (int l = i - 1; l <= i + 2; l++) ncy += nodeC(l, j + 2) + nodeC(l, j + 1) - nodeC(l, j) - nodeC(l, j - 1);
+  *gx = ncx;
+  *gy = ncy;
+}
+
 // Where no height is valid: the least-squares parabola through the markers on
 // the edges of the 5x5 cells around (i,j), in the frame of the node-colour
 // gradient (gx, gy) (pointing into colour 1); kappa = 2c / (1 + b^2)^(3/2) / h.
-// Points are summed H edges first (rows y, then x), then V edges.
-template <class GetN>
-__device__ bool ghfFit(const FracCtx &P, double h, int i, int j, int gx, int gy, GetN node, double *kap) {
+// Points are summed H edges first (rows y, then x), then V edges. node(x,y),
+// hoffAt(x,y) and voffAt(x,y) read the state at every window position, also
+// outside the grid or where no marker is (any value, NaN included): such an
+// edge contributes +0.0 to every sum through a select, which leaves each sum
+// bit-identical to skipping it (the sums start at +0.0 and so are never
+// -0.0), and the loop runs without branches.
+template <class GetN, class GetH, class GetV>
+__device__ bool ghfFit(int nx, int ny, double h, int i, int j, int gx, int gy, GetN node, GetH hoffAt, GetV voffAt,
+                       double *kap) {
   if (gx == 0 && gy == 0) return false;
   const double gl = sqrt((double)gx * (double)gx + (double)gy * (double)gy);
   const double nX = (double)gx / gl, nY = (double)gy / gl;
   const double xc = i + 0.5, yc = j + 0.5;
   double S0 = 0.0, S1 = 0.0, S2 = 0.0, S3 = 0.0, S4 = 0.0, T0 = 0.0, T1 = 0.0, T2 = 0.0;
-  auto add = [&](double px, double py) {
+  auto add = [&](bool on, double px, double py) {
     const double dx = px - xc, dy = py - yc;
-    const double X = dx * (-nY) + dy * nX;
-    const double Y = dx * nX + dy * nY;
+    const double Xp = dx * (-nY) + dy * nX;
+    const double Yp = dx * nX + dy * nY;
+    const double X = on ? Xp : 0.0, Y = on ? Yp : 0.0;
     const double X2 = X * X;
-    S0 += 1.0;
+    S0 += on ? 1.0 : 0.0;
     S1 += X;
     S2 += X2;
     S3 += X2 * X;
@@ -1239,23 +1263,21 @@ __device__ bool ghfFit(const FracCtx &P, double h, int i, int j, int gx, int gy,
     T1 += X * Y;
     T2 += X2 * Y;
   };
-  // rare path (cells where no height is valid): kept rolled so that it does
-  // not raise the register budget of the whole fraction pass
 #pragma unroll 1
-  for (int y = j - 2; y <= j + 3; y++)
-#pragma unroll 1
-    for (int x = i - 2; x <= i + 2; x++) {
-      if (x < 0 || x >= P.nx || y < 0 || y > P.ny) continue;
-      if (node(x, y) == node(x + 1, y)) continue;
-      add(x + P.hoff[(size_t)y * P.nx + x], (double)y);
+  for (int q = 0; q < 6; q++)
+#pragma unroll
+    for (int p = 0; p < 5; p++) {
+      const int x = i - 2 + p, y = j - 2 + q;
+      const bool on = x >= 0 && x < nx && y >= 0 && y <= ny && node(x, y) != node(x + 1, y);
+      add(on, x + hoffAt(x, y), (double)y);
     }
 #pragma unroll 1
-  for (int y = j - 2; y <= j + 2; y++)
-#pragma unroll 1
-    for (int x = i - 2; x <= i + 3; x++) {
-      if (x < 0 || x > P.nx || y < 0 || y >= P.ny) continue;
-      if (node(x, y) == node(x, y + 1)) continue;
-      add((double)x, y + P.voff[(size_t)y * (P.nx + 1) + x]);
+  for (int q = 0; q < 5; q++)
+#pragma unroll
+    for (int p = 0; p < 6; p++) {
+      const int x = i - 2 + p, y = j - 2 + q;
+      const bool on = x >= 0 && x <= nx && y >= 0 && y < ny && node(x, y) != node(x, y + 1);
+      add(on, (double)x, y + voffAt(x, y));
     }
   if (S0 < 3.0) return false;
   const double det = S0 * (S2 * S4 - S3 * S3) - S1 * (S1 * S4 - S3 * S2) + S2 * (S1 * S3 - S2 * S2);
@@ -1272,21 +1294,28 @@ __device__ bool ghfFit(const FracCtx &P, double h, int i, int j, int gx, int gy,
 // [0, nearBlocks) take the near tiles of the list (static stride): node
 // colours of the tile plus halo in LDS; C, marker count and BL colour of every
 // halo cell (mirrored across walls), polygons only where markers are; then C
-// and/or kappa of the tile's cells. Every later workgroup fills 16 consecutive
-// global tiles: cells of tiles that are neither near nor unowned get their
-// tile's colour as C and zero curvature, one 8-byte store per lane and row,
-// lanes along a grid row. MODE 1: C only; 2: kappa from the caller's C; 3: both.
-constexpr int FILL_TILES = 16;
+// and/or kappa of the tile's cells (two per thread). Cells whose heights fail
+// in both directions are handed to k_ghf (one entry per 64 cells that have
+// any), which keeps the rare parabola fit out of this kernel's register
+// budget. Workgroups are 128 threads: the near part is bound by the latency
+// of each tile's dependent rounds, and small workgroups keep 16 tiles in
+// flight per CU. Every later workgroup fills 8 consecutive global tiles:
+// cells of tiles that are neither near nor unowned get their tile's colour as
+// C and zero curvature, one 8-byte store per lane and row, lanes along a grid
+// row. MODE 1: C only; 2: kappa from the caller's C; 3: both.
+constexpr int FRAC_BS = 256;
+constexpr int FRAC_FILL_TILES = FRAC_BS / TS;
+constexpr int NS_FILL_TILES = 16;
 
 template <int MODE, bool ONE>
-__global__ __launch_bounds__(256) void k_frac_curv(FracArgs A, const Inst *__restrict__ inst,
-                                                   const uint32_t *__restrict__ tileInst) {
+__global__ __launch_bounds__(FRAC_BS, 8) void k_frac_curv(FracArgs A, const Inst *__restrict__ inst,
+                                                       const uint32_t *__restrict__ tileInst) {
   constexpr int W = TS + 6;  // halo cells per side
   constexpr int WN = W + 1;  // halo nodes per side
   const int tid = threadIdx.x;
   if ((int)blockIdx.x >= A.nearBlocks) {
     // --- dense fill ----------------------------------------------------------
-    const uint32_t t = (blockIdx.x - (uint32_t)A.nearBlocks) * FILL_TILES + (uint32_t)tid / TS;
+    const uint32_t t = (blockIdx.x - (uint32_t)A.nearBlocks) * FRAC_FILL_TILES + (uint32_t)tid / TS;
     if (t >= A.ntiles) return;
     const uint8_t ti = A.tinfo[t];
     if (ti & (TI_NEAR | TI_DEAD)) return;
@@ -1306,19 +1335,23 @@ __global__ __launch_bounds__(256) void k_frac_curv(FracArgs A, const Inst *__res
     }
     return;
   }
+  static_assert(TS * TS % FRAC_BS == 0 && FRAC_BS % 64 == 0, "whole cells per thread, whole wavefronts");
   __shared__ uint8_t sNode[WN][WN];
   __shared__ double sC[W][W];
   __shared__ uint8_t sN[W][W];
   __shared__ uint8_t sB[W][W];
-  __shared__ uint32_t sCnt[3];
-  if (tid < 3) sCnt[tid] = 0;
-  uint32_t interf = 0, hffail = 0, ghf = 0;
+  __shared__ uint32_t sCnt[2];
+  if (tid < 2) sCnt[tid] = 0;
+  if ((MODE & 2) && blockIdx.x == 0 && tid == 0) *A.ghfClear = 0u;  // the next curvature launch's count
+  uint32_t interf = 0, hffail = 0;
   const uint32_t ntile = *A.count;
   uint32_t ntiles_done = 0;
-  // node colours of the tile plus halo: three slots per thread, fetched for
-  // the next tile while this one computes
-  static_assert(WN * WN <= 3 * 256, "three node slots per thread");
-  uint8_t pn[3] = {0, 0, 0};
+  // node colours of the tile plus halo, NSLOT_N per thread, fetched for the
+  // next tile while this one computes
+  constexpr int NSLOT_N = (WN * WN + FRAC_BS - 1) / FRAC_BS;
+  uint8_t pn[NSLOT_N];
+#pragma unroll
+  for (int q = 0; q < NSLOT_N; q++) pn[q] = 0;
   auto entry = [&](uint32_t it) -> uint2 {
     const uint2 e = A.list[it];
     return make_uint2(uni(e.x), uni(e.y));
@@ -1330,8 +1363,8 @@ __global__ __launch_bounds__(256) void k_frac_curv(FracArgs A, const Inst *__res
     const int x0 = (int)(lt % (uint32_t)I.ntx) * TS, y0 = (int)(lt / (uint32_t)I.ntx) * TS;
     const GL uint8_t *col = gp(I.col[A.cur]);
 #pragma unroll
-    for (int q = 0; q < 3; q++) {
-      const int k = tid + 256 * q;
+    for (int q = 0; q < NSLOT_N; q++) {
+      const int k = tid + FRAC_BS * q;
       const int gx = x0 - 3 + k % WN, gy = y0 - 3 + k / WN;
       pn[q] = (k < WN * WN && gx >= 0 && gy >= 0 && gx <= nx && gy <= ny) ? col[(size_t)gy * (nx + 1) + gx] : 0;
     }
@@ -1348,8 +1381,8 @@ __global__ __launch_bounds__(256) void k_frac_curv(FracArgs A, const Inst *__res
     const int x0 = tx * TS, y0 = ty * TS;
     ntiles_done++;
 #pragma unroll
-    for (int q = 0; q < 3; q++) {
-      const int k = tid + 256 * q;
+    for (int q = 0; q < NSLOT_N; q++) {
+      const int k = tid + FRAC_BS * q;
       if (k < WN * WN) sNode[k / WN][k % WN] = pn[q];
     }
     __syncthreads();
@@ -1385,51 +1418,126 @@ __global__ __launch_bounds__(256) void k_frac_curv(FracArgs A, const Inst *__res
     // the next tile's colours are fetched while this one's heights run
     if (it + (uint32_t)A.nearBlocks < ntile) prefetch(entry(it + (uint32_t)A.nearBlocks));
     __syncthreads();
-    for (int k = tid; k < TS * TS; k += blockDim.x) {
+#pragma unroll 1
+    for (int r = 0; r < TS * TS / FRAC_BS; r++) {
+      const int k = tid + FRAC_BS * r;
       const int li = k % TS, lj = k / TS;
       const int i = x0 + li, j = y0 + lj;
-      if (i >= nx || j >= ny) continue;
+      const bool in = i < nx && j < ny;
       const size_t id = (size_t)j * nx + i;
-      if (MODE & 1) A.Cout[I.coff + id] = sC[lj + 3][li + 3];
+      if ((MODE & 1) && in) A.Cout[I.coff + id] = sC[lj + 3][li + 3];
       if (MODE & 2) {
-        double kap = 0.0;
-        if (sN[lj + 3][li + 3] >= 2) {
-          interf++;
-          auto nodeC = [&](int a, int b) -> int {
-            return sNode[mirrorNode(b, ny) - y0 + 3][mirrorNode(a, nx) - x0 + 3];
-          };
-          int ncx = 0, ncy = 0;
-          for (int m = j - 1; m <= j + 2; m++)
-            ncx += nodeC(i + 2, m) + nodeC(i + 1, m) - nodeC(i, m) - nodeC(i - 1, m);
-          for (int l = i - 1; l <= i + 2; l++)
-            ncy += nodeC(l, j + 2) + nodeC(l, j + 1) - nodeC(l, j) - nodeC(l, j - 1);
-          const int firstRows = abs(ncy) >= abs(ncx) ? 0 : 1;
-          auto getC = [&](int a, int b) -> double { return sC[b - y0 + 3][a - x0 + 3]; };
-          auto getN = [&](int a, int b) -> int { return sN[b - y0 + 3][a - x0 + 3]; };
-          auto getB = [&](int a, int b) -> int { return sB[b - y0 + 3][a - x0 + 3]; };
-          if (!hfTry(i, j, firstRows, I.h, getC, getN, getB, &kap) &&
-              !hfTry(i, j, 1 - firstRows, I.h, getC, getN, getB, &kap)) {
-            hffail++;
-            auto node = [&](int a, int b) -> int { return sNode[b - y0 + 3][a - x0 + 3]; };
-            if (ghfFit(P, I.h, i, j, ncx, ncy, node, &kap)) ghf++;
-            else kap = __builtin_nan("");
+        bool fallback = false;
+        if (in) {
+          double kap = 0.0;
+          if (sN[lj + 3][li + 3] >= 2) {
+            interf++;
+            int ncx, ncy;
+            nodeGradient(i, j, nx, ny, [&](int a, int b) -> int { return sNode[b - y0 + 3][a - x0 + 3]; }, &ncx,
+                         &ncy);
+            const int firstRows = abs(ncy) >= abs(ncx) ? 0 : 1;
+            auto getC = [&](int a, int b) -> double { return sC[b - y0 + 3][a - x0 + 3]; };
+            auto getN = [&](int a, int b) -> int { return sN[b - y0 + 3][a - x0 + 3]; };
+            auto getB = [&](int a, int b) -> int { return sB[b - y0 + 3][a - x0 + 3]; };
+            if (!hfTry(i, j, firstRows, I.h, getC, getN, getB, &kap) &&
+                !hfTry(i, j, 1 - firstRows, I.h, getC, getN, getB, &kap)) {
+              hffail++;
+              fallback = true;
+              kap = __builtin_nan("");  // k_ghf overwrites it where the parabola fit succeeds
+            }
           }
+          A.Kout[I.koff + id] = kap;
         }
-        A.Kout[I.koff + id] = kap;
+        // one entry per 64 cells k .. k+63 (a wavefront) with any fallback cell
+        const unsigned long long need = __ballot(fallback);
+        if (need && (tid & 63) == 0) {
+          const uint32_t slot = atomicAdd(A.ghfCount, 1u);
+          A.ghf[slot] = GhfEntry{te.x, te.y * 4u + (uint32_t)(k >> 6), need};
+        }
       }
     }
   }
   if (MODE & 2) {
     if (interf) atomicAdd(&sCnt[0], interf);
     if (hffail) atomicAdd(&sCnt[1], hffail);
-    if (ghf) atomicAdd(&sCnt[2], ghf);
     __syncthreads();
     if (tid == 0) {
-      if (sCnt[0]) atomicAdd(&A.ctr[C_INTERFACIAL], (unsigned long long)sCnt[0]);
-      if (sCnt[1]) atomicAdd(&A.ctr[C_HF_FAIL], (unsigned long long)sCnt[1]);
-      if (sCnt[2]) atomicAdd(&A.ctr[C_GHF_FIT], (unsigned long long)sCnt[2]);
-      if (ntiles_done) atomicAdd(&A.ctr[C_TILES_NEAR], (unsigned long long)ntiles_done);
+      if (sCnt[0]) atomicAdd(&ctrPart(A.ctr)[C_INTERFACIAL], (unsigned long long)sCnt[0]);
+      if (sCnt[1]) atomicAdd(&ctrPart(A.ctr)[C_HF_FAIL], (unsigned long long)sCnt[1]);
+      if (ntiles_done) atomicAdd(&ctrPart(A.ctr)[C_TILES_NEAR], (unsigned long long)ntiles_done);
     }
+  }
+}
+
+// The parabola fit of the cells a curvature launch left (heights failed in
+// both directions): one single-wavefront workgroup per entry, one lane per
+// cell. The entry's 4 rows x 16 cells need nodes x0-2..x0+18 and y0-2..y0+6
+// around them (y0 the first row), H offsets x0-2..x0+17, y0-2..y0+6 and V
+// offsets x0-2..x0+18, y0-2..y0+5: staged in LDS in one round of independent
+// loads (indexes clamped into the grid; clamped slots are never read). kappa
+// stays NaN where the fit has too few points or a singular system.
+constexpr int GW_X = 21, GW_Y = 9;  // node window
+template <bool ONE>
+__global__ __launch_bounds__(64, 4) void k_ghf(FracArgs A, const Inst *__restrict__ inst) {
+  __shared__ uint8_t sNw[GW_Y][GW_X];
+  __shared__ double sHw[GW_Y][GW_X - 1];
+  __shared__ double sVw[GW_Y - 1][GW_X];
+  const int lane = threadIdx.x;
+  const uint32_t n = *A.ghfCount;
+  for (uint32_t it = blockIdx.x; it < n; it += gridDim.x) {
+    const GhfEntry en = A.ghf[it];
+    const uint32_t tile = uni(en.tile), gw = uni(en.gridWave);
+    const unsigned long long mask = en.mask;
+    const Inst &I = ONE ? A.one : inst[gw >> 2];
+    const int nx = I.nx, ny = I.ny;
+    const uint32_t lt = tile - I.tile0;
+    const int wx0 = (int)(lt % (uint32_t)I.ntx) * TS - 2, wy0 = (int)(lt / (uint32_t)I.ntx) * TS + 4 * (int)(gw & 3u) - 2;
+    const GL uint8_t *col = gp(I.col[A.cur]);
+    const GL double *hoff = gp(I.hoff[A.cur]);
+    const GL double *voff = gp(I.voff[A.cur]);
+    const size_t W1 = (size_t)nx + 1;
+    __syncthreads();  // the previous entry's reads are done
+    constexpr int NW = (GW_Y * GW_X + 63) / 64;
+    uint8_t rn[NW];
+    double rh[NW], rv[NW];
+#pragma unroll
+    for (int r = 0; r < NW; r++) {
+      const int k = lane + 64 * r;
+      const int p = k % GW_X, q = k / GW_X;
+      const int x = min(max(wx0 + p, 0), nx), y = min(max(wy0 + q, 0), ny);
+      if (k < GW_Y * GW_X) {
+        rn[r] = col[(size_t)y * W1 + x];
+        rh[r] = hoff[(size_t)y * nx + min(x, nx - 1)];
+        rv[r] = voff[(size_t)min(y, ny - 1) * W1 + x];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < NW; r++) {
+      const int k = lane + 64 * r;
+      const int p = k % GW_X, q = k / GW_X;
+      if (k < GW_Y * GW_X) {
+        sNw[q][p] = rn[r];
+        if (p < GW_X - 1) sHw[q][p] = rh[r];
+        if (q < GW_Y - 1) sVw[q][p] = rv[r];
+      }
+    }
+    __syncthreads();
+    bool ok = false;
+    if ((mask >> lane) & 1ull) {
+      const int k = (int)(gw & 3u) * 64 + lane;
+      const int i = wx0 + 2 + k % TS, j = wy0 + 2 + lane / TS;
+      auto node = [&](int a, int b) -> int { return sNw[b - wy0][a - wx0]; };
+      auto hoffAt = [&](int a, int b) -> double { return sHw[b - wy0][a - wx0]; };
+      auto voffAt = [&](int a, int b) -> double { return sVw[b - wy0][a - wx0]; };
+      // the gradient's 4x4 nodes, mirrored across walls, lie in the window
+      int gx, gy;
+      nodeGradient(i, j, nx, ny, node, &gx, &gy);
+      double kap;
+      ok = ghfFit(nx, ny, I.h, i, j, gx, gy, node, hoffAt, voffAt, &kap);
+      if (ok) A.Kout[I.koff + (size_t)j * nx + i] = kap;
+    }
+    const unsigned long long got = __ballot(ok);
+    if (got && lane == 0) atomicAdd(&ctrPart(A.ctr)[C_GHF_FIT], (unsigned long long)__popcll(got));
   }
 }
 
@@ -1450,7 +1558,7 @@ __global__ __launch_bounds__(256) void k_ns(NsArgs A, const Inst *__restrict__ i
   const int tid = threadIdx.x;
   if ((int)blockIdx.x >= A.nearBlocks) {
     // --- uniform tiles: 16 consecutive global tiles, lanes along grid rows ---
-    const uint32_t t = (blockIdx.x - (uint32_t)A.nearBlocks) * FILL_TILES + (uint32_t)tid / TS;
+    const uint32_t t = (blockIdx.x - (uint32_t)A.nearBlocks) * NS_FILL_TILES + (uint32_t)tid / TS;
     if (t >= A.ntiles) return;
     const uint8_t ti = A.tinfo[t];
     if (ti & (TI_NEAR | TI_DEAD)) return;
@@ -1561,9 +1669,9 @@ int resident_blocks(int which) {
     case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_sweep<0, true>, SWEEP_BS, 0); break;
     case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fit<0, false>, 256, 0); break;  // fits only
     case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_centre<0, false>, 256, 0); break;
-    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_frac_curv<1, false>, 256, 0); break;
-    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_frac_curv<2, false>, 256, 0); break;
-    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_frac_curv<3, false>, 256, 0); break;
+    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_frac_curv<1, false>, FRAC_BS, 0); break;
+    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_frac_curv<2, false>, FRAC_BS, 0); break;
+    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_frac_curv<3, false>, FRAC_BS, 0); break;
   }
   if (e != hipSuccess) (void)hipGetLastError();  // a failed query must not surface at the next launch
   return (e == hipSuccess && n > 0) ? n : 1;
@@ -1638,22 +1746,30 @@ hipError_t launch_compact(bool one, const CompactArgs &a, hipStream_t s) {
   return hipGetLastError();
 }
 
-int frac_fill_blocks(uint32_t ntiles) { return (int)((ntiles + FILL_TILES - 1) / FILL_TILES); }
+int frac_fill_blocks(uint32_t ntiles) { return (int)((ntiles + FRAC_FILL_TILES - 1) / FRAC_FILL_TILES); }
+int ns_fill_blocks(uint32_t ntiles) { return (int)((ntiles + NS_FILL_TILES - 1) / NS_FILL_TILES); }
 
 hipError_t launch_ns(const NsArgs &a, int grid, hipStream_t s) {
   hipLaunchKernelGGL(k_ns, dim3(grid), dim3(256), 0, s, a, a.inst, a.tileInst);
   return hipGetLastError();
 }
 
+hipError_t launch_ghf(bool one, const FracArgs &a, int grid, hipStream_t s) {
+  if (one) hipLaunchKernelGGL(k_ghf<true>, dim3(grid), dim3(64), 0, s, a, a.inst);
+  else hipLaunchKernelGGL(k_ghf<false>, dim3(grid), dim3(64), 0, s, a, a.inst);
+  return hipGetLastError();
+}
+
 hipError_t launch_frac_curv(int mode, bool one, const FracArgs &a, int grid, hipStream_t s) {
+  const dim3 g(grid), b(FRAC_BS);
   if (one) {
-    if (mode == 1) EBIT_LAUNCH((k_frac_curv<1, true>), grid, s, a, a.inst, a.tileInst);
-    else if (mode == 2) EBIT_LAUNCH((k_frac_curv<2, true>), grid, s, a, a.inst, a.tileInst);
-    else EBIT_LAUNCH((k_frac_curv<3, true>), grid, s, a, a.inst, a.tileInst);
+    if (mode == 1) hipLaunchKernelGGL((k_frac_curv<1, true>), g, b, 0, s, a, a.inst, a.tileInst);
+    else if (mode == 2) hipLaunchKernelGGL((k_frac_curv<2, true>), g, b, 0, s, a, a.inst, a.tileInst);
+    else hipLaunchKernelGGL((k_frac_curv<3, true>), g, b, 0, s, a, a.inst, a.tileInst);
   } else {
-    if (mode == 1) EBIT_LAUNCH((k_frac_curv<1, false>), grid, s, a, a.inst, a.tileInst);
-    else if (mode == 2) EBIT_LAUNCH((k_frac_curv<2, false>), grid, s, a, a.inst, a.tileInst);
-    else EBIT_LAUNCH((k_frac_curv<3, false>), grid, s, a, a.inst, a.tileInst);
+    if (mode == 1) hipLaunchKernelGGL((k_frac_curv<1, false>), g, b, 0, s, a, a.inst, a.tileInst);
+    else if (mode == 2) hipLaunchKernelGGL((k_frac_curv<2, false>), g, b, 0, s, a, a.inst, a.tileInst);
+    else hipLaunchKernelGGL((k_frac_curv<3, false>), g, b, 0, s, a, a.inst, a.tileInst);
   }
   return hipGetLastError();
 }

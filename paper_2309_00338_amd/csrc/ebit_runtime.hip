@@ -73,7 +73,7 @@ struct Engine {
   uint32_t ntiles = 0;  // global tile space
   uint32_t maxGrids = 0;
   uint32_t jobCap = 0;
-  int sweepBlocks = 0, fitBlocks = 0, centreBlocks = 0, nearBlocks[3] = {0, 0, 0};
+  int sweepBlocks = 0, fitBlocks = 0, centreBlocks = 0, nearBlocks[3] = {0, 0, 0}, nsNearBlocks = 0;
   // device tables
   Inst *dinst = nullptr;
   uint32_t *tileInst = nullptr, *counts = nullptr, *errs = nullptr;
@@ -82,6 +82,10 @@ struct Engine {
   uint8_t *nearPrev = nullptr, *tinfo = nullptr;
   uint2 *jobs = nullptr;
   unsigned long long *ctr = nullptr;
+  GhfEntry *ghf = nullptr;      // cells left for the parabola fit, 4 entries per tile at most
+  uint32_t *ghfCnt = nullptr;   // entry counts of the two curvature-launch parities
+  uint32_t ghfPar = 0;          // parity of the next curvature launch
+  int ghfBlocks = 0;
   // host mirror
   std::vector<Inst> hinst;
   std::vector<uint8_t> live;
@@ -186,7 +190,9 @@ void carve_engine(Engine *e, char *base, Carve &c) {
   e->nearList = c.take<uint2>(base, e->ntiles);
   e->counts = c.take<uint32_t>(base, 2 * NSLOT);
   e->jobs = c.take<uint2>(base, e->jobCap);
-  e->ctr = c.take<unsigned long long>(base, NCOUNTERS);
+  e->ctr = c.take<unsigned long long>(base, (size_t)CTR_PARTS * CTR_STRIDE);
+  e->ghf = c.take<GhfEntry>(base, 4 * (size_t)e->ntiles);
+  e->ghfCnt = c.take<uint32_t>(base, 2);
 }
 
 // engine tables for ntiles tiles, maxGrids grids and jobCap fit jobs
@@ -207,9 +213,13 @@ void engine_launch_config(Engine *e) {
   e->sweepBlocks = cus * resident_blocks(0);
   e->fitBlocks = cus * resident_blocks(1);
   e->centreBlocks = cus * resident_blocks(2);
-  double perCU = 6.0;  // near-tile workgroups per CU of the fraction pass
+  e->ghfBlocks = cus * 16;  // single-wavefront workgroups, one per parabola-fit entry in the usual case
+  // near-tile workgroups per CU of the fraction pass: all resident slots (the
+  // fill workgroups take the slots the near ones leave as they finish)
+  double perCU = 64.0;
   if (const char *v = getenv("EBIT_FRAC_NEAR_BLOCKS_PER_CU")) perCU = atof(v);
-  if (!(perCU > 0.0)) perCU = 6.0;
+  if (!(perCU > 0.0)) perCU = 64.0;
+  e->nsNearBlocks = cus * 6;
   for (int m = 0; m < 3; m++) {
     int nb = (int)(cus * perCU);
     const int cap = cus * resident_blocks(3 + m);
@@ -221,8 +231,10 @@ void engine_launch_config(Engine *e) {
 // clears every table; all tiles start unowned
 int engine_reset(Engine *e) {
   HIPCHK(hipMemsetAsync(e->counts, 0, 2 * NSLOT * sizeof(uint32_t), e->stream));
-  HIPCHK(hipMemsetAsync(e->ctr, 0, NCOUNTERS * sizeof(unsigned long long), e->stream));
+  HIPCHK(hipMemsetAsync(e->ctr, 0, CTR_PARTS * CTR_STRIDE * sizeof(unsigned long long), e->stream));
   HIPCHK(hipMemsetAsync(e->errs, 0, e->maxGrids * sizeof(uint32_t), e->stream));
+  HIPCHK(hipMemsetAsync(e->ghfCnt, 0, 2 * sizeof(uint32_t), e->stream));
+  e->ghfPar = 0;
   HIPCHK(launch_clear_tiles(e->tileInst, e->has, e->nearPrev, e->tinfo, 0, e->ntiles, e->stream));
   e->slot = 1;
   return EBIT_OK;
@@ -348,8 +360,17 @@ int engine_frac(Engine *e, int mode, const double *Cin, double *Cout, double *Ko
   a.count = e->counts + NSLOT * e->slot + CNT_NEAR;
   a.nearBlocks = e->nearBlocks[mode - 1];
   a.ctr = e->ctr;
+  // a curvature launch appends to its parity's count (zeroed by the launch
+  // before it) and zeroes the other one for the launch after it
+  a.ghf = e->ghf;
+  a.ghfCount = e->ghfCnt + e->ghfPar;
+  a.ghfClear = e->ghfCnt + (e->ghfPar ^ 1u);
   a.one = e->hinst[0];
   HIPCHK(launch_frac_curv(mode, e->maxGrids == 1, a, a.nearBlocks + frac_fill_blocks(e->ntiles), e->stream));
+  if (mode & 2) {
+    HIPCHK(launch_ghf(e->maxGrids == 1, a, e->ghfBlocks, e->stream));
+    e->ghfPar ^= 1u;
+  }
   return EBIT_OK;
 }
 
@@ -378,8 +399,8 @@ int engine_ns(Engine *e, const double *C, const double *K, const ebit_fluid *f, 
   a.tinfo = e->tinfo;
   a.list = e->nearList;
   a.count = e->counts + NSLOT * e->slot + CNT_NEAR;
-  a.nearBlocks = e->nearBlocks[2];
-  HIPCHK(launch_ns(a, a.nearBlocks + frac_fill_blocks(e->ntiles), e->stream));
+  a.nearBlocks = e->nsNearBlocks;
+  HIPCHK(launch_ns(a, a.nearBlocks + ns_fill_blocks(e->ntiles), e->stream));
   return EBIT_OK;
 }
 
@@ -404,11 +425,15 @@ int engine_errors(Engine *e, int *status) {
 }
 
 int engine_counters(Engine *e, ebit_counters *out) {
-  unsigned long long v[NCOUNTERS];
+  unsigned long long v[CTR_PARTS * CTR_STRIDE];
   HIPCHK(hipMemcpyAsync(v, e->ctr, sizeof v, hipMemcpyDeviceToHost, e->stream));
   HIPCHK(hipStreamSynchronize(e->stream));
   int64_t *dst = (int64_t *)out;
-  for (int k = 0; k < NCOUNTERS; k++) dst[k] = (int64_t)v[k];
+  for (int k = 0; k < NCOUNTERS; k++) {
+    unsigned long long t = 0;
+    for (int p = 0; p < CTR_PARTS; p++) t += v[p * CTR_STRIDE + k];
+    dst[k] = (int64_t)t;
+  }
   return EBIT_OK;
 }
 
@@ -625,7 +650,7 @@ int ebit_set_state(ebit_handle *h, const ebit_state *state, int64_t step) {
   h->e.stepNo = (uint32_t)(step & 1);
   rc = engine_place(&h->e, 0, state);  // clears the marker history of every tile of the grid
   if (rc) return rc;
-  HIPCHK(hipMemsetAsync(h->e.ctr, 0, NCOUNTERS * sizeof(unsigned long long), h->e.stream));
+  HIPCHK(hipMemsetAsync(h->e.ctr, 0, CTR_PARTS * CTR_STRIDE * sizeof(unsigned long long), h->e.stream));
   rc = engine_compact(&h->e, 0, h->e.stepNo, 0);
   if (rc) return rc;
   h->e.epoch++;
@@ -641,7 +666,7 @@ int ebit_stats(ebit_handle *h, ebit_counters *out) {
 
 int ebit_stats_reset(ebit_handle *h) {
   if (!h) return EBIT_ERR_ARG;
-  HIPCHK(hipMemsetAsync(h->e.ctr, 0, NCOUNTERS * sizeof(unsigned long long), h->e.stream));
+  HIPCHK(hipMemsetAsync(h->e.ctr, 0, CTR_PARTS * CTR_STRIDE * sizeof(unsigned long long), h->e.stream));
   return EBIT_OK;
 }
 
