@@ -1235,26 +1235,60 @@ __device__ __forceinline__ void nodeGradient(int i, int j, int nx, int ny, NodeA
 // the edges of the 5x5 cells around (i,j), in the frame of the node-colour
 // gradient (gx, gy) (pointing into colour 1); kappa = 2c / (1 + b^2)^(3/2) / h.
 // Points are summed H edges first (rows y, then x), then V edges. node(x,y),
-// hoffAt(x,y) and voffAt(x,y) read the state at every window position, also
-// outside the grid or where no marker is (any value, NaN included): such an
-// edge contributes +0.0 to every sum through a select, which leaves each sum
-// bit-identical to skipping it (the sums start at +0.0 and so are never
-// -0.0), and the loop runs without branches.
+// hoffAt(x,y) and voffAt(x,y) read the state in the window x in [i-2, i+3],
+// y in [j-2, j+3]. The present edges are found first as a bit mask (bit
+// q*5+p the H edge (i-2+p, j-2+q), bit 30+q*6+p the V edge (i-2+p, j-2+q)),
+// then summed in ascending bit order, which is the order above: a wavefront
+// runs as many rounds as its busiest lane has markers, not one per edge.
 template <class GetN, class GetH, class GetV>
 __device__ bool ghfFit(int nx, int ny, double h, int i, int j, int gx, int gy, GetN node, GetH hoffAt, GetV voffAt,
                        double *kap) {
   if (gx == 0 && gy == 0) return false;
+  // node colours of the 6x6 window, bit q*6+p = node(i-2+p, j-2+q)
+  unsigned long long nb = 0;
+#pragma unroll
+  for (int q = 0; q < 6; q++)
+#pragma unroll
+    for (int p = 0; p < 6; p++) nb |= (unsigned long long)(node(i - 2 + p, j - 2 + q) & 1) << (q * 6 + p);
+  unsigned long long em = 0;
+#pragma unroll
+  for (int q = 0; q < 6; q++)
+#pragma unroll
+    for (int p = 0; p < 5; p++) {
+      const int x = i - 2 + p, y = j - 2 + q;
+      const bool on = x >= 0 && x < nx && y >= 0 && y <= ny && ((nb >> (q * 6 + p)) & 1) != ((nb >> (q * 6 + p + 1)) & 1);
+      em |= (unsigned long long)on << (q * 5 + p);
+    }
+#pragma unroll
+  for (int q = 0; q < 5; q++)
+#pragma unroll
+    for (int p = 0; p < 6; p++) {
+      const int x = i - 2 + p, y = j - 2 + q;
+      const bool on = x >= 0 && x <= nx && y >= 0 && y < ny && ((nb >> (q * 6 + p)) & 1) != ((nb >> (q * 6 + p + 6)) & 1);
+      em |= (unsigned long long)on << (30 + q * 6 + p);
+    }
   const double gl = sqrt((double)gx * (double)gx + (double)gy * (double)gy);
   const double nX = (double)gx / gl, nY = (double)gy / gl;
   const double xc = i + 0.5, yc = j + 0.5;
   double S0 = 0.0, S1 = 0.0, S2 = 0.0, S3 = 0.0, S4 = 0.0, T0 = 0.0, T1 = 0.0, T2 = 0.0;
-  auto add = [&](bool on, double px, double py) {
+  while (em) {
+    const int b = __ffsll((long long)em) - 1;
+    em &= em - 1;
+    double px, py;
+    if (b < 30) {
+      const int x = i - 2 + b % 5, y = j - 2 + b / 5;
+      px = x + hoffAt(x, y);
+      py = (double)y;
+    } else {
+      const int x = i - 2 + (b - 30) % 6, y = j - 2 + (b - 30) / 6;
+      px = (double)x;
+      py = y + voffAt(x, y);
+    }
     const double dx = px - xc, dy = py - yc;
-    const double Xp = dx * (-nY) + dy * nX;
-    const double Yp = dx * nX + dy * nY;
-    const double X = on ? Xp : 0.0, Y = on ? Yp : 0.0;
+    const double X = dx * (-nY) + dy * nX;
+    const double Y = dx * nX + dy * nY;
     const double X2 = X * X;
-    S0 += on ? 1.0 : 0.0;
+    S0 += 1.0;
     S1 += X;
     S2 += X2;
     S3 += X2 * X;
@@ -1262,23 +1296,7 @@ __device__ bool ghfFit(int nx, int ny, double h, int i, int j, int gx, int gy, G
     T0 += Y;
     T1 += X * Y;
     T2 += X2 * Y;
-  };
-#pragma unroll 1
-  for (int q = 0; q < 6; q++)
-#pragma unroll
-    for (int p = 0; p < 5; p++) {
-      const int x = i - 2 + p, y = j - 2 + q;
-      const bool on = x >= 0 && x < nx && y >= 0 && y <= ny && node(x, y) != node(x + 1, y);
-      add(on, x + hoffAt(x, y), (double)y);
-    }
-#pragma unroll 1
-  for (int q = 0; q < 5; q++)
-#pragma unroll
-    for (int p = 0; p < 6; p++) {
-      const int x = i - 2 + p, y = j - 2 + q;
-      const bool on = x >= 0 && x <= nx && y >= 0 && y < ny && node(x, y) != node(x, y + 1);
-      add(on, (double)x, y + voffAt(x, y));
-    }
+  }
   if (S0 < 3.0) return false;
   const double det = S0 * (S2 * S4 - S3 * S3) - S1 * (S1 * S4 - S3 * S2) + S2 * (S1 * S3 - S2 * S2);
   if (!(det > 1e-10 * (S0 * S2 * S4))) return false;

@@ -59,6 +59,18 @@ def test_many_circles_small():
     _run(ls, w.dts, every=3, fields_every=3)
 
 
+@pytest.mark.parametrize("rmin,rmax", [(0.6, 1.6), (1.5, 3.5)])
+def test_small_circles_parabola_fallback(rmin, rmax):
+    """Circles of one to a few cells: most interfacial cells have no valid
+    height (Sec. 2.5), so curvature comes from the parabola fit; kappa, its
+    NaN cells and the hf_fail / ghf_fit counts match the oracle every step."""
+    w = I.many_circles(n=256, count=200, rmin=rmin, rmax=rmax, period=4.0, nsteps=6, seed=78)
+    ls = Lockstep(w.state, w.u, w.v)
+    ls.fields("initial")
+    cnt = _run(ls, w.dts)
+    assert cnt["hf_fail"] > 1000 and cnt["ghf_fit"] > 1000, cnt
+
+
 @pytest.mark.parametrize("nx,ny", [(37, 53), (53, 19), (16, 16), (4, 4), (17, 33)])
 def test_ragged_rectangular_grids(nx, ny):
     rng = np.random.Generator(np.random.PCG64(nx * 1000 + ny))
