@@ -189,7 +189,9 @@ def main():
                                f"single vortex T={period:g}, CFL {cfl}",
                    "grid": [n, n], "circles": w.meta["circles"], "seed": w.meta["seed"],
                    "markers_per_step": M_sweeps / 2.0, "interfacial_per_step": I_step},
-        "roofline": {"bound": "hbm", "kernel": "k_frac_curv<3> (ebit_fraction_curvature)",
+        # one ebit_fraction_curvature call: k_frac_curv<3> then k_ghf (the
+        # parabola fits of the cells it left), timed together with events
+        "roofline": {"bound": "hbm", "kernel": "k_frac_curv<3> + k_ghf (one ebit_fraction_curvature call)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "us_per_launch": fc_ms * 1e3, "alg_bytes_per_launch": fc_bytes},
         "step_roofline": {"alg_bytes_per_step": step_bytes, "achieved_GBs": step_bytes / (ms_step * 1e-3) / 1e9,
