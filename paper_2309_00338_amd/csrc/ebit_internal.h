@@ -207,6 +207,7 @@ struct NsArgs {
   const uint2 *list;          // near tiles
   const uint32_t *count;
   int nearBlocks;
+  Inst one;                   // the descriptor itself when the engine holds one grid
 };
 
 __host__ __device__ inline int sweep_dir(const Inst &I, uint32_t stepNo, int phase) {
@@ -235,7 +236,7 @@ int frac_fill_blocks(uint32_t ntiles);
 int ns_fill_blocks(uint32_t ntiles);
 // the parabola fit of the cells a curvature launch left (same FracArgs)
 hipError_t launch_ghf(bool one, const FracArgs &a, int grid, hipStream_t s);
-hipError_t launch_ns(const NsArgs &a, int grid, hipStream_t s);
+hipError_t launch_ns(bool one, const NsArgs &a, int grid, hipStream_t s);
 
 }  // namespace ebit
 

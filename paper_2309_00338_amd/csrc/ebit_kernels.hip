@@ -1570,6 +1570,7 @@ __global__ __launch_bounds__(64, 4) void k_ghf(FracArgs A, const Inst *__restric
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double mixOf(double c, double a, double b) { return c * a + (1.0 - c) * b; }
 
+template <bool ONE>
 __global__ __launch_bounds__(256) void k_ns(NsArgs A, const Inst *__restrict__ inst,
                                             const uint32_t *__restrict__ tileInst) {
   constexpr int WC = TS + 1;  // cells per side with the left / bottom halo
@@ -1580,7 +1581,7 @@ __global__ __launch_bounds__(256) void k_ns(NsArgs A, const Inst *__restrict__ i
     if (t >= A.ntiles) return;
     const uint8_t ti = A.tinfo[t];
     if (ti & (TI_NEAR | TI_DEAD)) return;
-    const Inst &I = inst[tileInst[t]];
+    const Inst &I = ONE ? A.one : inst[tileInst[t]];
     const uint32_t lt = t - I.tile0;
     const int tx = (int)(lt % (uint32_t)I.ntx), ty = (int)(lt / (uint32_t)I.ntx);
     const int x = tx * TS + tid % TS;
@@ -1608,7 +1609,7 @@ __global__ __launch_bounds__(256) void k_ns(NsArgs A, const Inst *__restrict__ i
   for (uint32_t it = blockIdx.x; it < ntile; it += (uint32_t)A.nearBlocks) {
     __syncthreads();
     const uint2 te = make_uint2(uni(A.list[it].x), uni(A.list[it].y));
-    const Inst &I = inst[te.y];
+    const Inst &I = ONE ? A.one : inst[te.y];
     const int nx = I.nx, ny = I.ny;
     const uint32_t lt = te.x - I.tile0;
     const int x0 = (int)(lt % (uint32_t)I.ntx) * TS, y0 = (int)(lt / (uint32_t)I.ntx) * TS;
@@ -1767,8 +1768,9 @@ hipError_t launch_compact(bool one, const CompactArgs &a, hipStream_t s) {
 int frac_fill_blocks(uint32_t ntiles) { return (int)((ntiles + FRAC_FILL_TILES - 1) / FRAC_FILL_TILES); }
 int ns_fill_blocks(uint32_t ntiles) { return (int)((ntiles + NS_FILL_TILES - 1) / NS_FILL_TILES); }
 
-hipError_t launch_ns(const NsArgs &a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_ns, dim3(grid), dim3(256), 0, s, a, a.inst, a.tileInst);
+hipError_t launch_ns(bool one, const NsArgs &a, int grid, hipStream_t s) {
+  if (one) hipLaunchKernelGGL(k_ns<true>, dim3(grid), dim3(256), 0, s, a, a.inst, a.tileInst);
+  else hipLaunchKernelGGL(k_ns<false>, dim3(grid), dim3(256), 0, s, a, a.inst, a.tileInst);
   return hipGetLastError();
 }
 

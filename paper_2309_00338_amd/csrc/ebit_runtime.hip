@@ -400,7 +400,8 @@ int engine_ns(Engine *e, const double *C, const double *K, const ebit_fluid *f, 
   a.list = e->nearList;
   a.count = e->counts + NSLOT * e->slot + CNT_NEAR;
   a.nearBlocks = e->nsNearBlocks;
-  HIPCHK(launch_ns(a, a.nearBlocks + ns_fill_blocks(e->ntiles), e->stream));
+  a.one = e->hinst[0];
+  HIPCHK(launch_ns(e->maxGrids == 1, a, a.nearBlocks + ns_fill_blocks(e->ntiles), e->stream));
   return EBIT_OK;
 }
 

@@ -31,3 +31,70 @@ def test_config3a_merging_pairs_4096():
 
 def test_config3b_cosine_4096():
     _two_steps(I.cosine_interface(n=4096, nsteps=2))
+
+
+def test_config4_batched_256_grids():
+    """The batched workload at full size (256 grids, N log-uniform in
+    [64, 1024]) through one engine, as the benchmark runs it: two steps, then
+    every grid's state, C and kappa against its own oracle run."""
+    import torch
+
+    import oracle
+    from paper_2309_00338_amd import ebit
+    from tests.parity import compare_fields, compare_state
+
+    inst = I.batched_instances(count=256, steps=2)
+    print(f"[full] batched: {sum(st.nx * st.ny for st, _, _, _ in inst)} cells", flush=True)
+    b = ebit.EbitBatch([st for st, _, _, _ in inst])
+    U, V = b.pack_velocities([u for _, u, _, _ in inst], [v for _, _, v, _ in inst])
+    orc = [st.copy() for st, _, _, _ in inst]
+    ocnt = oracle.new_counters()
+    for k in range(2):
+        b.advect(U, V, torch.tensor([d[k] for _, _, _, d in inst], dtype=torch.float64, device="cuda:0"))
+        for g, (_, u, v, d) in enumerate(inst):
+            assert oracle.step(orc[g], u, v, d[k], counters=ocnt)[0] == oracle.OK
+    C, K = b.new_fields()
+    b.fraction_curvature(C, K)
+    torch.cuda.synchronize()
+    assert b.sync() == [0] * len(inst)
+    for g in range(len(inst)):
+        compare_state(b.get_state(g), orc[g], f"grid {g}")
+        Co = oracle.fraction(orc[g])
+        Ko, _ = oracle.curvature(orc[g], Co, counters=ocnt)
+        compare_fields(b.field(C, g).cpu().numpy(), b.field(K, g).cpu().numpy(), Co, Ko, orc[g].nx, orc[g].h,
+                       f"grid {g}")
+    got = {k: v for k, v in b.stats().items() if k not in ebit.SCHEDULE_COUNTERS}
+    assert got == oracle.counters_dict(ocnt)
+    print(f"[full] batched ok, {got['markers']} markers", flush=True)
+
+
+def test_config5_served_request_sizes():
+    """The first requests of the served stream (N log-uniform in [128, 2048],
+    up to 50 circles) admitted into one pool, stepped together, each against
+    its own oracle run."""
+    import oracle
+    from paper_2309_00338_amd import ebit
+    from tests.parity import compare_fields, compare_state
+
+    reqs = I.served_requests(8, rate=200.0)
+    pool = ebit.EbitPool(max_grids=8, max_tiles=1 << 16, arena_bytes=8 << 30)
+    live = {}
+    for req in reqs:
+        st, u, v, dt = I.served_instance(req)
+        slot = pool.admit(st, u, v, dt)
+        assert slot is not None
+        o = st.copy()
+        o.step = 0
+        live[slot] = (o, u, v, dt)
+    print(f"[full] served: sizes {[o.nx for o, _, _, _ in live.values()]}", flush=True)
+    for k in range(3):
+        pool.step()
+        for s, (o, u, v, dt) in live.items():
+            assert oracle.step(o, u, v, dt)[0] == oracle.OK
+    for s, (o, u, v, dt) in live.items():
+        C, K, steps, status = pool.read(s)
+        assert status == 0 and steps == o.step
+        compare_state(pool.get_state(s), o, f"slot {s}")
+        Co = oracle.fraction(o)
+        Ko, _ = oracle.curvature(o, Co)
+        compare_fields(C, K, Co, Ko, o.nx, o.h, f"slot {s}")
