@@ -234,6 +234,8 @@ hipError_t launch_compact(bool one, const CompactArgs &a, hipStream_t s);
 hipError_t launch_frac_curv(int mode, bool one, const FracArgs &a, int grid, hipStream_t s);
 int frac_fill_blocks(uint32_t ntiles);
 int ns_fill_blocks(uint32_t ntiles);
+// workgroups of the linear uniform-part passes of k_ns for one nx x ny grid
+int ns_linear_blocks(int nx, int ny);
 // the parabola fit of the cells a curvature launch left (same FracArgs)
 hipError_t launch_ghf(bool one, const FracArgs &a, int grid, hipStream_t s);
 hipError_t launch_ns(bool one, const NsArgs &a, int grid, hipStream_t s);

@@ -1570,18 +1570,83 @@ __global__ __launch_bounds__(64, 4) void k_ghf(FracArgs A, const Inst *__restric
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double mixOf(double c, double a, double b) { return c * a + (1.0 - c) * b; }
 
+// With one grid the uniform part is written as plain linear passes over each
+// output array: workgroup b takes elements [b * NS_CHUNK, (b + 1) * NS_CHUNK)
+// of one array, so that every wavefront store covers whole 128-byte lines
+// (fx rows are nx + 1 long and start anywhere in a line; per-tile rows left a
+// partial line at both ends of every wavefront's segment). Element (x, y) of a
+// W-wide array belongs to tile (min(x, nx-1) / 16, min(y, ny-1) / 16), the
+// tile whose near pass writes it; elements of near tiles are skipped.
+constexpr int NS_CHUNK = 4096;
+template <class Val>
+__device__ __forceinline__ void nsLinearFill(double *arr, size_t size, size_t k0, int W, const NsArgs &A,
+                                             const Inst &I, Val val) {
+  constexpr int NE_T = 16;  // elements per thread and group, 256 apart
+  size_t k = k0 + threadIdx.x;
+  int y = (int)(k / (size_t)W), x = (int)(k - (size_t)y * (size_t)W);
+  for (int g = 0; g < NS_CHUNK / (256 * NE_T); g++, k += 256 * NE_T) {
+    // owner tiles first, then all tile-info loads at once, then the stores
+    uint32_t tix[NE_T];
+#pragma unroll
+    for (int i = 0; i < NE_T; i++) {
+      tix[i] = I.tile0 + (uint32_t)(min(y, I.ny - 1) / TS) * (uint32_t)I.ntx + (uint32_t)(min(x, I.nx - 1) / TS);
+      x += 256;
+      while (x >= W) {
+        x -= W;
+        y++;
+      }
+    }
+    uint8_t ti[NE_T];
+#pragma unroll
+    for (int i = 0; i < NE_T; i++) ti[i] = k + 256u * i < size ? A.tinfo[tix[i]] : (uint8_t)TI_NEAR;
+#pragma unroll
+    for (int i = 0; i < NE_T; i++)
+      if (!(ti[i] & (TI_NEAR | TI_DEAD))) arr[k + 256u * i] = val(ti[i]);
+  }
+}
+
 template <bool ONE>
 __global__ __launch_bounds__(256) void k_ns(NsArgs A, const Inst *__restrict__ inst,
                                             const uint32_t *__restrict__ tileInst) {
   constexpr int WC = TS + 1;  // cells per side with the left / bottom halo
   const int tid = threadIdx.x;
-  if ((int)blockIdx.x >= A.nearBlocks) {
+  if (ONE && (int)blockIdx.x >= A.nearBlocks) {
+    // --- uniform part, one grid: linear passes over rho, mu, fx, fy ---------
+    const Inst &I = A.one;
+    const int nx = I.nx, ny = I.ny;
+    const size_t sc = (size_t)nx * ny, sx = (size_t)(nx + 1) * ny, sy = (size_t)nx * (ny + 1);
+    const uint32_t cc = (uint32_t)((sc + NS_CHUNK - 1) / NS_CHUNK), cx = (uint32_t)((sx + NS_CHUNK - 1) / NS_CHUNK);
+    uint32_t b = blockIdx.x - (uint32_t)A.nearBlocks;
+    auto colourOf = [](uint8_t ti) -> double { return (ti & TI_COLOUR) ? 1.0 : 0.0; };
+    if (b < cc) {
+      if (A.rho)
+        nsLinearFill(A.rho + I.coff, sc, (size_t)b * NS_CHUNK, nx, A, I,
+                     [&](uint8_t ti) { return mixOf(colourOf(ti), A.rho1, A.rho2); });
+      return;
+    }
+    b -= cc;
+    if (b < cc) {
+      if (A.mu)
+        nsLinearFill(A.mu + I.coff, sc, (size_t)b * NS_CHUNK, nx, A, I,
+                     [&](uint8_t ti) { return mixOf(colourOf(ti), A.mu1, A.mu2); });
+      return;
+    }
+    b -= cc;
+    if (b < cx) {
+      if (A.fx) nsLinearFill(A.fx + I.uoff, sx, (size_t)b * NS_CHUNK, nx + 1, A, I, [](uint8_t) { return 0.0; });
+      return;
+    }
+    b -= cx;
+    if (A.fy) nsLinearFill(A.fy + I.voffv, sy, (size_t)b * NS_CHUNK, nx, A, I, [](uint8_t) { return 0.0; });
+    return;
+  }
+  if (!ONE && (int)blockIdx.x >= A.nearBlocks) {
     // --- uniform tiles: 16 consecutive global tiles, lanes along grid rows ---
     const uint32_t t = (blockIdx.x - (uint32_t)A.nearBlocks) * NS_FILL_TILES + (uint32_t)tid / TS;
     if (t >= A.ntiles) return;
     const uint8_t ti = A.tinfo[t];
     if (ti & (TI_NEAR | TI_DEAD)) return;
-    const Inst &I = ONE ? A.one : inst[tileInst[t]];
+    const Inst &I = inst[tileInst[t]];
     const uint32_t lt = t - I.tile0;
     const int tx = (int)(lt % (uint32_t)I.ntx), ty = (int)(lt / (uint32_t)I.ntx);
     const int x = tx * TS + tid % TS;
@@ -1767,6 +1832,10 @@ hipError_t launch_compact(bool one, const CompactArgs &a, hipStream_t s) {
 
 int frac_fill_blocks(uint32_t ntiles) { return (int)((ntiles + FRAC_FILL_TILES - 1) / FRAC_FILL_TILES); }
 int ns_fill_blocks(uint32_t ntiles) { return (int)((ntiles + NS_FILL_TILES - 1) / NS_FILL_TILES); }
+int ns_linear_blocks(int nx, int ny) {
+  auto chunks = [](size_t n) { return (int)((n + NS_CHUNK - 1) / NS_CHUNK); };
+  return 2 * chunks((size_t)nx * ny) + chunks((size_t)(nx + 1) * ny) + chunks((size_t)nx * (ny + 1));
+}
 
 hipError_t launch_ns(bool one, const NsArgs &a, int grid, hipStream_t s) {
   if (one) hipLaunchKernelGGL(k_ns<true>, dim3(grid), dim3(256), 0, s, a, a.inst, a.tileInst);

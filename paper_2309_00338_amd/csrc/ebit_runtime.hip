@@ -401,7 +401,9 @@ int engine_ns(Engine *e, const double *C, const double *K, const ebit_fluid *f, 
   a.count = e->counts + NSLOT * e->slot + CNT_NEAR;
   a.nearBlocks = e->nsNearBlocks;
   a.one = e->hinst[0];
-  HIPCHK(launch_ns(e->maxGrids == 1, a, a.nearBlocks + ns_fill_blocks(e->ntiles), e->stream));
+  const bool one = e->maxGrids == 1;
+  const int fill = one ? ns_linear_blocks(e->hinst[0].nx, e->hinst[0].ny) : ns_fill_blocks(e->ntiles);
+  HIPCHK(launch_ns(one, a, a.nearBlocks + fill, e->stream));
   return EBIT_OK;
 }
 
