@@ -368,8 +368,10 @@ int engine_frac(Engine *e, int mode, const double *Cin, double *Cout, double *Ko
   a.one = e->hinst[0];
   HIPCHK(launch_frac_curv(mode, e->maxGrids == 1, a, a.nearBlocks + frac_fill_blocks(e->ntiles), e->stream));
   if (mode & 2) {
-    HIPCHK(launch_ghf(e->maxGrids == 1, a, e->ghfBlocks, e->stream));
+    // the launch above zeroed the other parity's count: the next curvature
+    // launch uses it, whatever happens to the fit launch below
     e->ghfPar ^= 1u;
+    HIPCHK(launch_ghf(e->maxGrids == 1, a, e->ghfBlocks, e->stream));
   }
   return EBIT_OK;
 }
