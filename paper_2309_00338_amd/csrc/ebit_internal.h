@@ -54,8 +54,11 @@ static_assert(NCOUNTERS <= CTR_STRIDE, "counters fit one partition");
 enum : uint32_t { ERRBIT_CFL = 1u, ERRBIT_DOMAIN = 2u };
 enum : uint32_t { INST_XY = 1u, INST_LINE = 2u };  // x then y every step; straight-line placement
 
-// tile info bits written by the compaction, read by the fraction pass
-enum : uint8_t { TI_NEAR = 1, TI_COLOUR = 2, TI_DEAD = 4 };
+// tile info bits written by the compaction, read by the fraction pass and
+// the interface consumers: TI_NEAR markers in the tile or within 3 cells of it
+// (the consumers' near set), TI_FRAC a marker on an edge of one of its cells
+// (the fraction pass's near set; its other tiles are uniform)
+enum : uint8_t { TI_NEAR = 1, TI_COLOUR = 2, TI_DEAD = 4, TI_FRAC = 8 };
 
 // One grid: geometry, both state copies, per-sweep scratch, and where its
 // velocities and output fields sit relative to the base pointers of a call.
@@ -127,7 +130,7 @@ __host__ __device__ inline SweepView sweep_view(const Inst &I, uint32_t cur, int
 // counts per compaction slot: active tiles of x-sweeping grids, of
 // y-sweeping grids, near tiles, fit jobs of the x and y sweeps
 constexpr int NSLOT = 8;
-enum { CNT_ACT_X = 0, CNT_ACT_Y = 1, CNT_NEAR = 2, CNT_JOBS_X = 3, CNT_JOBS_Y = 4 };
+enum { CNT_ACT_X = 0, CNT_ACT_Y = 1, CNT_NEAR = 2, CNT_JOBS_X = 3, CNT_JOBS_Y = 4, CNT_FRAC = 5 };
 
 // Arguments of the kernels of one sweep direction (sweep, fit, centre). The
 // x direction reads the active list and the job list from the front, the y
@@ -161,7 +164,7 @@ struct CompactArgs {
   int slot;
   const uint16_t *has;
   uint8_t *nearPrev, *tinfo;
-  uint2 *actList, *nearList;  // (global tile, grid)
+  uint2 *actList, *nearList, *fracList;  // (global tile, grid)
   uint32_t *counts;
   Inst one;                  // the descriptor itself when the engine holds one grid
 };

@@ -46,9 +46,12 @@ constexpr int NE = NH - 1;             // staged cells / edges per side (20)
 constexpr int NN = TS + 1;             // new nodes per side (17)
 constexpr int JOBCAP = 512;            // queued fit jobs per sweep workgroup (>= one tile's 256)
 
-// marker-position mask bits of a tile
+// marker-position mask bits of a tile: any marker; within STRIP cells of a
+// side or corner; on the tile's own left / bottom border edge (shared with
+// the cells of the neighbour on that side)
 enum : uint16_t {
-  M_ANY = 1, M_L = 2, M_R = 4, M_B = 8, M_T = 16, M_LB = 32, M_RB = 64, M_LT = 128, M_RT = 256
+  M_ANY = 1, M_L = 2, M_R = 4, M_B = 8, M_T = 16, M_LB = 32, M_RB = 64, M_LT = 128, M_RT = 256, M_L0 = 512,
+  M_B0 = 1024
 };
 constexpr int STRIP = 3;
 
@@ -64,6 +67,8 @@ __device__ __forceinline__ uint16_t maskAt(int lx0, int lx1, int ly0, int ly1) {
   if (r && b) m |= M_RB;
   if (l && t) m |= M_LT;
   if (r && t) m |= M_RT;
+  if (lx0 < 0) m |= M_L0;
+  if (ly0 < 0) m |= M_B0;
   return m;
 }
 // mask of an H edge (i,j) / V edge (i,j) in the tile with origin (x0,y0)
@@ -882,6 +887,17 @@ __device__ __forceinline__ void fitJob(const SweepView &W, uint32_t e, const Cou
   gp(W.zr)[e] = (uint8_t)((rR + 1) | ((rL + 1) << 2));
 }
 
+// a marker on an edge of one of the tile's cells: its own, or one on the
+// left border of the right neighbour or the bottom border of the one above
+// (edges on the right and top borders belong to those neighbours, except at
+// the walls, where the tile owns them)
+__device__ __forceinline__ bool fracNearOf(const uint16_t *__restrict__ has, int tx, int ty, int ntx, int nty) {
+  auto H = [&](int x, int y) -> uint32_t {
+    return (x < 0 || y < 0 || x >= ntx || y >= nty) ? 0u : (uint32_t)has[y * ntx + x];
+  };
+  return (H(tx, ty) & M_ANY) || (H(tx + 1, ty) & M_L0) || (H(tx, ty + 1) & M_B0);
+}
+
 __device__ __forceinline__ bool nearOf(const uint16_t *__restrict__ has, int tx, int ty, int ntx, int nty) {
   auto H = [&](int x, int y) -> uint32_t {
     return (x < 0 || y < 0 || x >= ntx || y >= nty) ? 0u : (uint32_t)has[y * ntx + x];
@@ -900,8 +916,8 @@ constexpr int CPT = 4;  // tiles per thread in the compaction
 // to its back.
 template <bool ONE>
 __device__ void compactBlock(const CompactArgs &C, uint32_t blk) {
-  __shared__ uint32_t sA[256], sB[256], sN[256];
-  __shared__ uint32_t sBaseA, sBaseB, sBaseN;
+  __shared__ uint32_t sA[256], sB[256], sN[256], sF[256];
+  __shared__ uint32_t sBaseA, sBaseB, sBaseN, sBaseF;
   const int tid = threadIdx.x;
   if (blk == 0 && tid == 0) {
     // the other slot's list counts start the next compaction from zero, and
@@ -911,11 +927,12 @@ __device__ void compactBlock(const CompactArgs &C, uint32_t blk) {
     other[CNT_ACT_X] = 0;
     other[CNT_ACT_Y] = 0;
     other[CNT_NEAR] = 0;
+    other[CNT_FRAC] = 0;
     mine[CNT_JOBS_X] = 0;
     mine[CNT_JOBS_Y] = 0;
   }
   const uint32_t base = (blk * blockDim.x + tid) * CPT;
-  uint32_t actBits = 0, dirBits = 0, nearBits = 0;
+  uint32_t actBits = 0, dirBits = 0, nearBits = 0, fracBits = 0;
   uint32_t kq[CPT];
   for (int q = 0; q < CPT; q++) {
     const uint32_t t = base + q;
@@ -928,29 +945,33 @@ __device__ void compactBlock(const CompactArgs &C, uint32_t blk) {
     const uint32_t lt = t - I.tile0;
     const int tx = (int)(lt % (uint32_t)I.ntx), ty = (int)(lt / (uint32_t)I.ntx);
     const bool nr = nearOf(C.has + I.tile0, tx, ty, I.ntx, I.nty);
+    const bool fr = fracNearOf(C.has + I.tile0, tx, ty, I.ntx, I.nty);
     const uint32_t pv = C.nearPrev[t];
     const uint32_t prev = C.afterSweep ? (pv & 1u) : ((pv >> 1) & 1u);
     const bool act = nr || prev;
     C.nearPrev[t] = (uint8_t)((nr ? 1u : 0u) | (prev << 1));
-    C.tinfo[t] = (uint8_t)((nr ? TI_NEAR : 0) |
+    C.tinfo[t] = (uint8_t)((nr ? TI_NEAR : 0) | (fr ? TI_FRAC : 0) |
                            (gp(I.col[C.cur])[(size_t)(ty * TS) * (I.nx + 1) + tx * TS] ? TI_COLOUR : 0));
     actBits |= (uint32_t)act << q;
     dirBits |= (uint32_t)(act && sweep_dir(I, C.stepNo, C.phase) == 1) << q;
     nearBits |= (uint32_t)nr << q;
+    fracBits |= (uint32_t)fr << q;
   }
   // exclusive block scan of the per-thread counts
-  const uint32_t cb = __popc(dirBits), ca = __popc(actBits) - cb, cn = __popc(nearBits);
+  const uint32_t cb = __popc(dirBits), ca = __popc(actBits) - cb, cn = __popc(nearBits), cf = __popc(fracBits);
   sA[tid] = ca;
   sB[tid] = cb;
   sN[tid] = cn;
+  sF[tid] = cf;
   __syncthreads();
   for (int off = 1; off < 256; off <<= 1) {
     const uint32_t xa = tid >= off ? sA[tid - off] : 0, xb = tid >= off ? sB[tid - off] : 0,
-                   xn = tid >= off ? sN[tid - off] : 0;
+                   xn = tid >= off ? sN[tid - off] : 0, xf = tid >= off ? sF[tid - off] : 0;
     __syncthreads();
     sA[tid] += xa;
     sB[tid] += xb;
     sN[tid] += xn;
+    sF[tid] += xf;
     __syncthreads();
   }
   uint32_t *cs = C.counts + NSLOT * C.slot;
@@ -958,15 +979,18 @@ __device__ void compactBlock(const CompactArgs &C, uint32_t blk) {
     sBaseA = sA[255] ? atomicAdd(&cs[CNT_ACT_X], sA[255]) : 0;
     sBaseB = sB[255] ? atomicAdd(&cs[CNT_ACT_Y], sB[255]) : 0;
     sBaseN = sN[255] ? atomicAdd(&cs[CNT_NEAR], sN[255]) : 0;
+    sBaseF = sF[255] ? atomicAdd(&cs[CNT_FRAC], sF[255]) : 0;
   }
   __syncthreads();
-  uint32_t pa = sBaseA + sA[tid] - ca, pb = sBaseB + sB[tid] - cb, pn = sBaseN + sN[tid] - cn;
+  uint32_t pa = sBaseA + sA[tid] - ca, pb = sBaseB + sB[tid] - cb, pn = sBaseN + sN[tid] - cn,
+           pf = sBaseF + sF[tid] - cf;
   for (int q = 0; q < CPT; q++) {
     if (actBits >> q & 1) {
       if (dirBits >> q & 1) C.actList[C.ntiles - 1u - pb++] = make_uint2(base + q, kq[q]);
       else C.actList[pa++] = make_uint2(base + q, kq[q]);
     }
     if (nearBits >> q & 1) C.nearList[pn++] = make_uint2(base + q, kq[q]);
+    if (fracBits >> q & 1) C.fracList[pf++] = make_uint2(base + q, kq[q]);
   }
 }
 
@@ -1336,7 +1360,7 @@ __global__ __launch_bounds__(FRAC_BS, 8) void k_frac_curv(FracArgs A, const Inst
     const uint32_t t = (blockIdx.x - (uint32_t)A.nearBlocks) * FRAC_FILL_TILES + (uint32_t)tid / TS;
     if (t >= A.ntiles) return;
     const uint8_t ti = A.tinfo[t];
-    if (ti & (TI_NEAR | TI_DEAD)) return;
+    if (ti & (TI_FRAC | TI_DEAD)) return;
     const Inst &I = ONE ? A.one : inst[tileInst[t]];
     const uint32_t lt = t - I.tile0;
     const int tx = (int)(lt % (uint32_t)I.ntx), ty = (int)(lt / (uint32_t)I.ntx);

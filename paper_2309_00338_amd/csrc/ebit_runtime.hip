@@ -77,7 +77,7 @@ struct Engine {
   // device tables
   Inst *dinst = nullptr;
   uint32_t *tileInst = nullptr, *counts = nullptr, *errs = nullptr;
-  uint2 *actList = nullptr, *nearList = nullptr;  // (global tile, grid)
+  uint2 *actList = nullptr, *nearList = nullptr, *fracList = nullptr;  // (global tile, grid)
   uint16_t *has = nullptr;
   uint8_t *nearPrev = nullptr, *tinfo = nullptr;
   uint2 *jobs = nullptr;
@@ -188,6 +188,7 @@ void carve_engine(Engine *e, char *base, Carve &c) {
   e->tinfo = c.take<uint8_t>(base, e->ntiles);
   e->actList = c.take<uint2>(base, e->ntiles);
   e->nearList = c.take<uint2>(base, e->ntiles);
+  e->fracList = c.take<uint2>(base, e->ntiles);
   e->counts = c.take<uint32_t>(base, 2 * NSLOT);
   e->jobs = c.take<uint2>(base, e->jobCap);
   e->ctr = c.take<unsigned long long>(base, (size_t)CTR_PARTS * CTR_STRIDE);
@@ -255,6 +256,7 @@ CompactArgs compact_args(Engine *e, int afterSweep, uint32_t nextStep, int nextP
   a.tinfo = e->tinfo;
   a.actList = e->actList;
   a.nearList = e->nearList;
+  a.fracList = e->fracList;
   a.counts = e->counts;
   a.one = e->hinst[0];
   return a;
@@ -356,8 +358,8 @@ int engine_frac(Engine *e, int mode, const double *Cin, double *Cout, double *Ko
   a.Cout = Cout;
   a.Kout = Kout;
   a.tinfo = e->tinfo;
-  a.list = e->nearList;
-  a.count = e->counts + NSLOT * e->slot + CNT_NEAR;
+  a.list = e->fracList;
+  a.count = e->counts + NSLOT * e->slot + CNT_FRAC;
   a.nearBlocks = e->nearBlocks[mode - 1];
   a.ctr = e->ctr;
   // a curvature launch appends to its parity's count (zeroed by the launch
