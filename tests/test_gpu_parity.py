@@ -224,7 +224,7 @@ def _ns_compare(got, want, where):
         assert (d / scale).max(initial=0) <= 1e-12, f"{where}: {name} max rel diff {(d / scale).max()}"
 
 
-@pytest.mark.parametrize("case", ["vortex64", "circles512", "ragged37x53"])
+@pytest.mark.parametrize("case", ["vortex64", "circles512", "ragged37x53", "narrow5x40", "wide300x6"])
 def test_ns_fields_match_oracle(case):
     """rho, mu and the surface-tension face forces from the GPU C and kappa,
     against the oracle from the oracle's C and kappa, after a few steps."""
@@ -236,10 +236,18 @@ def test_ns_fields_match_oracle(case):
     elif case == "circles512":
         w = I.many_circles(n=512, count=150, rmin=3.0, rmax=16.0, period=4.0, nsteps=6)
         st, u, v, dts = w.state, w.u, w.v, w.dts
-    else:
+    elif case == "ragged37x53":
         st = I.init_state(37, 53, [I.Ellipse(18.3, 26.1, 11.0, 7.0, 0.4)], h=1.0 / 53)
         u, v = I.uniform_faces(37, 53, 0.3, -0.2)
         dts = [0.5 / 53] * 6
+    else:
+        # rows shorter than a wavefront's stride of the uniform pass, or one
+        # tile row only: the linear passes wrap rows many times or never
+        nx, ny, sh = ((5, 40, I.Ellipse(2.6, 20.3, 1.7, 7.0, 0.1)) if case == "narrow5x40"
+                      else (300, 6, I.Ellipse(150.2, 3.1, 60.0, 1.8, 0.0)))
+        st = I.init_state(nx, ny, [sh], h=1.0 / max(nx, ny))
+        u, v = I.uniform_faces(nx, ny, 0.3, -0.2)
+        dts = [0.4 / max(nx, ny)] * 4
     ls = Lockstep(st, u, v)
     for k, dt in enumerate(dts):
         ls.step(dt, check_state=False, check_fields=False, where=f"step {k}")
