@@ -76,7 +76,7 @@ struct Inst {
   double *hoff[2];       // H-edge offsets, (ny+1) x nx
   double *voff[2];       // V-edge offsets, ny x (nx+1)
   double *sp;            // advected aligned offsets s' of the current sweep
-  double *dd;            // displacements of the unaligned markers of the current sweep
+  double *dd;            // per unaligned edge of the current sweep: old offset t, displacement d
   uint8_t *zr;           // per unaligned edge: centre-CV results of its fit
   uint32_t *err;         // error bits of this grid
 };

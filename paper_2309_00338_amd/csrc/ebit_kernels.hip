@@ -176,18 +176,16 @@ struct GView {
   const GL uint8_t *__restrict__ cen;   // old centre colours
   const GL uint8_t *__restrict__ ncol;  // new node colours
   const GL double *__restrict__ sp;     // aligned: s' (present edges)
-  const GL double *__restrict__ dd;     // unaligned: d (present edges)
-  const GL double *__restrict__ uno;    // unaligned: old offsets t
+  const GL double *__restrict__ td;     // unaligned: (old offset t, displacement d) pairs (present edges)
   __device__ GView(int nx, int ny, const uint8_t *col_, const uint8_t *cen_, const uint8_t *ncol_, const double *sp_,
-                   const double *dd_, const double *uno_)
-      : G(nx, ny), na(G.na), nb(G.nb), col(gp(col_)), cen(gp(cen_)), ncol(gp(ncol_)), sp(gp(sp_)), dd(gp(dd_)),
-        uno(gp(uno_)) {}
+                   const double *td_)
+      : G(nx, ny), na(G.na), nb(G.nb), col(gp(col_)), cen(gp(cen_)), ncol(gp(ncol_)), sp(gp(sp_)), td(gp(td_)) {}
   __device__ int C(int a, int b) const { return col[G.node(a, b)]; }
   __device__ bool presA(int a, int b) const { return C(a, b) != C(a + 1, b); }
   __device__ bool presU(int a, int b) const { return C(a, b) != C(a, b + 1); }
   __device__ double spv(int a, int b) const { return sp[G.ale(a, b)]; }
-  __device__ double dU(int a, int b) const { return dd[G.une(a, b)]; }
-  __device__ double tU(int a, int b) const { return uno[G.une(a, b)]; }
+  __device__ double dU(int a, int b) const { return td[2 * G.une(a, b) + 1]; }
+  __device__ double tU(int a, int b) const { return td[2 * G.une(a, b)]; }
   __device__ int cenv(int p, int q) const { return cen[G.cell(p, q)]; }
   __device__ uint16_t segc(int p, int q) const {
     return segCodeOf(C(p, q), C(p + 1, q), C(p + 1, q + 1), C(p, q + 1), cenv(p, q));
@@ -760,7 +758,10 @@ __global__ __launch_bounds__(SWEEP_BS, 8) void k_sweep(SweepArgs A, const Inst *
         const double d = ub * lam;
         const bool wall = a == 0 || a == na;
         // every listed unaligned marker belongs to this tile
-        ddg[G.une(a, b)] = wall ? 0.0 : d;
+        // old offset and displacement side by side: the fit reads both
+        const size_t e2 = 2 * G.une(a, b);
+        ddg[e2] = t;
+        ddg[e2 + 1] = wall ? 0.0 : d;
         // walls hold their markers (wall nodes never change colour)
         if (wall) unn[G.une(a, b)] = t;
         cnt.add(C_MARKERS, 1u);
@@ -876,7 +877,7 @@ __device__ __forceinline__ void eachGrid(uint32_t k, F f) {
 
 template <int DIR>
 __device__ __forceinline__ void fitJob(const SweepView &W, uint32_t e, const Counts &cnt) {
-  const GView<DIR> V(W.nx, W.ny, W.col, W.cen, W.ncol, W.sp, W.dd, DIR == 0 ? W.voff : W.hoff);
+  const GView<DIR> V(W.nx, W.ny, W.col, W.cen, W.ncol, W.sp, W.dd);
   GL double *__restrict__ unn = gp(DIR == 0 ? W.nvoff : W.nhoff);
   int a, b;
   if (DIR == 0) { b = (int)(e / (uint32_t)(W.nx + 1)); a = (int)(e % (uint32_t)(W.nx + 1)); }

@@ -108,7 +108,7 @@ void carve_grid(Inst *I, const ebit_grid &g, char *base, Carve &c) {
     I->voff[k] = c.take<double>(base, nv);
   }
   I->sp = c.take<double>(base, nn);
-  I->dd = c.take<double>(base, nn);
+  I->dd = c.take<double>(base, 2 * nn);
   I->zr = c.take<uint8_t>(base, nn);
 }
 
