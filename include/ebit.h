@@ -143,8 +143,12 @@ int ebit_fraction(ebit_handle *h, double *C_dev);
 /* Height-function curvature of the fraction C_dev produced by ebit_fraction
  * on the current state (Sec. 2.5), on a 7x3 stencil oriented by the corner
  * colours. Writes all ny*nx entries of K_dev: 0 in cells with fewer than two
- * markers, NaN where no height is valid, else kappa (> 0 for a convex
- * colour-1 region). EBIT_ERR_STATE if the state advanced since ebit_fraction. */
+ * markers, else kappa (> 0 for a convex colour-1 region). Where no height is
+ * valid, kappa of the least-squares parabola through the markers on the edges
+ * of the 5x5 cells around the cell, in the frame of the node-colour gradient
+ * (the generalised height function Sec. 2.5 refers to); NaN where that fit
+ * has fewer than 3 points, a zero gradient or a near-singular system.
+ * EBIT_ERR_STATE if the state advanced since ebit_fraction. */
 int ebit_curvature(ebit_handle *h, const double *C_dev, double *K_dev);
 
 /* ebit_fraction followed by ebit_curvature in one pass (same results). */
