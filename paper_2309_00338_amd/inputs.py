@@ -493,6 +493,19 @@ def random_instance(rng, n: int, nshapes: int, ellipses: bool = True, period: fl
     return st, u, v, vortex_dt_schedule(dt, period, steps)
 
 
+def random_colouring(nx: int, ny: int, seed: int, p: float = 0.5) -> State:
+    """A dense stress state: every node colour and centre colour drawn at
+    random (probability p of colour 1), every edge offset uniform in
+    [0.05, 0.95], so about half of all edges carry a marker and most cells
+    carry two or four."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    c = (rng.random((ny + 1, nx + 1)) < p).astype(np.uint8)
+    cc = (rng.random((ny, nx)) < 0.5).astype(np.uint8)
+    hoff = rng.uniform(0.05, 0.95, (ny + 1, nx))
+    voff = rng.uniform(0.05, 0.95, (ny, nx + 1))
+    return State(nx, ny, 1.0 / max(nx, ny), c, cc, hoff, voff)
+
+
 def batched_instances(count: int = 256, nmin: int = 64, nmax: int = 1024, steps: int = 100, seed: int = 1004,
                       max_shapes: int = 20):
     """Many independent grids for the batched form: N log-uniform in

@@ -71,6 +71,26 @@ def test_small_circles_parabola_fallback(rmin, rmax):
     assert cnt["hf_fail"] > 1000 and cnt["ghf_fit"] > 1000, cnt
 
 
+@pytest.mark.parametrize("nx,ny", [(64, 64), (53, 37)])
+def test_dense_random_colouring(nx, ny):
+    """Random node and centre colours with markers on about half of all edges:
+    hundreds of listed markers per tile (several rounds per thread in the
+    sweep), job-queue flushes, four-marker cells, heavy annihilation and many
+    parabola fits, all against the oracle every step."""
+    st = I.random_colouring(nx, ny, seed=7)
+    x = np.arange(nx + 1) / nx
+    y = np.arange(ny + 1) / ny
+    psi = (np.sin(np.pi * x)[None, :] ** 2) * (np.sin(np.pi * y)[:, None] ** 2) / np.pi
+    psi[0, :] = psi[-1, :] = 0.0
+    psi[:, 0] = psi[:, -1] = 0.0
+    u, v = I.faces_from_psi(psi, st.h)
+    dt = 0.45 * st.h / max(np.abs(u).max(), np.abs(v).max())
+    ls = Lockstep(st, u, v)
+    ls.fields("initial")
+    cnt = _run(ls, [dt] * 6)
+    assert cnt["annihilated"] > 100 and cnt["ghf_fit"] > 100, cnt
+
+
 @pytest.mark.parametrize("nx,ny", [(37, 53), (53, 19), (16, 16), (4, 4), (17, 33)])
 def test_ragged_rectangular_grids(nx, ny):
     rng = np.random.Generator(np.random.PCG64(nx * 1000 + ny))
