@@ -55,9 +55,10 @@ enum : uint32_t { ERRBIT_CFL = 1u, ERRBIT_DOMAIN = 2u };
 enum : uint32_t { INST_XY = 1u, INST_LINE = 2u };  // x then y every step; straight-line placement
 
 // tile info bits written by the compaction, read by the fraction pass and
-// the interface consumers: TI_NEAR markers in the tile or within 3 cells of it
-// (the consumers' near set), TI_FRAC a marker on an edge of one of its cells
-// (the fraction pass's near set; its other tiles are uniform)
+// the interface consumers: TI_NEAR a cut cell in the tile or on the side of
+// its left / lower neighbour that it shares (the consumers' near set),
+// TI_FRAC a cut cell in the tile (the fraction pass's near set; its other
+// tiles are uniform)
 enum : uint8_t { TI_NEAR = 1, TI_COLOUR = 2, TI_DEAD = 4, TI_FRAC = 8 };
 
 // One grid: geometry, both state copies, per-sweep scratch, and where its

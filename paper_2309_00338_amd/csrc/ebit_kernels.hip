@@ -48,10 +48,11 @@ constexpr int JOBCAP = 512;            // queued fit jobs per sweep workgroup (>
 
 // marker-position mask bits of a tile: any marker; within STRIP cells of a
 // side or corner; on the tile's own left / bottom border edge (shared with
-// the cells of the neighbour on that side)
+// the cells of the neighbour on that side); on an edge of a cell of the
+// tile's last column / top row
 enum : uint16_t {
   M_ANY = 1, M_L = 2, M_R = 4, M_B = 8, M_T = 16, M_LB = 32, M_RB = 64, M_LT = 128, M_RT = 256, M_L0 = 512,
-  M_B0 = 1024
+  M_B0 = 1024, M_R1 = 2048, M_T1 = 4096
 };
 constexpr int STRIP = 3;
 
@@ -69,6 +70,8 @@ __device__ __forceinline__ uint16_t maskAt(int lx0, int lx1, int ly0, int ly1) {
   if (r && t) m |= M_RT;
   if (lx0 < 0) m |= M_L0;
   if (ly0 < 0) m |= M_B0;
+  if (lx1 >= TS - 1) m |= M_R1;
+  if (ly1 >= TS - 1) m |= M_T1;
   return m;
 }
 // mask of an H edge (i,j) / V edge (i,j) in the tile with origin (x0,y0)
@@ -899,6 +902,17 @@ __device__ __forceinline__ bool fracNearOf(const uint16_t *__restrict__ has, int
   return (H(tx, ty) & M_ANY) || (H(tx + 1, ty) & M_L0) || (H(tx, ty + 1) & M_B0);
 }
 
+// the interface consumers' near set: a cut cell in the tile, or one in the
+// left neighbour's last column or the lower neighbour's top row (a face the
+// tile writes lies between them and the tile's cells); every other tile has
+// equal C on both sides of all its faces
+__device__ __forceinline__ bool nsNearOf(const uint16_t *__restrict__ has, int tx, int ty, int ntx, int nty) {
+  auto H = [&](int x, int y) -> uint32_t {
+    return (x < 0 || y < 0 || x >= ntx || y >= nty) ? 0u : (uint32_t)has[y * ntx + x];
+  };
+  return fracNearOf(has, tx, ty, ntx, nty) || (H(tx - 1, ty) & M_R1) || (H(tx, ty - 1) & M_T1);
+}
+
 __device__ __forceinline__ bool nearOf(const uint16_t *__restrict__ has, int tx, int ty, int ntx, int nty) {
   auto H = [&](int x, int y) -> uint32_t {
     return (x < 0 || y < 0 || x >= ntx || y >= nty) ? 0u : (uint32_t)has[y * ntx + x];
@@ -947,15 +961,16 @@ __device__ void compactBlock(const CompactArgs &C, uint32_t blk) {
     const int tx = (int)(lt % (uint32_t)I.ntx), ty = (int)(lt / (uint32_t)I.ntx);
     const bool nr = nearOf(C.has + I.tile0, tx, ty, I.ntx, I.nty);
     const bool fr = fracNearOf(C.has + I.tile0, tx, ty, I.ntx, I.nty);
+    const bool ns = nsNearOf(C.has + I.tile0, tx, ty, I.ntx, I.nty);
     const uint32_t pv = C.nearPrev[t];
     const uint32_t prev = C.afterSweep ? (pv & 1u) : ((pv >> 1) & 1u);
     const bool act = nr || prev;
     C.nearPrev[t] = (uint8_t)((nr ? 1u : 0u) | (prev << 1));
-    C.tinfo[t] = (uint8_t)((nr ? TI_NEAR : 0) | (fr ? TI_FRAC : 0) |
+    C.tinfo[t] = (uint8_t)((ns ? TI_NEAR : 0) | (fr ? TI_FRAC : 0) |
                            (gp(I.col[C.cur])[(size_t)(ty * TS) * (I.nx + 1) + tx * TS] ? TI_COLOUR : 0));
     actBits |= (uint32_t)act << q;
     dirBits |= (uint32_t)(act && sweep_dir(I, C.stepNo, C.phase) == 1) << q;
-    nearBits |= (uint32_t)nr << q;
+    nearBits |= (uint32_t)ns << q;
     fracBits |= (uint32_t)fr << q;
   }
   // exclusive block scan of the per-thread counts
