@@ -220,7 +220,7 @@ def main():
     log(f"[bench] ns_fields: {ns_us:.1f} us/launch")
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on one step of the same grid")
-        out["cpu_baseline"] = cpu_baseline(w, 1)
+        out["cpu_baseline"] = cpu_baseline(w, 2)
     print(json.dumps(out), flush=True)
 
 
