@@ -219,7 +219,7 @@ def main():
                         "frac": ns_bytes / (ns_us * 1e-6) / 1e9 / HBM_PEAK_GBS}
     log(f"[bench] ns_fields: {ns_us:.1f} us/launch")
     if not args.no_cpu_baseline:
-        log("[bench] timing the CPU oracle on one step of the same grid")
+        log("[bench] timing the CPU oracle on two steps of the same grid")
         out["cpu_baseline"] = cpu_baseline(w, 2)
     print(json.dumps(out), flush=True)
 
