@@ -127,23 +127,16 @@ __device__ __forceinline__ uint16_t segCodeOf(int k0, int k1, int k2, int k3, in
   return 0;
 }
 
+// The sweep's LDS view of its tile and halo: old colours and advected
+// aligned offsets, enough to gather the landers of each new aligned edge.
 struct Tile {
   int na, nb, a0, b0;
   const uint8_t (*col)[NH];   // old node colours   [b][a], a in [a0-2, a0+18]
-  const uint8_t (*cen)[NE];   // old centre colours [b][a], a in [a0-2, a0+17]
   const double (*sp)[NE];     // aligned (a,b): s' ; a in [a0-2,a0+17], b in [b0-2,b0+18]
-  const double (*dd)[NH];     // unaligned (a,b): d ; a in [a0-2,a0+18], b in [b0-2,b0+17]
-  const double (*tt)[NH];     // unaligned (a,b): t
-  const uint32_t *nrow;       // new node colours, row b-b0 in [0,16], bit a-a0 in [0,16]
 
   __device__ int C(int a, int b) const { return col[b - b0 + HALO][a - a0 + HALO]; }
   __device__ bool presA(int a, int b) const { return C(a, b) != C(a + 1, b); }
-  __device__ bool presU(int a, int b) const { return C(a, b) != C(a, b + 1); }
   __device__ double spv(int a, int b) const { return sp[b - b0 + HALO][a - a0 + HALO]; }
-  __device__ double dU(int a, int b) const { return dd[b - b0 + HALO][a - a0 + HALO]; }
-  __device__ double tU(int a, int b) const { return tt[b - b0 + HALO][a - a0 + HALO]; }
-  __device__ int cenv(int p, int q) const { return cen[q - b0 + HALO][p - a0 + HALO]; }
-  __device__ int newC(int a, int b) const { return (nrow[b - b0] >> (a - a0)) & 1; }
 
   // aligned markers landing on edge (a,b): their number and the kept source
   // (-1 when none): one lander is kept, of three the middle source
@@ -613,11 +606,7 @@ __global__ __launch_bounds__(SWEEP_BS, 8) void k_sweep(SweepArgs A, const Inst *
     T.na = na;
     T.nb = nb;
     T.col = sCol;
-    T.cen = sCen;
     T.sp = sSp;
-    T.dd = nullptr;  // displacements and old unaligned offsets are not staged:
-    T.tt = nullptr;  // the fit kernel reads them from the scratch and the state
-    T.nrow = sNRow;
     T.a0 = a0;
     T.b0 = b0;
     __syncthreads();  // the previous tile is done with LDS
