@@ -494,7 +494,7 @@ __global__ __launch_bounds__(SWEEP_BS, 8) void k_sweep(SweepArgs A, const Inst *
   __shared__ uint32_t sCnt[NCOUNTERS];
 
   const int tid = threadIdx.x;
-  const uint32_t cur = A.cur, nxt = cur ^ 1u;
+  const uint32_t cur = A.cur;
   if (tid < NCOUNTERS) sCnt[tid] = 0;
   if (tid == 0) sNJob = 0;
   if (tid < NH) sRow[tid] = 0;
