@@ -712,7 +712,7 @@ static int hf_try(int nx, int ny, double h, const uint8_t *c, const double *C, i
   double y[3];
   int sig = 0;
   for (int k = -1; k <= 1; k++) {
-    int ci, cj, ei0, ej0, ei1, ej1;
+    int ci = 0, cj = 0, ei0, ej0, ei1, ej1;
     if (!rows) {
       ci = mirror_cell(i + k, nx);
       ei0 = ci; ej0 = mirror_cell(j - 3, ny);
