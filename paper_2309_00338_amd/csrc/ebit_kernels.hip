@@ -44,7 +44,7 @@ constexpr int HALO = 2;
 constexpr int NH = TS + 2 * HALO + 1;  // staged nodes per side (21)
 constexpr int NE = NH - 1;             // staged cells / edges per side (20)
 constexpr int NN = TS + 1;             // new nodes per side (17)
-constexpr int JOBCAP = 512;            // queued fit jobs per sweep workgroup (>= one tile's 256)
+constexpr int JOBCAP = 384;            // queued fit jobs per sweep workgroup (>= one tile's 256)
 
 // marker-position mask bits of a tile: any marker; within STRIP cells of a
 // side or corner; on the tile's own left / bottom border edge (shared with
@@ -161,55 +161,177 @@ struct Tile {
   }
 };
 
-// The same view over global memory (old state, advected offsets and
-// displacements written by the sweep, new colours): used by the fit kernel,
-// where one lane handles one new unaligned marker.
+// One of 8 or 3 named registers, chosen by a tree of selects on the bits of
+// k (values kept in an array would be read with an index, from scratch)
+__device__ __forceinline__ double pick8(int k, double v0, double v1, double v2, double v3, double v4, double v5,
+                                        double v6, double v7) {
+  const bool b0 = (k & 1) != 0, b1 = (k & 2) != 0, b2 = (k & 4) != 0;
+  const double x01 = b0 ? v1 : v0, x23 = b0 ? v3 : v2, x45 = b0 ? v5 : v4, x67 = b0 ? v7 : v6;
+  const double y03 = b1 ? x23 : x01, y47 = b1 ? x67 : x45;
+  return b2 ? y47 : y03;
+}
+__device__ __forceinline__ double pick3(int k, double v0, double v1, double v2) {
+  const double x01 = (k & 1) != 0 ? v1 : v0;
+  return (k & 2) != 0 ? v2 : x01;
+}
+
+// One fit job's neighbourhood (used by the fit kernel, one lane per new
+// unaligned marker on line a, row b), gathered in one round of independent
+// loads: old node colours a-2..a+2 x b-1..b+2 and old centre colours
+// a-2..a+1 x b-1..b+1 as bit masks, the new colours of the line's two nodes,
+// the advected offsets s' of the aligned edges a-2..a+1 on rows b and b+1 and
+// the (t, d) pairs of the unaligned edges a-1..a+1 on row b. That covers every
+// read of the crossing search, the circles' inner points and the centre rules;
+// only the chain neighbours one row up or down or two lines away are read
+// from memory. Window slots outside the grid are read at the nearest edge
+// inside it (colours then masked to 0) and never used: every access of the
+// logic is guarded by the grid bounds.
 template <int DIR>
-struct GView {
+struct JobView {
   GMap<DIR> G;
-  int na, nb;
+  int na, nb, a, b;
   const GL uint8_t *__restrict__ col;   // old node colours
   const GL uint8_t *__restrict__ cen;   // old centre colours
   const GL uint8_t *__restrict__ ncol;  // new node colours
   const GL double *__restrict__ sp;     // aligned: s' (present edges)
   const GL double *__restrict__ td;     // unaligned: (old offset t, displacement d) pairs (present edges)
-  __device__ GView(int nx, int ny, const uint8_t *col_, const uint8_t *cen_, const uint8_t *ncol_, const double *sp_,
-                   const double *td_)
-      : G(nx, ny), na(G.na), nb(G.nb), col(gp(col_)), cen(gp(cen_)), ncol(gp(ncol_)), sp(gp(sp_)), td(gp(td_)) {}
-  __device__ int C(int a, int b) const { return col[G.node(a, b)]; }
-  __device__ bool presA(int a, int b) const { return C(a, b) != C(a + 1, b); }
-  __device__ bool presU(int a, int b) const { return C(a, b) != C(a, b + 1); }
-  __device__ double spv(int a, int b) const { return sp[G.ale(a, b)]; }
-  __device__ double dU(int a, int b) const { return td[2 * G.une(a, b) + 1]; }
-  __device__ double tU(int a, int b) const { return td[2 * G.une(a, b)]; }
-  __device__ int cenv(int p, int q) const { return cen[G.cell(p, q)]; }
+  uint32_t cm = 0;  // old node (a-2+i, b-1+j): bit j*5+i
+  uint32_t em = 0;  // old centre (a-2+i, b-1+j): bit j*4+i
+  uint32_t nm = 0;  // new colours of nodes (a,b) and (a,b+1): bits 0, 1
+  double s0, s1, s2, s3, s4, s5, s6, s7;  // s' of aligned (a-2+i, b+j): s<j*4+i>
+  double t0, t1, t2, d0, d1, d2;          // (t, d) of unaligned (a-1+i, b): t<i>, d<i>
+  __device__ JobView(const SweepView &W, int a_, int b_)
+      : G(W.nx, W.ny), na(G.na), nb(G.nb), a(a_), b(b_), col(gp(W.col)), cen(gp(W.cen)), ncol(gp(W.ncol)),
+        sp(gp(W.sp)), td(gp(W.dd)) {
+    // Every load is unconditional (all issue before the first wait): indices
+    // are clamped into the grid and slots outside it are masked afterwards.
+    // The colours of a window row that is contiguous in memory (frame rows
+    // for the x sweep, frame columns for the y sweep) come from the two
+    // aligned words holding its first in-grid byte: the row needs at most 5
+    // bytes, at most 3 after the word boundary. Arrays start 256-byte aligned
+    // and each colour array is followed by another array, so the read past a
+    // row's end (at most 5 bytes) stays inside the workspace.
+    auto cl = [](int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); };
+    auto words = [](const GL uint8_t *base, size_t first, size_t *at) -> uint64_t {
+      const size_t d = first & ~(size_t)3;
+      const GL uint32_t *w = (const GL uint32_t *)(base + d);
+      *at = d;
+      return (uint64_t)w[0] | ((uint64_t)w[1] << 32);
+    };
+    // node (x, y) of the window: its bit in the words holding it
+    auto bitOf = [](uint64_t w, size_t at, size_t idx) -> uint32_t { return (uint32_t)(w >> (8 * (idx - at))) & 1u; };
+    constexpr int NR = DIR == 0 ? 4 : 5;   // memory rows of the node window
+    constexpr int ER = DIR == 0 ? 3 : 4;   // memory rows of the centre window
+    uint64_t nw[NR], ew[ER];
+    size_t nat[NR], eat[ER];
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+      // x sweep: row y = b-1+r from x = a-2; y sweep: row a-2+r from b-1
+      const size_t first = DIR == 0 ? G.node(max(a - 2, 0), cl(b - 1 + r, 0, nb)) : G.node(cl(a - 2 + r, 0, na), max(b - 1, 0));
+      nw[r] = words(col, first, &nat[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < ER; r++) {
+      const size_t first =
+          DIR == 0 ? G.cell(max(a - 2, 0), cl(b - 1 + r, 0, nb - 1)) : G.cell(cl(a - 2 + r, 0, na - 1), max(b - 1, 0));
+      ew[r] = words(cen, first, &eat[r]);
+    }
+    const uint8_t n0 = ncol[G.node(a, b)], n1 = ncol[G.node(a, b + 1)];
+    auto al = [&](int i, int j) -> double { return sp[G.ale(cl(a - 2 + i, 0, na - 1), b + j)]; };
+    s0 = al(0, 0), s1 = al(1, 0), s2 = al(2, 0), s3 = al(3, 0);
+    s4 = al(0, 1), s5 = al(1, 1), s6 = al(2, 1), s7 = al(3, 1);
+    // (t, d) pairs are 16-byte aligned: one load each
+    struct alignas(16) TD {
+      double t, d;
+    };
+    auto un = [&](int i) -> TD {
+      const GL TD *q = (const GL TD *)td + G.une(cl(a - 1 + i, 0, na), b);
+      return TD{q->t, q->d};
+    };
+    const TD p0 = un(0), p1 = un(1), p2 = un(2);
+    t0 = p0.t, t1 = p1.t, t2 = p2.t;
+    d0 = p0.d, d1 = p1.d, d2 = p2.d;
+#pragma unroll
+    for (int j = 0; j < 4; j++)
+#pragma unroll
+      for (int i = 0; i < 5; i++) {
+        const int x = a - 2 + i, y = b - 1 + j;
+        if (x >= 0 && x <= na && y >= 0 && y <= nb) {
+          const int r = DIR == 0 ? j : i;
+          cm |= bitOf(nw[r], nat[r], G.node(x, y)) << (j * 5 + i);
+        }
+      }
+#pragma unroll
+    for (int j = 0; j < 3; j++)
+#pragma unroll
+      for (int i = 0; i < 4; i++) {
+        const int x = a - 2 + i, y = b - 1 + j;
+        if (x >= 0 && x < na && y >= 0 && y < nb) {
+          const int r = DIR == 0 ? j : i;
+          em |= bitOf(ew[r], eat[r], G.cell(x, y)) << (j * 4 + i);
+        }
+      }
+    nm = (uint32_t)(n0 & 1u) | ((uint32_t)(n1 & 1u) << 1);
+  }
+  __device__ int C(int p, int q) const {
+    const int i = p - (a - 2), j = q - (b - 1);
+    if (i >= 0 && i < 5 && j >= 0 && j < 4) return (int)((cm >> (j * 5 + i)) & 1u);
+    return col[G.node(p, q)];
+  }
+  __device__ int cenv(int p, int q) const {
+    const int i = p - (a - 2), j = q - (b - 1);
+    if (i >= 0 && i < 4 && j >= 0 && j < 3) return (int)((em >> (j * 4 + i)) & 1u);
+    return cen[G.cell(p, q)];
+  }
+  __device__ bool presA(int p, int q) const { return C(p, q) != C(p + 1, q); }
+  __device__ double spv(int p, int q) const {
+    const int i = p - (a - 2), j = q - b;
+    if (i >= 0 && i < 4 && j >= 0 && j < 2) return pick8(j * 4 + i, s0, s1, s2, s3, s4, s5, s6, s7);
+    return sp[G.ale(p, q)];
+  }
+  __device__ double tU(int p, int q) const {
+    const int i = p - (a - 1);
+    if (q == b && i >= 0 && i < 3) return pick3(i, t0, t1, t2);
+    return td[2 * G.une(p, q)];
+  }
+  __device__ double dU(int p, int q) const {
+    const int i = p - (a - 1);
+    if (q == b && i >= 0 && i < 3) return pick3(i, d0, d1, d2);
+    return td[2 * G.une(p, q) + 1];
+  }
   __device__ uint16_t segc(int p, int q) const {
     return segCodeOf(C(p, q), C(p + 1, q), C(p + 1, q + 1), C(p, q + 1), cenv(p, q));
   }
-  __device__ int newC(int a, int b) const { return ncol[G.node(a, b)]; }
-  __device__ int landers(int a, int b, int *keepSrc) const {
+  __device__ int newC(int p, int q) const {
+    if (p == a && q == b) return (int)(nm & 1u);
+    if (p == a && q == b + 1) return (int)((nm >> 1) & 1u);
+    return ncol[G.node(p, q)];
+  }
+  // aligned markers landing on edge (p,q): their number and the kept source
+  // (-1 when none): one lander is kept, of three the middle source
+  __device__ int landers(int p, int q, int *keepSrc) const {
     int n = 0, first = -1, second = -1;
-    if (a >= 1 && presA(a - 1, b) && spv(a - 1, b) >= 1.0) { first = a - 1; n++; }
-    if (presA(a, b)) {
-      const double s = spv(a, b);
-      if (s >= 0.0 && s < 1.0) {
-        if (n == 0) first = a;
-        else second = a;
+    if (p >= 1 && presA(p - 1, q) && spv(p - 1, q) >= 1.0) { first = p - 1; n++; }
+    if (presA(p, q)) {
+      const double v = spv(p, q);
+      if (v >= 0.0 && v < 1.0) {
+        if (n == 0) first = p;
+        else second = p;
         n++;
       }
     }
-    if (a + 1 < na && presA(a + 1, b) && spv(a + 1, b) < 0.0) {
-      if (n == 0) first = a + 1;
-      else if (n == 1) second = a + 1;
+    if (p + 1 < na && presA(p + 1, q) && spv(p + 1, q) < 0.0) {
+      if (n == 0) first = p + 1;
+      else if (n == 1) second = p + 1;
       n++;
     }
     *keepSrc = n == 1 ? first : (n == 3 ? second : -1);
     return n;
   }
   __device__ int landTarget(int p, int q) const {
-    const double s = spv(p, q);
-    const int t = s >= 1.0 ? p + 1 : (s < 0.0 ? p - 1 : p);
-    return (t < 0 || t >= na) ? -1 : t;
+    const double v = spv(p, q);
+    const int tg = v >= 1.0 ? p + 1 : (v < 0.0 ? p - 1 : p);
+    return (tg < 0 || tg >= na) ? -1 : tg;
   }
   __device__ bool keptOn(int p, int q, int target) const {
     if (landTarget(p, q) != target) return false;
@@ -256,7 +378,7 @@ __device__ __forceinline__ bool leftOf(const View &T, MRef m, int a0) {
 // chain neighbour of the marker on edge e of old cell (p,q), away from it:
 // its partner in the cell across edge e
 template <class View>
-__device__ bool chainNb(const View &T, int p, int q, int e, MRef *out) {
+__device__ __forceinline__ bool chainNb(const View &T, int p, int q, int e, MRef *out) {
   int pp = p, qq = q;
   if (e == 0) qq = q - 1;
   else if (e == 1) pp = p + 1;
@@ -347,7 +469,7 @@ struct Counts {
 // colours): its offset, and the centre-CV results for the cell right of the
 // line (cell a) and left of it (cell a-1): -1 or the new centre colour.
 template <class View>
-__device__ double newUnaligned(const View &T, int a, int b, int *resRight, int *resLeft, const Counts &cnt, bool count,
+__device__ __forceinline__ double newUnaligned(const View &T, int a, int b, int *resRight, int *resLeft, const Counts &cnt, bool count,
                                bool line) {
   *resRight = -1;
   *resLeft = -1;
@@ -476,18 +598,18 @@ __device__ __forceinline__ uint32_t uni(uint32_t x) { return __builtin_amdgcn_re
 
 // ONE: the engine holds a single grid, whose descriptor comes with the kernel
 // arguments (loop-invariant, no descriptor loads per tile).
-constexpr int SWEEP_BS = 256;
-constexpr int STAGE_SLOTS = 2;  // halo nodes / cells staged per thread
+constexpr int SWEEP_BS = 128;
+constexpr int STAGE_SLOTS = (NH * NH + SWEEP_BS - 1) / SWEEP_BS;  // halo nodes / cells staged per thread
+constexpr int NTILES_LDS = 32;  // tile entries read once at the start
 
 template <int DIR, bool ONE>
 __global__ __launch_bounds__(SWEEP_BS, 8) void k_sweep(SweepArgs A, const Inst *__restrict__ inst) {
   __shared__ uint8_t sCol[NH][NH];
-  __shared__ uint8_t sCen[NE][NE];
   __shared__ double sSp[NH][NE];
   __shared__ uint32_t sRow[NH];     // old colours, bit la of frame row lb
   __shared__ uint32_t sNRow[NN];    // new colours, bit a-a0 of row b-b0
   __shared__ uint32_t sRecv[NN];    // new aligned edges (a,b) that receive a lander, bit a-a0
-  __shared__ uint2 sTiles[64];      // this workgroup's first (tile, grid) entries
+  __shared__ uint2 sTiles[NTILES_LDS];  // this workgroup's first (tile, grid) entries
   __shared__ uint16_t sAdv[2 * NH * NE];
   __shared__ uint2 sJob[JOBCAP];    // new interior unaligned markers of this workgroup's tiles
   __shared__ uint32_t sNAdv, sNJob, sHas, sJobBase;
@@ -509,25 +631,25 @@ __global__ __launch_bounds__(SWEEP_BS, 8) void k_sweep(SweepArgs A, const Inst *
     if (tid == 0) sNJob = 0;
   };
 
-  // Staging of colours and centre colours: each thread owns two node slots
-  // and two cell slots of the halo (memory order). The next tile's bytes are
-  // fetched into registers while the current tile computes.
-  static_assert(NH * NH <= STAGE_SLOTS * SWEEP_BS && NE * NE <= STAGE_SLOTS * SWEEP_BS, "staging slots per thread");
-  uint8_t pc[STAGE_SLOTS], pe[STAGE_SLOTS];
+  // Staging of colours: each thread owns STAGE_SLOTS node slots of the halo
+  // (memory order). The next tile's bytes are fetched into registers while the
+  // current tile computes.
+  static_assert(NH * NH <= STAGE_SLOTS * SWEEP_BS && TS * TS % SWEEP_BS == 0, "staging slots per thread");
+  uint8_t pc[STAGE_SLOTS];
 #pragma unroll
-  for (int q = 0; q < STAGE_SLOTS; q++) pc[q] = pe[q] = 0;
+  for (int q = 0; q < STAGE_SLOTS; q++) pc[q] = 0;
   auto prefetch = [&](uint2 te) {
     const uint32_t gt = te.x;
     int nx, ny, ntx;
     uint32_t tile0;
-    const GL uint8_t *col, *cen;
+    const GL uint8_t *col;
     if (ONE) {
       nx = A.one.nx, ny = A.one.ny, ntx = A.one.ntx, tile0 = A.one.tile0;
-      col = gp(A.one.col), cen = gp(A.one.cen);
+      col = gp(A.one.col);
     } else {
       const Inst &I = inst[te.y];
       nx = I.nx, ny = I.ny, ntx = I.ntx, tile0 = I.tile0;
-      col = gp(I.col[cur]), cen = gp(I.cen[cur]);
+      col = gp(I.col[cur]);
     }
     const uint32_t lt = gt - tile0;
     const int px0 = (int)(lt % (uint32_t)ntx) * TS, py0 = (int)(lt / (uint32_t)ntx) * TS;
@@ -536,16 +658,8 @@ __global__ __launch_bounds__(SWEEP_BS, 8) void k_sweep(SweepArgs A, const Inst *
       const int x = px0 - HALO + k % NH, y = py0 - HALO + k / NH;
       return (x >= 0 && y >= 0 && x <= nx && y <= ny) ? col[(size_t)y * (nx + 1) + x] : (uint8_t)0;
     };
-    auto cell = [&](int k) -> uint8_t {
-      if (k >= NE * NE) return 0;
-      const int x = px0 - HALO + k % NE, y = py0 - HALO + k / NE;
-      return (x >= 0 && y >= 0 && x < nx && y < ny) ? cen[(size_t)y * nx + x] : (uint8_t)0;
-    };
 #pragma unroll
-    for (int q = 0; q < STAGE_SLOTS; q++) {
-      pc[q] = node(tid + SWEEP_BS * q);
-      pe[q] = cell(tid + SWEEP_BS * q);
-    }
+    for (int q = 0; q < STAGE_SLOTS; q++) pc[q] = node(tid + SWEEP_BS * q);
   };
 
   const uint32_t ntile = *A.count;
@@ -565,11 +679,11 @@ __global__ __launch_bounds__(SWEEP_BS, 8) void k_sweep(SweepArgs A, const Inst *
     itEnd = min(ntile, itBeg + chunk);
     itStep = 1;
   }
-  if (tid < 64 && itBeg + tid * itStep < itEnd) sTiles[tid] = entry(itBeg + tid * itStep);
+  if (tid < NTILES_LDS && itBeg + tid * itStep < itEnd) sTiles[tid] = entry(itBeg + tid * itStep);
   __syncthreads();
   auto tileAt = [&](uint32_t it) -> uint2 {
     const uint32_t k = (it - itBeg) / itStep;
-    const uint2 e = k < 64 ? sTiles[k] : entry(it);
+    const uint2 e = k < NTILES_LDS ? sTiles[k] : entry(it);
     return make_uint2(uni(e.x), uni(e.y));
   };
   if (itBeg < itEnd) prefetch(tileAt(itBeg));
@@ -615,7 +729,27 @@ __global__ __launch_bounds__(SWEEP_BS, 8) void k_sweep(SweepArgs A, const Inst *
       sHas = 0;
     }
     if (tid < NN) sRecv[tid] = 0;
-    // --- stage old colours and centre colours --------------------------------
+    // centre colours of the tile's own cells carry over unchanged (the centre
+    // kernel applies rules (1)-(5) afterwards): loaded before the marker loads,
+    // stored with the tile's other outputs
+    constexpr int CEN_SLOTS = TS * TS / SWEEP_BS;
+    uint8_t ce[CEN_SLOTS];
+    {
+      const GL uint8_t *__restrict__ cen = gp(W.cen);
+#pragma unroll
+      for (int q = 0; q < CEN_SLOTS; q++) {
+        const int k = tid + SWEEP_BS * q, x = x0 + k % TS, y = y0 + k / TS;
+        ce[q] = (x < nx && y < ny) ? cen[(size_t)y * nx + x] : (uint8_t)0;
+      }
+    }
+    auto storeCen = [&]() {
+#pragma unroll
+      for (int q = 0; q < CEN_SLOTS; q++) {
+        const int k = tid + SWEEP_BS * q, x = x0 + k % TS, y = y0 + k / TS;
+        if (x < nx && y < ny) ncen[(size_t)y * nx + x] = ce[q];
+      }
+    };
+    // --- stage old colours -----------------------------------------------------
     {
       auto putNode = [&](int k, uint8_t c) {
         if (k >= NH * NH) return;
@@ -623,17 +757,8 @@ __global__ __launch_bounds__(SWEEP_BS, 8) void k_sweep(SweepArgs A, const Inst *
         if (DIR == 0) sCol[hy][hx] = c;
         else sCol[hx][hy] = c;
       };
-      auto putCell = [&](int k, uint8_t c) {
-        if (k >= NE * NE) return;
-        const int hx = k % NE, hy = k / NE;
-        if (DIR == 0) sCen[hy][hx] = c;
-        else sCen[hx][hy] = c;
-      };
 #pragma unroll
-      for (int q = 0; q < STAGE_SLOTS; q++) {
-        putNode(tid + SWEEP_BS * q, pc[q]);
-        putCell(tid + SWEEP_BS * q, pe[q]);
-      }
+      for (int q = 0; q < STAGE_SLOTS; q++) putNode(tid + SWEEP_BS * q, pc[q]);
     }
     // colour-1 nodes set their bit in the frame-row masks (zero since the
     // previous tile)
@@ -696,9 +821,8 @@ __global__ __launch_bounds__(SWEEP_BS, 8) void k_sweep(SweepArgs A, const Inst *
         const int hx = li + HALO, hy = lj + HALO;
         if ((li < TS || x == nx) && (lj < TS || y == ny))
           ncol[(size_t)y * (nx + 1) + x] = DIR == 0 ? sCol[hy][hx] : sCol[hx][hy];
-        if (li < TS && lj < TS && x < nx && y < ny)
-          ncen[(size_t)y * nx + x] = DIR == 0 ? sCen[hy][hx] : sCen[hx][hy];
       }
+      storeCen();
       if (tid == 0) {
         A.has[gt] = 0;
         cnt.add(C_TILES_EMPTY, 1u);
@@ -826,12 +950,7 @@ __global__ __launch_bounds__(SWEEP_BS, 8) void k_sweep(SweepArgs A, const Inst *
         }
       }
     }
-    // centre colours carry over; the centre kernel applies rules (1)-(5)
-    for (int k = tid; k < TS * TS; k += blockDim.x) {
-      const int hx = k % TS, hy = k / TS;
-      const int x = x0 + hx, y = y0 + hy;
-      if (x < nx && y < ny) ncen[(size_t)y * nx + x] = DIR == 0 ? sCen[hy + HALO][hx + HALO] : sCen[hx + HALO][hy + HALO];
-    }
+    storeCen();
     if (hasm) atomicOr(&sHas, hasm);
     __syncthreads();
     if (tid == 0) A.has[gt] = (uint16_t)sHas;
@@ -869,11 +988,11 @@ __device__ __forceinline__ void eachGrid(uint32_t k, F f) {
 
 template <int DIR>
 __device__ __forceinline__ void fitJob(const SweepView &W, uint32_t e, const Counts &cnt) {
-  const GView<DIR> V(W.nx, W.ny, W.col, W.cen, W.ncol, W.sp, W.dd);
   GL double *__restrict__ unn = gp(DIR == 0 ? W.nvoff : W.nhoff);
   int a, b;
   if (DIR == 0) { b = (int)(e / (uint32_t)(W.nx + 1)); a = (int)(e % (uint32_t)(W.nx + 1)); }
   else { a = (int)(e / (uint32_t)W.nx); b = (int)(e % (uint32_t)W.nx); }
+  const JobView<DIR> V(W, a, b);
   int rR, rL;
   const double y = newUnaligned(V, a, b, &rR, &rL, cnt, true, W.line != 0);
   unn[e] = y;
@@ -1426,6 +1545,8 @@ __global__ __launch_bounds__(FRAC_BS, 8) void k_frac_curv(FracArgs A, const Inst
     const uint32_t lt = te.x - I.tile0;
     const int tx = (int)(lt % (uint32_t)I.ntx), ty = (int)(lt / (uint32_t)I.ntx);
     const int x0 = tx * TS, y0 = ty * TS;
+    // every cell's 4x4 gradient nodes lie inside the grid
+    const bool inner = x0 >= 1 && y0 >= 1 && x0 + TS + 1 <= nx && y0 + TS + 1 <= ny;
     ntiles_done++;
 #pragma unroll
     for (int q = 0; q < NSLOT_N; q++) {
@@ -1479,9 +1600,22 @@ __global__ __launch_bounds__(FRAC_BS, 8) void k_frac_curv(FracArgs A, const Inst
           double kap = 0.0;
           if (sN[lj + 3][li + 3] >= 2) {
             interf++;
-            int ncx, ncy;
-            nodeGradient(i, j, nx, ny, [&](int a, int b) -> int { return sNode[b - y0 + 3][a - x0 + 3]; }, &ncx,
-                         &ncy);
+            int ncx = 0, ncy = 0;
+            if (inner) {
+              // nodes i-1..i+2, j-1..j+2 are all inside the grid: the same sums
+              // without mirroring (node (i-1, j-1) is slot (li+2, lj+2))
+#pragma unroll
+              for (int m = 0; m < 4; m++)
+                ncx += sNode[lj + 2 + m][li + 5] + sNode[lj + 2 + m][li + 4] - sNode[lj + 2 + m][li + 3] -
+                       sNode[lj + 2 + m][li + 2];
+#pragma unroll
+              for (int l = 0; l < 4; l++)
+                ncy += sNode[lj + 5][li + 2 + l] + sNode[lj + 4][li + 2 + l] - sNode[lj + 3][li + 2 + l] -
+                       sNode[lj + 2][li + 2 + l];
+            } else {
+              nodeGradient(i, j, nx, ny, [&](int a, int b) -> int { return sNode[b - y0 + 3][a - x0 + 3]; }, &ncx,
+                           &ncy);
+            }
             const int firstRows = abs(ncy) >= abs(ncx) ? 0 : 1;
             auto getC = [&](int a, int b) -> double { return sC[b - y0 + 3][a - x0 + 3]; };
             auto getN = [&](int a, int b) -> int { return sN[b - y0 + 3][a - x0 + 3]; };
