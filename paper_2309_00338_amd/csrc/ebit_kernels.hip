@@ -45,6 +45,7 @@ constexpr int NH = TS + 2 * HALO + 1;  // staged nodes per side (21)
 constexpr int NE = NH - 1;             // staged cells / edges per side (20)
 constexpr int NN = TS + 1;             // new nodes per side (17)
 constexpr int JOBCAP = 384;            // queued fit jobs per sweep workgroup (>= one tile's 256)
+constexpr uint32_t NXCD = 8;          // XCDs of the GPU, each with its own L2
 
 // marker-position mask bits of a tile: any marker; within STRIP cells of a
 // side or corner; on the tile's own left / bottom border edge (shared with
@@ -669,7 +670,15 @@ __global__ __launch_bounds__(SWEEP_BS, 8) void k_sweep(SweepArgs A, const Inst *
   // chunk of it for many (consecutive entries mostly share a grid, and so do
   // the fit jobs the workgroup queues, which keeps fit wavefronts on one grid)
   uint32_t itBeg, itEnd, itStep;
-  if (ONE) {
+  if (ONE && gridDim.x % NXCD == 0u) {
+    // workgroups are dispatched round-robin over the XCDs, each with its own
+    // L2: XCD x takes the x-th share of the list (neighbouring tiles, whose
+    // halos overlap, sit close together in it), a stride of it per workgroup
+    const uint32_t x = blockIdx.x % NXCD, per = gridDim.x / NXCD, share = (ntile + NXCD - 1u) / NXCD;
+    itBeg = x * share + blockIdx.x / NXCD;
+    itEnd = min(ntile, (x + 1u) * share);
+    itStep = per;
+  } else if (ONE) {
     itBeg = blockIdx.x;
     itEnd = ntile;
     itStep = gridDim.x;
@@ -1299,32 +1308,34 @@ __device__ double cellFraction(const FracCtx &P, int i, int j, int kBL, int kBR,
   const double vl = pl ? P.voff[(size_t)j * W1 + i] : 0.0;
   const double vr = pr ? P.voff[(size_t)j * W1 + i + 1] : 0.0;
   if (n == 2) {
-    // shoelace over the colour-1 corners and both markers, counter-clockwise
-    // from the bottom-left corner; each edge term is added as its second
-    // vertex arrives, the closing edge last
-    double fx = 0.0, fy = 0.0, qx = 0.0, qy = 0.0, acc = 0.0;
-    bool started = false;
-    auto vert = [&](double x, double y) {
-      if (!started) {
-        fx = x;
-        fy = y;
-        started = true;
+    // the chord cuts off a corner triangle (markers on two adjacent edges) or
+    // splits the cell into two trapezoids (opposite edges): the area of the
+    // part holding corner k, which has k's colour (the same area as the
+    // polygon of the colour-1 corners and the markers, up to rounding)
+    double area;
+    int k;
+    if (pb && pt) {
+      area = 0.5 * (hb + ht);
+      k = kBL;
+    } else if (pl && pr) {
+      area = 0.5 * (vl + vr);
+      k = kBL;
+    } else if (pb) {
+      if (pl) {
+        area = 0.5 * (hb * vl);
+        k = kBL;
       } else {
-        acc += qx * y - x * qy;
+        area = 0.5 * ((1.0 - hb) * vr);
+        k = kBR;
       }
-      qx = x;
-      qy = y;
-    };
-    if (kBL) vert(0.0, 0.0);
-    if (pb) vert(hb, 0.0);
-    if (kBR) vert(1.0, 0.0);
-    if (pr) vert(1.0, vr);
-    if (kTR) vert(1.0, 1.0);
-    if (pt) vert(ht, 1.0);
-    if (kTL) vert(0.0, 1.0);
-    if (pl) vert(0.0, vl);
-    acc += qx * fy - fx * qy;
-    return 0.5 * acc;
+    } else if (pl) {
+      area = 0.5 * (ht * (1.0 - vl));
+      k = kTL;
+    } else {
+      area = 0.5 * ((1.0 - ht) * (1.0 - vr));
+      k = kTR;
+    }
+    return k ? area : 1.0 - area;
   }
   // four markers: isolated corner triangles keep their corner colour, the
   // central region carries the centre colour
@@ -1470,6 +1481,7 @@ __device__ bool ghfFit(int nx, int ny, double h, int i, int j, int gx, int gy, G
 // C and zero curvature, one 8-byte store per lane and row, lanes along a grid
 // row. MODE 1: C only; 2: kappa from the caller's C; 3: both.
 constexpr int FRAC_BS = 256;
+constexpr int NEAR_ENT = 16;  // tile entries a near workgroup keeps in LDS
 constexpr int FRAC_FILL_TILES = FRAC_BS / TS;
 constexpr int NS_FILL_TILES = 16;
 
@@ -1507,6 +1519,7 @@ __global__ __launch_bounds__(FRAC_BS, 8) void k_frac_curv(FracArgs A, const Inst
   __shared__ uint8_t sN[W][W];
   __shared__ uint8_t sB[W][W];
   __shared__ uint32_t sCnt[2];
+  __shared__ uint2 sEnt[NEAR_ENT];
   if (tid < 2) sCnt[tid] = 0;
   if ((MODE & 2) && blockIdx.x == 0 && tid == 0) *A.ghfClear = 0u;  // the next curvature launch's count
   uint32_t interf = 0, hffail = 0;
@@ -1518,8 +1531,15 @@ __global__ __launch_bounds__(FRAC_BS, 8) void k_frac_curv(FracArgs A, const Inst
   uint8_t pn[NSLOT_N];
 #pragma unroll
   for (int q = 0; q < NSLOT_N; q++) pn[q] = 0;
-  auto entry = [&](uint32_t it) -> uint2 {
-    const uint2 e = A.list[it];
+  // this workgroup's first tile entries, read once: the colour prefetch of
+  // the next tile then needs no load of its entry first
+  if (tid < NEAR_ENT) {
+    const uint32_t it = blockIdx.x + (uint32_t)tid * (uint32_t)A.nearBlocks;
+    if (it < ntile) sEnt[tid] = A.list[it];
+  }
+  __syncthreads();
+  auto entry = [&](uint32_t it, uint32_t n) -> uint2 {
+    const uint2 e = n < (uint32_t)NEAR_ENT ? sEnt[n] : A.list[it];
     return make_uint2(uni(e.x), uni(e.y));
   };
   auto prefetch = [&](uint2 te) {
@@ -1535,10 +1555,11 @@ __global__ __launch_bounds__(FRAC_BS, 8) void k_frac_curv(FracArgs A, const Inst
       pn[q] = (k < WN * WN && gx >= 0 && gy >= 0 && gx <= nx && gy <= ny) ? col[(size_t)gy * (nx + 1) + gx] : 0;
     }
   };
-  if (blockIdx.x < ntile) prefetch(entry(blockIdx.x));
-  for (uint32_t it = blockIdx.x; it < ntile; it += (uint32_t)A.nearBlocks) {
+  if (blockIdx.x < ntile) prefetch(entry(blockIdx.x, 0));
+  uint32_t n = 0;  // this workgroup's tile count
+  for (uint32_t it = blockIdx.x; it < ntile; it += (uint32_t)A.nearBlocks, n++) {
     __syncthreads();
-    const uint2 te = entry(it);
+    const uint2 te = entry(it, n);
     const Inst &I = ONE ? A.one : inst[te.y];
     const int nx = I.nx, ny = I.ny;
     const FracCtx P{nx, ny, gp(I.col[A.cur]), gp(I.cen[A.cur]), gp(I.hoff[A.cur]), gp(I.voff[A.cur])};
@@ -1584,7 +1605,7 @@ __global__ __launch_bounds__(FRAC_BS, 8) void k_frac_curv(FracArgs A, const Inst
       sB[lj][li] = (uint8_t)kBL;
     }
     // the next tile's colours are fetched while this one's heights run
-    if (it + (uint32_t)A.nearBlocks < ntile) prefetch(entry(it + (uint32_t)A.nearBlocks));
+    if (it + (uint32_t)A.nearBlocks < ntile) prefetch(entry(it + (uint32_t)A.nearBlocks, n + 1));
     __syncthreads();
 #pragma unroll 1
     for (int r = 0; r < TS * TS / FRAC_BS; r++) {
@@ -1833,10 +1854,18 @@ __global__ __launch_bounds__(256) void k_ns(NsArgs A, const Inst *__restrict__ i
   __shared__ uint8_t sNode[WC + 1][WC + 1];
   __shared__ double sC[WC][WC], sK[WC][WC];
   __shared__ uint8_t sDef[WC][WC];
+  __shared__ uint2 sEnt[NEAR_ENT];
   const uint32_t ntile = *A.count;
-  for (uint32_t it = blockIdx.x; it < ntile; it += (uint32_t)A.nearBlocks) {
+  // this workgroup's first tile entries, read once
+  if (tid < NEAR_ENT) {
+    const uint32_t it = blockIdx.x + (uint32_t)tid * (uint32_t)A.nearBlocks;
+    if (it < ntile) sEnt[tid] = A.list[it];
+  }
+  uint32_t n = 0;
+  for (uint32_t it = blockIdx.x; it < ntile; it += (uint32_t)A.nearBlocks, n++) {
     __syncthreads();
-    const uint2 te = make_uint2(uni(A.list[it].x), uni(A.list[it].y));
+    const uint2 e = n < (uint32_t)NEAR_ENT ? sEnt[n] : A.list[it];
+    const uint2 te = make_uint2(uni(e.x), uni(e.y));
     const Inst &I = ONE ? A.one : inst[te.y];
     const int nx = I.nx, ny = I.ny;
     const uint32_t lt = te.x - I.tile0;
