@@ -73,7 +73,8 @@ struct Inst {
   uint64_t uoff, voffv;  // element offsets of u and v in the call's velocity buffers
   uint64_t coff, koff;   // element offsets of C and kappa in the call's field buffers
   uint8_t *col[2];       // node colours, (ny+1) x (nx+1), both copies
-  uint8_t *cen[2];       // centre colours, ny x nx
+  uint8_t *cen[2];       // centre colours, ny x nx: one array in both entries (the centre kernel
+                         // updates it in place after the fits have read the old values)
   double *hoff[2];       // H-edge offsets, (ny+1) x nx
   double *voff[2];       // V-edge offsets, ny x (nx+1)
   double *sp;            // advected aligned offsets s' of the current sweep

@@ -178,13 +178,13 @@ __device__ __forceinline__ double pick3(int k, double v0, double v1, double v2) 
 
 // One fit job's neighbourhood (used by the fit kernel, one lane per new
 // unaligned marker on line a, row b), gathered in one round of independent
-// loads: old node colours a-2..a+2 x b-1..b+2 and old centre colours
-// a-2..a+1 x b-1..b+1 as bit masks, the new colours of the line's two nodes,
+// loads: old node colours a-2..a+2 x b-1..b+2 as a bit mask, the new colours
+// of the line's two nodes,
 // the advected offsets s' of the aligned edges a-2..a+1 on rows b and b+1 and
 // the (t, d) pairs of the unaligned edges a-1..a+1 on row b. That covers every
 // read of the crossing search, the circles' inner points and the centre rules;
-// only the chain neighbours one row up or down or two lines away are read
-// from memory. Window slots outside the grid are read at the nearest edge
+// only the chain neighbours one row up or down or two lines away, and the old
+// centre colour of a cell with four markers (rare), are read from memory. Window slots outside the grid are read at the nearest edge
 // inside it (colours then masked to 0) and never used: every access of the
 // logic is guarded by the grid bounds.
 template <int DIR>
@@ -197,7 +197,6 @@ struct JobView {
   const GL double *__restrict__ sp;     // aligned: s' (present edges)
   const GL double *__restrict__ td;     // unaligned: (old offset t, displacement d) pairs (present edges)
   uint32_t cm = 0;  // old node (a-2+i, b-1+j): bit j*5+i
-  uint32_t em = 0;  // old centre (a-2+i, b-1+j): bit j*4+i
   uint32_t nm = 0;  // new colours of nodes (a,b) and (a,b+1): bits 0, 1
   double s0, s1, s2, s3, s4, s5, s6, s7;  // s' of aligned (a-2+i, b+j): s<j*4+i>
   double t0, t1, t2, d0, d1, d2;          // (t, d) of unaligned (a-1+i, b): t<i>, d<i>
@@ -206,12 +205,12 @@ struct JobView {
         sp(gp(W.sp)), td(gp(W.dd)) {
     // Every load is unconditional (all issue before the first wait): indices
     // are clamped into the grid and slots outside it are masked afterwards.
-    // The colours of a window row that is contiguous in memory (frame rows
-    // for the x sweep, frame columns for the y sweep) come from the two
+    // The node colours of a window row that is contiguous in memory (frame
+    // rows for the x sweep, frame columns for the y sweep) come from the two
     // aligned words holding its first in-grid byte: the row needs at most 5
     // bytes, at most 3 after the word boundary. Arrays start 256-byte aligned
-    // and each colour array is followed by another array, so the read past a
-    // row's end (at most 5 bytes) stays inside the workspace.
+    // and each node-colour array is followed by another array, so the read
+    // past a row's end (at most 5 bytes) stays inside the workspace.
     auto cl = [](int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); };
     auto words = [](const GL uint8_t *base, size_t first, size_t *at) -> uint64_t {
       const size_t d = first & ~(size_t)3;
@@ -222,20 +221,13 @@ struct JobView {
     // node (x, y) of the window: its bit in the words holding it
     auto bitOf = [](uint64_t w, size_t at, size_t idx) -> uint32_t { return (uint32_t)(w >> (8 * (idx - at))) & 1u; };
     constexpr int NR = DIR == 0 ? 4 : 5;   // memory rows of the node window
-    constexpr int ER = DIR == 0 ? 3 : 4;   // memory rows of the centre window
-    uint64_t nw[NR], ew[ER];
-    size_t nat[NR], eat[ER];
+    uint64_t nw[NR];
+    size_t nat[NR];
 #pragma unroll
     for (int r = 0; r < NR; r++) {
       // x sweep: row y = b-1+r from x = a-2; y sweep: row a-2+r from b-1
       const size_t first = DIR == 0 ? G.node(max(a - 2, 0), cl(b - 1 + r, 0, nb)) : G.node(cl(a - 2 + r, 0, na), max(b - 1, 0));
       nw[r] = words(col, first, &nat[r]);
-    }
-#pragma unroll
-    for (int r = 0; r < ER; r++) {
-      const size_t first =
-          DIR == 0 ? G.cell(max(a - 2, 0), cl(b - 1 + r, 0, nb - 1)) : G.cell(cl(a - 2 + r, 0, na - 1), max(b - 1, 0));
-      ew[r] = words(cen, first, &eat[r]);
     }
     const uint8_t n0 = ncol[G.node(a, b)], n1 = ncol[G.node(a, b + 1)];
     auto al = [&](int i, int j) -> double { return sp[G.ale(cl(a - 2 + i, 0, na - 1), b + j)]; };
@@ -262,16 +254,6 @@ struct JobView {
           cm |= bitOf(nw[r], nat[r], G.node(x, y)) << (j * 5 + i);
         }
       }
-#pragma unroll
-    for (int j = 0; j < 3; j++)
-#pragma unroll
-      for (int i = 0; i < 4; i++) {
-        const int x = a - 2 + i, y = b - 1 + j;
-        if (x >= 0 && x < na && y >= 0 && y < nb) {
-          const int r = DIR == 0 ? j : i;
-          em |= bitOf(ew[r], eat[r], G.cell(x, y)) << (j * 4 + i);
-        }
-      }
     nm = (uint32_t)(n0 & 1u) | ((uint32_t)(n1 & 1u) << 1);
   }
   __device__ int C(int p, int q) const {
@@ -279,11 +261,7 @@ struct JobView {
     if (i >= 0 && i < 5 && j >= 0 && j < 4) return (int)((cm >> (j * 5 + i)) & 1u);
     return col[G.node(p, q)];
   }
-  __device__ int cenv(int p, int q) const {
-    const int i = p - (a - 2), j = q - (b - 1);
-    if (i >= 0 && i < 4 && j >= 0 && j < 3) return (int)((em >> (j * 4 + i)) & 1u);
-    return cen[G.cell(p, q)];
-  }
+  __device__ int cenv(int p, int q) const { return cen[G.cell(p, q)]; }
   __device__ bool presA(int p, int q) const { return C(p, q) != C(p + 1, q); }
   __device__ double spv(int p, int q) const {
     const int i = p - (a - 2), j = q - b;
@@ -300,8 +278,11 @@ struct JobView {
     if (q == b && i >= 0 && i < 3) return pick3(i, d0, d1, d2);
     return td[2 * G.une(p, q) + 1];
   }
+  // the centre colour only decides the pairing of a cell with four markers
   __device__ uint16_t segc(int p, int q) const {
-    return segCodeOf(C(p, q), C(p + 1, q), C(p + 1, q + 1), C(p, q + 1), cenv(p, q));
+    const int k0 = C(p, q), k1 = C(p + 1, q), k2 = C(p + 1, q + 1), k3 = C(p, q + 1);
+    const bool four = k0 != k1 && k1 != k2 && k3 != k2 && k0 != k3;
+    return segCodeOf(k0, k1, k2, k3, four ? cenv(p, q) : 0);
   }
   __device__ int newC(int p, int q) const {
     if (p == a && q == b) return (int)(nm & 1u);
@@ -635,7 +616,7 @@ __global__ __launch_bounds__(SWEEP_BS, 8) void k_sweep(SweepArgs A, const Inst *
   // Staging of colours: each thread owns STAGE_SLOTS node slots of the halo
   // (memory order). The next tile's bytes are fetched into registers while the
   // current tile computes.
-  static_assert(NH * NH <= STAGE_SLOTS * SWEEP_BS && TS * TS % SWEEP_BS == 0, "staging slots per thread");
+  static_assert(NH * NH <= STAGE_SLOTS * SWEEP_BS, "staging slots per thread");
   uint8_t pc[STAGE_SLOTS];
 #pragma unroll
   for (int q = 0; q < STAGE_SLOTS; q++) pc[q] = 0;
@@ -713,7 +694,6 @@ __global__ __launch_bounds__(SWEEP_BS, 8) void k_sweep(SweepArgs A, const Inst *
     GL double *__restrict__ unn = gp(DIR == 0 ? W.nvoff : W.nhoff);
     const GL double *__restrict__ vel = gp(W.vel);
     GL uint8_t *__restrict__ ncol = gp(W.ncol);
-    GL uint8_t *__restrict__ ncen = gp(W.ncen);
     GL double *__restrict__ spg = gp(W.sp);
     GL double *__restrict__ ddg = gp(W.dd);
     uint32_t *errg = W.err;  // written only on an error
@@ -738,26 +718,6 @@ __global__ __launch_bounds__(SWEEP_BS, 8) void k_sweep(SweepArgs A, const Inst *
       sHas = 0;
     }
     if (tid < NN) sRecv[tid] = 0;
-    // centre colours of the tile's own cells carry over unchanged (the centre
-    // kernel applies rules (1)-(5) afterwards): loaded before the marker loads,
-    // stored with the tile's other outputs
-    constexpr int CEN_SLOTS = TS * TS / SWEEP_BS;
-    uint8_t ce[CEN_SLOTS];
-    {
-      const GL uint8_t *__restrict__ cen = gp(W.cen);
-#pragma unroll
-      for (int q = 0; q < CEN_SLOTS; q++) {
-        const int k = tid + SWEEP_BS * q, x = x0 + k % TS, y = y0 + k / TS;
-        ce[q] = (x < nx && y < ny) ? cen[(size_t)y * nx + x] : (uint8_t)0;
-      }
-    }
-    auto storeCen = [&]() {
-#pragma unroll
-      for (int q = 0; q < CEN_SLOTS; q++) {
-        const int k = tid + SWEEP_BS * q, x = x0 + k % TS, y = y0 + k / TS;
-        if (x < nx && y < ny) ncen[(size_t)y * nx + x] = ce[q];
-      }
-    };
     // --- stage old colours -----------------------------------------------------
     {
       auto putNode = [&](int k, uint8_t c) {
@@ -831,7 +791,6 @@ __global__ __launch_bounds__(SWEEP_BS, 8) void k_sweep(SweepArgs A, const Inst *
         if ((li < TS || x == nx) && (lj < TS || y == ny))
           ncol[(size_t)y * (nx + 1) + x] = DIR == 0 ? sCol[hy][hx] : sCol[hx][hy];
       }
-      storeCen();
       if (tid == 0) {
         A.has[gt] = 0;
         cnt.add(C_TILES_EMPTY, 1u);
@@ -959,7 +918,8 @@ __global__ __launch_bounds__(SWEEP_BS, 8) void k_sweep(SweepArgs A, const Inst *
         }
       }
     }
-    storeCen();
+    // centre colours stay where they are (one array); the centre kernel
+    // applies rules (1)-(5) to the cells next to this sweep's new markers
     if (hasm) atomicOr(&sHas, hasm);
     __syncthreads();
     if (tid == 0) A.has[gt] = (uint16_t)sHas;

@@ -103,10 +103,13 @@ void carve_grid(Inst *I, const ebit_grid &g, char *base, Carve &c) {
   const size_t nn = (nx + 1) * (ny + 1), nc = nx * ny, nh = nx * (ny + 1), nv = (nx + 1) * ny;
   for (int k = 0; k < 2; k++) {
     I->col[k] = c.take<uint8_t>(base, nn);
-    I->cen[k] = c.take<uint8_t>(base, nc);
     I->hoff[k] = c.take<double>(base, nh);
     I->voff[k] = c.take<double>(base, nv);
   }
+  // centre colours are single-buffered: a sweep leaves them unchanged and its
+  // centre kernel, which runs after every fit has read the old values,
+  // rewrites the cells it settles in place
+  I->cen[0] = I->cen[1] = c.take<uint8_t>(base, nc);
   I->sp = c.take<double>(base, nn);
   I->dd = c.take<double>(base, 2 * nn);
   I->zr = c.take<uint8_t>(base, nn);
@@ -283,7 +286,6 @@ int engine_place(Engine *e, uint32_t k, const ebit_state *s) {
   HIPCHK(hipMemcpyAsync(I.hoff[c], s->hoff, nh * sizeof(double), hipMemcpyHostToDevice, e->stream));
   HIPCHK(hipMemcpyAsync(I.voff[c], s->voff, nv * sizeof(double), hipMemcpyHostToDevice, e->stream));
   HIPCHK(hipMemcpyAsync(I.col[o], I.col[c], nn, hipMemcpyDeviceToDevice, e->stream));
-  HIPCHK(hipMemcpyAsync(I.cen[o], I.cen[c], nc, hipMemcpyDeviceToDevice, e->stream));
   HIPCHK(hipMemcpyAsync(I.hoff[o], I.hoff[c], nh * sizeof(double), hipMemcpyDeviceToDevice, e->stream));
   HIPCHK(hipMemcpyAsync(I.voff[o], I.voff[c], nv * sizeof(double), hipMemcpyDeviceToDevice, e->stream));
   HIPCHK(hipMemsetAsync(e->errs + k, 0, sizeof(uint32_t), e->stream));
