@@ -152,7 +152,11 @@ struct SweepArgs {
   uint32_t jobCap;           // length of the job list
   uint32_t *njobs;           // fit jobs of this direction
   unsigned long long *ctr;
+  // one grid: the centre rules of the step's first sweep, when they are left
+  // to this (second) sweep's launch; its job count (null: none) and view
+  const uint32_t *pendJobs;
   SweepView one;             // the grid's view when the engine holds one grid
+  SweepView pend;
 };
 
 struct CompactArgs {

@@ -584,6 +584,10 @@ constexpr int SWEEP_BS = 128;
 constexpr int STAGE_SLOTS = (NH * NH + SWEEP_BS - 1) / SWEEP_BS;  // halo nodes / cells staged per thread
 constexpr int NTILES_LDS = 32;  // tile entries read once at the start
 
+// centre rules of one job (defined with the centre kernel below)
+template <int DIR>
+__device__ __forceinline__ void centreJob(const SweepView &W, uint32_t e, const Counts &cnt);
+
 template <int DIR, bool ONE>
 __global__ __launch_bounds__(SWEEP_BS, 8) void k_sweep(SweepArgs A, const Inst *__restrict__ inst) {
   __shared__ uint8_t sCol[NH][NH];
@@ -677,6 +681,14 @@ __global__ __launch_bounds__(SWEEP_BS, 8) void k_sweep(SweepArgs A, const Inst *
     return make_uint2(uni(e.x), uni(e.y));
   };
   if (itBeg < itEnd) prefetch(tileAt(itBeg));
+  if (ONE && A.pendJobs) {
+    // the centre rules of the step's first sweep (the other direction, whose
+    // jobs sit at the other end of the list), while the first tile's colours
+    // are on their way
+    const uint32_t nj = *A.pendJobs;
+    for (uint32_t w = blockIdx.x * blockDim.x + tid; w < nj; w += gridDim.x * blockDim.x)
+      centreJob<1 - DIR>(A.pend, A.jobs[DIR == 1 ? w : A.jobCap - 1u - w].y, cnt);
+  }
 
   for (uint32_t it = itBeg; it < itEnd; it += itStep) {
     const uint2 te = tileAt(it);

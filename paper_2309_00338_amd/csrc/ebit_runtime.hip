@@ -92,6 +92,11 @@ struct Engine {
   std::vector<ebit_grid> grids;
   uint32_t cur = 0, stepNo = 0;
   int slot = 1;
+  // one grid: the first sweep's centre rules, run by the second sweep's launch
+  const uint32_t *pendJobs = nullptr;
+  SweepView pendView{};
+  int pendDir = 0;
+  SweepArgs pendArgs{};  // to launch them on their own when no second sweep follows
   int64_t epoch = 0, fracEpoch = -1;
 };
 
@@ -296,6 +301,14 @@ int engine_place(Engine *e, uint32_t k, const ebit_state *s) {
   return EBIT_OK;
 }
 
+// launches the centre kernel of a first sweep whose rules no second sweep
+// took over
+hipError_t engine_flush_centre(Engine *e) {
+  if (!e->pendJobs) return hipSuccess;
+  e->pendJobs = nullptr;
+  return launch_centre(e->pendDir, true, e->pendArgs, e->centreBlocks, e->stream);
+}
+
 int engine_sweep(Engine *e, int phase, const double *u, const double *v, const double *dts, double dt) {
   bool dirs[2] = {false, false};
   for (uint32_t k = 0; k < e->maxGrids; k++)
@@ -314,9 +327,11 @@ int engine_sweep(Engine *e, int phase, const double *u, const double *v, const d
   a.jobs = e->jobs;
   a.jobCap = e->jobCap;
   a.ctr = e->ctr;
+  a.pendJobs = nullptr;
   uint32_t *cs = e->counts + NSLOT * e->slot;
   const uint32_t nextStep = phase == 0 ? e->stepNo : e->stepNo + 1;
   if (!dirs[0] && !dirs[1]) {
+    HIPCHK(engine_flush_centre(e));
     e->cur ^= 1u;
     return engine_compact(e, 1, nextStep, phase == 0 ? 1 : 0);
   }
@@ -333,9 +348,28 @@ int engine_sweep(Engine *e, int phase, const double *u, const double *v, const d
     a.njobs = cs + (d == 0 ? CNT_JOBS_X : CNT_JOBS_Y);
     // the single grid's view, resolved here (the kernels read it from their arguments)
     a.one = sweep_view(e->hinst[0], e->cur, d, u, v, dts ? 0.0 : dt / e->hinst[0].h);
+    // one grid: the first sweep's centre rules ride with the second sweep (it
+    // reads neither centre colours nor the first fits' results, and the
+    // second fits, which read both, start after it)
+    const bool fold = e->maxGrids == 1 && e->pendJobs && e->pendDir != d;
+    if (fold) {
+      a.pendJobs = e->pendJobs;
+      a.pend = e->pendView;
+    } else {
+      HIPCHK(engine_flush_centre(e));
+    }
     HIPCHK(launch_sweep(d, e->maxGrids == 1, a, e->sweepBlocks, e->stream));
+    a.pendJobs = nullptr;
+    e->pendJobs = nullptr;
     HIPCHK(launch_fit(d, e->maxGrids == 1, a, e->fitBlocks, d == last ? &c : nullptr, e->stream));
-    HIPCHK(launch_centre(d, e->maxGrids == 1, a, e->centreBlocks, e->stream));
+    if (e->maxGrids == 1 && phase == 0) {
+      e->pendJobs = a.njobs;
+      e->pendView = a.one;
+      e->pendDir = d;
+      e->pendArgs = a;
+    } else {
+      HIPCHK(launch_centre(d, e->maxGrids == 1, a, e->centreBlocks, e->stream));
+    }
   }
   e->cur ^= 1u;
   e->slot ^= 1;
@@ -345,6 +379,11 @@ int engine_sweep(Engine *e, int phase, const double *u, const double *v, const d
 int engine_advect(Engine *e, const double *u, const double *v, const double *dts, double dt) {
   int rc = engine_sweep(e, 0, u, v, dts, dt);
   if (!rc) rc = engine_sweep(e, 1, u, v, dts, dt);
+  if (!rc) {
+    const hipError_t he = engine_flush_centre(e);
+    if (he != hipSuccess) rc = device_failed(he, "engine_flush_centre", __LINE__);
+  }
+  e->pendJobs = nullptr;
   e->stepNo++;
   e->epoch++;
   return rc;
