@@ -681,6 +681,9 @@ __global__ __launch_bounds__(SWEEP_BS, 8) void k_sweep(SweepArgs A, const Inst *
     return make_uint2(uni(e.x), uni(e.y));
   };
   if (itBeg < itEnd) prefetch(tileAt(itBeg));
+  // one grid: lambda = dt / h from the view, or from the grid's device dt when
+  // the call passes one per grid (a batch or pool holding a single grid)
+  const double lamOne = ONE ? (A.dts ? A.dts[0] / inst[0].h : A.one.lam) : 0.0;
   if (ONE && A.pendJobs) {
     // the centre rules of the step's first sweep (the other direction, whose
     // jobs sit at the other end of the list), while the first tile's colours
@@ -699,7 +702,7 @@ __global__ __launch_bounds__(SWEEP_BS, 8) void k_sweep(SweepArgs A, const Inst *
     const int nx = W.nx, ny = W.ny;
     const GMap<DIR> G(nx, ny);
     const int na = G.na, nb = G.nb;
-    const double lam = W.lam;
+    const double lam = ONE ? lamOne : W.lam;
     const GL double *__restrict__ alo = gp(DIR == 0 ? W.hoff : W.voff);
     const GL double *__restrict__ uno = gp(DIR == 0 ? W.voff : W.hoff);
     GL double *__restrict__ aln = gp(DIR == 0 ? W.nhoff : W.nvoff);

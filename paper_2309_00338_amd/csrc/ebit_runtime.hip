@@ -73,6 +73,10 @@ struct Engine {
   uint32_t ntiles = 0;  // global tile space
   uint32_t maxGrids = 0;
   uint32_t jobCap = 0;
+  // the single-grid kernels (descriptor in the kernel arguments, every tile of
+  // the engine the grid's): only for a fixed engine of exactly one grid, never
+  // for a pool, whose slot may be empty and whose tile space is larger
+  bool one = false;
   int sweepBlocks = 0, fitBlocks = 0, centreBlocks = 0, nearBlocks[3] = {0, 0, 0}, nsNearBlocks = 0;
   // device tables
   Inst *dinst = nullptr;
@@ -273,7 +277,7 @@ CompactArgs compact_args(Engine *e, int afterSweep, uint32_t nextStep, int nextP
 int engine_compact(Engine *e, int afterSweep, uint32_t nextStep, int nextPhase) {
   e->slot ^= 1;
   const CompactArgs a = compact_args(e, afterSweep, nextStep, nextPhase);
-  HIPCHK(launch_compact(e->maxGrids == 1, a, e->stream));
+  HIPCHK(launch_compact(e->one, a, e->stream));
   return EBIT_OK;
 }
 
@@ -347,28 +351,29 @@ int engine_sweep(Engine *e, int phase, const double *u, const double *v, const d
     a.count = cs + (d == 0 ? CNT_ACT_X : CNT_ACT_Y);
     a.njobs = cs + (d == 0 ? CNT_JOBS_X : CNT_JOBS_Y);
     // the single grid's view, resolved here (the kernels read it from their arguments)
+    // (with per-grid device dts the single-grid sweep reads lambda from dts[0])
     a.one = sweep_view(e->hinst[0], e->cur, d, u, v, dts ? 0.0 : dt / e->hinst[0].h);
     // one grid: the first sweep's centre rules ride with the second sweep (it
     // reads neither centre colours nor the first fits' results, and the
     // second fits, which read both, start after it)
-    const bool fold = e->maxGrids == 1 && e->pendJobs && e->pendDir != d;
+    const bool fold = e->one && e->pendJobs && e->pendDir != d;
     if (fold) {
       a.pendJobs = e->pendJobs;
       a.pend = e->pendView;
     } else {
       HIPCHK(engine_flush_centre(e));
     }
-    HIPCHK(launch_sweep(d, e->maxGrids == 1, a, e->sweepBlocks, e->stream));
+    HIPCHK(launch_sweep(d, e->one, a, e->sweepBlocks, e->stream));
     a.pendJobs = nullptr;
     e->pendJobs = nullptr;
-    HIPCHK(launch_fit(d, e->maxGrids == 1, a, e->fitBlocks, d == last ? &c : nullptr, e->stream));
-    if (e->maxGrids == 1 && phase == 0) {
+    HIPCHK(launch_fit(d, e->one, a, e->fitBlocks, d == last ? &c : nullptr, e->stream));
+    if (e->one && phase == 0) {
       e->pendJobs = a.njobs;
       e->pendView = a.one;
       e->pendDir = d;
       e->pendArgs = a;
     } else {
-      HIPCHK(launch_centre(d, e->maxGrids == 1, a, e->centreBlocks, e->stream));
+      HIPCHK(launch_centre(d, e->one, a, e->centreBlocks, e->stream));
     }
   }
   e->cur ^= 1u;
@@ -409,12 +414,12 @@ int engine_frac(Engine *e, int mode, const double *Cin, double *Cout, double *Ko
   a.ghfCount = e->ghfCnt + e->ghfPar;
   a.ghfClear = e->ghfCnt + (e->ghfPar ^ 1u);
   a.one = e->hinst[0];
-  HIPCHK(launch_frac_curv(mode, e->maxGrids == 1, a, a.nearBlocks + frac_fill_blocks(e->ntiles), e->stream));
+  HIPCHK(launch_frac_curv(mode, e->one, a, a.nearBlocks + frac_fill_blocks(e->ntiles), e->stream));
   if (mode & 2) {
     // the launch above zeroed the other parity's count: the next curvature
     // launch uses it, whatever happens to the fit launch below
     e->ghfPar ^= 1u;
-    HIPCHK(launch_ghf(e->maxGrids == 1, a, e->ghfBlocks, e->stream));
+    HIPCHK(launch_ghf(e->one, a, e->ghfBlocks, e->stream));
   }
   return EBIT_OK;
 }
@@ -446,7 +451,7 @@ int engine_ns(Engine *e, const double *C, const double *K, const ebit_fluid *f, 
   a.count = e->counts + NSLOT * e->slot + CNT_NEAR;
   a.nearBlocks = e->nsNearBlocks;
   a.one = e->hinst[0];
-  const bool one = e->maxGrids == 1;
+  const bool one = e->one;
   const int fill = one ? ns_linear_blocks(e->hinst[0].nx, e->hinst[0].ny) : ns_fill_blocks(e->ntiles);
   HIPCHK(launch_ns(one, a, a.nearBlocks + fill, e->stream));
   return EBIT_OK;
@@ -541,6 +546,7 @@ int engine_create_fixed(Engine *e, int n, const ebit_grid *grids, const ebit_sta
   }
   e->ntiles = ntiles;
   e->maxGrids = (uint32_t)n;
+  e->one = n == 1;
   e->jobCap = jobCap;
   if (bytes < engine_bytes(ntiles, (uint32_t)n, jobCap) + gb) return EBIT_ERR_NOMEM;
   e->stream = (hipStream_t)stream;
@@ -877,6 +883,7 @@ int ebit_pool_create(int max_grids, uint32_t max_tiles, void *ws_dev, size_t ws_
   Engine *e = &p->e;
   e->ntiles = max_tiles;
   e->maxGrids = (uint32_t)max_grids;
+  e->one = false;
   e->jobCap = max_tiles * JOBS_PER_TILE;
   e->stream = (hipStream_t)hip_stream;
   Carve c;

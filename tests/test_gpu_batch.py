@@ -207,3 +207,44 @@ def test_batch_ns_fields_per_grid():
         for name, gg, o in zip(("rho", "mu", "fx", "fy"), got, want):
             d = np.abs(gg.cpu().numpy() - o) / np.maximum(np.abs(o), 1.0)
             assert d.max(initial=0) <= 1e-12, (g, name, d.max())
+
+
+def test_one_grid_batch_and_pool_match_oracle():
+    """A batch of one grid and a pool of one slot run the single-grid kernels
+    (the step's first centre pass inside the second sweep's launch), with a
+    device dt and with the pool's own velocities; the pool also steps empty
+    between a retire and the next admission."""
+    import torch
+
+    st, u, v, dts = _instances()[2]
+    b = ebit.EbitBatch([st])
+    U, V = b.pack_velocities([u], [v])
+    o = st.copy()
+    C, K = b.new_fields()
+    for k in range(8):
+        b.advect(U, V, torch.tensor([dts[k]], dtype=torch.float64, device="cuda:0"))
+        assert oracle.step(o, u, v, dts[k])[0] == oracle.OK
+        compare_state(b.get_state(0), o, f"batch step {k}")
+    b.fraction_curvature(C, K)
+    Co = oracle.fraction(o)
+    Ko, _ = oracle.curvature(o, Co)
+    compare_fields(b.field(C, 0).cpu().numpy(), b.field(K, 0).cpu().numpy(), Co, Ko, o.nx, o.h, "batch")
+    assert b.sync() == [0]
+
+    pool = ebit.EbitPool(max_grids=1, max_tiles=64, arena_bytes=64 << 20)
+    for seed in (21, 22):
+        pst, pu, pv, pdt = _pool_instance(44, 3, seed)
+        slot = pool.admit(pst, pu, pv, pdt)
+        assert slot == 0
+        ref = _Ref(pst, pu, pv, pdt)
+        for k in range(5):
+            pool.step()
+            ref.step(None)
+        Cp, Kp, steps, status = pool.read(slot)
+        assert status == 0 and steps == ref.o.step
+        compare_state(pool.get_state(slot), ref.o, f"pool seed {seed}")
+        Co = oracle.fraction(ref.o)
+        Ko, _ = oracle.curvature(ref.o, Co)
+        compare_fields(Cp, Kp, Co, Ko, ref.o.nx, ref.o.h, f"pool seed {seed}")
+        pool.retire(slot)
+        pool.step()  # nothing live: no sweep, nothing pending
