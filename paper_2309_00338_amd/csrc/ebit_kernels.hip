@@ -46,6 +46,7 @@ constexpr int NE = NH - 1;             // staged cells / edges per side (20)
 constexpr int NN = TS + 1;             // new nodes per side (17)
 constexpr int JOBCAP = 384;            // queued fit jobs per sweep workgroup (>= one tile's 256)
 constexpr uint32_t NXCD = 8;          // XCDs of the GPU, each with its own L2
+constexpr uint32_t SWEEP_MIN_CHUNK = 8;  // tiles per sweep workgroup, at least, with several grids
 
 // marker-position mask bits of a tile: any marker; within STRIP cells of a
 // side or corner; on the tile's own left / bottom border edge (shared with
@@ -161,6 +162,40 @@ struct Tile {
     return n;
   }
 };
+
+// Aligned markers landing on edge (a,b) of a fit view: their number and the
+// kept source (-1 when none): one lander is kept, of three the middle source.
+template <class View>
+__device__ __forceinline__ int viewLanders(const View &T, int a, int b, int *keepSrc) {
+  int n = 0, first = -1, second = -1;
+  if (a >= 1 && T.presA(a - 1, b) && T.spv(a - 1, b) >= 1.0) { first = a - 1; n++; }
+  if (T.presA(a, b)) {
+    const double v = T.spv(a, b);
+    if (v >= 0.0 && v < 1.0) {
+      if (n == 0) first = a;
+      else second = a;
+      n++;
+    }
+  }
+  if (a + 1 < T.na && T.presA(a + 1, b) && T.spv(a + 1, b) < 0.0) {
+    if (n == 0) first = a + 1;
+    else if (n == 1) second = a + 1;
+    n++;
+  }
+  *keepSrc = n == 1 ? first : (n == 3 ? second : -1);
+  return n;
+}
+// The aligned marker (p,q) landed on edge (target,q) and is the one kept there.
+template <class View>
+__device__ __forceinline__ bool viewKeptOn(const View &T, int p, int q, int target) {
+  const double v = T.spv(p, q);
+  int tg = v >= 1.0 ? p + 1 : (v < 0.0 ? p - 1 : p);
+  if (tg < 0 || tg >= T.na) tg = -1;
+  if (tg != target) return false;
+  int keep;
+  viewLanders(T, target, q, &keep);
+  return keep == p;
+}
 
 // One of 8 or 3 named registers, chosen by a tree of selects on the bits of
 // k (values kept in an array would be read with an index, from scratch)
@@ -289,38 +324,6 @@ struct JobView {
     if (p == a && q == b + 1) return (int)((nm >> 1) & 1u);
     return ncol[G.node(p, q)];
   }
-  // aligned markers landing on edge (p,q): their number and the kept source
-  // (-1 when none): one lander is kept, of three the middle source
-  __device__ int landers(int p, int q, int *keepSrc) const {
-    int n = 0, first = -1, second = -1;
-    if (p >= 1 && presA(p - 1, q) && spv(p - 1, q) >= 1.0) { first = p - 1; n++; }
-    if (presA(p, q)) {
-      const double v = spv(p, q);
-      if (v >= 0.0 && v < 1.0) {
-        if (n == 0) first = p;
-        else second = p;
-        n++;
-      }
-    }
-    if (p + 1 < na && presA(p + 1, q) && spv(p + 1, q) < 0.0) {
-      if (n == 0) first = p + 1;
-      else if (n == 1) second = p + 1;
-      n++;
-    }
-    *keepSrc = n == 1 ? first : (n == 3 ? second : -1);
-    return n;
-  }
-  __device__ int landTarget(int p, int q) const {
-    const double v = spv(p, q);
-    const int tg = v >= 1.0 ? p + 1 : (v < 0.0 ? p - 1 : p);
-    return (tg < 0 || tg >= na) ? -1 : tg;
-  }
-  __device__ bool keptOn(int p, int q, int target) const {
-    if (landTarget(p, q) != target) return false;
-    int keep;
-    landers(target, q, &keep);
-    return keep == p;
-  }
 };
 
 struct MRef {
@@ -360,7 +363,7 @@ __device__ __forceinline__ bool leftOf(const View &T, MRef m, int a0) {
 // chain neighbour of the marker on edge e of old cell (p,q), away from it:
 // its partner in the cell across edge e
 template <class View>
-__device__ __forceinline__ bool chainNb(const View &T, int p, int q, int e, MRef *out) {
+__device__ bool chainNb(const View &T, int p, int q, int e, MRef *out) {
   int pp = p, qq = q;
   if (e == 0) qq = q - 1;
   else if (e == 1) pp = p + 1;
@@ -451,7 +454,7 @@ struct Counts {
 // colours): its offset, and the centre-CV results for the cell right of the
 // line (cell a) and left of it (cell a-1): -1 or the new centre colour.
 template <class View>
-__device__ __forceinline__ double newUnaligned(const View &T, int a, int b, int *resRight, int *resLeft, const Counts &cnt, bool count,
+__device__ double newUnaligned(const View &T, int a, int b, int *resRight, int *resLeft, const Counts &cnt, bool count,
                                bool line) {
   *resRight = -1;
   *resLeft = -1;
@@ -550,7 +553,7 @@ __device__ __forceinline__ double newUnaligned(const View &T, int a, int b, int 
   // when it is an aligned marker kept on that cell's bottom or top edge; the
   // corner it shares with this line is then isolated.
   auto qualifies = [&](MRef m, int cellA) -> bool {
-    return m.kind == 0 && (m.b == b || m.b == b + 1) && T.keptOn(m.a, m.b, cellA);
+    return m.kind == 0 && (m.b == b || m.b == b + 1) && viewKeptOn(T, m.a, m.b, cellA);
   };
   if (a < T.na) {
     // cell a, right of the line
@@ -668,7 +671,10 @@ __global__ __launch_bounds__(SWEEP_BS, 8) void k_sweep(SweepArgs A, const Inst *
     itEnd = ntile;
     itStep = gridDim.x;
   } else {
-    const uint32_t chunk = (ntile + gridDim.x - 1) / gridDim.x;
+    // at least SWEEP_MIN_CHUNK tiles per workgroup: a workgroup queues its fit
+    // jobs together, and the fit runs once per distinct grid of a wavefront,
+    // so short chunks (few active tiles) would mix grids in every wavefront
+    const uint32_t chunk = max((ntile + gridDim.x - 1) / gridDim.x, SWEEP_MIN_CHUNK);
     itBeg = min(ntile, blockIdx.x * chunk);
     itEnd = min(ntile, itBeg + chunk);
     itStep = 1;
@@ -970,15 +976,24 @@ __device__ __forceinline__ void eachGrid(uint32_t k, F f) {
   }
 }
 
+// The fit on the register window, with every call inlined (the window then
+// stays in registers; a call taking it by reference would put it in scratch
+// memory).
+template <int DIR>
+__device__ __attribute__((always_inline, flatten)) double fitWindow(const SweepView &W, int a, int b, int *rR,
+                                                                     int *rL, const Counts &cnt) {
+  const JobView<DIR> V(W, a, b);
+  return newUnaligned(V, a, b, rR, rL, cnt, true, W.line != 0);
+}
+
 template <int DIR>
 __device__ __forceinline__ void fitJob(const SweepView &W, uint32_t e, const Counts &cnt) {
   GL double *__restrict__ unn = gp(DIR == 0 ? W.nvoff : W.nhoff);
   int a, b;
   if (DIR == 0) { b = (int)(e / (uint32_t)(W.nx + 1)); a = (int)(e % (uint32_t)(W.nx + 1)); }
   else { a = (int)(e / (uint32_t)W.nx); b = (int)(e % (uint32_t)W.nx); }
-  const JobView<DIR> V(W, a, b);
   int rR, rL;
-  const double y = newUnaligned(V, a, b, &rR, &rL, cnt, true, W.line != 0);
+  const double y = fitWindow<DIR>(W, a, b, &rR, &rL, cnt);
   unn[e] = y;
   gp(W.zr)[e] = (uint8_t)((rR + 1) | ((rL + 1) << 2));
 }
