@@ -1,8 +1,9 @@
 // EBIT interface step: gfx950 kernels.
 //
-// Layout in HBM (per grid): node colours and centre colours as bytes, marker
-// offsets as FP64 structure-of-arrays (hoff, voff), each twice (ping-pong: a
-// sweep reads one copy and writes the other). Every grid is cut into
+// Layout in HBM (per grid): node colours as bytes and marker offsets as FP64
+// structure-of-arrays (hoff, voff), each twice (ping-pong: a sweep reads one
+// copy and writes the other); centre colours as bytes, once (a sweep leaves
+// them alone and its centre kernel rewrites the cells it settles in place). Every grid is cut into
 // 16x16-cell tiles; the tiles of all grids an engine holds share one global
 // index space, so one launch per phase serves any number of grids. Each tile
 // keeps a small mask of where its own markers sit (anywhere, within 3 cells
@@ -16,10 +17,10 @@
 // A sweep is a gather: each output (node colour, edge offset, centre colour)
 // is a function of the old state within two cells, so there are no atomics on
 // state and no ordering between tiles. A workgroup stages its tile plus a
-// 2-cell halo in LDS (colours, centre colours, advected aligned offsets,
-// unaligned displacements), computes new colours and lander choices and
-// queues the present new unaligned edges; the fit kernel then places them one
-// per lane and the centre kernel sets the centre colours. Every FP64
+// 2-cell halo in LDS (node colours, advected aligned offsets), computes new
+// colours and lander choices and queues the present new unaligned edges; the
+// fit kernel then places them one per lane and the centre kernel sets the
+// centre colours. Every FP64
 // expression is written in one fixed order and the file is built with
 // -ffp-contract=off.
 #include <hip/hip_runtime.h>
@@ -1461,15 +1462,14 @@ __device__ bool ghfFit(int nx, int ny, double h, int i, int j, int gx, int gy, G
 // [0, nearBlocks) take the near tiles of the list (static stride): node
 // colours of the tile plus halo in LDS; C, marker count and BL colour of every
 // halo cell (mirrored across walls), polygons only where markers are; then C
-// and/or kappa of the tile's cells (two per thread). Cells whose heights fail
+// and/or kappa of the tile's cells (one per thread). Cells whose heights fail
 // in both directions are handed to k_ghf (one entry per 64 cells that have
 // any), which keeps the rare parabola fit out of this kernel's register
-// budget. Workgroups are 128 threads: the near part is bound by the latency
-// of each tile's dependent rounds, and small workgroups keep 16 tiles in
-// flight per CU. Every later workgroup fills 8 consecutive global tiles:
-// cells of tiles that are neither near nor unowned get their tile's colour as
-// C and zero curvature, one 8-byte store per lane and row, lanes along a grid
-// row. MODE 1: C only; 2: kappa from the caller's C; 3: both.
+// budget. Workgroups are 256 threads, 8 resident per CU, all of them near
+// workgroups at first. Every later workgroup fills 16 consecutive global
+// tiles: cells of tiles that are neither near nor unowned get their tile's
+// colour as C and zero curvature, one 8-byte store per lane and row, lanes
+// along a grid row. MODE 1: C only; 2: kappa from the caller's C; 3: both.
 constexpr int FRAC_BS = 256;
 constexpr int NEAR_ENT = 16;  // tile entries a near workgroup keeps in LDS
 constexpr int FRAC_FILL_TILES = FRAC_BS / TS;
