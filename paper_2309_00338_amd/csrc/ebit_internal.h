@@ -61,6 +61,18 @@ enum : uint32_t { INST_XY = 1u, INST_LINE = 2u };  // x then y every step; strai
 // tiles are uniform)
 enum : uint8_t { TI_NEAR = 1, TI_COLOUR = 2, TI_DEAD = 4, TI_FRAC = 8 };
 
+// Node colours are a bit plane in blocks of 16 x 16 nodes: block (bx, by)
+// holds nodes x in [16 bx, 16 bx + 16), y in [16 by, 16 by + 16) as 16 words
+// of 16 bits, word y & 15, bit x & 15; blocks are row-major with nx / 16 + 1
+// per block row (ny / 16 + 1 block rows), and bits of nodes outside the grid
+// are 0. A tile and its halo then sit in 3 x 3 blocks, 3 runs of 96 bytes.
+__host__ __device__ inline int cb_nbx(int nx) { return (nx >> 4) + 1; }
+__host__ __device__ inline size_t cb_words(int nx, int ny) { return (size_t)cb_nbx(nx) * (size_t)cb_nbx(ny) * 16u; }
+// word of row y in the block holding node (x, y); x and y inside the grid
+__host__ __device__ inline size_t cb_word(int nx, int x, int y) {
+  return ((size_t)(y >> 4) * (size_t)cb_nbx(nx) + (size_t)(x >> 4)) * 16u + (size_t)(y & 15);
+}
+
 // One grid: geometry, both state copies, per-sweep scratch, and where its
 // velocities and output fields sit relative to the base pointers of a call.
 struct Inst {
@@ -72,7 +84,7 @@ struct Inst {
   double h;
   uint64_t uoff, voffv;  // element offsets of u and v in the call's velocity buffers
   uint64_t coff, koff;   // element offsets of C and kappa in the call's field buffers
-  uint8_t *col[2];       // node colours, (ny+1) x (nx+1), both copies
+  uint16_t *col[2];      // node colours as a bit plane (cb_word), both copies
   uint8_t *cen[2];       // centre colours, ny x nx: one array in both entries (the centre kernel
                          // updates it in place after the fits have read the old values)
   double *hoff[2];       // H-edge offsets, (ny+1) x nx
@@ -90,9 +102,11 @@ struct SweepView {
   int32_t nx, ny, ntx, pad;
   uint32_t tile0;
   double lam;
-  const uint8_t *col, *cen;   // state before the sweep
+  const uint16_t *col;        // state before the sweep
+  const uint8_t *cen;
   const double *hoff, *voff;
-  uint8_t *ncol, *ncen;       // state after the sweep
+  uint16_t *ncol;             // state after the sweep
+  uint8_t *ncen;
   double *nhoff, *nvoff;
   const double *vel;          // u for the x sweep, v for the y sweep
   double *sp, *dd;

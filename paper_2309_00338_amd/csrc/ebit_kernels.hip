@@ -1,8 +1,9 @@
 // EBIT interface step: gfx950 kernels.
 //
-// Layout in HBM (per grid): node colours as bytes and marker offsets as FP64
-// structure-of-arrays (hoff, voff), each twice (ping-pong: a sweep reads one
-// copy and writes the other); centre colours as bytes, once (a sweep leaves
+// Layout in HBM (per grid): node colours as a bit plane in 16x16-node blocks
+// (cb_word) and marker offsets as FP64 structure-of-arrays (hoff, voff), each
+// twice (ping-pong: a sweep reads one copy and writes the other); centre
+// colours as bytes, once (a sweep leaves
 // them alone and its centre kernel rewrites the cells it settles in place). Every grid is cut into
 // 16x16-cell tiles; the tiles of all grids an engine holds share one global
 // index space, so one launch per phase serves any number of grids. Each tile
@@ -101,7 +102,17 @@ struct GMap {
   __device__ size_t ale(int a, int b) const { return DIR == 0 ? (size_t)b * nx + a : (size_t)a * (nx + 1) + b; }
   __device__ size_t une(int a, int b) const { return DIR == 0 ? (size_t)b * (nx + 1) + a : (size_t)a * nx + b; }
   __device__ size_t cell(int a, int b) const { return DIR == 0 ? (size_t)b * nx + a : (size_t)a * nx + b; }
+  // colour of frame node (a, b) from a bit plane
+  __device__ int colour(const GL uint16_t *cb, int a, int b) const {
+    const int x = DIR == 0 ? a : b, y = DIR == 0 ? b : a;
+    return (int)((cb[cb_word(nx, x, y)] >> (x & 15)) & 1u);
+  }
 };
+
+// colour of node (x, y), inside the grid, from a bit plane
+__device__ __forceinline__ int colAt(const GL uint16_t *cb, int nx, int x, int y) {
+  return (int)((cb[cb_word(nx, x, y)] >> (x & 15)) & 1u);
+}
 
 // ---------------------------------------------------------------------------
 // Tile view over the LDS staging (frame coordinates).
@@ -134,10 +145,10 @@ __device__ __forceinline__ uint16_t segCodeOf(int k0, int k1, int k2, int k3, in
 // aligned offsets, enough to gather the landers of each new aligned edge.
 struct Tile {
   int na, nb, a0, b0;
-  const uint8_t (*col)[NH];   // old node colours   [b][a], a in [a0-2, a0+18]
+  const uint32_t *rows;       // old node colours: bit a-a0+2 of frame row b-b0+2, a in [a0-2, a0+18]
   const double (*sp)[NE];     // aligned (a,b): s' ; a in [a0-2,a0+17], b in [b0-2,b0+18]
 
-  __device__ int C(int a, int b) const { return col[b - b0 + HALO][a - a0 + HALO]; }
+  __device__ int C(int a, int b) const { return (int)((rows[b - b0 + HALO] >> (a - a0 + HALO)) & 1u); }
   __device__ bool presA(int a, int b) const { return C(a, b) != C(a + 1, b); }
   __device__ double spv(int a, int b) const { return sp[b - b0 + HALO][a - a0 + HALO]; }
 
@@ -214,8 +225,8 @@ __device__ __forceinline__ double pick3(int k, double v0, double v1, double v2) 
 
 // One fit job's neighbourhood (used by the fit kernel, one lane per new
 // unaligned marker on line a, row b), gathered in one round of independent
-// loads: old node colours a-2..a+2 x b-1..b+2 as a bit mask, the new colours
-// of the line's two nodes,
+// loads: old node colours a-2..a+2 x b-1..b+2 as a bit mask (four 8-byte
+// loads of the bit plane), the new colours of the line's two nodes,
 // the advected offsets s' of the aligned edges a-2..a+1 on rows b and b+1 and
 // the (t, d) pairs of the unaligned edges a-1..a+1 on row b. That covers every
 // read of the crossing search, the circles' inner points and the centre rules;
@@ -227,9 +238,9 @@ template <int DIR>
 struct JobView {
   GMap<DIR> G;
   int na, nb, a, b;
-  const GL uint8_t *__restrict__ col;   // old node colours
-  const GL uint8_t *__restrict__ cen;   // old centre colours
-  const GL uint8_t *__restrict__ ncol;  // new node colours
+  const GL uint16_t *__restrict__ col;   // old node colours (bit plane)
+  const GL uint8_t *__restrict__ cen;    // old centre colours
+  const GL uint16_t *__restrict__ ncol;  // new node colours (bit plane)
   const GL double *__restrict__ sp;     // aligned: s' (present edges)
   const GL double *__restrict__ td;     // unaligned: (old offset t, displacement d) pairs (present edges)
   uint32_t cm = 0;  // old node (a-2+i, b-1+j): bit j*5+i
@@ -241,31 +252,27 @@ struct JobView {
         sp(gp(W.sp)), td(gp(W.dd)) {
     // Every load is unconditional (all issue before the first wait): indices
     // are clamped into the grid and slots outside it are masked afterwards.
-    // The node colours of a window row that is contiguous in memory (frame
-    // rows for the x sweep, frame columns for the y sweep) come from the two
-    // aligned words holding its first in-grid byte: the row needs at most 5
-    // bytes, at most 3 after the word boundary. Arrays start 256-byte aligned
-    // and each node-colour array is followed by another array, so the read
-    // past a row's end (at most 5 bytes) stays inside the workspace.
+    // The node window, in grid coordinates columns xs .. xs+NX-1 and rows
+    // ys .. ys+NY-1 (x sweep 5 x 4 from (a-2, b-1), y sweep 4 x 5 from
+    // (b-1, a-2)), lies in two groups of 4 rows (rows 4g .. 4g+3, one aligned
+    // 8-byte piece of a block) in each of two block columns.
     auto cl = [](int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); };
-    auto words = [](const GL uint8_t *base, size_t first, size_t *at) -> uint64_t {
-      const size_t d = first & ~(size_t)3;
-      const GL uint32_t *w = (const GL uint32_t *)(base + d);
-      *at = d;
-      return (uint64_t)w[0] | ((uint64_t)w[1] << 32);
+    constexpr int NX = DIR == 0 ? 5 : 4, NY = DIR == 0 ? 4 : 5;
+    const int xs = DIR == 0 ? a - 2 : b - 1, ys = DIR == 0 ? b - 1 : a - 2;
+    const int nbx = cb_nbx(W.nx), nby = cb_nbx(W.ny);
+    const int bxl = xs >> 4, g1 = ys >> 2;  // floor, also below 0
+    auto piece = [&](int g, int bx) -> uint64_t {
+      const int by = g >> 2;
+      const size_t w = ((size_t)cl(by, 0, nby - 1) * (size_t)nbx + (size_t)cl(bx, 0, nbx - 1)) * 16u + 4u * (size_t)(g & 3);
+      return *(const GL uint64_t *)(col + w);
     };
-    // node (x, y) of the window: its bit in the words holding it
-    auto bitOf = [](uint64_t w, size_t at, size_t idx) -> uint32_t { return (uint32_t)(w >> (8 * (idx - at))) & 1u; };
-    constexpr int NR = DIR == 0 ? 4 : 5;   // memory rows of the node window
-    uint64_t nw[NR];
-    size_t nat[NR];
-#pragma unroll
-    for (int r = 0; r < NR; r++) {
-      // x sweep: row y = b-1+r from x = a-2; y sweep: row a-2+r from b-1
-      const size_t first = DIR == 0 ? G.node(max(a - 2, 0), cl(b - 1 + r, 0, nb)) : G.node(cl(a - 2 + r, 0, na), max(b - 1, 0));
-      nw[r] = words(col, first, &nat[r]);
-    }
-    const uint8_t n0 = ncol[G.node(a, b)], n1 = ncol[G.node(a, b + 1)];
+    const uint64_t q00 = piece(g1, bxl), q01 = piece(g1, bxl + 1), q10 = piece(g1 + 1, bxl),
+                   q11 = piece(g1 + 1, bxl + 1);
+    auto ncolAt = [&](int p, int q) -> uint32_t {
+      const int x = DIR == 0 ? p : q, y = DIR == 0 ? q : p;
+      return (uint32_t)(ncol[cb_word(W.nx, x, y)] >> (x & 15));
+    };
+    const uint32_t n0 = ncolAt(a, b), n1 = ncolAt(a, b + 1);
     auto al = [&](int i, int j) -> double { return sp[G.ale(cl(a - 2 + i, 0, na - 1), b + j)]; };
     s0 = al(0, 0), s1 = al(1, 0), s2 = al(2, 0), s3 = al(3, 0);
     s4 = al(0, 1), s5 = al(1, 1), s6 = al(2, 1), s7 = al(3, 1);
@@ -280,22 +287,40 @@ struct JobView {
     const TD p0 = un(0), p1 = un(1), p2 = un(2);
     t0 = p0.t, t1 = p1.t, t2 = p2.t;
     d0 = p0.d, d1 = p1.d, d2 = p2.d;
+    // pieces of blocks outside the grid read as 0
+    const bool okL = bxl >= 0, okR = bxl + 1 < nbx, ok1 = g1 >= 0, ok2 = ((g1 + 1) >> 2) < nby;
+    const uint64_t p00 = okL && ok1 ? q00 : 0, p01 = okR && ok1 ? q01 : 0, p10 = okL && ok2 ? q10 : 0,
+                   p11 = okR && ok2 ? q11 : 0;
+#pragma unroll
+    for (int r = 0; r < NY; r++) {
+      // grid row ys + r: its group, its word in both block columns, the window's bits
+      const int y = ys + r;
+      const bool second = (y >> 2) != g1;
+      const int sh = 16 * (y & 3);
+      const uint32_t lo = (uint32_t)((second ? p10 : p00) >> sh) & 0xFFFFu;
+      const uint32_t hi = (uint32_t)((second ? p11 : p01) >> sh) & 0xFFFFu;
+      const uint32_t bits = ((lo | (hi << 16)) >> (xs & 15)) & ((1u << NX) - 1u);
+      if (DIR == 0) {
+        cm |= bits << (r * 5);  // frame row j = r, frame column i = bit
+      } else {
+#pragma unroll
+        for (int c = 0; c < NX; c++) cm |= ((bits >> c) & 1u) << (c * 5 + r);  // frame (i, j) = (r, c)
+      }
+    }
+    // nodes outside the grid are 0
 #pragma unroll
     for (int j = 0; j < 4; j++)
 #pragma unroll
       for (int i = 0; i < 5; i++) {
         const int x = a - 2 + i, y = b - 1 + j;
-        if (x >= 0 && x <= na && y >= 0 && y <= nb) {
-          const int r = DIR == 0 ? j : i;
-          cm |= bitOf(nw[r], nat[r], G.node(x, y)) << (j * 5 + i);
-        }
+        if (!(x >= 0 && x <= na && y >= 0 && y <= nb)) cm &= ~(1u << (j * 5 + i));
       }
-    nm = (uint32_t)(n0 & 1u) | ((uint32_t)(n1 & 1u) << 1);
+    nm = (n0 & 1u) | ((n1 & 1u) << 1);
   }
   __device__ int C(int p, int q) const {
     const int i = p - (a - 2), j = q - (b - 1);
     if (i >= 0 && i < 5 && j >= 0 && j < 4) return (int)((cm >> (j * 5 + i)) & 1u);
-    return col[G.node(p, q)];
+    return G.colour(col, p, q);
   }
   __device__ int cenv(int p, int q) const { return cen[G.cell(p, q)]; }
   __device__ bool presA(int p, int q) const { return C(p, q) != C(p + 1, q); }
@@ -323,7 +348,7 @@ struct JobView {
   __device__ int newC(int p, int q) const {
     if (p == a && q == b) return (int)(nm & 1u);
     if (p == a && q == b + 1) return (int)((nm >> 1) & 1u);
-    return ncol[G.node(p, q)];
+    return G.colour(ncol, p, q);
   }
 };
 
@@ -585,7 +610,6 @@ __device__ __forceinline__ uint32_t uni(uint32_t x) { return __builtin_amdgcn_re
 // ONE: the engine holds a single grid, whose descriptor comes with the kernel
 // arguments (loop-invariant, no descriptor loads per tile).
 constexpr int SWEEP_BS = 128;
-constexpr int STAGE_SLOTS = (NH * NH + SWEEP_BS - 1) / SWEEP_BS;  // halo nodes / cells staged per thread
 constexpr int NTILES_LDS = 32;  // tile entries read once at the start
 
 // centre rules of one job (defined with the centre kernel below)
@@ -594,7 +618,7 @@ __device__ __forceinline__ void centreJob(const SweepView &W, uint32_t e, const 
 
 template <int DIR, bool ONE>
 __global__ __launch_bounds__(SWEEP_BS, 8) void k_sweep(SweepArgs A, const Inst *__restrict__ inst) {
-  __shared__ uint8_t sCol[NH][NH];
+  __shared__ uint64_t sBlk[NH];     // colour words of halo row r: block columns tx-1, tx, tx+1
   __shared__ double sSp[NH][NE];
   __shared__ uint32_t sRow[NH];     // old colours, bit la of frame row lb
   __shared__ uint32_t sNRow[NN];    // new colours, bit a-a0 of row b-b0
@@ -621,18 +645,20 @@ __global__ __launch_bounds__(SWEEP_BS, 8) void k_sweep(SweepArgs A, const Inst *
     if (tid == 0) sNJob = 0;
   };
 
-  // Staging of colours: each thread owns STAGE_SLOTS node slots of the halo
-  // (memory order). The next tile's bytes are fetched into registers while the
-  // current tile computes.
-  static_assert(NH * NH <= STAGE_SLOTS * SWEEP_BS, "staging slots per thread");
-  uint8_t pc[STAGE_SLOTS];
-#pragma unroll
-  for (int q = 0; q < STAGE_SLOTS; q++) pc[q] = 0;
+  // Staging of colours: the tile and its halo (nodes x0-2 .. x0+18, rows
+  // y0-2 .. y0+18) sit in 3 x 3 blocks of the bit plane; lane k < 3 NH holds
+  // the word of halo row k / 3 in block column tx-1 + k % 3. The next tile's
+  // words are fetched into a register while the current tile computes. The
+  // load is unconditional: its indices are clamped into the grid, and words of
+  // rows or blocks outside it are zeroed when staged.
+  static_assert(3 * NH <= SWEEP_BS && HALO <= TS && NH - HALO <= 2 * TS, "staging words");
+  uint32_t pc = 0;
+  bool pin = false;
   auto prefetch = [&](uint2 te) {
     const uint32_t gt = te.x;
     int nx, ny, ntx;
     uint32_t tile0;
-    const GL uint8_t *col;
+    const GL uint16_t *col;
     if (ONE) {
       nx = A.one.nx, ny = A.one.ny, ntx = A.one.ntx, tile0 = A.one.tile0;
       col = gp(A.one.col);
@@ -642,14 +668,10 @@ __global__ __launch_bounds__(SWEEP_BS, 8) void k_sweep(SweepArgs A, const Inst *
       col = gp(I.col[cur]);
     }
     const uint32_t lt = gt - tile0;
-    const int px0 = (int)(lt % (uint32_t)ntx) * TS, py0 = (int)(lt / (uint32_t)ntx) * TS;
-    auto node = [&](int k) -> uint8_t {
-      if (k >= NH * NH) return 0;
-      const int x = px0 - HALO + k % NH, y = py0 - HALO + k / NH;
-      return (x >= 0 && y >= 0 && x <= nx && y <= ny) ? col[(size_t)y * (nx + 1) + x] : (uint8_t)0;
-    };
-#pragma unroll
-    for (int q = 0; q < STAGE_SLOTS; q++) pc[q] = node(tid + SWEEP_BS * q);
+    const int tx = (int)(lt % (uint32_t)ntx), py0 = (int)(lt / (uint32_t)ntx) * TS;
+    const int k = min(tid, 3 * NH - 1), y = py0 - HALO + k / 3, bx = tx - 1 + k % 3, nbx = cb_nbx(nx);
+    pin = y >= 0 && y <= ny && bx >= 0 && bx < nbx;
+    pc = col[cb_word(nx, min(max(bx, 0), nbx - 1) * TS, min(max(y, 0), ny))];
   };
 
   const uint32_t ntile = *A.count;
@@ -715,7 +737,7 @@ __global__ __launch_bounds__(SWEEP_BS, 8) void k_sweep(SweepArgs A, const Inst *
     GL double *__restrict__ aln = gp(DIR == 0 ? W.nhoff : W.nvoff);
     GL double *__restrict__ unn = gp(DIR == 0 ? W.nvoff : W.nhoff);
     const GL double *__restrict__ vel = gp(W.vel);
-    GL uint8_t *__restrict__ ncol = gp(W.ncol);
+    GL uint16_t *__restrict__ ncol = gp(W.ncol);
     GL double *__restrict__ spg = gp(W.sp);
     GL double *__restrict__ ddg = gp(W.dd);
     uint32_t *errg = W.err;  // written only on an error
@@ -730,7 +752,7 @@ __global__ __launch_bounds__(SWEEP_BS, 8) void k_sweep(SweepArgs A, const Inst *
     Tile T;
     T.na = na;
     T.nb = nb;
-    T.col = sCol;
+    T.rows = sRow;
     T.sp = sSp;
     T.a0 = a0;
     T.b0 = b0;
@@ -741,27 +763,19 @@ __global__ __launch_bounds__(SWEEP_BS, 8) void k_sweep(SweepArgs A, const Inst *
     }
     if (tid < NN) sRecv[tid] = 0;
     // --- stage old colours -----------------------------------------------------
-    {
-      auto putNode = [&](int k, uint8_t c) {
-        if (k >= NH * NH) return;
-        const int hx = k % NH, hy = k / NH;
-        if (DIR == 0) sCol[hy][hx] = c;
-        else sCol[hx][hy] = c;
-      };
-#pragma unroll
-      for (int q = 0; q < STAGE_SLOTS; q++) putNode(tid + SWEEP_BS * q, pc[q]);
-    }
-    // colour-1 nodes set their bit in the frame-row masks (zero since the
-    // previous tile)
-    {
-      auto bitNode = [&](int k, uint8_t c) {
-        if (k >= NH * NH || !c) return;
-        const int hx = k % NH, hy = k / NH;
-        const int la = DIR == 0 ? hx : hy, lb = DIR == 0 ? hy : hx;
-        atomicOr(&sRow[lb], 1u << la);
-      };
-#pragma unroll
-      for (int q = 0; q < STAGE_SLOTS; q++) bitNode(tid + SWEEP_BS * q, pc[q]);
+    if (tid < 3 * NH) ((uint16_t *)&sBlk[tid / 3])[tid % 3] = pin ? (uint16_t)pc : (uint16_t)0;
+    __syncthreads();
+    // frame-row masks: bit la of row lb is halo node (a0-2+la, b0-2+lb); the
+    // halo nodes of physical row r are bits TS-HALO .. TS-HALO+NH-1 of its words
+    if (tid < NH) {
+      auto phys = [&](int r) -> uint32_t { return (uint32_t)(sBlk[r] >> (TS - HALO)) & ((1u << NH) - 1u); };
+      if (DIR == 0) {
+        sRow[tid] = phys(tid);
+      } else {
+        uint32_t m = 0;
+        for (int r = 0; r < NH; r++) m |= ((phys(r) >> tid) & 1u) << r;
+        sRow[tid] = m;
+      }
     }
     __syncthreads();
     // --- list the present edges -----------------------------------------------
@@ -802,22 +816,31 @@ __global__ __launch_bounds__(SWEEP_BS, 8) void k_sweep(SweepArgs A, const Inst *
     // new colours start from the old ones: node (a0+i, b0+j) = slot (i+2, j+2)
     if (tid < NN) sNRow[tid] = (sRow[tid + HALO] >> HALO) & ((1u << NN) - 1u);
     __syncthreads();
+    // new colours out: the tile's own nodes and, where the tile ends at the
+    // grid's last node row or column, those nodes too; one 16-bit word per
+    // node row (the last column's node alone in its block's word)
+    auto writeColours = [&]() {
+      const int r = tid, y = y0 + r;
+      if (r <= TS && y <= ny && (r < TS || y == ny)) {
+        uint32_t w = 0;  // bit i: node (x0 + i, y), i in [0, TS]
+        if (DIR == 0) {
+          w = sNRow[r];
+        } else {
+          for (int i = 0; i < NN; i++) w |= ((sNRow[i] >> r) & 1u) << i;
+        }
+        w &= (2u << min(TS, nx - x0)) - 1u;
+        ncol[cb_word(nx, x0, y)] = (uint16_t)w;
+        if (x0 + TS == nx) ncol[cb_word(nx, nx, y)] = (uint16_t)(w >> TS);
+      }
+    };
     const uint32_t nadv = sNAdv;
     if (nadv == 0) {
       // no marker in reach: the tile keeps its state
-      for (int k = tid; k < NN * NN; k += blockDim.x) {
-        const int li = k % NN, lj = k / NN;
-        const int x = x0 + li, y = y0 + lj;
-        if (x > nx || y > ny) continue;
-        const int hx = li + HALO, hy = lj + HALO;
-        if ((li < TS || x == nx) && (lj < TS || y == ny))
-          ncol[(size_t)y * (nx + 1) + x] = DIR == 0 ? sCol[hy][hx] : sCol[hx][hy];
-      }
+      writeColours();
       if (tid == 0) {
         A.has[gt] = 0;
         cnt.add(C_TILES_EMPTY, 1u);
       }
-      if (tid < NH) sRow[tid] = 0;
       if (it + itStep < itEnd) prefetch(tileAt(it + itStep));
       continue;
     }
@@ -879,15 +902,8 @@ __global__ __launch_bounds__(SWEEP_BS, 8) void k_sweep(SweepArgs A, const Inst *
     if (it + itStep < itEnd) prefetch(tileAt(it + itStep));
     __syncthreads();
     uint32_t hasm = 0;
-    if (tid < NH) sRow[tid] = 0;  // read last by the edge list; ready for the next tile
     // --- new node colours out; new aligned edges; unaligned work list --------
-    for (int k = tid; k < NN * NN; k += blockDim.x) {
-      const int hx = k % NN, hy = k / NN;
-      const int la = DIR == 0 ? hx : hy, lb = DIR == 0 ? hy : hx;
-      const int a = a0 + la, b = b0 + lb;
-      if (a <= na && b <= nb && (la < TS || a == na) && (lb < TS || b == nb))
-        ncol[G.node(a, b)] = (uint8_t)((sNRow[lb] >> la) & 1u);
-    }
+    writeColours();
     if (tid < NN) {
       // new aligned edges (a,b), a in [a0, a0+15], on row b = b0+tid
       const int j = tid, b = b0 + j;
@@ -1075,7 +1091,7 @@ __device__ void compactBlock(const CompactArgs &C, uint32_t blk) {
     const bool act = nr || prev;
     C.nearPrev[t] = (uint8_t)((nr ? 1u : 0u) | (prev << 1));
     C.tinfo[t] = (uint8_t)((ns ? TI_NEAR : 0) | (fr ? TI_FRAC : 0) |
-                           (gp(I.col[C.cur])[(size_t)(ty * TS) * (I.nx + 1) + tx * TS] ? TI_COLOUR : 0));
+                           (colAt(gp(I.col[C.cur]), I.nx, tx * TS, ty * TS) ? TI_COLOUR : 0));
     actBits |= (uint32_t)act << q;
     dirBits |= (uint32_t)(act && sweep_dir(I, C.stepNo, C.phase) == 1) << q;
     nearBits |= (uint32_t)ns << q;
@@ -1163,10 +1179,10 @@ template <int DIR>
 __device__ __forceinline__ void centreJob(const SweepView &W, uint32_t e, const Counts &cnt) {
   const GMap<DIR> G(W.nx, W.ny);
   const int na = G.na;
-  const GL uint8_t *__restrict__ ncol = gp(W.ncol);
+  const GL uint16_t *__restrict__ ncol = gp(W.ncol);
   GL uint8_t *__restrict__ ncen = gp(W.ncen);
   const GL uint8_t *__restrict__ zr = gp(W.zr);
-  auto newC = [&](int a, int b) -> int { return ncol[G.node(a, b)]; };
+  auto newC = [&](int a, int b) -> int { return G.colour(ncol, a, b); };
   int a, b;
   if (DIR == 0) { b = (int)(e / (uint32_t)(W.nx + 1)); a = (int)(e % (uint32_t)(W.nx + 1)); }
   else { a = (int)(e / (uint32_t)W.nx); b = (int)(e % (uint32_t)W.nx); }
@@ -1233,7 +1249,7 @@ __global__ void k_init_tiles(const Inst *__restrict__ inst, uint32_t kinst, uint
   const int nx = I.nx, ny = I.ny;
   const int tx = (int)(lt % (uint32_t)I.ntx), ty = (int)(lt / (uint32_t)I.ntx);
   const int x0 = tx * TS, y0 = ty * TS;
-  const GL uint8_t *__restrict__ col = gp(I.col[cur]);
+  const GL uint16_t *__restrict__ col = gp(I.col[cur]);
   __shared__ uint32_t sh;
   if (threadIdx.x == 0) sh = 0;
   __syncthreads();
@@ -1244,9 +1260,9 @@ __global__ void k_init_tiles(const Inst *__restrict__ inst, uint32_t kinst, uint
     if (i > nx || j > ny) continue;
     const bool ownI = li < TS || i == nx;
     const bool ownJ = lj < TS || j == ny;
-    const uint8_t c = col[(size_t)j * (nx + 1) + i];
-    if (i < nx && li < TS && ownJ && c != col[(size_t)j * (nx + 1) + i + 1]) m |= maskH(i, j, x0, y0);
-    if (j < ny && lj < TS && ownI && c != col[(size_t)(j + 1) * (nx + 1) + i]) m |= maskV(i, j, x0, y0);
+    const int c = colAt(col, nx, i, j);
+    if (i < nx && li < TS && ownJ && c != colAt(col, nx, i + 1, j)) m |= maskH(i, j, x0, y0);
+    if (j < ny && lj < TS && ownI && c != colAt(col, nx, i, j + 1)) m |= maskV(i, j, x0, y0);
   }
   if (m) atomicOr(&sh, m);
   __syncthreads();
@@ -1282,7 +1298,7 @@ __device__ __forceinline__ int haloCell(int k, int n) {
 
 struct FracCtx {
   int nx, ny;
-  const GL uint8_t *__restrict__ col;
+  const GL uint16_t *__restrict__ col;
   const GL uint8_t *__restrict__ cen;
   const GL double *__restrict__ hoff;
   const GL double *__restrict__ voff;
@@ -1515,12 +1531,15 @@ __global__ __launch_bounds__(FRAC_BS, 8) void k_frac_curv(FracArgs A, const Inst
   uint32_t interf = 0, hffail = 0;
   const uint32_t ntile = *A.count;
   uint32_t ntiles_done = 0;
-  // node colours of the tile plus halo, NSLOT_N per thread, fetched for the
-  // next tile while this one computes
-  constexpr int NSLOT_N = (WN * WN + FRAC_BS - 1) / FRAC_BS;
-  uint8_t pn[NSLOT_N];
-#pragma unroll
-  for (int q = 0; q < NSLOT_N; q++) pn[q] = 0;
+  // node colours of the tile plus halo (nodes x0-3 .. x0+19, rows y0-3 ..
+  // y0+19: 3 x 3 blocks of the bit plane): lane k < 3 WN holds the word of
+  // halo row k / 3 in block column tx-1 + k % 3, fetched for the next tile
+  // while this one computes (clamped indices; words of rows or blocks outside
+  // the grid are zeroed when staged)
+  static_assert(3 * WN <= FRAC_BS && 3 <= TS && WN - 3 <= 2 * TS, "staging words");
+  __shared__ uint64_t sBlk[WN];
+  uint32_t pn = 0;
+  bool pin = false;
   // this workgroup's first tile entries, read once: the colour prefetch of
   // the next tile then needs no load of its entry first
   if (tid < NEAR_ENT) {
@@ -1536,14 +1555,11 @@ __global__ __launch_bounds__(FRAC_BS, 8) void k_frac_curv(FracArgs A, const Inst
     const Inst &I = ONE ? A.one : inst[te.y];
     const int nx = I.nx, ny = I.ny;
     const uint32_t lt = te.x - I.tile0;
-    const int x0 = (int)(lt % (uint32_t)I.ntx) * TS, y0 = (int)(lt / (uint32_t)I.ntx) * TS;
-    const GL uint8_t *col = gp(I.col[A.cur]);
-#pragma unroll
-    for (int q = 0; q < NSLOT_N; q++) {
-      const int k = tid + FRAC_BS * q;
-      const int gx = x0 - 3 + k % WN, gy = y0 - 3 + k / WN;
-      pn[q] = (k < WN * WN && gx >= 0 && gy >= 0 && gx <= nx && gy <= ny) ? col[(size_t)gy * (nx + 1) + gx] : 0;
-    }
+    const int tx = (int)(lt % (uint32_t)I.ntx), y0 = (int)(lt / (uint32_t)I.ntx) * TS;
+    const GL uint16_t *col = gp(I.col[A.cur]);
+    const int k = min(tid, 3 * WN - 1), y = y0 - 3 + k / 3, bx = tx - 1 + k % 3, nbx = cb_nbx(nx);
+    pin = y >= 0 && y <= ny && bx >= 0 && bx < nbx;
+    pn = col[cb_word(nx, min(max(bx, 0), nbx - 1) * TS, min(max(y, 0), ny))];
   };
   if (blockIdx.x < ntile) prefetch(entry(blockIdx.x, 0));
   uint32_t n = 0;  // this workgroup's tile count
@@ -1559,10 +1575,12 @@ __global__ __launch_bounds__(FRAC_BS, 8) void k_frac_curv(FracArgs A, const Inst
     // every cell's 4x4 gradient nodes lie inside the grid
     const bool inner = x0 >= 1 && y0 >= 1 && x0 + TS + 1 <= nx && y0 + TS + 1 <= ny;
     ntiles_done++;
-#pragma unroll
-    for (int q = 0; q < NSLOT_N; q++) {
-      const int k = tid + FRAC_BS * q;
-      if (k < WN * WN) sNode[k / WN][k % WN] = pn[q];
+    if (tid < 3 * WN) ((uint16_t *)&sBlk[tid / 3])[tid % 3] = pin ? (uint16_t)pn : (uint16_t)0;
+    __syncthreads();
+    // halo node (x0-3+hx, y0-3+hy) is bit TS-3+hx of row hy's words
+    for (int k = tid; k < WN * WN; k += FRAC_BS) {
+      const int hx = k % WN, hy = k / WN;
+      sNode[hy][hx] = (uint8_t)((sBlk[hy] >> (TS - 3 + hx)) & 1u);
     }
     __syncthreads();
     for (int k = tid; k < W * W; k += blockDim.x) {
@@ -1580,11 +1598,10 @@ __global__ __launch_bounds__(FRAC_BS, 8) void k_frac_curv(FracArgs A, const Inst
         // ghost cell: the data of its mirror cell
         gi = haloCell(gx, nx);
         gj = haloCell(gy, ny);
-        const size_t W1 = (size_t)nx + 1;
-        kBL = P.col[(size_t)gj * W1 + gi];
-        kBR = P.col[(size_t)gj * W1 + gi + 1];
-        kTR = P.col[(size_t)(gj + 1) * W1 + gi + 1];
-        kTL = P.col[(size_t)(gj + 1) * W1 + gi];
+        kBL = colAt(P.col, nx, gi, gj);
+        kBR = colAt(P.col, nx, gi + 1, gj);
+        kTR = colAt(P.col, nx, gi + 1, gj + 1);
+        kTL = colAt(P.col, nx, gi, gj + 1);
       }
       const int nm = (kBL != kBR) + (kBR != kTR) + (kTL != kTR) + (kBL != kTL);
       double c;
@@ -1684,7 +1701,7 @@ __global__ __launch_bounds__(64, 4) void k_ghf(FracArgs A, const Inst *__restric
     const int nx = I.nx, ny = I.ny;
     const uint32_t lt = tile - I.tile0;
     const int wx0 = (int)(lt % (uint32_t)I.ntx) * TS - 2, wy0 = (int)(lt / (uint32_t)I.ntx) * TS + 4 * (int)(gw & 3u) - 2;
-    const GL uint8_t *col = gp(I.col[A.cur]);
+    const GL uint16_t *col = gp(I.col[A.cur]);
     const GL double *hoff = gp(I.hoff[A.cur]);
     const GL double *voff = gp(I.voff[A.cur]);
     const size_t W1 = (size_t)nx + 1;
@@ -1698,7 +1715,7 @@ __global__ __launch_bounds__(64, 4) void k_ghf(FracArgs A, const Inst *__restric
       const int p = k % GW_X, q = k / GW_X;
       const int x = min(max(wx0 + p, 0), nx), y = min(max(wy0 + q, 0), ny);
       if (k < GW_Y * GW_X) {
-        rn[r] = col[(size_t)y * W1 + x];
+        rn[r] = (uint8_t)colAt(col, nx, x, y);
         rh[r] = hoff[(size_t)y * nx + min(x, nx - 1)];
         rv[r] = voff[(size_t)min(y, ny - 1) * W1 + x];
       }
@@ -1860,14 +1877,14 @@ __global__ __launch_bounds__(256) void k_ns(NsArgs A, const Inst *__restrict__ i
     const int nx = I.nx, ny = I.ny;
     const uint32_t lt = te.x - I.tile0;
     const int x0 = (int)(lt % (uint32_t)I.ntx) * TS, y0 = (int)(lt / (uint32_t)I.ntx) * TS;
-    const GL uint8_t *col = gp(I.col[A.cur]);
+    const GL uint16_t *col = gp(I.col[A.cur]);
     const GL double *Cg = gp(A.C + I.coff);
     const GL double *Kg = gp(A.K + I.koff);
     // nodes x0-1 .. x0+16, cells x0-1 .. x0+15 (and the same in y)
     for (int k = tid; k < (WC + 1) * (WC + 1); k += blockDim.x) {
       const int li = k % (WC + 1), lj = k / (WC + 1);
       const int gx = x0 - 1 + li, gy = y0 - 1 + lj;
-      sNode[lj][li] = (gx >= 0 && gy >= 0 && gx <= nx && gy <= ny) ? col[(size_t)gy * (nx + 1) + gx] : (uint8_t)0;
+      sNode[lj][li] = (gx >= 0 && gy >= 0 && gx <= nx && gy <= ny) ? (uint8_t)colAt(col, nx, gx, gy) : (uint8_t)0;
     }
     for (int k = tid; k < WC * WC; k += blockDim.x) {
       const int li = k % WC, lj = k / WC;

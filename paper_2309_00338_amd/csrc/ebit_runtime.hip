@@ -106,12 +106,31 @@ struct Engine {
 
 namespace {
 
+// node colours, one byte per node (row-major, (ny+1) x (nx+1)), to and from
+// the device bit plane (cb_word); bits outside the grid stay 0
+std::vector<uint16_t> pack_colours(const uint8_t *c, int nx, int ny) {
+  std::vector<uint16_t> w(cb_words(nx, ny), 0);
+  for (int y = 0; y <= ny; y++) {
+    const uint8_t *row = c + (size_t)y * (nx + 1);
+    for (int x0 = 0; x0 <= nx; x0 += 16) {
+      uint32_t v = 0;
+      for (int i = 0; i < 16 && x0 + i <= nx; i++) v |= (uint32_t)(row[x0 + i] != 0) << i;
+      w[cb_word(nx, x0, y)] = (uint16_t)v;
+    }
+  }
+  return w;
+}
+void unpack_colours(const std::vector<uint16_t> &w, int nx, int ny, uint8_t *c) {
+  for (int y = 0; y <= ny; y++)
+    for (int x = 0; x <= nx; x++) c[(size_t)y * (nx + 1) + x] = (uint8_t)((w[cb_word(nx, x, y)] >> (x & 15)) & 1u);
+}
+
 // per-grid device arrays: both state copies and the sweep scratch
 void carve_grid(Inst *I, const ebit_grid &g, char *base, Carve &c) {
   const size_t nx = g.nx, ny = g.ny;
   const size_t nn = (nx + 1) * (ny + 1), nc = nx * ny, nh = nx * (ny + 1), nv = (nx + 1) * ny;
   for (int k = 0; k < 2; k++) {
-    I->col[k] = c.take<uint8_t>(base, nn);
+    I->col[k] = c.take<uint16_t>(base, cb_words(g.nx, g.ny));
     I->hoff[k] = c.take<double>(base, nh);
     I->voff[k] = c.take<double>(base, nv);
   }
@@ -286,21 +305,24 @@ int engine_compact(Engine *e, int afterSweep, uint32_t nextStep, int nextPhase) 
 int engine_place(Engine *e, uint32_t k, const ebit_state *s) {
   const Inst &I = e->hinst[k];
   const size_t nx = I.nx, ny = I.ny;
-  const size_t nn = (nx + 1) * (ny + 1), nc = nx * ny, nh = nx * (ny + 1), nv = (nx + 1) * ny;
+  const size_t nc = nx * ny, nh = nx * (ny + 1), nv = (nx + 1) * ny;
   HIPCHK(hipMemcpyAsync(e->dinst + k, &e->hinst[k], sizeof(Inst), hipMemcpyHostToDevice, e->stream));
   // the current copy from the host, the other one on the device
   const uint32_t c = e->cur, o = e->cur ^ 1u;
-  HIPCHK(hipMemcpyAsync(I.col[c], s->node_color, nn, hipMemcpyHostToDevice, e->stream));
+  const size_t ncw = cb_words(I.nx, I.ny);
+  const std::vector<uint16_t> packed = pack_colours(s->node_color, I.nx, I.ny);
+  HIPCHK(hipMemcpyAsync(I.col[c], packed.data(), ncw * sizeof(uint16_t), hipMemcpyHostToDevice, e->stream));
   HIPCHK(hipMemcpyAsync(I.cen[c], s->cell_color, nc, hipMemcpyHostToDevice, e->stream));
   HIPCHK(hipMemcpyAsync(I.hoff[c], s->hoff, nh * sizeof(double), hipMemcpyHostToDevice, e->stream));
   HIPCHK(hipMemcpyAsync(I.voff[c], s->voff, nv * sizeof(double), hipMemcpyHostToDevice, e->stream));
-  HIPCHK(hipMemcpyAsync(I.col[o], I.col[c], nn, hipMemcpyDeviceToDevice, e->stream));
+  HIPCHK(hipMemcpyAsync(I.col[o], I.col[c], ncw * sizeof(uint16_t), hipMemcpyDeviceToDevice, e->stream));
   HIPCHK(hipMemcpyAsync(I.hoff[o], I.hoff[c], nh * sizeof(double), hipMemcpyDeviceToDevice, e->stream));
   HIPCHK(hipMemcpyAsync(I.voff[o], I.voff[c], nv * sizeof(double), hipMemcpyDeviceToDevice, e->stream));
   HIPCHK(hipMemsetAsync(e->errs + k, 0, sizeof(uint32_t), e->stream));
   HIPCHK(launch_init_tiles(e->dinst, k, (uint32_t)(I.ntx * I.nty), e->cur, e->tileInst, e->has, e->nearPrev,
                            e->stream));
-  // the uploads read host memory the caller may reuse after return
+  // the uploads read host memory the caller may reuse after return (and the
+  // packed colours, freed on return)
   HIPCHK(hipStreamSynchronize(e->stream));
   return EBIT_OK;
 }
@@ -494,11 +516,14 @@ int engine_get_state(Engine *e, uint32_t k, uint8_t *node_color, uint8_t *cell_c
   const Inst &I = e->hinst[k];
   const size_t nx = I.nx, ny = I.ny;
   const uint32_t c = e->cur;
-  if (node_color) HIPCHK(hipMemcpyAsync(node_color, I.col[c], (nx + 1) * (ny + 1), hipMemcpyDeviceToHost, e->stream));
+  std::vector<uint16_t> packed(node_color ? cb_words(I.nx, I.ny) : 0);
+  if (node_color)
+    HIPCHK(hipMemcpyAsync(packed.data(), I.col[c], packed.size() * sizeof(uint16_t), hipMemcpyDeviceToHost, e->stream));
   if (cell_color) HIPCHK(hipMemcpyAsync(cell_color, I.cen[c], nx * ny, hipMemcpyDeviceToHost, e->stream));
   if (hoff) HIPCHK(hipMemcpyAsync(hoff, I.hoff[c], nx * (ny + 1) * sizeof(double), hipMemcpyDeviceToHost, e->stream));
   if (voff) HIPCHK(hipMemcpyAsync(voff, I.voff[c], (nx + 1) * ny * sizeof(double), hipMemcpyDeviceToHost, e->stream));
   HIPCHK(hipStreamSynchronize(e->stream));
+  if (node_color) unpack_colours(packed, I.nx, I.ny, node_color);
   return EBIT_OK;
 }
 
