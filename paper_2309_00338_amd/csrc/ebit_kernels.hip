@@ -1491,6 +1491,22 @@ constexpr int NEAR_ENT = 16;  // tile entries a near workgroup keeps in LDS
 constexpr int FRAC_FILL_TILES = FRAC_BS / TS;
 constexpr int NS_FILL_TILES = 16;
 
+// The uniform tiles' C and kappa go out with streaming (non-temporal) stores
+// when a 16-cell row of a tile is one whole 128-byte line (one grid, nx a
+// multiple of 16, both outputs line-aligned): the 1 GB write stream of a large
+// grid then does not evict the marker data the next step's sweeps and fits
+// read. Partial lines (several grids packed, ragged rows) keep ordinary
+// stores, which the L2 merges before they reach memory; so do the near tiles,
+// whose stores are few.
+template <int MODE, bool ONE>
+__device__ __forceinline__ bool streamOut(const FracArgs &A, const Inst &I) {
+  if (!ONE || (I.nx & 15) != 0) return false;
+  uintptr_t al = 0;
+  if (MODE & 1) al |= (uintptr_t)(A.Cout + I.coff);
+  if (MODE & 2) al |= (uintptr_t)(A.Kout + I.koff);
+  return (al & 127u) == 0;
+}
+
 template <int MODE, bool ONE>
 __global__ __launch_bounds__(FRAC_BS, 8) void k_frac_curv(FracArgs A, const Inst *__restrict__ inst,
                                                        const uint32_t *__restrict__ tileInst) {
@@ -1512,10 +1528,18 @@ __global__ __launch_bounds__(FRAC_BS, 8) void k_frac_curv(FracArgs A, const Inst
     const double c = (ti & TI_COLOUR) ? 1.0 : 0.0;
     double *Cp = (MODE & 1) ? A.Cout + I.coff + (size_t)(ty * TS) * nx + x : nullptr;
     double *Kp = (MODE & 2) ? A.Kout + I.koff + (size_t)(ty * TS) * nx + x : nullptr;
+    if (streamOut<MODE, ONE>(A, I)) {
 #pragma unroll 4
-    for (int r = 0; r < rows; r++) {
-      if (MODE & 1) Cp[(size_t)r * nx] = c;
-      if (MODE & 2) Kp[(size_t)r * nx] = 0.0;
+      for (int r = 0; r < rows; r++) {
+        if (MODE & 1) __builtin_nontemporal_store(c, &Cp[(size_t)r * nx]);
+        if (MODE & 2) __builtin_nontemporal_store(0.0, &Kp[(size_t)r * nx]);
+      }
+    } else {
+#pragma unroll 4
+      for (int r = 0; r < rows; r++) {
+        if (MODE & 1) Cp[(size_t)r * nx] = c;
+        if (MODE & 2) Kp[(size_t)r * nx] = 0.0;
+      }
     }
     return;
   }
@@ -1767,7 +1791,9 @@ __device__ __forceinline__ double mixOf(double c, double a, double b) { return c
 // (fx rows are nx + 1 long and start anywhere in a line; per-tile rows left a
 // partial line at both ends of every wavefront's segment). Element (x, y) of a
 // W-wide array belongs to tile (min(x, nx-1) / 16, min(y, ny-1) / 16), the
-// tile whose near pass writes it; elements of near tiles are skipped.
+// tile whose near pass writes it; elements of near tiles are skipped. The
+// stores are streaming (non-temporal): whole lines that nothing reads back
+// soon, kept out of the caches.
 constexpr int NS_CHUNK = 4096;
 template <class Val>
 __device__ __forceinline__ void nsLinearFill(double *arr, size_t size, size_t k0, int W, const NsArgs &A,
@@ -1792,7 +1818,7 @@ __device__ __forceinline__ void nsLinearFill(double *arr, size_t size, size_t k0
     for (int i = 0; i < NE_T; i++) ti[i] = k + 256u * i < size ? A.tinfo[tix[i]] : (uint8_t)TI_NEAR;
 #pragma unroll
     for (int i = 0; i < NE_T; i++)
-      if (!(ti[i] & (TI_NEAR | TI_DEAD))) arr[k + 256u * i] = val(ti[i]);
+      if (!(ti[i] & (TI_NEAR | TI_DEAD))) __builtin_nontemporal_store(val(ti[i]), &arr[k + 256u * i]);
   }
 }
 
