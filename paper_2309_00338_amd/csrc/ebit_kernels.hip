@@ -1015,35 +1015,35 @@ __device__ __forceinline__ void fitJob(const SweepView &W, uint32_t e, const Cou
   gp(W.zr)[e] = (uint8_t)((rR + 1) | ((rL + 1) << 2));
 }
 
-// a marker on an edge of one of the tile's cells: its own, or one on the
-// left border of the right neighbour or the bottom border of the one above
-// (edges on the right and top borders belong to those neighbours, except at
-// the walls, where the tile owns them)
-__device__ __forceinline__ bool fracNearOf(const uint16_t *__restrict__ has, int tx, int ty, int ntx, int nty) {
-  auto H = [&](int x, int y) -> uint32_t {
-    return (x < 0 || y < 0 || x >= ntx || y >= nty) ? 0u : (uint32_t)has[y * ntx + x];
+// The near tests of tile (tx, ty) from its own and its 8 neighbours' marker
+// masks, loaded together (indices clamped into the grid, masks outside it 0):
+// nr (the sweeps' set): a marker in the tile or one close enough to a shared
+// side or corner; fr (the fraction pass): a marker on an edge of one of the
+// tile's cells, its own or one on the left border of the right neighbour or
+// the bottom border of the one above (edges on the right and top borders
+// belong to those neighbours, except at the walls, where the tile owns them);
+// ns (the interface consumers): fr, or a cut cell in the left neighbour's
+// last column or the lower neighbour's top row (a face the tile writes lies
+// between them and the tile's cells; every other tile has equal C on both
+// sides of all its faces).
+struct NearTests {
+  bool nr, fr, ns;
+};
+__device__ __forceinline__ NearTests nearTests(const uint16_t *__restrict__ has, int tx, int ty, int ntx, int nty) {
+  auto H = [&](int dx, int dy) -> uint32_t {
+    const int x = tx + dx, y = ty + dy;
+    const bool in = x >= 0 && y >= 0 && x < ntx && y < nty;
+    const uint32_t v = has[min(max(y, 0), nty - 1) * ntx + min(max(x, 0), ntx - 1)];
+    return in ? v : 0u;
   };
-  return (H(tx, ty) & M_ANY) || (H(tx + 1, ty) & M_L0) || (H(tx, ty + 1) & M_B0);
-}
-
-// the interface consumers' near set: a cut cell in the tile, or one in the
-// left neighbour's last column or the lower neighbour's top row (a face the
-// tile writes lies between them and the tile's cells); every other tile has
-// equal C on both sides of all its faces
-__device__ __forceinline__ bool nsNearOf(const uint16_t *__restrict__ has, int tx, int ty, int ntx, int nty) {
-  auto H = [&](int x, int y) -> uint32_t {
-    return (x < 0 || y < 0 || x >= ntx || y >= nty) ? 0u : (uint32_t)has[y * ntx + x];
-  };
-  return fracNearOf(has, tx, ty, ntx, nty) || (H(tx - 1, ty) & M_R1) || (H(tx, ty - 1) & M_T1);
-}
-
-__device__ __forceinline__ bool nearOf(const uint16_t *__restrict__ has, int tx, int ty, int ntx, int nty) {
-  auto H = [&](int x, int y) -> uint32_t {
-    return (x < 0 || y < 0 || x >= ntx || y >= nty) ? 0u : (uint32_t)has[y * ntx + x];
-  };
-  return (H(tx, ty) & M_ANY) || (H(tx - 1, ty) & M_R) || (H(tx + 1, ty) & M_L) || (H(tx, ty - 1) & M_T) ||
-         (H(tx, ty + 1) & M_B) || (H(tx - 1, ty - 1) & M_RT) || (H(tx + 1, ty - 1) & M_LT) ||
-         (H(tx - 1, ty + 1) & M_RB) || (H(tx + 1, ty + 1) & M_LB);
+  const uint32_t c = H(0, 0), l = H(-1, 0), r = H(1, 0), d = H(0, -1), u = H(0, 1);
+  const uint32_t ld = H(-1, -1), rd = H(1, -1), lu = H(-1, 1), ru = H(1, 1);
+  NearTests t;
+  t.nr = ((c & M_ANY) | (l & M_R) | (r & M_L) | (d & M_T) | (u & M_B) | (ld & M_RT) | (rd & M_LT) | (lu & M_RB) |
+          (ru & M_LB)) != 0u;
+  t.fr = ((c & M_ANY) | (r & M_L0) | (u & M_B0)) != 0u;
+  t.ns = t.fr || ((l & M_R1) | (d & M_T1)) != 0u;
+  return t;
 }
 
 constexpr int CPT = 4;  // tiles per thread in the compaction
@@ -1073,29 +1073,53 @@ __device__ void compactBlock(const CompactArgs &C, uint32_t blk) {
   const uint32_t base = (blk * blockDim.x + tid) * CPT;
   uint32_t actBits = 0, dirBits = 0, nearBits = 0, fracBits = 0;
   uint32_t kq[CPT];
-  for (int q = 0; q < CPT; q++) {
-    const uint32_t t = base + q;
-    kq[q] = 0;
-    if (t >= C.ntiles) break;
-    const uint32_t k = ONE ? 0u : C.tileInst[t];
-    kq[q] = k;
-    if (k == NO_INST) continue;
-    const Inst &I = ONE ? C.one : C.inst[k];
-    const uint32_t lt = t - I.tile0;
-    const int tx = (int)(lt % (uint32_t)I.ntx), ty = (int)(lt / (uint32_t)I.ntx);
-    const bool nr = nearOf(C.has + I.tile0, tx, ty, I.ntx, I.nty);
-    const bool fr = fracNearOf(C.has + I.tile0, tx, ty, I.ntx, I.nty);
-    const bool ns = nsNearOf(C.has + I.tile0, tx, ty, I.ntx, I.nty);
-    const uint32_t pv = C.nearPrev[t];
+  // one tile's lists and bookkeeping from its tests, history and colour
+  auto finish = [&](int q, uint32_t t, const Inst &I, NearTests nt, uint32_t pv, int colour) {
     const uint32_t prev = C.afterSweep ? (pv & 1u) : ((pv >> 1) & 1u);
-    const bool act = nr || prev;
-    C.nearPrev[t] = (uint8_t)((nr ? 1u : 0u) | (prev << 1));
-    C.tinfo[t] = (uint8_t)((ns ? TI_NEAR : 0) | (fr ? TI_FRAC : 0) |
-                           (colAt(gp(I.col[C.cur]), I.nx, tx * TS, ty * TS) ? TI_COLOUR : 0));
+    const bool act = nt.nr || prev;
+    C.nearPrev[t] = (uint8_t)((nt.nr ? 1u : 0u) | (prev << 1));
+    C.tinfo[t] = (uint8_t)((nt.ns ? TI_NEAR : 0) | (nt.fr ? TI_FRAC : 0) | (colour ? TI_COLOUR : 0));
     actBits |= (uint32_t)act << q;
     dirBits |= (uint32_t)(act && sweep_dir(I, C.stepNo, C.phase) == 1) << q;
-    nearBits |= (uint32_t)ns << q;
-    fracBits |= (uint32_t)fr << q;
+    nearBits |= (uint32_t)nt.ns << q;
+    fracBits |= (uint32_t)nt.fr << q;
+  };
+  if (ONE) {
+    // one grid: every load of the thread's tiles first (indices clamped into
+    // the tile range), then the tests and stores
+    const Inst &I = C.one;
+    NearTests nt[CPT];
+    uint32_t pv[CPT];
+    int colour[CPT];
+#pragma unroll
+    for (int q = 0; q < CPT; q++) {
+      const uint32_t t = min(base + q, C.ntiles - 1u);
+      const uint32_t lt = t - I.tile0;
+      const int tx = (int)(lt % (uint32_t)I.ntx), ty = (int)(lt / (uint32_t)I.ntx);
+      nt[q] = nearTests(C.has + I.tile0, tx, ty, I.ntx, I.nty);
+      pv[q] = C.nearPrev[t];
+      colour[q] = colAt(gp(I.col[C.cur]), I.nx, tx * TS, ty * TS);
+    }
+#pragma unroll
+    for (int q = 0; q < CPT; q++) {
+      const uint32_t t = base + q;
+      kq[q] = 0;
+      if (t < C.ntiles) finish(q, t, I, nt[q], pv[q], colour[q]);
+    }
+  } else {
+    for (int q = 0; q < CPT; q++) {
+      const uint32_t t = base + q;
+      kq[q] = 0;
+      if (t >= C.ntiles) break;
+      const uint32_t k = C.tileInst[t];
+      kq[q] = k;
+      if (k == NO_INST) continue;
+      const Inst &I = C.inst[k];
+      const uint32_t lt = t - I.tile0;
+      const int tx = (int)(lt % (uint32_t)I.ntx), ty = (int)(lt / (uint32_t)I.ntx);
+      finish(q, t, I, nearTests(C.has + I.tile0, tx, ty, I.ntx, I.nty), C.nearPrev[t],
+             colAt(gp(I.col[C.cur]), I.nx, tx * TS, ty * TS));
+    }
   }
   // exclusive block scan of the per-thread counts
   const uint32_t cb = __popc(dirBits), ca = __popc(actBits) - cb, cn = __popc(nearBits), cf = __popc(fracBits);
