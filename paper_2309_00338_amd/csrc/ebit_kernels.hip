@@ -1505,9 +1505,9 @@ __device__ bool ghfFit(int nx, int ny, double h, int i, int j, int gx, int gy, G
 // and/or kappa of the tile's cells (one per thread). Cells whose heights fail
 // in both directions are handed to k_ghf (one entry per 64 cells that have
 // any), which keeps the rare parabola fit out of this kernel's register
-// budget. Workgroups are 256 threads, 8 resident per CU; the first ones (all
-// 8 slots per CU, or 5.5 when the fill streams its stores, so that the fill
-// runs beside them) take the near tiles. Every later workgroup fills 16 consecutive global
+// budget. Workgroups are 256 threads, 8 resident per CU; the first ones (5.5
+// per CU, so that the fill runs beside them) take the near tiles. Every later
+// workgroup fills 16 consecutive global
 // tiles: cells of tiles that are neither near nor unowned get their tile's
 // colour as C and zero curvature, one 8-byte store per lane and row, lanes
 // along a grid row. MODE 1: C only; 2: kappa from the caller's C; 3: both.

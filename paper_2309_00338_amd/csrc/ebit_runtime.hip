@@ -79,7 +79,6 @@ struct Engine {
   // for a pool, whose slot may be empty and whose tile space is larger
   bool one = false;
   int sweepBlocks = 0, fitBlocks = 0, centreBlocks = 0, nearBlocks[3] = {0, 0, 0}, nsNearBlocks = 0;
-  int nearBlocksStream[3] = {0, 0, 0};  // the same when the fill streams its stores
   // device tables
   Inst *dinst = nullptr;
   uint32_t *tileInst = nullptr, *counts = nullptr, *errs = nullptr;
@@ -248,22 +247,19 @@ void engine_launch_config(Engine *e) {
   e->fitBlocks = cus * resident_blocks(1);
   e->centreBlocks = cus * resident_blocks(2);
   e->ghfBlocks = cus * 16;  // single-wavefront workgroups, one per parabola-fit entry in the usual case
-  // near-tile workgroups per CU of the fraction pass. With ordinary stores:
-  // all resident slots (the fill workgroups take the slots the near ones
-  // leave as they finish; a fill running beside the near tiles evicts their
-  // data and slows them more than it gains). When the fill streams its stores
-  // (one grid, whole-line rows), 5.5 of the 8 slots: the fill then runs beside
-  // the near tiles from the start (8192^2: call 240 -> 192 us).
-  double perCU = 64.0, perCUStream = 5.5;
-  if (const char *v = getenv("EBIT_FRAC_NEAR_BLOCKS_PER_CU")) perCU = perCUStream = atof(v);
-  if (!(perCU > 0.0)) perCU = 64.0;
-  if (!(perCUStream > 0.0)) perCUStream = 5.5;
+  // near-tile workgroups per CU of the fraction pass: 5.5 of the 8 resident
+  // slots, so that fill workgroups run beside the near ones from the start
+  // and take the other slots as the near ones finish (8192^2 with the fill's
+  // streaming stores: call 240 -> 192 us against all 8 slots; the batch of
+  // 256 grids, ordinary stores: 679 -> 658 us per step)
+  double perCU = 5.5;
+  if (const char *v = getenv("EBIT_FRAC_NEAR_BLOCKS_PER_CU")) perCU = atof(v);
+  if (!(perCU > 0.0)) perCU = 5.5;
   e->nsNearBlocks = cus * 6;
   for (int m = 0; m < 3; m++) {
     const int cap = cus * resident_blocks(3 + m);
-    const int nb = std::min((int)(cus * perCU), cap), nbs = std::min((int)(cus * perCUStream), cap);
+    const int nb = std::min((int)(cus * perCU), cap);
     e->nearBlocks[m] = nb < 1 ? 1 : nb;
-    e->nearBlocksStream[m] = nbs < 1 ? 1 : nbs;
   }
 }
 
@@ -435,13 +431,7 @@ int engine_frac(Engine *e, int mode, const double *Cin, double *Cout, double *Ko
   a.tinfo = e->tinfo;
   a.list = e->fracList;
   a.count = e->counts + NSLOT * e->slot + CNT_FRAC;
-  // the kernel streams the uniform fill's stores under the same condition
-  const Inst &I0 = e->hinst[0];
-  uintptr_t al = 0;
-  if (mode & 1) al |= (uintptr_t)(Cout + I0.coff);
-  if (mode & 2) al |= (uintptr_t)(Kout + I0.koff);
-  const bool streams = e->one && (I0.nx & 15) == 0 && (al & 127u) == 0;
-  a.nearBlocks = streams ? e->nearBlocksStream[mode - 1] : e->nearBlocks[mode - 1];
+  a.nearBlocks = e->nearBlocks[mode - 1];
   a.ctr = e->ctr;
   // a curvature launch appends to its parity's count (zeroed by the launch
   // before it) and zeroes the other one for the launch after it
