@@ -91,7 +91,9 @@ def test_dense_random_colouring(nx, ny):
     assert cnt["annihilated"] > 100 and cnt["ghf_fit"] > 100, cnt
 
 
-@pytest.mark.parametrize("nx,ny", [(37, 53), (53, 19), (16, 16), (4, 4), (17, 33)])
+# (64, 37) and (37, 48): the last node column (row) alone in its block of the
+# colour bit plane on one axis, a ragged last tile on the other
+@pytest.mark.parametrize("nx,ny", [(37, 53), (53, 19), (16, 16), (4, 4), (17, 33), (64, 37), (37, 48)])
 def test_ragged_rectangular_grids(nx, ny):
     rng = np.random.Generator(np.random.PCG64(nx * 1000 + ny))
     shapes = []
