@@ -60,7 +60,17 @@ bool grid_ok(const ebit_grid *g) {
 }
 
 uint32_t tiles_of(const ebit_grid &g) { return (uint32_t)(((g.nx + TS - 1) / TS) * ((g.ny + TS - 1) / TS)); }
-size_t jobs_of(const ebit_grid &g) { return (size_t)(g.nx + 1) * (g.ny + 1); }
+// Fit-job list entries a grid needs. A sweep queues one job per new interior
+// unaligned marker: at most (nx-1)*ny for an x sweep, nx*(ny-1) for a y sweep.
+// With several grids each grid sweeps one direction per phase and its centre
+// rules run before the next phase, so one direction's bound suffices. An
+// engine of one grid leaves the first sweep's jobs in the list (read from the
+// other end) until the second sweep's launch has run their centre rules, so
+// both directions' jobs are alive at once and the list holds both bounds.
+size_t jobs_of(const ebit_grid &g, bool both) {
+  const size_t x = (size_t)(g.nx - 1) * g.ny, y = (size_t)g.nx * (g.ny - 1);
+  return both ? x + y : std::max(x, y);
+}
 
 constexpr uint32_t MAX_POOL_TILES = (1u << 24) - 1u;  // keeps the job list within 32-bit indices
 constexpr uint32_t JOBS_PER_TILE = TS * TS;            // interior unaligned edges a tile owns, at most
@@ -550,7 +560,7 @@ int batch_sizes(int n, const ebit_grid *grids, uint32_t *ntiles, uint32_t *jobCa
   for (int k = 0; k < n; k++) {
     if (!grid_ok(&grids[k])) return EBIT_ERR_ARG;
     nt += tiles_of(grids[k]);
-    nj += jobs_of(grids[k]);
+    nj += jobs_of(grids[k], n == 1);
     gb += grid_bytes(grids[k]);
   }
   if (nt >= 0xffffffffull || nj >= 0xffffffffull) return EBIT_ERR_ARG;
@@ -655,7 +665,7 @@ extern "C" {
 // ---------------------------------------------------------------------------
 int ebit_workspace_bytes(const ebit_grid *grid, size_t *bytes) {
   if (!grid_ok(grid) || !bytes) return EBIT_ERR_ARG;
-  *bytes = engine_bytes(tiles_of(*grid), 1, (uint32_t)jobs_of(*grid)) + grid_bytes(*grid);
+  *bytes = engine_bytes(tiles_of(*grid), 1, (uint32_t)jobs_of(*grid, true)) + grid_bytes(*grid);
   return EBIT_OK;
 }
 

@@ -289,9 +289,32 @@ def uniform_faces(nx: int, ny: int, U: float, V: float):
     return np.full((ny, nx + 1), float(U)), np.full((ny + 1, nx), float(V))
 
 
-def vortex_dt_schedule(dt: float, period: float, nsteps: int) -> List[float]:
-    """dt_n = dt cos(pi t_n / T), t_n = n dt: the vortex time factor folded in."""
-    return [dt * math.cos(math.pi * (k * dt) / period) for k in range(nsteps)]
+def vortex_dt_schedule(dt: float, period: float, nsteps: int, sample: str = "start") -> List[float]:
+    """dt_n = dt cos(pi t / T): the vortex time factor folded into the step.
+
+    sample="start" takes t = t_n = n dt, the velocity of time level n that the
+    explicit Euler update of Eq. (Eq_marker_dis) uses; over a full period the
+    factors then sum to dt, not 0 (the discrete flow ends one start-of-period
+    step short of reversing). sample="mid" takes t = t_n + dt/2, whose factors
+    are antisymmetric about T/2 and sum to 0 over a whole period."""
+    off = {"start": 0.0, "mid": 0.5}[sample]
+    return [dt * math.cos(math.pi * ((k + off) * dt) / period) for k in range(nsteps)]
+
+
+def shear_faces(nx: int, ny: int, seed: int, amp: float = 1.0) -> Tuple[np.ndarray, np.ndarray]:
+    """Random face velocities whose sign alternates row by row for u and column
+    by column for v (magnitudes uniform in [0.3, 1] amp), zero on the walls: a
+    strongly sheared, converging and diverging field that drives markers of
+    neighbouring rows past each other (not divergence-free; the kinematic step
+    does not need it). Scale dt so that amp * dt / h <= 0.5."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    sr = np.where(np.arange(ny) % 2 == 0, 1.0, -1.0)[:, None]
+    sc = np.where(np.arange(nx) % 2 == 0, 1.0, -1.0)[None, :]
+    u = sr * rng.uniform(0.3 * amp, amp, (ny, nx + 1))
+    v = sc * rng.uniform(0.3 * amp, amp, (ny + 1, nx))
+    u[:, 0] = u[:, -1] = 0.0
+    v[0, :] = v[-1, :] = 0.0
+    return np.ascontiguousarray(u), np.ascontiguousarray(v)
 
 
 # --------------------------------------------------------------------------
@@ -500,6 +523,18 @@ def random_colouring(nx: int, ny: int, seed: int, p: float = 0.5) -> State:
     carry two or four."""
     rng = np.random.Generator(np.random.PCG64(seed))
     c = (rng.random((ny + 1, nx + 1)) < p).astype(np.uint8)
+    cc = (rng.random((ny, nx)) < 0.5).astype(np.uint8)
+    hoff = rng.uniform(0.05, 0.95, (ny + 1, nx))
+    voff = rng.uniform(0.05, 0.95, (ny, nx + 1))
+    return State(nx, ny, 1.0 / max(nx, ny), c, cc, hoff, voff)
+
+
+def checkerboard(nx: int, ny: int, seed: int) -> State:
+    """Node colours alternating in both directions: every edge carries a
+    marker and every cell has four (the densest state there is); centre colours
+    random, offsets uniform in [0.05, 0.95]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    c = (np.add.outer(np.arange(ny + 1), np.arange(nx + 1)) & 1).astype(np.uint8)
     cc = (rng.random((ny, nx)) < 0.5).astype(np.uint8)
     hoff = rng.uniform(0.05, 0.95, (ny + 1, nx))
     voff = rng.uniform(0.05, 0.95, (ny, nx + 1))

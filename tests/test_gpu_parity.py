@@ -292,3 +292,62 @@ def test_ns_fields_require_current_fraction():
     with pytest.raises(ebit.EbitError) as e:
         ls.g.ns_fields(C, K, 1, 1, 1, 1, 1)
     assert e.value.code == ebit.EBIT_ERR_STATE
+
+
+def test_checkerboard_both_sweeps_queue_more_jobs_than_one_grid_edge_count():
+    """Alternating node colours: every edge carries a marker and every cell
+    four. The first sweep's fit jobs stay listed until the second sweep's
+    launch has applied their centre rules, so both sweeps' jobs are alive at
+    once; here they outnumber (nx+1)(ny+1), the list length that once held
+    them. States, fields and counters match the oracle every step."""
+    n = 64
+    st = I.checkerboard(n, n, seed=11)
+    x = np.arange(n + 1) / n
+    psi = (np.sin(np.pi * x)[None, :] ** 2) * (np.sin(np.pi * x)[:, None] ** 2) / np.pi
+    psi[0, :] = psi[-1, :] = psi[:, 0] = psi[:, -1] = 0.0
+    u, v = I.faces_from_psi(psi, st.h)
+    dt = 0.2 * st.h / max(np.abs(u).max(), np.abs(v).max())
+    o = st.copy()
+    assert oracle.sweep(o, u, v, dt, 0)[0] == oracle.OK
+    jobs_x = int(o.v_present()[:, 1:-1].sum())
+    assert oracle.sweep(o, u, v, dt, 1)[0] == oracle.OK
+    jobs_y = int(o.h_present()[1:-1, :].sum())
+    assert jobs_x + jobs_y > (n + 1) * (n + 1), (jobs_x, jobs_y)
+    ls = Lockstep(st, u, v)
+    ls.fields("initial")
+    cnt = _run(ls, [dt] * 4)
+    assert cnt["cv_set"] > 1000, cnt
+
+
+@pytest.mark.parametrize("nx,ny,seed", [(64, 64, 33), (53, 37, 38), (160, 96, 35)])
+def test_rare_branches_under_sheared_random_faces(nx, ny, seed):
+    """Random colouring under a field whose sign alternates between rows
+    (columns for v): markers of neighbouring rows converge and pass each other,
+    which reaches the branches smooth flows never do: three aligned markers
+    landing on one edge (the middle kept), a new unaligned edge crossed by three
+    advected segments (the median taken) and four-marker cells that no
+    centre rule settles. Each count is nonzero and equal to the oracle's, and
+    the states and fields match every step."""
+    st = I.random_colouring(nx, ny, seed=seed)
+    u, v = I.shear_faces(nx, ny, seed + 500)
+    dt = 0.49 * st.h / max(np.abs(u).max(), np.abs(v).max())
+    ls = Lockstep(st, u, v)
+    ls.fields("initial")
+    cnt = _run(ls, [dt] * 6)
+    assert cnt["three_landers"] > 0 and cnt["three_crossings"] > 0 and cnt["cv_unresolved"] > 0, cnt
+    print(cnt)
+
+
+def test_wall_markers_hold_under_wall_normal_motion():
+    """A nearly flat interface touching both side walls, translated by a
+    uniform field whose wall faces are not zero: the wall-line markers keep
+    their offsets in the x sweep (counted as wall violations) and slide along
+    the walls in the y sweep; no marker leaves the grid."""
+    n = 96
+    st = I.init_state(n, n, [I.CosineBelow(n, 0.5, 0.004)])
+    u, v = I.uniform_faces(n, n, 0.6, 0.4)
+    dt = 0.5 * st.h  # 0.3 and 0.2 cells per sweep
+    ls = Lockstep(st, u, v)
+    ls.fields("initial")
+    cnt = _run(ls, [dt] * 8)
+    assert cnt["wall_violation"] >= 16, cnt

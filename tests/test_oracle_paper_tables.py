@@ -67,14 +67,19 @@ def _close(ours, paper, rel):
     return abs(ours - paper) <= rel * paper
 
 
-def test_vortex_T2_within_factor_3_of_table_3():
+# ours / paper for the T = 2 circle-fit rows at N = 32, 64 (time factor at t_n):
+# E_area 0.70, 0.66; E_shape 0.60, 0.54; E_sym 0.79, 0.82
+T2_BOUNDS = {"E_area": (0.6, 1.25), "E_shape": (0.45, 1.25), "E_sym": (0.6, 1.25)}
+
+
+def test_vortex_T2_close_to_table_3():
     tab = GOLD["vortex_T2"]
     prev = None
     for n in (32, 64):
         e = _vortex(n, 2.0)
         k = tab["N"].index(n)
-        for key in ("E_area", "E_shape", "E_sym"):
-            assert tab[key][k] / 3 <= e[key] <= tab[key][k] * 3, (n, key, e[key])
+        for key, (lo, hi) in T2_BOUNDS.items():
+            assert lo * tab[key][k] <= e[key] <= hi * tab[key][k], (n, key, e[key], tab[key][k])
         if prev:
             assert e["E_area"] < prev["E_area"] and e["E_shape"] < prev["E_shape"]
         prev = e

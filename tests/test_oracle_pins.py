@@ -659,3 +659,146 @@ def test_curvature_fallback_leaves_no_nan_on_small_circles(R):
         err = np.abs(K[fin] * st.h * R - 1.0)
         assert err.max() < 0.2 and np.median(err) < 0.12, (R, err.max(), np.median(err))
     assert fails > 0
+
+
+# ----------------------------------------------------------------------------
+# Odd counts (Sec. 2.4: one marker per edge) worked out by hand
+# ----------------------------------------------------------------------------
+def test_three_landers_keep_the_positional_middle():
+    """Three aligned markers of one grid row land on edge H(3, 2): the one from
+    H(2, 2) moves right across node 3, the one on H(3, 2) stays, the one from
+    H(4, 2) moves left across node 4. One marker per edge (Sec. 2.4) keeps one
+    of them and annihilates the outer pair; under a face CFL of at most 0.5 the
+    landing map keeps the row's order, so the kept one is the middle of the
+    three landed positions. Hand values, lambda = 1, columns of u uniform in y:
+    H(2): s = 0.8, u = 0.4 -> 1.2 -> lands at 0.2;
+    H(3): s = 0.5, ubar = (0.4 - 0.35) / 2 = 0.025 -> stays at 0.525;
+    H(4): s = 0.1, ubar = -0.35 + 0.1 * (0.1 + 0.35) = -0.305 -> -0.205 ->
+    lands at 0.795. Kept: 0.525."""
+    nx, ny = 8, 4
+    c = np.zeros((ny + 1, nx + 1), np.uint8)
+    c[2, 0:3] = 1
+    c[2, 4] = 1  # row 2: 1 1 1 0 1 0 0 0 0 -> markers on H(2), H(3), H(4)
+    st = I.State(nx, ny, 1.0, c, np.zeros((ny, nx), np.uint8), np.full((ny + 1, nx), 0.5),
+                 np.full((ny, nx + 1), 0.5))
+    st.hoff[2, 2], st.hoff[2, 3], st.hoff[2, 4] = 0.8, 0.5, 0.1
+    cols = np.array([0.0, 0.2, 0.4, 0.4, -0.35, 0.1, 0.0, 0.0, 0.0])
+    u = np.ascontiguousarray(np.tile(cols, (ny, 1)))
+    v = np.zeros((ny + 1, nx))
+    rc, cnt = oracle.sweep(st, u, v, 1.0, 0)
+    assert rc == oracle.OK
+    d = oracle.counters_dict(cnt)
+    assert d["three_landers"] == 1 and d["annihilated"] == 2, d
+    assert list(st.c[2]) == [1, 1, 1, 1, 0, 0, 0, 0, 0]
+    hp = st.h_present()
+    assert hp[2, 3] and not hp[2, 2] and not hp[2, 4]
+    landed = sorted([0.8 + 0.4 - 1.0, 0.525, 0.1 - 0.305 + 1.0])
+    assert abs(st.hoff[2, 3] - landed[1]) < 1e-15 and abs(st.hoff[2, 3] - 0.525) < 1e-15
+
+
+def _three_crossing_state():
+    """Line x = 3 in row 1 is crossed by three advected segments (lambda = 1,
+    only the x sweep): cell (2,1) holds the segment V(2,1)-V(3,1); cell (3,1)
+    holds four markers with centre colour 1, so its isolated corners are BR and
+    TL and its segments H(3,1)-V(4,1) and H(3,2)-V(3,1). Column 3 and 4 faces
+    are -0.6, 0.2, -0.6 in rows 0, 1, 2: the markers at s = 0.05 on H(3,1) and
+    H(3,2) average -0.6 and 0.2 and move -0.2, across nodes (3,1) and (3,2);
+    the gray points of V(3,1) and V(4,1) (t = 0.5) move +0.2; column 2 moves
+    +0.05."""
+    nx, ny = 6, 4
+    c = np.zeros((ny + 1, nx + 1), np.uint8)
+    c[1, 2] = c[1, 3] = c[2, 4] = 1
+    cc = np.zeros((ny, nx), np.uint8)
+    cc[1, 3] = 1
+    hoff = np.full((ny + 1, nx), 0.5)
+    voff = np.full((ny, nx + 1), 0.5)
+    hoff[1, 3] = hoff[2, 3] = 0.05
+    voff[1, 2], voff[1, 3], voff[1, 4] = 0.3, 0.5, 0.5
+    voff[0, 3], voff[2, 4] = 0.95, 0.2  # keep the other gray points within half a cell
+    u = np.zeros((ny, nx + 1))
+    u[0, 3] = u[0, 4] = u[2, 3] = u[2, 4] = -0.6
+    u[1, 3] = u[1, 4] = 0.2
+    u[:, 1] = u[:, 2] = 0.05
+    return I.State(nx, ny, 1.0, c, cc, hoff, voff), u, np.zeros((ny + 1, nx))
+
+
+def test_three_crossings_take_the_median_worked_by_hand():
+    """Crossing heights of line x = 3 above node (3, 1), by hand:
+    cell (2,1): (2.05, 0.3) -> (3.2, 0.5): 0.3 + 0.2 * 0.95 / 1.15 = 0.46522;
+    BR segment: (2.85, 0) -> (4.2, 0.5): 0.5 * 0.15 / 1.35 = 0.05556;
+    TL segment: (2.85, 1) -> (3.2, 0.5): 1 - 0.5 * 0.15 / 0.35 = 0.78571.
+    With the straight-line placement the new marker sits at the median crossing
+    0.46522; the circle fit starts from the same segment, whose chain gives a
+    different but valid offset. Both count one three-crossing edge, and the new
+    colours follow the two flips."""
+    st, u, v = _three_crossing_state()
+    o = st.copy()
+    rc, cnt = oracle.sweep(o, u, v, 1.0, 0, line=True)
+    assert rc == oracle.OK
+    d = oracle.counters_dict(cnt)
+    assert d["three_crossings"] == 1 and d["parity_fallback"] == 0 and d["ties"] == 0, d
+    assert o.c[1, 3] == 0 and o.c[2, 3] == 1 and o.v_present()[1, 3]
+    assert abs(o.voff[1, 3] - (0.3 + 0.2 * 0.95 / 1.15)) < 1e-15
+    o = st.copy()
+    rc, cnt = oracle.sweep(o, u, v, 1.0, 0)
+    assert rc == oracle.OK and oracle.counters_dict(cnt)["three_crossings"] == 1
+    assert 0.0 <= o.voff[1, 3] <= 1.0
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_crossing_parity_equals_colour_parity(seed):
+    """For a new unaligned edge of line a, count the advected segments of the
+    two old cells beside it that cross the line. Each marker on the shared edge
+    ends two of those segments and every other marker of the two cells one, so
+    the count's parity is the number of the cells' outer markers left of the
+    line: the left edge's gray point always (it moves at most half a cell), the
+    right edge's never, and a bottom or top aligned marker exactly when it did
+    not cross node a (or crossed it leftwards). That sum is the new colour
+    difference of the edge's two nodes: an even count where the colours say
+    "marker" cannot occur in a valid sweep, so the mid-edge fallback never
+    fires (also with offsets exactly on nodes), and the lander count always has
+    the colours' parity."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    seen = valid = 0
+    for k in range(300):
+        n = 12
+        c = (rng.random((n + 1, n + 1)) < 0.5).astype(np.uint8)
+        cc = (rng.random((n, n)) < 0.5).astype(np.uint8)
+        hoff, voff = rng.uniform(0, 1, (n + 1, n)), rng.uniform(0, 1, (n, n + 1))
+        for a in (hoff, voff):
+            m = rng.random(a.shape) < 0.15
+            a[m] = rng.integers(0, 2, int(m.sum())).astype(np.float64)
+        st = I.State(n, n, 1.0, c, cc, hoff, voff)
+        u, v = rng.uniform(-0.5, 0.5, (n, n + 1)), rng.uniform(-0.5, 0.5, (n + 1, n))
+        u[:, 0] = u[:, -1] = 0.0
+        v[0, :] = v[-1, :] = 0.0
+        rc, cnt = oracle.sweep(st, u, v, 1.0, k & 1)
+        if rc == oracle.ERR_DOMAIN:  # a marker pushed through a wall: no valid sweep
+            continue
+        assert rc == oracle.OK
+        valid += 1
+        d = oracle.counters_dict(cnt)
+        assert d["parity_fallback"] == 0 and d["invariant_fail"] == 0, (k, d)
+        seen += d["three_crossings"] + d["three_landers"]
+    assert valid > 50 and seen > 0, (valid, seen)
+
+
+def test_midpoint_time_factor_sums_to_zero_and_reverses_closer():
+    """The vortex's cos(pi t / T) folded into dt: sampled at t_n (the velocity
+    of time level n in Eq. Eq_marker_dis) the factors of one period sum to dt;
+    sampled at t_n + dt/2 they sum to zero and the interface ends closer to
+    where it started."""
+    n, T = 32, 2.0
+    dt = 0.125 / n
+    steps = int(round(T / dt))
+    start = I.vortex_dt_schedule(dt, T, steps)
+    mid = I.vortex_dt_schedule(dt, T, steps, sample="mid")
+    assert abs(sum(start) - dt) < 1e-12 and abs(sum(mid)) < 1e-14
+    w = I.single_vortex(n, period=T, cfl=0.125)
+    shape = {}
+    for name, dts in (("start", start), ("mid", mid)):
+        st = w.state.copy()
+        for d in dts:
+            assert oracle.step(st, w.u, w.v, d)[0] == oracle.OK
+        shape[name] = e_shape(st, 0.5 * n, 0.75 * n, 0.15 * n)
+    assert shape["mid"] < shape["start"]
