@@ -167,7 +167,10 @@ class EbitGrid:
             _chk(_lib.ebit_create(ctypes.byref(self.grid), ctypes.byref(s), self.ws.data_ptr(), nbytes,
                                   self.stream.cuda_stream, ctypes.byref(handle)), "ebit_create")
         self._h = handle
-        self.step = state.step
+        self.step = 0
+        if state.step:
+            # ebit_create starts at step 0; the step number picks the sweep order
+            self.set_state(state)
 
     # -- checks ---------------------------------------------------------
     def _dev(self, t, shape, name):
