@@ -288,6 +288,43 @@ int ebit_pool_retire(ebit_pool *p, int slot);
 int ebit_pool_stats(ebit_pool *p, ebit_counters *out);
 int ebit_pool_destroy(ebit_pool *p);
 
+/* ===========================================================================
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ *
+ * One whole step (as ebit_create, ebit_advect, ebit_fraction_curvature) of a
+ * grid whose state lives in the caller's device buffers, in the layout of the
+ * header comment: node_color_dev, cell_color_dev, hoff_dev and voff_dev are
+ * read, then overwritten with the state after the step; u_dev, v_dev as in
+ * ebit_advect; C_dev and K_dev are fully written as by
+ * ebit_fraction_curvature. `step` is the grid's step number (its parity picks
+ * the sweep order, EBIT_SWEEP_ALTERNATE). Every intermediate (engine tables,
+ * both state copies, sweep scratch) lives in one array of the library's own
+ * per GPU, EBIT_STATIC_SCRATCH_BYTES long, held from the library's first use
+ * on that GPU until the process ends; nothing is allocated, neither by this
+ * call nor by the library on its behalf. Grids whose ebit_workspace_bytes
+ * exceed EBIT_STATIC_SCRATCH_BYTES (about 1060 x 1060 cells) are rejected
+ * with EBIT_ERR_NOMEM before any device work.
+ *
+ * Asynchronous on hip_stream (NULL = default stream): the call returns after
+ * enqueueing, and *status_dev (device, one int32) receives EBIT_OK,
+ * EBIT_ERR_CFL, EBIT_ERR_DOMAIN, or EBIT_ERR_ARG for an invalid state (a
+ * colour byte above 1, an offset outside [0,1] on an edge whose end colours
+ * differ); after an error the outputs are undefined. The return value reports
+ * argument errors and failed HIP calls (EBIT_ERR_DEVICE). Tables are cleared
+ * by kernels, not memset nodes, so the call may be captured into a graph.
+ *
+ * Every call on a GPU shares that GPU's array and the library's host record
+ * of it, and each call starts by clearing and reloading both: calls that
+ * overlap on one GPU (from several host threads, or on several streams whose
+ * work may run at once) race; serialise them.
+ * =========================================================================== */
+#define EBIT_STATIC_SCRATCH_BYTES (80u << 20)
+
+int ebit_step_static(const ebit_grid *grid, uint8_t *node_color_dev, uint8_t *cell_color_dev, double *hoff_dev,
+                     double *voff_dev, const double *u_dev, const double *v_dev, double dt, int64_t step,
+                     double *C_dev, double *K_dev, int32_t *status_dev, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -51,7 +51,7 @@ constexpr int CTR_PARTS = 64;
 constexpr int CTR_STRIDE = 32;
 static_assert(NCOUNTERS <= CTR_STRIDE, "counters fit one partition");
 
-enum : uint32_t { ERRBIT_CFL = 1u, ERRBIT_DOMAIN = 2u };
+enum : uint32_t { ERRBIT_CFL = 1u, ERRBIT_DOMAIN = 2u, ERRBIT_ARG = 4u };  // ARG: an invalid imported state
 enum : uint32_t { INST_XY = 1u, INST_LINE = 2u };  // x then y every step; straight-line placement
 
 // tile info bits written by the compaction, read by the fraction pass and
@@ -262,6 +262,17 @@ int ns_linear_blocks(int nx, int ny);
 // the parabola fit of the cells a curvature launch left (same FracArgs)
 hipError_t launch_ghf(bool one, const FracArgs &a, int grid, hipStream_t s);
 hipError_t launch_ns(bool one, const NsArgs &a, int grid, hipStream_t s);
+// small kernels of the entry point that keeps no state between calls: a fill
+// (clears tables without memset nodes), the descriptor upload, the state
+// import into both copies / export of copy cur in the public layout, and the
+// latched error as a public status code
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);
+hipError_t launch_put_inst(const Inst &I, Inst *dst, hipStream_t s);
+hipError_t launch_import_state(const Inst &I, const uint8_t *node, const uint8_t *cell, const double *hoff,
+                               const double *voff, hipStream_t s);
+hipError_t launch_export_state(const Inst &I, uint32_t cur, uint8_t *node, uint8_t *cell, double *hoff, double *voff,
+                               hipStream_t s);
+hipError_t launch_status(const uint32_t *err, int32_t *status, hipStream_t s);
 
 }  // namespace ebit
 

@@ -1991,6 +1991,107 @@ __global__ __launch_bounds__(256) void k_ns(NsArgs A, const Inst *__restrict__ i
 }
 
 // ---------------------------------------------------------------------------
+// State import and export in the caller's device buffers (the layout of the
+// public header: node colours one byte per node, centre colours one byte per
+// cell, offsets row-major), for the entry point that keeps no state of its own
+// between calls. Import writes both state copies; a colour byte above 1, or an
+// offset outside [0, 1] (or NaN) on an edge whose end colours differ, latches
+// ERRBIT_ARG.
+// ---------------------------------------------------------------------------
+__global__ void k_fill_u32(uint32_t *p, uint32_t v, size_t n) {
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) p[k] = v;
+}
+
+__global__ void k_put_inst(Inst I, Inst *dst) {
+  if (threadIdx.x == 0) *dst = I;
+}
+
+// one thread per colour word (16 nodes of one row) of the bit plane
+__global__ void k_import_colours(Inst I, const uint8_t *__restrict__ node) {
+  const int nx = I.nx, ny = I.ny, nbx = cb_nbx(nx);
+  const size_t words = (size_t)nbx * (size_t)(ny + 1);
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < words; k += (size_t)gridDim.x * blockDim.x) {
+    const int y = (int)(k / (size_t)nbx), x0 = (int)(k % (size_t)nbx) * TS;
+    uint32_t w = 0, bad = 0;
+    for (int i = 0; i < TS && x0 + i <= nx; i++) {
+      const uint32_t c = node[(size_t)y * (nx + 1) + x0 + i];
+      bad |= c > 1u;
+      w |= (c & 1u) << i;
+    }
+    const size_t at = cb_word(nx, x0, y);
+    gp(I.col[0])[at] = (uint16_t)w;
+    gp(I.col[1])[at] = (uint16_t)w;
+    if (bad) atomicOr(I.err, ERRBIT_ARG);
+  }
+  // block rows past the last node row are part of the plane: zero them
+  const size_t tail = cb_words(nx, ny) - (size_t)(ny + 1) * (size_t)nbx;
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < tail; k += (size_t)gridDim.x * blockDim.x) {
+    const size_t r = (size_t)(ny + 1) + k / (size_t)nbx, bx = k % (size_t)nbx;
+    const size_t at = ((r >> 4) * (size_t)nbx + bx) * 16u + (r & 15u);
+    gp(I.col[0])[at] = 0;
+    gp(I.col[1])[at] = 0;
+  }
+}
+
+__device__ __forceinline__ int nodeByte(const uint8_t *__restrict__ node, int nx, int x, int y) {
+  return node[(size_t)y * (nx + 1) + x] & 1;
+}
+
+// offsets and centre colours into both copies (one thread per element)
+__global__ void k_import_rest(Inst I, const uint8_t *__restrict__ node, const uint8_t *__restrict__ cell,
+                              const double *__restrict__ hoff, const double *__restrict__ voff) {
+  const int nx = I.nx, ny = I.ny;
+  const size_t nh = (size_t)nx * (ny + 1), nv = (size_t)(nx + 1) * ny, nc = (size_t)nx * ny;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  uint32_t bad = 0;
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < nh; k += stride) {
+    const double o = hoff[k];
+    const int y = (int)(k / (size_t)nx), x = (int)(k % (size_t)nx);
+    if (nodeByte(node, nx, x, y) != nodeByte(node, nx, x + 1, y) && !(o >= 0.0 && o <= 1.0)) bad = 1;
+    gp(I.hoff[0])[k] = o;
+    gp(I.hoff[1])[k] = o;
+  }
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < nv; k += stride) {
+    const double o = voff[k];
+    const int y = (int)(k / (size_t)(nx + 1)), x = (int)(k % (size_t)(nx + 1));
+    if (nodeByte(node, nx, x, y) != nodeByte(node, nx, x, y + 1) && !(o >= 0.0 && o <= 1.0)) bad = 1;
+    gp(I.voff[0])[k] = o;
+    gp(I.voff[1])[k] = o;
+  }
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < nc; k += stride) {
+    const uint8_t c = cell[k];
+    bad |= c > 1u;
+    gp(I.cen[0])[k] = c;
+  }
+  if (bad) atomicOr(I.err, ERRBIT_ARG);
+}
+
+// copy `cur` of the state back to the caller's buffers
+__global__ void k_export_state(Inst I, uint32_t cur, uint8_t *__restrict__ node, uint8_t *__restrict__ cell,
+                               double *__restrict__ hoff, double *__restrict__ voff) {
+  const int nx = I.nx, ny = I.ny;
+  const size_t nn = (size_t)(nx + 1) * (ny + 1), nh = (size_t)nx * (ny + 1), nv = (size_t)(nx + 1) * ny,
+               nc = (size_t)nx * ny;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  const GL uint16_t *col = gp(I.col[cur]);
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < nn; k += stride) {
+    const int y = (int)(k / (size_t)(nx + 1)), x = (int)(k % (size_t)(nx + 1));
+    node[k] = (uint8_t)colAt(col, nx, x, y);
+  }
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < nh; k += stride) hoff[k] = gp(I.hoff[cur])[k];
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < nv; k += stride) voff[k] = gp(I.voff[cur])[k];
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < nc; k += stride) cell[k] = gp(I.cen[cur])[k];
+}
+
+// the grid's latched error bits as a status code of the public header
+__global__ void k_status(const uint32_t *err, int32_t *status) {
+  if (threadIdx.x == 0) {
+    const uint32_t b = *err;
+    *status = (b & ERRBIT_ARG) ? 1 : ((b & ERRBIT_CFL) ? 3 : ((b & ERRBIT_DOMAIN) ? 4 : 0));
+  }
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 // Workgroups of a kernel that are resident on one CU at once (persistent
@@ -2096,6 +2197,38 @@ hipError_t launch_ns(bool one, const NsArgs &a, int grid, hipStream_t s) {
 hipError_t launch_ghf(bool one, const FracArgs &a, int grid, hipStream_t s) {
   if (one) hipLaunchKernelGGL(k_ghf<true>, dim3(grid), dim3(64), 0, s, a, a.inst);
   else hipLaunchKernelGGL(k_ghf<false>, dim3(grid), dim3(64), 0, s, a, a.inst);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const size_t b = (n + 255) / 256;
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)(b < 4096 ? b : 4096)), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_put_inst(const Inst &I, Inst *dst, hipStream_t s) {
+  hipLaunchKernelGGL(k_put_inst, dim3(1), dim3(64), 0, s, I, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_import_state(const Inst &I, const uint8_t *node, const uint8_t *cell, const double *hoff,
+                               const double *voff, hipStream_t s) {
+  hipLaunchKernelGGL(k_import_colours, dim3(256), dim3(256), 0, s, I, node);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_import_rest, dim3(1024), dim3(256), 0, s, I, node, cell, hoff, voff);
+  return hipGetLastError();
+}
+
+hipError_t launch_export_state(const Inst &I, uint32_t cur, uint8_t *node, uint8_t *cell, double *hoff, double *voff,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(k_export_state, dim3(1024), dim3(256), 0, s, I, cur, node, cell, hoff, voff);
+  return hipGetLastError();
+}
+
+hipError_t launch_status(const uint32_t *err, int32_t *status, hipStream_t s) {
+  hipLaunchKernelGGL(k_status, dim3(1), dim3(64), 0, s, err, status);
   return hipGetLastError();
 }
 

@@ -75,6 +75,39 @@ size_t jobs_of(const ebit_grid &g, bool both) {
 constexpr uint32_t MAX_POOL_TILES = (1u << 24) - 1u;  // keeps the job list within 32-bit indices
 constexpr uint32_t JOBS_PER_TILE = TS * TS;            // interior unaligned edges a tile owns, at most
 
+// Host records of an engine's grids. One grid is held inline, so that an
+// engine of one grid needs no heap memory (the entry point that allocates
+// nothing relies on it); more grids live on the heap.
+template <class T>
+struct GridRecords {
+  T inl{};
+  std::vector<T> heap;
+  T *p = &inl;
+  GridRecords() = default;
+  GridRecords(const GridRecords &) = delete;
+  GridRecords &operator=(const GridRecords &) = delete;
+  void assign(size_t n, const T &v) {
+    if (n <= 1) {
+      inl = v;
+      p = &inl;
+    } else {
+      heap.assign(n, v);
+      p = heap.data();
+    }
+  }
+  void assign(const T *b, const T *e) {
+    if (e - b <= 1) {
+      if (e > b) inl = *b;
+      p = &inl;
+    } else {
+      heap.assign(b, e);
+      p = heap.data();
+    }
+  }
+  T &operator[](size_t i) { return p[i]; }
+  const T &operator[](size_t i) const { return p[i]; }
+};
+
 }  // namespace
 
 // One grid's host-side descriptor copy lives here; the device copy is what
@@ -102,9 +135,9 @@ struct Engine {
   uint32_t ghfPar = 0;          // parity of the next curvature launch
   int ghfBlocks = 0;
   // host mirror
-  std::vector<Inst> hinst;
-  std::vector<uint8_t> live;
-  std::vector<ebit_grid> grids;
+  GridRecords<Inst> hinst;
+  GridRecords<uint8_t> live;
+  GridRecords<ebit_grid> grids;
   uint32_t cur = 0, stepNo = 0;
   int slot = 1;
   // one grid: the first sweep's centre rules, run by the second sweep's launch
@@ -493,6 +526,7 @@ int engine_ns(Engine *e, const double *C, const double *K, const ebit_fluid *f, 
 }
 
 int status_of(uint32_t bits) {
+  if (bits & ERRBIT_ARG) return EBIT_ERR_ARG;
   if (bits & ERRBIT_CFL) return EBIT_ERR_CFL;
   if (bits & ERRBIT_DOMAIN) return EBIT_ERR_DOMAIN;
   return EBIT_OK;
@@ -655,6 +689,43 @@ size_t pool_grid_bytes(const ebit_grid &g) {
 size_t pool_table_bytes(int max_grids, uint32_t max_tiles) {
   return engine_bytes(max_tiles, (uint32_t)max_grids, max_tiles * JOBS_PER_TILE) +
          align256((size_t)max_grids * sizeof(double));
+}
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// The library's own scratch for ebit_step_static: one array per GPU, in the
+// device's global memory, holding the engine tables, both state copies and the
+// sweep scratch of one grid. Host code never names the array in a kernel
+// argument or copy: on each device it asks once for the array's device address
+// (each GPU holds its own copy at its own address) and uses that.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[EBIT_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int STATIC_MAX_DEVICES = 64;
+struct StaticSlot {
+  char *ptr = nullptr;  // device address of `scratch` on this device
+  bool ready = false;
+  Engine e;             // host record of the grid the scratch holds (one grid: inline)
+};
+StaticSlot g_static[STATIC_MAX_DEVICES];
+
+// The device's scratch, set up on its first use with the device current.
+int static_slot(StaticSlot **out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= STATIC_MAX_DEVICES) return EBIT_ERR_ARG;
+  StaticSlot &S = g_static[dev];
+  if (!S.ready) {
+    void *p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p || ((uintptr_t)p & 255) != 0) return EBIT_ERR_DEVICE;
+    S.ptr = (char *)p;
+    engine_launch_config(&S.e);
+    S.ready = true;
+  }
+  *out = &S;
+  return EBIT_OK;
 }
 }  // namespace
 
@@ -1084,6 +1155,59 @@ int ebit_pool_stats(ebit_pool *p, ebit_counters *out) {
 int ebit_pool_destroy(ebit_pool *p) {
   if (!p) return EBIT_ERR_ARG;
   delete p;
+  return EBIT_OK;
+}
+
+int ebit_step_static(const ebit_grid *grid, uint8_t *node_color_dev, uint8_t *cell_color_dev, double *hoff_dev,
+                     double *voff_dev, const double *u_dev, const double *v_dev, double dt, int64_t step,
+                     double *C_dev, double *K_dev, int32_t *status_dev, void *hip_stream) {
+  if (!grid_ok(grid) || !node_color_dev || !cell_color_dev || !hoff_dev || !voff_dev || !u_dev || !v_dev || !C_dev ||
+      !K_dev || !status_dev || !isfinite(dt) || step < 0)
+    return EBIT_ERR_ARG;
+  size_t need = 0;
+  ebit_workspace_bytes(grid, &need);
+  if (need > (size_t)EBIT_STATIC_SCRATCH_BYTES) return EBIT_ERR_NOMEM;
+  StaticSlot *S = nullptr;
+  int rc = static_slot(&S);
+  if (rc) return rc;
+  Engine *e = &S->e;
+  hipStream_t st = (hipStream_t)hip_stream;
+  // one grid laid out over the scratch exactly as over a caller's workspace
+  e->stream = st;
+  e->ntiles = tiles_of(*grid);
+  e->maxGrids = 1;
+  e->one = true;
+  e->jobCap = (uint32_t)jobs_of(*grid, true);
+  Carve c;
+  carve_engine(e, S->ptr, c);
+  e->hinst.assign(1, Inst());
+  e->live.assign(1, 1);
+  e->grids.assign(grid, grid + 1);
+  Inst &I = e->hinst[0];
+  fill_inst(&I, *grid, 0, 0, e->errs);
+  carve_grid(&I, *grid, S->ptr, c);
+  e->cur = 0;
+  e->stepNo = (uint32_t)(step & 1);
+  e->slot = 1;
+  e->ghfPar = 0;
+  e->pendJobs = nullptr;
+  // the last call's contents stay in the scratch: clear what starts at zero
+  // with kernels (no memset nodes, for callers that capture the stream)
+  static_assert(sizeof(unsigned long long) == 2 * sizeof(uint32_t), "counter words");
+  HIPCHK(launch_fill_u32(e->counts, 0u, 2 * NSLOT, st));
+  HIPCHK(launch_fill_u32((uint32_t *)e->ctr, 0u, 2 * (size_t)CTR_PARTS * CTR_STRIDE, st));
+  HIPCHK(launch_fill_u32(e->errs, 0u, 1, st));
+  HIPCHK(launch_fill_u32(e->ghfCnt, 0u, 2, st));
+  HIPCHK(launch_clear_tiles(e->tileInst, e->has, e->nearPrev, e->tinfo, 0, e->ntiles, st));
+  HIPCHK(launch_put_inst(I, e->dinst, st));
+  HIPCHK(launch_import_state(I, node_color_dev, cell_color_dev, hoff_dev, voff_dev, st));
+  HIPCHK(launch_init_tiles(e->dinst, 0, e->ntiles, 0, e->tileInst, e->has, e->nearPrev, st));
+  rc = engine_compact(e, 0, e->stepNo, 0);
+  if (!rc) rc = engine_advect(e, u_dev, v_dev, nullptr, dt);
+  if (!rc) rc = engine_frac(e, 3, nullptr, C_dev, K_dev);
+  if (rc) return rc;
+  HIPCHK(launch_export_state(I, e->cur, node_color_dev, cell_color_dev, hoff_dev, voff_dev, st));
+  HIPCHK(launch_status(e->errs, status_dev, st));
   return EBIT_OK;
 }
 

@@ -106,6 +106,7 @@ def _load() -> ctypes.CDLL:
         "ebit_pool_retire": [P, i32],
         "ebit_pool_stats": [P, ctypes.POINTER(ebit_counters)],
         "ebit_pool_destroy": [P],
+        "ebit_step_static": [G, vp, vp, vp, vp, vp, vp, ctypes.c_double, ctypes.c_int64, vp, vp, vp, vp],
     })
     for name, args in sigs.items():
         f = getattr(lib, name)
@@ -139,6 +140,31 @@ def workspace_bytes(nx: int, ny: int, h: float, flags: int = 0) -> int:
     n = ctypes.c_size_t(0)
     _chk(_lib.ebit_workspace_bytes(ctypes.byref(g), ctypes.byref(n)), "ebit_workspace_bytes")
     return n.value
+
+
+STATIC_SCRATCH_BYTES = 80 << 20  # EBIT_STATIC_SCRATCH_BYTES of include/ebit.h
+
+
+def step_static(grid: ebit_grid, node, cell, hoff, voff, u, v, dt: float, step: int, C, K, status, stream=None):
+    """ebit_step_static on device tensors (uint8 node/cell colours, float64
+    offsets, velocities and fields, one int32 status), all on the current
+    device: the state tensors are overwritten with the state after the step.
+    Returns the call's status code (argument and HIP errors); the device-side
+    status lands in `status`."""
+    import torch
+
+    st = stream if stream is not None else torch.cuda.current_stream()
+    want = {"node": (node, torch.uint8, (grid.ny + 1, grid.nx + 1)), "cell": (cell, torch.uint8, (grid.ny, grid.nx)),
+            "hoff": (hoff, torch.float64, (grid.ny + 1, grid.nx)), "voff": (voff, torch.float64, (grid.ny, grid.nx + 1)),
+            "u": (u, torch.float64, (grid.ny, grid.nx + 1)), "v": (v, torch.float64, (grid.ny + 1, grid.nx)),
+            "C": (C, torch.float64, (grid.ny, grid.nx)), "K": (K, torch.float64, (grid.ny, grid.nx)),
+            "status": (status, torch.int32, (1,))}
+    for name, (t, dt_, shape) in want.items():
+        if t.dtype != dt_ or tuple(t.shape) != shape or not t.is_contiguous() or not t.is_cuda:
+            raise ValueError(f"{name} must be a contiguous {dt_} device tensor of shape {shape}")
+    return _lib.ebit_step_static(ctypes.byref(grid), node.data_ptr(), cell.data_ptr(), hoff.data_ptr(),
+                                 voff.data_ptr(), u.data_ptr(), v.data_ptr(), float(dt), int(step), C.data_ptr(),
+                                 K.data_ptr(), status.data_ptr(), st.cuda_stream)
 
 
 def _host_state(st: State):
