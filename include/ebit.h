@@ -250,6 +250,26 @@ int ebit_batch_stats(ebit_batch *b, ebit_counters *out);
 int ebit_batch_sync(ebit_batch *b, int *status);
 int ebit_batch_destroy(ebit_batch *b);
 
+/* K steps of the batch recorded once as a HIP graph of kernel launches and
+ * replayed with one call: step k (0 <= k < ksteps) is ebit_batch_advect with
+ * dt_dev = dts_dev + k*n (dts_dev: device, ksteps x n doubles, row k = the
+ * grids' dt of step k), then ebit_batch_fraction_curvature into C_packed,
+ * K_packed. The buffers must stay valid while the graph exists; their
+ * contents are read at each replay. ksteps must be even (a step flips the
+ * engine's schedule between two alternating layouts; an even count returns it
+ * to where it started). Capturing runs nothing. EBIT_ERR_ARG for an odd or
+ * small ksteps or a null buffer. The graph holds no memset or copy nodes. */
+typedef struct ebit_graph ebit_graph;
+int ebit_batch_capture(ebit_batch *b, int ksteps, const double *u_packed, const double *v_packed,
+                       const double *dts_dev, double *C_packed, double *K_packed, ebit_graph **out);
+
+/* Replay the K steps on the batch's stream (asynchronous). EBIT_ERR_STATE if
+ * the batch is not at a point where the capture's schedule holds (an odd
+ * number of other steps or fraction calls since the capture). */
+int ebit_graph_launch(ebit_graph *g);
+/* Destroy every graph of a batch before the batch itself. */
+int ebit_graph_destroy(ebit_graph *g);
+
 /* ===========================================================================
  * Served form: a pool that admits grids between steps, advances every admitted
  * grid by one step per ebit_pool_step (advection, then fraction and curvature

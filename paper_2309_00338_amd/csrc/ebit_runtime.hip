@@ -963,6 +963,112 @@ int ebit_batch_destroy(ebit_batch *b) {
   return EBIT_OK;
 }
 
+}  // extern "C"
+
+// K captured steps of a batch. The launches of a step depend on the engine's
+// host schedule (which state copy is current, which list slot, which
+// parabola-fit list parity, the step's sweep order); after an even number of
+// steps all of them are back where they started, so the captured launches are
+// valid for every replay that starts from the same schedule.
+struct ebit_graph {
+  ebit_batch *b = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int ksteps = 0;
+  uint32_t cur = 0, slot = 0, ghfPar = 0, stepPar = 0;
+};
+
+namespace {
+bool graph_schedule_matches(const ebit_graph *g) {
+  const Engine &e = g->b->e;
+  return e.cur == g->cur && (uint32_t)e.slot == g->slot && e.ghfPar == g->ghfPar && (e.stepNo & 1u) == g->stepPar &&
+         !e.pendJobs;
+}
+void graph_free(ebit_graph *g) {
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
+}
+}  // namespace
+
+extern "C" {
+
+int ebit_batch_capture(ebit_batch *b, int ksteps, const double *u_packed, const double *v_packed,
+                       const double *dts_dev, double *C_packed, double *K_packed, ebit_graph **out) {
+  if (!out) return EBIT_ERR_ARG;
+  *out = nullptr;
+  if (!b || ksteps < 2 || (ksteps & 1) || !u_packed || !v_packed || !dts_dev || !C_packed || !K_packed)
+    return EBIT_ERR_ARG;
+  Engine *e = &b->e;
+  if (e->pendJobs) return EBIT_ERR_STATE;
+  ebit_graph *g = new (std::nothrow) ebit_graph();
+  if (!g) return EBIT_ERR_NOMEM;
+  g->b = b;
+  g->ksteps = ksteps;
+  g->cur = e->cur;
+  g->slot = (uint32_t)e->slot;
+  g->ghfPar = e->ghfPar;
+  g->stepPar = e->stepNo & 1u;
+  const uint32_t stepNo0 = e->stepNo;
+  const int64_t epoch0 = e->epoch, fracEpoch0 = e->fracEpoch;
+  // the null stream cannot be captured: record on a stream of our own
+  hipStream_t cap = nullptr;
+  hipError_t he = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+  if (he != hipSuccess) {
+    delete g;
+    return device_failed(he, "hipStreamCreateWithFlags", __LINE__);
+  }
+  const hipStream_t saved = e->stream;
+  e->stream = cap;
+  int rc = EBIT_OK;
+  he = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+  if (he != hipSuccess) rc = device_failed(he, "hipStreamBeginCapture", __LINE__);
+  if (!rc) {
+    for (int k = 0; k < ksteps && !rc; k++) {
+      rc = engine_advect(e, u_packed, v_packed, dts_dev + (size_t)k * (size_t)b->n, 0.0);
+      if (!rc) rc = engine_frac(e, 3, nullptr, C_packed, K_packed);
+    }
+    hipGraph_t graph = nullptr;
+    he = hipStreamEndCapture(cap, &graph);
+    if (!rc && he != hipSuccess) rc = device_failed(he, "hipStreamEndCapture", __LINE__);
+    g->graph = graph;
+  }
+  e->stream = saved;
+  (void)hipStreamDestroy(cap);
+  // capturing ran nothing: the engine's step counts stay where they were
+  e->stepNo = stepNo0;
+  e->epoch = epoch0;
+  e->fracEpoch = fracEpoch0;
+  if (!rc && !graph_schedule_matches(g)) rc = EBIT_ERR_STATE;
+  if (!rc) {
+    he = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    if (he != hipSuccess) rc = device_failed(he, "hipGraphInstantiate", __LINE__);
+  }
+  if (rc) {
+    graph_free(g);
+    return rc;
+  }
+  *out = g;
+  return EBIT_OK;
+}
+
+int ebit_graph_launch(ebit_graph *g) {
+  if (!g) return EBIT_ERR_ARG;
+  if (!graph_schedule_matches(g)) return EBIT_ERR_STATE;
+  Engine *e = &g->b->e;
+  HIPCHK(hipGraphLaunch(g->exec, e->stream));
+  e->stepNo += (uint32_t)g->ksteps;
+  e->epoch += g->ksteps;
+  e->fracEpoch = e->epoch;
+  return EBIT_OK;
+}
+
+int ebit_graph_destroy(ebit_graph *g) {
+  if (!g) return EBIT_ERR_ARG;
+  graph_free(g);
+  return EBIT_OK;
+}
+
 // ---------------------------------------------------------------------------
 // pool (served form)
 // ---------------------------------------------------------------------------

@@ -106,6 +106,9 @@ def _load() -> ctypes.CDLL:
         "ebit_pool_retire": [P, i32],
         "ebit_pool_stats": [P, ctypes.POINTER(ebit_counters)],
         "ebit_pool_destroy": [P],
+        "ebit_batch_capture": [B, i32, vp, vp, vp, vp, vp, ctypes.POINTER(vp)],
+        "ebit_graph_launch": [vp],
+        "ebit_graph_destroy": [vp],
         "ebit_step_static": [G, vp, vp, vp, vp, vp, vp, ctypes.c_double, ctypes.c_int64, vp, vp, vp, vp],
     })
     for name, args in sigs.items():
@@ -334,6 +337,7 @@ class EbitBatch:
         self.u_off, self.v_off, self.c_off = list(uo), list(vo), list(co)
         self.totals = tuple(tot)
         self.step = 0
+        self._graphs = []
 
     def pack_velocities(self, us, vs):
         """Device buffers holding grid k's u and v (host arrays) at the layout's offsets."""
@@ -409,7 +413,22 @@ class EbitBatch:
         _lib.ebit_batch_sync(self._h, st)
         return list(st)
 
+    def capture(self, ksteps: int, U, V, dts, C, K):
+        """ebit_batch_capture: the next ksteps (even) steps of every grid,
+        step k with the dts[k] row (device tensor of ksteps x n), then fraction
+        and curvature into C, K, recorded as one graph (EbitGraph)."""
+        pd = self._buf(dts, ksteps * self.n, "dts")
+        out = ctypes.c_void_p()
+        _chk(_lib.ebit_batch_capture(self._h, int(ksteps), self._buf(U, self.totals[0], "u"),
+                                     self._buf(V, self.totals[1], "v"), pd, self._buf(C, self.totals[2], "C"),
+                                     self._buf(K, self.totals[2], "K"), ctypes.byref(out)), "ebit_batch_capture")
+        g = EbitGraph(self, out, int(ksteps), (U, V, dts, C, K))
+        self._graphs.append(g)
+        return g
+
     def close(self):
+        for g in getattr(self, "_graphs", []):
+            g.close()
         if getattr(self, "_h", None):
             _lib.ebit_batch_destroy(self._h)
             self._h = None
@@ -419,6 +438,23 @@ class EbitBatch:
             self.close()
         except Exception:
             pass
+
+
+class EbitGraph:
+    """K captured steps of a batch; launch() replays them on the batch's stream."""
+
+    def __init__(self, batch, handle, ksteps, buffers):
+        self.batch, self._h, self.ksteps = batch, handle, ksteps
+        self._keep = buffers  # the graph reads these at every replay
+
+    def launch(self):
+        _chk(_lib.ebit_graph_launch(self._h), "ebit_graph_launch")
+        self.batch.step += self.ksteps
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.ebit_graph_destroy(self._h)
+            self._h = None
 
 
 class EbitPool:

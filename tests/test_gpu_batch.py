@@ -248,3 +248,62 @@ def test_one_grid_batch_and_pool_match_oracle():
         compare_fields(Cp, Kp, Co, Ko, ref.o.nx, ref.o.h, f"pool seed {seed}")
         pool.retire(slot)
         pool.step()  # nothing live: no sweep, nothing pending
+
+
+@pytest.mark.parametrize("which", ["many", "one"])
+def test_graph_replay_matches_eager_steps_and_oracle(which):
+    """ebit_batch_capture records 4 steps (advect + fraction/curvature) as one
+    graph; three replays, with the program's own eager work and
+    synchronisations between them, give bit for bit the states, C and kappa of
+    12 eager steps of an identical batch, and the oracle's after the last.
+    "one": a batch of a single grid (the one-grid kernels, whose first centre
+    pass rides with the second sweep)."""
+    import torch
+
+    inst = _instances()
+    if which == "one":
+        inst = inst[3:4]
+    K = 4
+    states = [s for s, _, _, _ in inst]
+    eager, graphed = ebit.EbitBatch(states), ebit.EbitBatch(states, stream=torch.cuda.Stream())
+    U, V = eager.pack_velocities([u for _, u, _, _ in inst], [v for _, _, v, _ in inst])
+    dts = torch.tensor([[d[k] for _, _, _, d in inst] for k in range(K)], dtype=torch.float64, device="cuda:0")
+    Ce, Ke = eager.new_fields()
+    Cg, Kg = graphed.new_fields()
+    graph = graphed.capture(K, U, V, dts, Cg, Kg)
+    orc = [s.copy() for s in states]
+    for rep in range(3):
+        for k in range(K):
+            eager.advect(U, V, dts[k])
+            eager.fraction_curvature(Ce, Ke)
+            for g, (st, u, v, d) in enumerate(inst):
+                assert oracle.step(orc[g], u, v, d[k])[0] == oracle.OK
+        graph.launch()
+        # eager work of the program between replays
+        x = torch.randn(256, 256, device="cuda:0", dtype=torch.float64)
+        (x @ x).sum().item()
+        torch.cuda.synchronize()
+        for g in range(len(inst)):
+            a, b = eager.get_state(g), graphed.get_state(g)
+            assert a.step == b.step == (rep + 1) * K
+            assert np.array_equal(a.c, b.c) and np.array_equal(a.cc, b.cc), (rep, g)
+            assert np.array_equal(a.hoff * a.h_present(), b.hoff * b.h_present()), (rep, g)
+            assert np.array_equal(a.voff * a.v_present(), b.voff * b.v_present()), (rep, g)
+            fe, fg = eager.field(Ce, g).cpu().numpy(), graphed.field(Cg, g).cpu().numpy()
+            assert np.array_equal(fe, fg), (rep, g)
+            ke, kg = eager.field(Ke, g).cpu().numpy(), graphed.field(Kg, g).cpu().numpy()
+            assert np.array_equal(np.isnan(ke), np.isnan(kg)) and np.array_equal(ke[~np.isnan(ke)], kg[~np.isnan(kg)])
+    assert graphed.sync() == [0] * len(inst)
+    for g in range(len(inst)):
+        compare_state(graphed.get_state(g), orc[g], f"grid {g} after {3 * K} steps")
+        Co = oracle.fraction(orc[g])
+        Ko, _ = oracle.curvature(orc[g], Co)
+        compare_fields(graphed.field(Cg, g).cpu().numpy(), graphed.field(Kg, g).cpu().numpy(), Co, Ko, orc[g].nx,
+                       orc[g].h, f"grid {g}")
+    # an odd number of eager steps breaks the captured schedule: refused, nothing runs
+    graphed.advect(U, V, dts[0])
+    with pytest.raises(ebit.EbitError) as e:
+        graph.launch()
+    assert e.value.code == ebit.EBIT_ERR_STATE
+    graph.close()
+    graphed.close()
