@@ -779,18 +779,19 @@ __global__ __launch_bounds__(SWEEP_BS, 8) void k_sweep(SweepArgs A, const Inst *
     }
     __syncthreads();
     // --- list the present edges -----------------------------------------------
-    // aligned (a,b), halo included (their advected offsets feed the landers):
-    // la in [0,20) with a in [0,na), b = b0-2+lb in [0,nb];
+    // aligned (a,b) whose advected offsets feed this tile's landers and flips:
+    // a in [a0-1, a0+16] (la in [1, 19)) inside [0, na), rows b in [b0, b0+16]
+    // (lb in [2, 19)) inside [0, nb];
     // unaligned (a,b), only those of this tile (nothing reads the others):
     // lb in [2,18) with b < nb, la in [2,18) or the wall a = na
-    const int laMinA = max(0, HALO - a0), laMaxA = min(NE - 1, na - 1 - a0 + HALO);
+    const int laMinA = max(HALO - 1, HALO - a0), laMaxA = min(NE - 2, na - 1 - a0 + HALO);
     const int laMaxU = min(HALO + TS - 1 + (na - a0 == TS ? 1 : 0), na - a0 + HALO);
     const uint32_t maskA = laMaxA >= laMinA ? ((2u << laMaxA) - 1u) & ~((1u << laMinA) - 1u) : 0u;
     const uint32_t maskU = ((2u << laMaxU) - 1u) & ~((1u << HALO) - 1u);
     if (tid < NH) {
       const int lb = tid, b = b0 - HALO + lb;
       const uint32_t r = sRow[lb];
-      if (b >= 0 && b <= nb) {
+      if (lb >= HALO && lb <= HALO + TS && b <= nb) {
         uint32_t m = (r ^ (r >> 1)) & maskA;
         if (m) {
           uint32_t w = atomicAdd(&sNAdv, (uint32_t)__popc(m));
