@@ -212,6 +212,12 @@ struct FracArgs {
   GhfEntry *ghf;             // cells left for the parabola fit (4 entries per tile at most)
   uint32_t *ghfCount;        // entries of this launch (zero on entry)
   uint32_t *ghfClear;        // the other launch parity's count, zeroed by this launch
+  // the uniform cells' fill, a linear pass over each grid's C and kappa in
+  // chunks of FILL_CHUNK elements: entry k of fillTab is (first chunk, grid)
+  // of the k-th grid with cells (ascending first chunks); fillGrids entries
+  // (one grid: no table)
+  const uint2 *fillTab;
+  uint32_t fillGrids;
   Inst one;                  // the descriptor itself when the engine holds one grid
 };
 
@@ -255,7 +261,9 @@ hipError_t launch_clear_tiles(uint32_t *tileInst, uint16_t *has, uint8_t *nearPr
                               uint32_t ntiles, hipStream_t s);
 hipError_t launch_compact(bool one, const CompactArgs &a, hipStream_t s);
 hipError_t launch_frac_curv(int mode, bool one, const FracArgs &a, int grid, hipStream_t s);
-int frac_fill_blocks(uint32_t ntiles);
+// elements of C (and kappa) one fill workgroup writes
+constexpr uint32_t FILL_CHUNK = 4096;
+inline uint32_t fill_chunks(size_t cells) { return (uint32_t)((cells + FILL_CHUNK - 1) / FILL_CHUNK); }
 int ns_fill_blocks(uint32_t ntiles);
 // workgroups of the linear uniform-part passes of k_ns for one nx x ny grid
 int ns_linear_blocks(int nx, int ny);

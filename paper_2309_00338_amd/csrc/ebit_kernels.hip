@@ -1514,23 +1514,92 @@ __device__ bool ghfFit(int nx, int ny, double h, int i, int j, int gx, int gy, G
 // along a grid row. MODE 1: C only; 2: kappa from the caller's C; 3: both.
 constexpr int FRAC_BS = 256;
 constexpr int NEAR_ENT = 16;  // tile entries a near workgroup keeps in LDS
-constexpr int FRAC_FILL_TILES = FRAC_BS / TS;
+static_assert(FILL_CHUNK % FRAC_BS == 0, "whole rounds per fill thread");
+constexpr uint32_t FILL_TI_LDS = 2048;  // tile-info bytes a fill workgroup stages
 constexpr int NS_FILL_TILES = 16;
 
-// The uniform tiles' C and kappa go out with streaming (non-temporal) stores
-// when a 16-cell row of a tile is one whole 128-byte line (one grid, nx a
-// multiple of 16, both outputs line-aligned): the 1 GB write stream of a large
-// grid then does not evict the marker data the next step's sweeps and fits
-// read. Partial lines (several grids packed, ragged rows) keep ordinary
-// stores, which the L2 merges before they reach memory; so do the near tiles,
-// whose stores are few.
-template <int MODE, bool ONE>
-__device__ __forceinline__ bool streamOut(const FracArgs &A, const Inst &I) {
-  if (!ONE || (I.nx & 15) != 0) return false;
+// The uniform cells' C and kappa: a linear pass over each grid's arrays,
+// FILL_CHUNK consecutive elements per workgroup (16 per thread, 256 apart),
+// so that each wavefront store covers whole 128-byte lines whatever the row
+// length and however the grids are packed. Element (x, y) belongs to tile
+// (x / 16, y / 16); elements of tiles with a cut cell are left to the near
+// workgroups. The stores are streaming (non-temporal): the write stream of a
+// large grid then does not evict the marker data the next step's sweeps and
+// fits read. The owner tiles' info is loaded 16 at a time before the stores.
+template <int MODE>
+__device__ __forceinline__ void fracLinearFill(const FracArgs &A, const Inst &I, uint32_t chunk, uint8_t *sTi) {
+  constexpr int NE_T = (int)(FILL_CHUNK / FRAC_BS);
+  const int nx = I.nx, ny = I.ny;
+  const size_t n = (size_t)nx * (size_t)ny;
+  const size_t k0 = (size_t)chunk * FILL_CHUNK;
+  if (k0 >= n) return;  // workgroup-uniform: no barrier below is skipped by part of it
+  // the info bytes of the chunk's tile rows (one contiguous run of the tile
+  // table) in LDS, when they fit
+  const int yf = (int)(k0 / (size_t)nx), yl = (int)(min(n - 1, k0 + FILL_CHUNK - 1) / (size_t)nx);
+  const uint32_t t0 = I.tile0 + (uint32_t)(yf / TS) * (uint32_t)I.ntx;
+  const uint32_t nt = (uint32_t)(yl / TS - yf / TS + 1) * (uint32_t)I.ntx;
+  const bool staged = nt <= FILL_TI_LDS;
+  if (staged)
+    for (uint32_t t = threadIdx.x; t < nt; t += FRAC_BS) sTi[t] = A.tinfo[t0 + t];
+  __syncthreads();
+  size_t k = k0 + threadIdx.x;
+  int y = (int)(k / (size_t)nx), x = (int)(k - (size_t)y * (size_t)nx);
+  uint32_t tix[NE_T];
+#pragma unroll
+  for (int i = 0; i < NE_T; i++) {
+    tix[i] = (uint32_t)(min(y, ny - 1) / TS - yf / TS) * (uint32_t)I.ntx + (uint32_t)(x / TS);
+    x += FRAC_BS;
+    while (x >= nx) {
+      x -= nx;
+      y++;
+    }
+  }
+  uint8_t ti[NE_T];
+#pragma unroll
+  for (int i = 0; i < NE_T; i++)
+    ti[i] = k + (size_t)FRAC_BS * i < n ? (staged ? sTi[tix[i]] : A.tinfo[t0 + tix[i]]) : (uint8_t)TI_FRAC;
+  double *Cp = (MODE & 1) ? A.Cout + I.coff : nullptr;
+  double *Kp = (MODE & 2) ? A.Kout + I.koff : nullptr;
+#pragma unroll
+  for (int i = 0; i < NE_T; i++) {
+    if (ti[i] & TI_FRAC) continue;
+    const size_t e = k + (size_t)FRAC_BS * i;
+    if (MODE & 1) __builtin_nontemporal_store((ti[i] & TI_COLOUR) ? 1.0 : 0.0, &Cp[e]);
+    if (MODE & 2) __builtin_nontemporal_store(0.0, &Kp[e]);
+  }
+}
+
+// One grid whose 16-cell tile rows are whole 128-byte lines (nx a multiple of
+// 16, both outputs line-aligned): a fill workgroup takes 16 consecutive tiles
+// of a tile row, a lane a column, and stores 16 rows. Tiles of a row start at
+// FILL_CHUNK / (16 * 16) = 16 tiles per chunk, so chunk f covers tiles
+// 16 f .. 16 f + 15 of the grid.
+template <int MODE>
+__device__ __forceinline__ bool wholeLineRows(const FracArgs &A, const Inst &I) {
+  if ((I.nx & 15) != 0) return false;
   uintptr_t al = 0;
   if (MODE & 1) al |= (uintptr_t)(A.Cout + I.coff);
   if (MODE & 2) al |= (uintptr_t)(A.Kout + I.koff);
   return (al & 127u) == 0;
+}
+template <int MODE>
+__device__ __forceinline__ void fracTileFill(const FracArgs &A, const Inst &I, uint32_t f) {
+  constexpr uint32_t TPB = FILL_CHUNK / (TS * TS);
+  static_assert(TPB * TS == FRAC_BS, "a lane per column of the chunk's tiles");
+  const uint32_t lt = f * TPB + threadIdx.x / TS;
+  if (lt >= (uint32_t)(I.ntx * I.nty)) return;
+  const uint8_t ti = A.tinfo[I.tile0 + lt];
+  if (ti & TI_FRAC) return;
+  const int tx = (int)(lt % (uint32_t)I.ntx), ty = (int)(lt / (uint32_t)I.ntx);
+  const int nx = I.nx, x = tx * TS + (int)(threadIdx.x % TS), rows = min(TS, I.ny - ty * TS);
+  const double c = (ti & TI_COLOUR) ? 1.0 : 0.0;
+  double *Cp = (MODE & 1) ? A.Cout + I.coff + (size_t)(ty * TS) * nx + x : nullptr;
+  double *Kp = (MODE & 2) ? A.Kout + I.koff + (size_t)(ty * TS) * nx + x : nullptr;
+#pragma unroll 4
+  for (int r = 0; r < rows; r++) {
+    if (MODE & 1) __builtin_nontemporal_store(c, &Cp[(size_t)r * nx]);
+    if (MODE & 2) __builtin_nontemporal_store(0.0, &Kp[(size_t)r * nx]);
+  }
 }
 
 template <int MODE, bool ONE>
@@ -1540,32 +1609,23 @@ __global__ __launch_bounds__(FRAC_BS, 8) void k_frac_curv(FracArgs A, const Inst
   constexpr int WN = W + 1;  // halo nodes per side
   const int tid = threadIdx.x;
   if ((int)blockIdx.x >= A.nearBlocks) {
-    // --- dense fill ----------------------------------------------------------
-    const uint32_t t = (blockIdx.x - (uint32_t)A.nearBlocks) * FRAC_FILL_TILES + (uint32_t)tid / TS;
-    if (t >= A.ntiles) return;
-    const uint8_t ti = A.tinfo[t];
-    if (ti & (TI_FRAC | TI_DEAD)) return;
-    const Inst &I = ONE ? A.one : inst[tileInst[t]];
-    const uint32_t lt = t - I.tile0;
-    const int tx = (int)(lt % (uint32_t)I.ntx), ty = (int)(lt / (uint32_t)I.ntx);
-    const int x = tx * TS + tid % TS;
-    if (x >= I.nx) return;
-    const int nx = I.nx, rows = min(TS, I.ny - ty * TS);
-    const double c = (ti & TI_COLOUR) ? 1.0 : 0.0;
-    double *Cp = (MODE & 1) ? A.Cout + I.coff + (size_t)(ty * TS) * nx + x : nullptr;
-    double *Kp = (MODE & 2) ? A.Kout + I.koff + (size_t)(ty * TS) * nx + x : nullptr;
-    if (streamOut<MODE, ONE>(A, I)) {
-#pragma unroll 4
-      for (int r = 0; r < rows; r++) {
-        if (MODE & 1) __builtin_nontemporal_store(c, &Cp[(size_t)r * nx]);
-        if (MODE & 2) __builtin_nontemporal_store(0.0, &Kp[(size_t)r * nx]);
-      }
+    // --- uniform cells: linear fill -------------------------------------------
+    __shared__ uint8_t sTi[FILL_TI_LDS];
+    uint32_t f = blockIdx.x - (uint32_t)A.nearBlocks;
+    if (ONE && wholeLineRows<MODE>(A, A.one)) {
+      fracTileFill<MODE>(A, A.one, f);
+    } else if (ONE) {
+      fracLinearFill<MODE>(A, A.one, f, sTi);
     } else {
-#pragma unroll 4
-      for (int r = 0; r < rows; r++) {
-        if (MODE & 1) Cp[(size_t)r * nx] = c;
-        if (MODE & 2) Kp[(size_t)r * nx] = 0.0;
+      // the grid of chunk f: the last table entry starting at or before it
+      uint32_t lo = 0, hi = A.fillGrids;
+      while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (A.fillTab[mid].x <= f) lo = mid;
+        else hi = mid;
       }
+      const uint2 t = A.fillTab[lo];
+      fracLinearFill<MODE>(A, inst[t.y], f - t.x, sTi);
     }
     return;
   }
@@ -2182,7 +2242,6 @@ hipError_t launch_compact(bool one, const CompactArgs &a, hipStream_t s) {
   return hipGetLastError();
 }
 
-int frac_fill_blocks(uint32_t ntiles) { return (int)((ntiles + FRAC_FILL_TILES - 1) / FRAC_FILL_TILES); }
 int ns_fill_blocks(uint32_t ntiles) { return (int)((ntiles + NS_FILL_TILES - 1) / NS_FILL_TILES); }
 int ns_linear_blocks(int nx, int ny) {
   auto chunks = [](size_t n) { return (int)((n + NS_CHUNK - 1) / NS_CHUNK); };

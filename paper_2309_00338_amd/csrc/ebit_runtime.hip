@@ -134,6 +134,11 @@ struct Engine {
   uint32_t *ghfCnt = nullptr;   // entry counts of the two curvature-launch parities
   uint32_t ghfPar = 0;          // parity of the next curvature launch
   int ghfBlocks = 0;
+  // the fraction pass's linear fill: (first chunk, grid) per live grid (several
+  // grids only), its host source and the chunk total
+  uint2 *fillTab = nullptr;
+  std::vector<uint2> fillHost;
+  uint32_t fillGrids = 0, fillTotal = 0;
   // host mirror
   GridRecords<Inst> hinst;
   GridRecords<uint8_t> live;
@@ -269,6 +274,7 @@ void carve_engine(Engine *e, char *base, Carve &c) {
   e->ctr = c.take<unsigned long long>(base, (size_t)CTR_PARTS * CTR_STRIDE);
   e->ghf = c.take<GhfEntry>(base, 4 * (size_t)e->ntiles);
   e->ghfCnt = c.take<uint32_t>(base, 2);
+  e->fillTab = c.take<uint2>(base, e->maxGrids);
 }
 
 // engine tables for ntiles tiles, maxGrids grids and jobCap fit jobs
@@ -304,6 +310,32 @@ void engine_launch_config(Engine *e) {
     const int nb = std::min((int)(cus * perCU), cap);
     e->nearBlocks[m] = nb < 1 ? 1 : nb;
   }
+}
+
+// The fill's chunk table of the live grids. One grid needs none (its chunks
+// start at 0). The upload reads the host vector before the call returns
+// (pageable source), so rebuilding it later is safe.
+int engine_fill_table(Engine *e) {
+  if (e->one) {
+    // the linear fill's chunks, or 16 tiles per workgroup when tile rows are
+    // whole lines (decided in the kernel from the output alignment)
+    e->fillGrids = 1;
+    e->fillTotal = std::max(fill_chunks((size_t)e->hinst[0].nx * (size_t)e->hinst[0].ny), (e->ntiles + 15u) / 16u);
+    return EBIT_OK;
+  }
+  e->fillHost.clear();
+  uint32_t total = 0;
+  for (uint32_t k = 0; k < e->maxGrids; k++) {
+    if (!e->live[k]) continue;
+    e->fillHost.push_back(make_uint2(total, k));
+    total += fill_chunks((size_t)e->hinst[k].nx * (size_t)e->hinst[k].ny);
+  }
+  e->fillGrids = (uint32_t)e->fillHost.size();
+  e->fillTotal = total;
+  if (e->fillGrids)
+    HIPCHK(hipMemcpyAsync(e->fillTab, e->fillHost.data(), e->fillGrids * sizeof(uint2), hipMemcpyHostToDevice,
+                          e->stream));
+  return EBIT_OK;
 }
 
 // clears every table; all tiles start unowned
@@ -481,8 +513,10 @@ int engine_frac(Engine *e, int mode, const double *Cin, double *Cout, double *Ko
   a.ghf = e->ghf;
   a.ghfCount = e->ghfCnt + e->ghfPar;
   a.ghfClear = e->ghfCnt + (e->ghfPar ^ 1u);
+  a.fillTab = e->fillTab;
+  a.fillGrids = e->fillGrids;
   a.one = e->hinst[0];
-  HIPCHK(launch_frac_curv(mode, e->one, a, a.nearBlocks + frac_fill_blocks(e->ntiles), e->stream));
+  HIPCHK(launch_frac_curv(mode, e->one, a, a.nearBlocks + (int)e->fillTotal, e->stream));
   if (mode & 2) {
     // the launch above zeroed the other parity's count: the next curvature
     // launch uses it, whatever happens to the fit launch below
@@ -641,6 +675,7 @@ int engine_create_fixed(Engine *e, int n, const ebit_grid *grids, const ebit_sta
     if (rc) return rc;
   }
   rc = engine_compact(e, 0, e->stepNo, 0);
+  if (!rc) rc = engine_fill_table(e);
   if (rc) return rc;
   HIPCHK(hipStreamSynchronize(e->stream));
   e->epoch++;
@@ -1217,6 +1252,7 @@ int ebit_pool_step(ebit_pool *p) {
   for (uint32_t k = 0; k < e->maxGrids; k++) any = any || e->live[k];
   if (p->dirty) {
     int rc = engine_compact(e, 0, e->stepNo, 0);
+    if (!rc) rc = engine_fill_table(e);
     if (rc) return rc;
     p->dirty = false;
   }
@@ -1309,6 +1345,7 @@ int ebit_step_static(const ebit_grid *grid, uint8_t *node_color_dev, uint8_t *ce
   HIPCHK(launch_import_state(I, node_color_dev, cell_color_dev, hoff_dev, voff_dev, st));
   HIPCHK(launch_init_tiles(e->dinst, 0, e->ntiles, 0, e->tileInst, e->has, e->nearPrev, st));
   rc = engine_compact(e, 0, e->stepNo, 0);
+  if (!rc) rc = engine_fill_table(e);
   if (!rc) rc = engine_advect(e, u_dev, v_dev, nullptr, dt);
   if (!rc) rc = engine_frac(e, 3, nullptr, C_dev, K_dev);
   if (rc) return rc;
