@@ -113,6 +113,29 @@ typedef struct {
 
 typedef struct ebit_handle ebit_handle;
 
+/* Launch schedule of an engine (a handle, batch or pool): how its persistent
+ * kernels spread over the GPU. It decides only which workgroup handles which
+ * tile or marker, never a result: states, C and kappa are bit-identical under
+ * every schedule. Values are clamped to what the device can hold resident
+ * (per compute unit); 0 in any field means the device's default for it.
+ *   sweep_per_cu      sweep workgroups per CU (default: all resident, 16)
+ *   fit_per_cu        fit workgroups per CU (default: all resident)
+ *   sweep_min_chunk   several grids: tiles per sweep workgroup, at least (8)
+ *   frac_near_per_cu  fraction/curvature pass: workgroups per CU that take the
+ *                     tiles with cut cells, the others filling the uniform
+ *                     cells beside them (5.5 of 8)
+ *   ns_near_per_cu    the same split for ebit_ns_fields (6 of 8) */
+typedef struct {
+  uint32_t sweep_per_cu, fit_per_cu, sweep_min_chunk;
+  double frac_near_per_cu, ns_near_per_cu;
+} ebit_schedule;
+
+/* The schedule in force (every field resolved, no zeros). */
+int ebit_get_schedule(const ebit_handle *h, ebit_schedule *out);
+/* Replace it (takes effect at the next call; EBIT_ERR_ARG for a negative or
+ * non-finite field). */
+int ebit_set_schedule(ebit_handle *h, const ebit_schedule *s);
+
 /* Bytes of device workspace a grid needs (both state buffers, tile tables,
  * lists, counters, sweep scratch). Returns EBIT_ERR_ARG for an invalid grid. */
 int ebit_workspace_bytes(const ebit_grid *grid, size_t *bytes);
@@ -250,6 +273,11 @@ int ebit_batch_stats(ebit_batch *b, ebit_counters *out);
 int ebit_batch_sync(ebit_batch *b, int *status);
 int ebit_batch_destroy(ebit_batch *b);
 
+/* The batch's schedule (as ebit_get_schedule / ebit_set_schedule). A graph
+ * captured before a change keeps the schedule it was captured with. */
+int ebit_batch_get_schedule(const ebit_batch *b, ebit_schedule *out);
+int ebit_batch_set_schedule(ebit_batch *b, const ebit_schedule *s);
+
 /* K steps of the batch recorded once as a HIP graph of kernel launches and
  * replayed with one call: step k (0 <= k < ksteps) is ebit_batch_advect with
  * dt_dev = dts_dev + k*n (dts_dev: device, ksteps x n doubles, row k = the
@@ -306,6 +334,8 @@ int ebit_pool_get_state(ebit_pool *p, int slot, uint8_t *node_color, uint8_t *ce
 /* Release the slot, its tiles and its arena space (asynchronous). */
 int ebit_pool_retire(ebit_pool *p, int slot);
 int ebit_pool_stats(ebit_pool *p, ebit_counters *out);
+int ebit_pool_get_schedule(const ebit_pool *p, ebit_schedule *out);
+int ebit_pool_set_schedule(ebit_pool *p, const ebit_schedule *s);
 int ebit_pool_destroy(ebit_pool *p);
 
 /* ===========================================================================

@@ -165,6 +165,7 @@ struct SweepArgs {
   uint2 *jobs;               // fit jobs: (grid, unaligned-edge index)
   uint32_t jobCap;           // length of the job list
   uint32_t *njobs;           // fit jobs of this direction
+  uint32_t minChunk;         // several grids: tiles per sweep workgroup, at least
   unsigned long long *ctr;
   // one grid: the centre rules of the step's first sweep, when they are left
   // to this (second) sweep's launch; its job count (null: none) and view

@@ -48,7 +48,6 @@ constexpr int NE = NH - 1;             // staged cells / edges per side (20)
 constexpr int NN = TS + 1;             // new nodes per side (17)
 constexpr int JOBCAP = 384;            // queued fit jobs per sweep workgroup (>= one tile's 256)
 constexpr uint32_t NXCD = 8;          // XCDs of the GPU, each with its own L2
-constexpr uint32_t SWEEP_MIN_CHUNK = 8;  // tiles per sweep workgroup, at least, with several grids
 
 // marker-position mask bits of a tile: any marker; within STRIP cells of a
 // side or corner; on the tile's own left / bottom border edge (shared with
@@ -694,10 +693,10 @@ __global__ __launch_bounds__(SWEEP_BS, 8) void k_sweep(SweepArgs A, const Inst *
     itEnd = ntile;
     itStep = gridDim.x;
   } else {
-    // at least SWEEP_MIN_CHUNK tiles per workgroup: a workgroup queues its fit
+    // at least A.minChunk tiles per workgroup: a workgroup queues its fit
     // jobs together, and the fit runs once per distinct grid of a wavefront,
     // so short chunks (few active tiles) would mix grids in every wavefront
-    const uint32_t chunk = max((ntile + gridDim.x - 1) / gridDim.x, SWEEP_MIN_CHUNK);
+    const uint32_t chunk = max((ntile + gridDim.x - 1) / gridDim.x, max(A.minChunk, 1u));
     itBeg = min(ntile, blockIdx.x * chunk);
     itEnd = min(ntile, itBeg + chunk);
     itStep = 1;

@@ -122,6 +122,8 @@ struct Engine {
   // for a pool, whose slot may be empty and whose tile space is larger
   bool one = false;
   int sweepBlocks = 0, fitBlocks = 0, centreBlocks = 0, nearBlocks[3] = {0, 0, 0}, nsNearBlocks = 0;
+  ebit_schedule sched{};  // as set by the caller (0 = device default)
+  ebit_schedule used{};   // resolved
   // device tables
   Inst *dinst = nullptr;
   uint32_t *tileInst = nullptr, *counts = nullptr, *errs = nullptr;
@@ -288,28 +290,47 @@ size_t engine_bytes(uint32_t ntiles, uint32_t maxGrids, uint32_t jobCap) {
   return align256(c.off);
 }
 
+// Default schedule: every resident sweep and fit workgroup; 8 tiles per
+// sweep workgroup at least with several grids; 5.5 of the 8 resident
+// fraction-pass slots per CU for the tiles with cut cells, so that fill
+// workgroups run beside them from the start and take the other slots as they
+// finish (8192^2 with the fill's streaming stores: call 240 -> 192 us against
+// all 8 slots; the batch of 256 grids: 679 -> 658 us per step); 6 for the
+// interface consumers.
+constexpr double DEF_FRAC_NEAR = 5.5, DEF_NS_NEAR = 6.0;
+constexpr uint32_t DEF_MIN_CHUNK = 8;
+
 void engine_launch_config(Engine *e) {
   int dev = 0, cus = 256;
   if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     cus = 256;
-  e->sweepBlocks = cus * resident_blocks(0);
-  e->fitBlocks = cus * resident_blocks(1);
+  const ebit_schedule &s = e->sched;
+  const int rs = resident_blocks(0), rf = resident_blocks(1);
+  const int sp = s.sweep_per_cu ? std::min((int)s.sweep_per_cu, rs) : rs;
+  const int fp = s.fit_per_cu ? std::min((int)s.fit_per_cu, rf) : rf;
+  e->sweepBlocks = cus * sp;
+  e->fitBlocks = cus * fp;
   e->centreBlocks = cus * resident_blocks(2);
   e->ghfBlocks = cus * 16;  // single-wavefront workgroups, one per parabola-fit entry in the usual case
-  // near-tile workgroups per CU of the fraction pass: 5.5 of the 8 resident
-  // slots, so that fill workgroups run beside the near ones from the start
-  // and take the other slots as the near ones finish (8192^2 with the fill's
-  // streaming stores: call 240 -> 192 us against all 8 slots; the batch of
-  // 256 grids, ordinary stores: 679 -> 658 us per step)
-  double perCU = 5.5;
-  if (const char *v = getenv("EBIT_FRAC_NEAR_BLOCKS_PER_CU")) perCU = atof(v);
-  if (!(perCU > 0.0)) perCU = 5.5;
-  e->nsNearBlocks = cus * 6;
+  const double perCU = s.frac_near_per_cu > 0.0 ? s.frac_near_per_cu : DEF_FRAC_NEAR;
+  const double nsPerCU = s.ns_near_per_cu > 0.0 ? s.ns_near_per_cu : DEF_NS_NEAR;
+  const int rn = resident_blocks(5);
+  e->nsNearBlocks = std::max(1, std::min((int)(cus * nsPerCU), cus * rn));
   for (int m = 0; m < 3; m++) {
     const int cap = cus * resident_blocks(3 + m);
     const int nb = std::min((int)(cus * perCU), cap);
     e->nearBlocks[m] = nb < 1 ? 1 : nb;
   }
+  e->used.sweep_per_cu = (uint32_t)sp;
+  e->used.fit_per_cu = (uint32_t)fp;
+  e->used.sweep_min_chunk = s.sweep_min_chunk ? s.sweep_min_chunk : DEF_MIN_CHUNK;
+  e->used.frac_near_per_cu = std::min(perCU, (double)resident_blocks(5));
+  e->used.ns_near_per_cu = std::min(nsPerCU, (double)rn);
+}
+
+bool schedule_ok(const ebit_schedule *s) {
+  return s && isfinite(s->frac_near_per_cu) && isfinite(s->ns_near_per_cu) && s->frac_near_per_cu >= 0.0 &&
+         s->ns_near_per_cu >= 0.0 && s->sweep_min_chunk <= (1u << 20);
 }
 
 // The fill's chunk table of the live grids. One grid needs none (its chunks
@@ -430,6 +451,7 @@ int engine_sweep(Engine *e, int phase, const double *u, const double *v, const d
   a.has = e->has;
   a.jobs = e->jobs;
   a.jobCap = e->jobCap;
+  a.minChunk = e->used.sweep_min_chunk;
   a.ctr = e->ctr;
   a.pendJobs = nullptr;
   uint32_t *cs = e->counts + NSLOT * e->slot;
@@ -862,6 +884,19 @@ int ebit_stats(ebit_handle *h, ebit_counters *out) {
   return engine_errors(&h->e, nullptr);
 }
 
+int ebit_get_schedule(const ebit_handle *h, ebit_schedule *out) {
+  if (!h || !out) return EBIT_ERR_ARG;
+  *out = h->e.used;
+  return EBIT_OK;
+}
+
+int ebit_set_schedule(ebit_handle *h, const ebit_schedule *s) {
+  if (!h || !schedule_ok(s)) return EBIT_ERR_ARG;
+  h->e.sched = *s;
+  engine_launch_config(&h->e);
+  return EBIT_OK;
+}
+
 int ebit_stats_reset(ebit_handle *h) {
   if (!h) return EBIT_ERR_ARG;
   HIPCHK(hipMemsetAsync(h->e.ctr, 0, CTR_PARTS * CTR_STRIDE * sizeof(unsigned long long), h->e.stream));
@@ -985,6 +1020,19 @@ int ebit_batch_get_state(ebit_batch *b, int k, uint8_t *node_color, uint8_t *cel
 int ebit_batch_stats(ebit_batch *b, ebit_counters *out) {
   if (!b || !out) return EBIT_ERR_ARG;
   return engine_counters(&b->e, out);
+}
+
+int ebit_batch_get_schedule(const ebit_batch *b, ebit_schedule *out) {
+  if (!b || !out) return EBIT_ERR_ARG;
+  *out = b->e.used;
+  return EBIT_OK;
+}
+
+int ebit_batch_set_schedule(ebit_batch *b, const ebit_schedule *s) {
+  if (!b || !schedule_ok(s)) return EBIT_ERR_ARG;
+  b->e.sched = *s;
+  engine_launch_config(&b->e);
+  return EBIT_OK;
 }
 
 int ebit_batch_sync(ebit_batch *b, int *status) {
@@ -1292,6 +1340,19 @@ int ebit_pool_get_state(ebit_pool *p, int slot, uint8_t *node_color, uint8_t *ce
 int ebit_pool_stats(ebit_pool *p, ebit_counters *out) {
   if (!p || !out) return EBIT_ERR_ARG;
   return engine_counters(&p->e, out);
+}
+
+int ebit_pool_get_schedule(const ebit_pool *p, ebit_schedule *out) {
+  if (!p || !out) return EBIT_ERR_ARG;
+  *out = p->e.used;
+  return EBIT_OK;
+}
+
+int ebit_pool_set_schedule(ebit_pool *p, const ebit_schedule *s) {
+  if (!p || !schedule_ok(s)) return EBIT_ERR_ARG;
+  p->e.sched = *s;
+  engine_launch_config(&p->e);
+  return EBIT_OK;
 }
 
 int ebit_pool_destroy(ebit_pool *p) {

@@ -45,6 +45,18 @@ class ebit_fluid(ctypes.Structure):
                 ("mu2", ctypes.c_double), ("sigma", ctypes.c_double)]
 
 
+class ebit_schedule(ctypes.Structure):
+    _fields_ = [("sweep_per_cu", ctypes.c_uint32), ("fit_per_cu", ctypes.c_uint32),
+                ("sweep_min_chunk", ctypes.c_uint32), ("frac_near_per_cu", ctypes.c_double),
+                ("ns_near_per_cu", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+SCHEDULE_FIELDS = tuple(k for k, _ in ebit_schedule._fields_)
+
+
 class ebit_counters(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in COUNTERS]
 
@@ -80,6 +92,12 @@ def _load() -> ctypes.CDLL:
         "ebit_set_state": [vp, S, ctypes.c_int64],
         "ebit_stats": [vp, ctypes.POINTER(ebit_counters)],
         "ebit_stats_reset": [vp],
+        "ebit_get_schedule": [vp, ctypes.POINTER(ebit_schedule)],
+        "ebit_set_schedule": [vp, ctypes.POINTER(ebit_schedule)],
+        "ebit_batch_get_schedule": [vp, ctypes.POINTER(ebit_schedule)],
+        "ebit_batch_set_schedule": [vp, ctypes.POINTER(ebit_schedule)],
+        "ebit_pool_get_schedule": [vp, ctypes.POINTER(ebit_schedule)],
+        "ebit_pool_set_schedule": [vp, ctypes.POINTER(ebit_schedule)],
         "ebit_sync": [vp],
         "ebit_destroy": [vp],
     }
@@ -168,6 +186,17 @@ def step_static(grid: ebit_grid, node, cell, hoff, voff, u, v, dt: float, step: 
     return _lib.ebit_step_static(ctypes.byref(grid), node.data_ptr(), cell.data_ptr(), hoff.data_ptr(),
                                  voff.data_ptr(), u.data_ptr(), v.data_ptr(), float(dt), int(step), C.data_ptr(),
                                  K.data_ptr(), status.data_ptr(), st.cuda_stream)
+
+
+def _get_schedule(fn, h) -> dict:
+    out = ebit_schedule()
+    _chk(fn(h, ctypes.byref(out)), fn.__name__)
+    return out.as_dict()
+
+
+def _set_schedule(fn, h, sched: dict):
+    s = ebit_schedule(**{k: sched.get(k, 0) for k in SCHEDULE_FIELDS})
+    _chk(fn(h, ctypes.byref(s)), fn.__name__)
 
 
 def _host_state(st: State):
@@ -268,6 +297,13 @@ class EbitGrid:
         s, keep = _host_state(state)
         _chk(_lib.ebit_set_state(self._h, ctypes.byref(s), int(state.step)), "ebit_set_state")
         self.step = state.step
+
+    def get_schedule(self) -> dict:
+        return _get_schedule(_lib.ebit_get_schedule, self._h)
+
+    def set_schedule(self, sched: dict):
+        """Launch schedule (ebit_schedule fields; missing or 0 = device default)."""
+        _set_schedule(_lib.ebit_set_schedule, self._h, sched)
 
     def stats(self) -> dict:
         out = ebit_counters()
@@ -402,6 +438,12 @@ class EbitBatch:
         st.step = int(step.value)
         return st
 
+    def get_schedule(self) -> dict:
+        return _get_schedule(_lib.ebit_batch_get_schedule, self._h)
+
+    def set_schedule(self, sched: dict):
+        _set_schedule(_lib.ebit_batch_set_schedule, self._h, sched)
+
     def stats(self) -> dict:
         out = ebit_counters()
         _chk(_lib.ebit_batch_stats(self._h, ctypes.byref(out)), "ebit_batch_stats")
@@ -524,6 +566,12 @@ class EbitPool:
     def retire(self, slot: int):
         _chk(_lib.ebit_pool_retire(self._h, slot), "ebit_pool_retire")
         self.shapes.pop(slot, None)
+
+    def get_schedule(self) -> dict:
+        return _get_schedule(_lib.ebit_pool_get_schedule, self._h)
+
+    def set_schedule(self, sched: dict):
+        _set_schedule(_lib.ebit_pool_set_schedule, self._h, sched)
 
     def stats(self) -> dict:
         out = ebit_counters()
