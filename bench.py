@@ -1,25 +1,28 @@
 """Benchmark of the EBIT interface step on one MI355X.
 
-Default workload (the headline line): 8192 x 8192 FP64 grid, 2000 seeded
+Headline (the `value` of the JSON line): 8192 x 8192 FP64 grid, 2000 seeded
 non-overlapping circles (radii uniform in [4, 32] cells), single-vortex face
 velocity with period T = 4 at CFL 0.5 (dt = h/2, time factor cos(pi t / T)
 folded into dt). One step is the whole hot path: ebit_advect (x and y sweeps
 with circle fit, Color Vertex update and topology change) followed by
-ebit_fraction_curvature.
+ebit_fraction_curvature. Its launch schedule is tuned first on the same grid
+(paper_2309_00338_amd/tune.py), outside the timed region.
 
-Prints one JSON line: throughput in cell-steps/s over the timed steps (state
-and velocities already resident in HBM), the roofline of the dominant kernel
-(fraction + curvature, timed live with events on its stream), the whole-step
-algorithmic-bytes roofline, and the CPU oracle timed on a bounded sample.
+The same line carries the rest of the metric:
+  roofline / step_roofline: the dominant kernel (fraction + curvature, timed
+      live with events on its stream) and the whole step against HBM peak;
+  batched: 256 independent grids (N log-uniform in [64, 1024], 1-20 circles or
+      ellipses, own vortex period each) as one HIP graph of K steps, as eager
+      batched launches, and as a loop of plain per-grid calls;
+  served: a Poisson stream of requests (200/s, N log-uniform in [128, 2048],
+      steady random fields, 16-256 steps each) through the pool, with
+      arrival-to-result latency percentiles, against a plain per-request loop;
+  cpu_baseline: the CPU oracle timed on a bounded sample of the headline grid.
 
---workload batched: 256 independent grids (N log-uniform in [64, 1024], 1-20
-circles or ellipses, own vortex period each) advanced by the batched entry
-points, against a loop of per-grid handles on one stream.
---workload served: a pool serving a Poisson stream of requests (200/s, N
-log-uniform in [128, 2048], steady random fields, 16-256 steps each); reports
-cell-steps/s and the arrival-to-result latency percentiles.
+--workload single|batched|served runs one part alone (its own JSON line).
 """
 import argparse
+import collections
 import json
 import math
 import os
@@ -56,6 +59,18 @@ def traffic_from_profile(kernel, n):
         return None
 
 
+def host_cpu():
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model, len(os.sched_getaffinity(0))
+
+
 def cpu_baseline(w, nsteps=1):
     """The oracle (single-threaded C) on the same grid: nsteps full steps."""
     import oracle
@@ -68,53 +83,22 @@ def cpu_baseline(w, nsteps=1):
         C = oracle.fraction(st)
         oracle.curvature(st, C)
     el = time.perf_counter() - t0
+    model, avail = host_cpu()
     return {"value": st.nx * st.ny * nsteps / el, "unit": "cell-steps/s", "cores": 1, "kind": "oracle",
+            "cpu_model": model, "host_cores_available": avail,
             "sample": f"{nsteps} full step(s) (advect + fraction + curvature) of the same {st.nx}x{st.ny} "
-                      f"workload from its initial state, single-threaded C, {el:.1f} s"}
+                      f"workload from its initial state, single-threaded C on one core, {el:.1f} s"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=64)
-    ap.add_argument("--warmup", type=int, default=4)
-    ap.add_argument("--n", type=int, default=8192)
-    ap.add_argument("--circles", type=int, default=2000)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=("single", "batched", "served"), default="single")
-    ap.add_argument("--grids", type=int, default=256, help="batched: number of grids")
-    ap.add_argument("--served-seconds", type=float, default=4.0, help="served: seconds of arrivals")
-    ap.add_argument("--rate", type=float, default=200.0, help="served: arrivals per second")
-    ap.add_argument("--pool-tiles", type=int, default=1 << 18, help="served: tile capacity of the pool")
-    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
-                    help="only copy a MIB-sized device buffer 5 times (a plain copy kernel of known size, "
-                         "the reference for scaling hardware byte counters), then exit")
-    args = ap.parse_args()
-    if args.calibrate_copy:
-        import torch
-
-        nbytes = args.calibrate_copy << 20
-        a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
-        b = torch.empty_like(a)
-        for _ in range(5):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        print(json.dumps({"calibrate_copy_bytes": nbytes, "copies": 5}), flush=True)
-        return
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
-                          "n_gpus": args.gpus}), flush=True)
-        sys.exit(2)
-
-    if args.workload == "batched":
-        return bench_batched(args)
-    if args.workload == "served":
-        return bench_served(args)
-
+# ---------------------------------------------------------------------------
+# headline: one large grid
+# ---------------------------------------------------------------------------
+def run_single(args):
     import torch
 
     from paper_2309_00338_amd import ebit
     from paper_2309_00338_amd import inputs as I
+    from paper_2309_00338_amd import tune
 
     t0 = time.perf_counter()
     period, cfl = 4.0, 0.5
@@ -132,6 +116,23 @@ def main():
     stream = g.stream
     torch.cuda.synchronize()
     log(f"[bench] uploaded; workspace {g.ws.numel() / 2**30:.2f} GiB")
+
+    # launch schedule: tuned on this grid, then the grid is reset to its start
+    tuned = None
+    if not args.no_tune:
+        k = [0]
+
+        def tstep():
+            g.advect(u, v, w.dts[k[0] % len(w.dts)])
+            g.fraction_curvature(C, K)
+            k[0] += 1
+
+        best, info = tune.tune(g, tstep, stream, fields=tune.ONE_GRID, steps=4, reps=2)
+        tuned = {"schedule": best, "us_per_step": info["us_per_step"],
+                 "candidates_us": info["table"], "method": "coordinate descent, best of 2 x 4 steps each"}
+        g.sync()
+        g.set_state(w.state)
+        log(f"[bench] tuned schedule {best}")
 
     for k in range(args.warmup):
         g.advect(u, v, w.dts[k])
@@ -196,6 +197,8 @@ def main():
                      "traffic": traffic, "us_per_launch": fc_ms * 1e3, "alg_bytes_per_launch": fc_bytes},
         "step_roofline": {"alg_bytes_per_step": step_bytes, "achieved_GBs": step_bytes / (ms_step * 1e-3) / 1e9,
                           "frac": step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "schedule": g.get_schedule(),
+        "tuning": tuned,
         "counters": st,
     }
     # consumers of C and kappa (not part of the step): rho, mu and the face forces
@@ -218,185 +221,365 @@ def main():
                         "achieved_GBs": ns_bytes / (ns_us * 1e-6) / 1e9,
                         "frac": ns_bytes / (ns_us * 1e-6) / 1e9 / HBM_PEAK_GBS}
     log(f"[bench] ns_fields: {ns_us:.1f} us/launch")
+    g.close()
+    del g, u, v, C, K, rho, mu, fx, fy
+    torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on two steps of the same grid")
         out["cpu_baseline"] = cpu_baseline(w, 2)
-    print(json.dumps(out), flush=True)
+    return out
 
 
-def bench_batched(args):
-    """Batched form against a loop of per-grid handles, same grids and steps."""
+# ---------------------------------------------------------------------------
+# batched form
+# ---------------------------------------------------------------------------
+def run_batched(args, steps, warmup):
+    """The batched form (graph of K steps and eager launches) against a loop of
+    plain per-grid calls, same grids and steps."""
     import torch
 
     from paper_2309_00338_amd import ebit
     from paper_2309_00338_amd import inputs as I
+    from paper_2309_00338_amd import tune
 
+    steps += steps & 1  # the graph needs an even count
     t0 = time.perf_counter()
-    nsteps = args.warmup + args.steps
+    nsteps = warmup + steps
     inst = I.batched_instances(count=args.grids, steps=nsteps)
     cells = sum(st.nx * st.ny for st, _, _, _ in inst)
-    log(f"[bench] generated {len(inst)} grids, {cells:.3e} cells in {time.perf_counter() - t0:.1f}s")
+    log(f"[bench] batched: {len(inst)} grids, {cells:.3e} cells, generated in {time.perf_counter() - t0:.1f}s")
     dev = torch.device("cuda:0")
-    b = ebit.EbitBatch([st for st, _, _, _ in inst], device=dev)
-    U, V = b.pack_velocities([u for _, u, _, _ in inst], [v for _, _, v, _ in inst])
+    states = [st for st, _, _, _ in inst]
     dts = torch.tensor([[d[k] for _, _, _, d in inst] for k in range(nsteps)], dtype=torch.float64, device=dev)
-    C, K = b.new_fields()
-    stream = b.stream
 
-    def timed(step_fn):
-        for k in range(args.warmup):
-            step_fn(k)
+    def timed(stream, fn, n):
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        for k in range(args.warmup, nsteps):
-            step_fn(k)
+        fn()
         e1.record(stream)
         torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / args.steps
+        return e0.elapsed_time(e1) * 1e3 / n  # us per step
 
-    def batched_step(k):
+    # tune the batch's schedule on a scratch batch
+    tb = ebit.EbitBatch(states, device=dev)
+    U, V = tb.pack_velocities([u for _, u, _, _ in inst], [v for _, _, v, _ in inst])
+    C, K = tb.new_fields()
+    kk = [0]
+
+    def tstep():
+        tb.advect(U, V, dts[kk[0] % nsteps])
+        tb.fraction_curvature(C, K)
+        kk[0] += 1
+
+    sched = None
+    if not args.no_tune:
+        sched, _ = tune.tune(tb, tstep, tb.stream, fields=tune.SEVERAL, steps=2, reps=1)
+    tb.close()
+    del tb
+
+    # eager batched launches
+    b = ebit.EbitBatch(states, device=dev)
+    if sched:
+        b.set_schedule(sched)
+    for k in range(warmup):
         b.advect(U, V, dts[k])
         b.fraction_curvature(C, K)
 
-    ms_b = timed(batched_step)
-    st_b = b.sync()
-    if any(st_b):
-        raise RuntimeError(f"batched run reported device errors: {sorted(set(st_b))}")
-    log(f"[bench] batched: {ms_b * 1e3:.1f} us/step")
+    def eager():
+        for k in range(warmup, nsteps):
+            b.advect(U, V, dts[k])
+            b.fraction_curvature(C, K)
+
+    us_eager = timed(b.stream, eager, steps)
+    if any(b.sync()):
+        raise RuntimeError("batched run reported device errors")
+    b.close()
+    del b
+
+    # the same steps as one captured graph (on a stream of its own)
+    gs = torch.cuda.Stream(device=dev)
+    b = ebit.EbitBatch(states, device=dev, stream=gs)
+    if sched:
+        b.set_schedule(sched)
+    for k in range(warmup):
+        b.advect(U, V, dts[k])
+        b.fraction_curvature(C, K)
+    graph = b.capture(steps, U, V, dts[warmup:].contiguous(), C, K)
+    us_graph = timed(gs, graph.launch, steps)
+    if any(b.sync()):
+        raise RuntimeError("graph replay reported device errors")
+    graph.close()
+    b.close()
     del b, U, V, C, K
     torch.cuda.empty_cache()
+    log(f"[bench] batched: graph {us_graph:.1f} us/step, eager {us_eager:.1f} us/step")
 
-    grids = [ebit.EbitGrid(st, device=dev) for st, _, _, _ in inst]
+    # plain loop of per-grid handles on one stream
+    grids = [ebit.EbitGrid(st, device=dev) for st in states]
     vel = [(torch.from_numpy(u).to(dev), torch.from_numpy(v).to(dev)) for _, u, v, _ in inst]
-    fields = [g.new_field() for g in grids]
-    kfields = [g.new_field() for g in grids]
-
-    def plain_step(k):
-        for g, (u, v), (_, _, _, d), c, kk in zip(grids, vel, inst, fields, kfields):
+    fields = [(g.new_field(), g.new_field()) for g in grids]
+    hd = [d for _, _, _, d in inst]
+    for k in range(warmup):
+        for g, (u, v), d, (c, kf) in zip(grids, vel, hd, fields):
             g.advect(u, v, d[k])
-            g.fraction_curvature(c, kk)
+            g.fraction_curvature(c, kf)
 
-    ms_p = timed(plain_step)
+    def plain():
+        for k in range(warmup, nsteps):
+            for g, (u, v), d, (c, kf) in zip(grids, vel, hd, fields):
+                g.advect(u, v, d[k])
+                g.fraction_curvature(c, kf)
+
+    us_plain = timed(grids[0].stream, plain, steps)
     for g in grids:
         g.sync()
-    log(f"[bench] plain loop: {ms_p * 1e3:.1f} us/step")
-    out = {
-        "metric": METRIC, "value": cells / (ms_b * 1e-3), "unit": "cell-steps/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_b, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"batched: {len(inst)} grids, N log-uniform in [64,1024], 1-20 circles/ellipses, "
-                               f"single vortex T~U[1,8], CFL 0.5", "grids": len(inst), "cells": cells, "seed": 1004},
-        "plain": {"value": cells / (ms_p * 1e-3), "ms_per_step": ms_p,
+        g.close()
+    del grids, vel, fields
+    torch.cuda.empty_cache()
+    log(f"[bench] batched: plain per-grid loop {us_plain:.1f} us/step")
+    return {
+        "workload": f"batched: {len(inst)} grids, N log-uniform in [64,1024], 1-20 circles/ellipses, "
+                    f"single vortex T~U[1,8], CFL 0.5, seed 1004",
+        "grids": len(inst), "cells": cells, "steps": steps, "warmup": warmup,
+        "graph": {"us_per_step": us_graph, "cell_steps_per_s": cells / (us_graph * 1e-6),
+                  "what": f"ebit_batch_capture of {steps} steps, one ebit_graph_launch"},
+        "eager": {"us_per_step": us_eager, "cell_steps_per_s": cells / (us_eager * 1e-6),
+                  "what": "ebit_batch_advect + ebit_batch_fraction_curvature per step"},
+        "plain": {"us_per_step": us_plain, "cell_steps_per_s": cells / (us_plain * 1e-6),
                   "what": "one ebit_advect + ebit_fraction_curvature per grid per step, one stream"},
-        "batched_vs_plain": ms_p / ms_b,
+        "graph_vs_plain": us_plain / us_graph, "eager_vs_plain": us_plain / us_eager,
+        "schedule": sched,
     }
-    print(json.dumps(out), flush=True)
 
 
-def bench_served(args):
-    """Pool serving a Poisson request stream. The clock is wall time minus the
-    client's time spent building requests; a request's latency runs from its
-    arrival to the end of the GPU step that completes it."""
-    import collections
+# ---------------------------------------------------------------------------
+# served form
+# ---------------------------------------------------------------------------
+def _make_request(req):
+    """Worker: one request's instance as plain arrays (generation is the
+    client's work, done before the clock starts)."""
+    from paper_2309_00338_amd import inputs as I
 
+    st, u, v, dt = I.served_instance(req)
+    return {"id": req["id"], "arrival": req["arrival"], "steps": req["steps"], "nx": st.nx, "ny": st.ny,
+            "h": st.h, "c": st.c, "cc": st.cc, "hoff": st.hoff, "voff": st.voff, "u": u, "v": v, "dt": dt}
+
+
+def generate_requests(args, seconds):
+    """The request stream, generated by worker processes before anything
+    touches the GPU (they run numpy only)."""
+    from concurrent.futures import ProcessPoolExecutor
+
+    from paper_2309_00338_amd import inputs as I
+
+    count = max(1, int(round(seconds * args.rate)))
+    t0 = time.perf_counter()
+    reqs = list(I.served_requests(count, rate=args.rate))
+    workers = max(1, min(16, len(os.sched_getaffinity(0))) - 1)
+    if workers <= 1:
+        out = [_make_request(r) for r in reqs]
+    else:
+        with ProcessPoolExecutor(max_workers=workers) as ex:
+            out = list(ex.map(_make_request, reqs, chunksize=4))
+    log(f"[bench] served: {count} requests generated in {time.perf_counter() - t0:.1f}s ({workers} workers)")
+    return out
+
+
+def run_served(args, seconds, plain_count, reqs):
+    """The pool serving a Poisson request stream, clock = wall time from the
+    first arrival's origin (requests were generated beforehand). Admission,
+    stepping, retirement and status polling are all asynchronous: the host
+    enqueues, and a request's completion time is the GPU timestamp of the
+    event after the step that finished it (its fields are then in HBM), on the
+    same origin as the arrival times. The same requests (a prefix of them)
+    then run through a plain per-request loop for comparison."""
     import numpy as np
     import torch
 
     from paper_2309_00338_amd import ebit
-    from paper_2309_00338_amd import inputs as I
 
-    count = max(1, int(round(args.served_seconds * args.rate)))
-    reqs = I.served_requests(count, rate=args.rate)
+    count = len(reqs)
+    t0 = time.perf_counter()
+    for r in reqs:  # pinned host memory: the admission uploads overlap the GPU's work
+        for k in ("c", "cc", "hoff", "voff", "u", "v"):
+            r[k] = torch.from_numpy(np.ascontiguousarray(r[k])).pin_memory()
+    offered = sum(r["nx"] * r["ny"] * r["steps"] for r in reqs)
+    log(f"[bench] served: {count} requests pinned in {time.perf_counter() - t0:.1f}s")
+
     dev = torch.device("cuda:0")
-    free, total = torch.cuda.mem_get_info(dev)
-    arena = int(min(free * 0.6, 96 << 30))
-    pool = ebit.EbitPool(max_grids=256, max_tiles=args.pool_tiles, arena_bytes=arena, device=dev)
+    free, _ = torch.cuda.mem_get_info(dev)
+    arena = int(min(free * 0.5, 96 << 30))
+    max_grids = 256
+    pool = ebit.EbitPool(max_grids=max_grids, max_tiles=args.pool_tiles, arena_bytes=arena, device=dev)
     stream = pool.stream
-    gen_time = 0.0
+    status_dev = torch.empty(max_grids, dtype=torch.int32, device=dev)
+    ring = [torch.empty(max_grids, dtype=torch.int32).pin_memory() for _ in range(64)]
+    ref = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
     wall0 = time.perf_counter()
+    ref.record(stream)
+    live = {}  # slot -> [request, steps left]
+    inflight = collections.deque()  # (event, finished [(request, slot)], status buffer or None)
+    lat, cell_steps, pool_steps, nxt, depth_waits = [], 0, 0, 0, 0
+    gpu_end = 0.0
+    ring_i = 0
 
-    def clock():
-        return time.perf_counter() - wall0 - gen_time
+    def reap(block):
+        nonlocal gpu_end
+        while inflight and (block or inflight[0][0].query()):
+            ev, done, sbuf = inflight.popleft()
+            ev.synchronize()
+            t_done = ref.elapsed_time(ev) * 1e-3
+            gpu_end = max(gpu_end, t_done)
+            for req, slot in done:
+                if int(sbuf[slot]) != 0:
+                    raise RuntimeError(f"request {req['id']} failed with status {int(sbuf[slot])}")
+                lat.append(t_done - req["arrival"])
+            block = False
 
-    pending = collections.deque()
-    nxt = None
-    exhausted = False
-    live = {}  # slot -> (request, cells)
-    lat, cell_steps, steps_run = [], 0, 0
-    offered, last_arrival = 0, 0.0
-    skip = 0.0  # idle time skipped when nothing is live and the next arrival is in the future
-    done_all = False
-    while not done_all:
-        # bring in every request that has arrived
-        while True:
-            if nxt is None and not exhausted:
-                try:
-                    t = time.perf_counter()
-                    req = next(reqs)
-                    req["inst"] = I.served_instance(req)
-                    gen_time += time.perf_counter() - t
-                    nxt = req
-                except StopIteration:
-                    exhausted = True
-            if nxt is not None and nxt["arrival"] <= clock() + skip:
-                pending.append(nxt)
-                nxt = None
-                continue
-            break
-        # admit in arrival order while the pool has room
-        while pending:
-            req = pending[0]
-            st, u, v, dt = req["inst"]
-            slot = pool.admit(st, u, v, dt)
+    while nxt < count or live or inflight:
+        now = time.perf_counter() - wall0
+        while nxt < count and reqs[nxt]["arrival"] <= now:
+            r = reqs[nxt]
+            slot = pool.admit(r, r["u"], r["v"], r["dt"])
             if slot is None:
                 break
-            pending.popleft()
-            live[slot] = (req, st.nx * st.ny)
-            offered += st.nx * st.ny * req["steps"]
-            last_arrival = req["arrival"]
-            req.pop("inst")
-        if not live:
-            if exhausted and not pending and nxt is None:
-                done_all = True
-                continue
-            if nxt is not None:
-                skip = max(skip, nxt["arrival"] - clock())
-            continue
-        pool.step()
-        torch.cuda.synchronize()
-        steps_run += 1
-        now = clock() + skip
-        for slot in list(live):
-            req, cells = live[slot]
-            cell_steps += cells
-            req["done"] = req.get("done", 0) + 1
-            if req["done"] >= req["steps"]:
-                _, _, _, status = pool.read(slot, fields=False)
-                if status:
-                    raise RuntimeError(f"request {req['id']} failed with status {status}")
-                lat.append(now - req["arrival"])
-                pool.retire(slot)
-                del live[slot]
-    elapsed = clock() + skip
-    busy = clock()
+            live[slot] = [r, r["steps"]]
+            nxt += 1
+        if live:
+            pool.step()
+            pool_steps += 1
+            done = []
+            for slot, ent in list(live.items()):
+                cell_steps += ent[0]["nx"] * ent[0]["ny"]
+                ent[1] -= 1
+                if ent[1] == 0:
+                    done.append((ent[0], slot))
+                    del live[slot]
+            sbuf = None
+            if done:
+                pool.status(status_dev)
+                sbuf = ring[ring_i % len(ring)]
+                ring_i += 1
+                sbuf.copy_(status_dev, non_blocking=True)
+                for _, slot in done:
+                    pool.retire(slot)  # enqueued after the status copy: the slot is free for later admissions
+            ev = torch.cuda.Event(enable_timing=True)
+            ev.record(stream)
+            inflight.append((ev, done, sbuf))
+            # keep the host a few steps ahead of the GPU, no more (the status ring is finite)
+            if len(inflight) > 8:
+                depth_waits += 1
+                reap(True)
+        elif nxt < count:
+            time.sleep(max(0.0, min(reqs[nxt]["arrival"] - (time.perf_counter() - wall0), 0.01)))
+        reap(False)
+    torch.cuda.synchronize()
+    span = max(gpu_end, time.perf_counter() - wall0)
+    pool.close()
     lat_ms = np.array(lat) * 1e3
-    out = {
-        "metric": METRIC, "value": cell_steps / elapsed, "unit": "cell-steps/s", "n_gpus": 1, "steps": steps_run,
-        "warmup": 0, "ms_per_step": busy / max(steps_run, 1) * 1e3, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"served: Poisson {args.rate:g}/s for {args.served_seconds:g} s, N log-uniform in "
-                               f"[128,2048], 1-50 circles, steady 4-mode fields, 16-256 steps", "requests": count,
-                   "seed": 1005},
+    log(f"[bench] served: {len(lat)} requests, {pool_steps} pool steps, {span:.2f} s, "
+        f"p50 {np.percentile(lat_ms, 50):.1f} ms p99 {np.percentile(lat_ms, 99):.1f} ms")
+
+    # plain per-request loop over the first requests, one after the other
+    sub = reqs[:plain_count]
+    torch.cuda.synchronize()
+    p0 = time.perf_counter()
+    plain_cells = 0
+    from paper_2309_00338_amd.inputs import State
+
+    for r in sub:
+        st = State(r["nx"], r["ny"], r["h"], r["c"].numpy(), r["cc"].numpy(), r["hoff"].numpy(), r["voff"].numpy())
+        g = ebit.EbitGrid(st, device=dev)
+        u, v = r["u"].to(dev), r["v"].to(dev)
+        Cp, Kp = g.new_field(), g.new_field()
+        for _ in range(r["steps"]):
+            g.advect(u, v, r["dt"])
+            g.fraction_curvature(Cp, Kp)
+        g.sync()
+        g.close()
+        plain_cells += r["nx"] * r["ny"] * r["steps"]
+    torch.cuda.synchronize()
+    plain_s = time.perf_counter() - p0
+    sub_served = sum(r["nx"] * r["ny"] * r["steps"] for r in sub)
+    assert sub_served == plain_cells
+    log(f"[bench] served: plain loop over {len(sub)} requests {plain_s:.2f} s")
+    return {
+        "workload": f"served: Poisson {args.rate:g}/s for {seconds:g} s of arrivals, N log-uniform in [128,2048], "
+                    f"1-50 circles, steady 4-mode fields, 16-256 steps, seed 1005",
+        "requests": len(lat), "pool_steps": pool_steps, "span_s": span,
+        "cell_steps_per_s": cell_steps / span,
+        "offered_cell_steps_per_s": offered / max(reqs[-1]["arrival"], 1e-9),
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99)),
                        "max": float(lat_ms.max())},
-        "served": {"requests": len(lat), "cell_steps": cell_steps, "pool_steps": steps_run,
-                   "offered_cell_steps_per_s": offered / max(last_arrival, 1e-9),
-                   "busy_cell_steps_per_s": cell_steps / busy, "span_s": elapsed, "busy_s": busy,
-                   "client_generation_s": gen_time,
-                   "what": "value = cell-steps delivered / span (arrival clock); busy rate excludes idle gaps; "
-                           "latency = arrival to the end of the step completing the request, fields in HBM"},
+        "host_waits_on_gpu": depth_waits,
+        "plain": {"requests": len(sub), "cell_steps_per_s": plain_cells / plain_s, "seconds": plain_s,
+                  "what": "per request: ebit_create, then its steps of ebit_advect + ebit_fraction_curvature, "
+                          "one request after the other, no arrival waits"},
+        "served_vs_plain": (cell_steps / span) / (plain_cells / plain_s),
+        "what": "cell-steps delivered / span from the first arrival's origin to the last result; latency = "
+                "arrival to the GPU end of the step completing the request (fields in HBM)",
     }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=64)
+    ap.add_argument("--warmup", type=int, default=4)
+    ap.add_argument("--n", type=int, default=8192)
+    ap.add_argument("--circles", type=int, default=2000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="keep the device-default launch schedule")
+    ap.add_argument("--workload", choices=("all", "single", "batched", "served"), default="all")
+    ap.add_argument("--grids", type=int, default=256, help="batched: number of grids")
+    ap.add_argument("--batched-steps", type=int, default=8, help="batched: timed steps inside the full line")
+    ap.add_argument("--served-seconds", type=float, default=1.5, help="served: seconds of arrivals")
+    ap.add_argument("--plain-requests", type=int, default=60, help="served: requests of the plain loop")
+    ap.add_argument("--rate", type=float, default=200.0, help="served: arrivals per second")
+    ap.add_argument("--pool-tiles", type=int, default=1 << 18, help="served: tile capacity of the pool")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only copy a MIB-sized device buffer 5 times (a plain copy kernel of known size, "
+                         "the reference for scaling hardware byte counters), then exit")
+    args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+
+        nbytes = args.calibrate_copy << 20
+        a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": nbytes, "copies": 5}), flush=True)
+        return
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+
+    def line(part, d, steps, warmup, ms, value):
+        return {"metric": METRIC, "value": value, "unit": "cell-steps/s", "n_gpus": 1, "steps": steps,
+                "warmup": warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+                "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+                "config": {"workload": d["workload"]}, part: d}
+
+    if args.workload == "batched":
+        d = run_batched(args, args.steps, args.warmup)
+        print(json.dumps(line("batched", d, d["steps"], args.warmup, d["graph"]["us_per_step"] * 1e-3,
+                              d["graph"]["cell_steps_per_s"])), flush=True)
+        return
+    reqs = generate_requests(args, args.served_seconds) if args.workload in ("all", "served") else None
+    if args.workload == "served":
+        d = run_served(args, args.served_seconds, args.plain_requests, reqs)
+        print(json.dumps(line("served", d, d["pool_steps"], 0, d["span_s"] / max(d["pool_steps"], 1) * 1e3,
+                              d["cell_steps_per_s"])), flush=True)
+        return
+    out = run_single(args)
+    if args.workload == "all":
+        out["batched"] = run_batched(args, args.batched_steps, 2)
+        out["served"] = run_served(args, args.served_seconds, args.plain_requests, reqs)
     print(json.dumps(out), flush=True)
 
 

@@ -315,10 +315,17 @@ int ebit_pool_grid_bytes(const ebit_grid *grid, size_t *bytes, uint32_t *tiles);
 int ebit_pool_create(int max_grids, uint32_t max_tiles, void *ws_dev, size_t ws_bytes, void *hip_stream,
                      ebit_pool **out);
 
-/* Admit a grid: validate and upload its state, u_host and v_host (host,
- * layout above) and dt; synchronous with respect to the host buffers. Returns
- * its slot. EBIT_ERR_NOMEM when no slot, tile range or arena space is free
- * (nothing changes; admit again after a retire). */
+/* Admit a grid: its state, u_host and v_host (host, layout above) and dt.
+ * Returns its slot at once; EBIT_ERR_NOMEM when no slot, tile range or arena
+ * space is free (nothing changes; admit again after a retire). Asynchronous:
+ * the uploads are enqueued on the pool's stream and read the host arrays
+ * later, so those must stay unchanged until the stream has passed this point
+ * (the next ebit_pool_read or a synchronisation of the stream); from pinned
+ * host memory the copies overlap the GPU's work, from pageable memory the HIP
+ * runtime may copy before returning. The state is validated on the device: a
+ * colour above 1 or an offset outside [0,1] on an edge whose end colours
+ * differ latches EBIT_ERR_ARG in the grid's status (ebit_pool_read,
+ * ebit_pool_status). */
 int ebit_pool_admit(ebit_pool *p, const ebit_grid *grid, const ebit_state *init, const double *u_host,
                     const double *v_host, double dt, int *slot_out);
 
@@ -330,6 +337,12 @@ int ebit_pool_step(ebit_pool *p);
 int ebit_pool_read(ebit_pool *p, int slot, double *C_host, double *K_host, int64_t *steps, int *status);
 int ebit_pool_get_state(ebit_pool *p, int slot, uint8_t *node_color, uint8_t *cell_color, double *hoff,
                         double *voff);
+
+/* Every slot's latched status (EBIT_OK, EBIT_ERR_CFL, EBIT_ERR_DOMAIN,
+ * EBIT_ERR_ARG; EBIT_OK for empty slots) into status_dev (device, max_grids
+ * int32), asynchronously: a caller polling many requests copies it back once
+ * per step instead of waiting on the stream per request. */
+int ebit_pool_status(ebit_pool *p, int32_t *status_dev);
 
 /* Release the slot, its tiles and its arena space (asynchronous). */
 int ebit_pool_retire(ebit_pool *p, int slot);

@@ -282,6 +282,7 @@ hipError_t launch_import_state(const Inst &I, const uint8_t *node, const uint8_t
 hipError_t launch_export_state(const Inst &I, uint32_t cur, uint8_t *node, uint8_t *cell, double *hoff, double *voff,
                                hipStream_t s);
 hipError_t launch_status(const uint32_t *err, int32_t *status, hipStream_t s);
+hipError_t launch_status_many(const uint32_t *err, int32_t *status, uint32_t n, hipStream_t s);
 
 }  // namespace ebit
 

@@ -2143,11 +2143,11 @@ __global__ void k_export_state(Inst I, uint32_t cur, uint8_t *__restrict__ node,
   for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < nc; k += stride) cell[k] = gp(I.cen[cur])[k];
 }
 
-// the grid's latched error bits as a status code of the public header
-__global__ void k_status(const uint32_t *err, int32_t *status) {
-  if (threadIdx.x == 0) {
-    const uint32_t b = *err;
-    *status = (b & ERRBIT_ARG) ? 1 : ((b & ERRBIT_CFL) ? 3 : ((b & ERRBIT_DOMAIN) ? 4 : 0));
+// latched error bits as status codes of the public header, one per grid
+__global__ void k_status(const uint32_t *err, int32_t *status, uint32_t n) {
+  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+    const uint32_t b = err[k];
+    status[k] = (b & ERRBIT_ARG) ? 1 : ((b & ERRBIT_CFL) ? 3 : ((b & ERRBIT_DOMAIN) ? 4 : 0));
   }
 }
 
@@ -2287,7 +2287,11 @@ hipError_t launch_export_state(const Inst &I, uint32_t cur, uint8_t *node, uint8
 }
 
 hipError_t launch_status(const uint32_t *err, int32_t *status, hipStream_t s) {
-  hipLaunchKernelGGL(k_status, dim3(1), dim3(64), 0, s, err, status);
+  return launch_status_many(err, status, 1u, s);
+}
+
+hipError_t launch_status_many(const uint32_t *err, int32_t *status, uint32_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_status, dim3((n + 255) / 256), dim3(256), 0, s, err, status, n);
   return hipGetLastError();
 }
 

@@ -1217,9 +1217,9 @@ int ebit_pool_create(int max_grids, uint32_t max_tiles, void *ws_dev, size_t ws_
 
 int ebit_pool_admit(ebit_pool *p, const ebit_grid *grid, const ebit_state *init, const double *u_host,
                     const double *v_host, double dt, int *slot_out) {
-  if (!p || !slot_out || !grid_ok(grid) || !u_host || !v_host || !isfinite(dt)) return EBIT_ERR_ARG;
-  int rc = validate_state(grid, init);
-  if (rc) return rc;
+  if (!p || !slot_out || !grid_ok(grid) || !u_host || !v_host || !isfinite(dt) || !init || !init->node_color ||
+      !init->cell_color || !init->hoff || !init->voff)
+    return EBIT_ERR_ARG;
   Engine *e = &p->e;
   int k = -1;
   for (uint32_t s = 0; s < e->maxGrids; s++)
@@ -1248,6 +1248,7 @@ int ebit_pool_admit(ebit_pool *p, const ebit_grid *grid, const ebit_state *init,
   c.off = a0;
   carve_grid(&I, *grid, p->arena, c);
   const size_t nx = grid->nx, ny = grid->ny;
+  const size_t nn = (nx + 1) * (ny + 1), nc = nx * ny, nh = nx * (ny + 1), nv = (nx + 1) * ny;
   double *u = c.take<double>(p->arena, ny * (nx + 1));
   double *v = c.take<double>(p->arena, (ny + 1) * nx);
   double *C = c.take<double>(p->arena, nx * ny);
@@ -1259,14 +1260,33 @@ int ebit_pool_admit(ebit_pool *p, const ebit_grid *grid, const ebit_state *init,
   I.koff = (size_t)(K - base);
   e->grids[k] = *grid;
   p->hdts[k] = dt;
-  {
-    hipError_t err = hipMemcpyAsync(u, u_host, ny * (nx + 1) * sizeof(double), hipMemcpyHostToDevice, e->stream);
-    if (err == hipSuccess)
-      err = hipMemcpyAsync(v, v_host, (ny + 1) * nx * sizeof(double), hipMemcpyHostToDevice, e->stream);
-    if (err == hipSuccess) err = hipMemcpyAsync(p->dts + k, &p->hdts[k], sizeof(double), hipMemcpyHostToDevice, e->stream);
-    if (err != hipSuccess) rc = device_failed(err, "velocity upload", __LINE__);
-  }
-  if (!rc) rc = engine_place(e, (uint32_t)k, init);
+  // Everything is enqueued on the stream, nothing waits: the caller's arrays
+  // go straight to the device (the node bytes into the grid's sweep scratch,
+  // free until its first sweep), and kernels pack the colours, validate the
+  // state (an invalid one latches EBIT_ERR_ARG in the grid's status), fill the
+  // second state copy, set the descriptor, dt and error word, and mark the
+  // grid's tiles.
+  uint8_t *nodeBytes = (uint8_t *)I.dd;
+  uint64_t dtBits;
+  memcpy(&dtBits, &dt, sizeof dtBits);
+  const hipStream_t st = e->stream;
+  int rc = EBIT_OK;
+  hipError_t err = hipMemcpyAsync(u, u_host, nv * sizeof(double), hipMemcpyHostToDevice, st);
+  if (err == hipSuccess) err = hipMemcpyAsync(v, v_host, nh * sizeof(double), hipMemcpyHostToDevice, st);
+  if (err == hipSuccess) err = hipMemcpyAsync(nodeBytes, init->node_color, nn, hipMemcpyHostToDevice, st);
+  if (err == hipSuccess) err = hipMemcpyAsync(I.cen[0], init->cell_color, nc, hipMemcpyHostToDevice, st);
+  if (err == hipSuccess) err = hipMemcpyAsync(I.hoff[0], init->hoff, nh * sizeof(double), hipMemcpyHostToDevice, st);
+  if (err == hipSuccess) err = hipMemcpyAsync(I.voff[0], init->voff, nv * sizeof(double), hipMemcpyHostToDevice, st);
+  if (err != hipSuccess) rc = device_failed(err, "admission upload", __LINE__);
+  if (!rc) err = launch_fill_u32(e->errs + k, 0u, 1, st);
+  if (!rc && err == hipSuccess) err = launch_fill_u32((uint32_t *)(p->dts + k), (uint32_t)dtBits, 1, st);
+  if (!rc && err == hipSuccess) err = launch_fill_u32((uint32_t *)(p->dts + k) + 1, (uint32_t)(dtBits >> 32), 1, st);
+  if (!rc && err == hipSuccess) err = launch_put_inst(I, e->dinst + k, st);
+  if (!rc && err == hipSuccess) err = launch_import_state(I, nodeBytes, I.cen[0], I.hoff[0], I.voff[0], st);
+  if (!rc && err == hipSuccess)
+    err = launch_init_tiles(e->dinst, (uint32_t)k, (uint32_t)(I.ntx * I.nty), e->cur, e->tileInst, e->has,
+                            e->nearPrev, st);
+  if (!rc && err != hipSuccess) rc = device_failed(err, "admission kernels", __LINE__);
   if (rc) {
     p->tileAlloc.give(t0, nt);
     p->arenaAlloc.give(a0, gb);
@@ -1275,6 +1295,12 @@ int ebit_pool_admit(ebit_pool *p, const ebit_grid *grid, const ebit_state *init,
   e->live[k] = 1;
   p->dirty = true;
   *slot_out = k;
+  return EBIT_OK;
+}
+
+int ebit_pool_status(ebit_pool *p, int32_t *status_dev) {
+  if (!p || !status_dev) return EBIT_ERR_ARG;
+  HIPCHK(launch_status_many(p->e.errs, status_dev, p->e.maxGrids, p->e.stream));
   return EBIT_OK;
 }
 

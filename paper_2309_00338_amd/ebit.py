@@ -122,6 +122,7 @@ def _load() -> ctypes.CDLL:
         "ebit_pool_read": [P, i32, vp, vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int)],
         "ebit_pool_get_state": [P, i32, vp, vp, vp, vp],
         "ebit_pool_retire": [P, i32],
+        "ebit_pool_status": [P, vp],
         "ebit_pool_stats": [P, ctypes.POINTER(ebit_counters)],
         "ebit_pool_destroy": [P],
         "ebit_batch_capture": [B, i32, vp, vp, vp, vp, vp, ctypes.POINTER(vp)],
@@ -519,6 +520,8 @@ class EbitPool:
                                        self.stream.cuda_stream, ctypes.byref(handle)), "ebit_pool_create")
         self._h = handle
         self.shapes = {}
+        self.max_grids = max_grids
+        self._inflight = []  # host arrays of admissions the stream may not have read yet
 
     @staticmethod
     def grid_bytes(nx: int, ny: int, h: float):
@@ -527,25 +530,56 @@ class EbitPool:
         _chk(_lib.ebit_pool_grid_bytes(ctypes.byref(g), ctypes.byref(b), ctypes.byref(t)), "ebit_pool_grid_bytes")
         return b.value, t.value
 
-    def admit(self, state: State, u, v, dt: float, flags: int = EBIT_SWEEP_ALTERNATE):
-        """Slot of the admitted grid, or None when the pool is full."""
-        g = ebit_grid(state.nx, state.ny, state.h, flags)
-        s, keep = _host_state(state)
-        u = np.ascontiguousarray(u, np.float64)
-        v = np.ascontiguousarray(v, np.float64)
-        if u.shape != (state.ny, state.nx + 1) or v.shape != (state.ny + 1, state.nx):
-            raise ValueError("u, v shapes do not match the grid")
+    def admit(self, state, u, v, dt: float, flags: int = EBIT_SWEEP_ALTERNATE):
+        """Slot of the admitted grid, or None when the pool is full. The state
+        arrays (a State, or a dict with nx, ny, h, c, cc, hoff, voff) and u, v
+        may be numpy arrays or CPU torch tensors (pinned ones keep the upload
+        asynchronous); they are referenced here until the stream has passed
+        the admission (a later read() or sync())."""
+        get = (lambda k: state[k]) if isinstance(state, dict) else (lambda k: getattr(state, k))
+        nx, ny, h = int(get("nx")), int(get("ny")), float(get("h"))
+        arrs = {}
+        want = {"c": ((ny + 1, nx + 1), np.uint8), "cc": ((ny, nx), np.uint8), "hoff": ((ny + 1, nx), np.float64),
+                "voff": ((ny, nx + 1), np.float64), "u": ((ny, nx + 1), np.float64), "v": ((ny + 1, nx), np.float64)}
+        src = {"c": get("c"), "cc": get("cc"), "hoff": get("hoff"), "voff": get("voff"), "u": u, "v": v}
+        ptrs = {}
+        for k, (shape, dt_) in want.items():
+            a = src[k]
+            if isinstance(a, self.torch.Tensor):
+                if a.is_cuda or tuple(a.shape) != shape or not a.is_contiguous() or \
+                        a.dtype != {np.uint8: self.torch.uint8, np.float64: self.torch.float64}[dt_]:
+                    raise ValueError(f"{k}: a contiguous CPU tensor of shape {shape} and dtype {dt_} is required")
+                ptrs[k] = a.data_ptr()
+            else:
+                a = np.ascontiguousarray(a, dt_)
+                if a.shape != shape:
+                    raise ValueError(f"{k}: shape {a.shape}, expected {shape}")
+                ptrs[k] = a.ctypes.data
+            arrs[k] = a
+        g = ebit_grid(nx, ny, h, flags)
+        s = ebit_state(ptrs["c"], ptrs["cc"], ptrs["hoff"], ptrs["voff"])
         slot = ctypes.c_int(-1)
-        rc = _lib.ebit_pool_admit(self._h, ctypes.byref(g), ctypes.byref(s), u.ctypes.data, v.ctypes.data,
-                                  float(dt), ctypes.byref(slot))
+        rc = _lib.ebit_pool_admit(self._h, ctypes.byref(g), ctypes.byref(s), ptrs["u"], ptrs["v"], float(dt),
+                                  ctypes.byref(slot))
         if rc == EBIT_ERR_NOMEM:
             return None
         _chk(rc, "ebit_pool_admit")
-        self.shapes[slot.value] = (state.nx, state.ny, state.h)
+        self.shapes[slot.value] = (nx, ny, h)
+        self._inflight.append(arrs)
         return slot.value
 
     def step(self):
         _chk(_lib.ebit_pool_step(self._h), "ebit_pool_step")
+
+    def status(self, out=None):
+        """Every slot's status into a device int32 tensor (asynchronous)."""
+        out = self.torch.empty(self.max_grids, dtype=self.torch.int32, device=self.device) if out is None else out
+        _chk(_lib.ebit_pool_status(self._h, out.data_ptr()), "ebit_pool_status")
+        return out
+
+    def sync(self):
+        self.stream.synchronize()
+        self._inflight = []
 
     def read(self, slot: int, fields: bool = True):
         nx, ny, _ = self.shapes[slot]
@@ -554,6 +588,7 @@ class EbitPool:
         steps, status = ctypes.c_int64(0), ctypes.c_int(0)
         _chk(_lib.ebit_pool_read(self._h, slot, C.ctypes.data if fields else None, K.ctypes.data if fields else None,
                                  ctypes.byref(steps), ctypes.byref(status)), "ebit_pool_read")
+        self._inflight = []  # the read waited on the stream
         return C, K, int(steps.value), int(status.value)
 
     def get_state(self, slot: int) -> State:

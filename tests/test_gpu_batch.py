@@ -307,3 +307,50 @@ def test_graph_replay_matches_eager_steps_and_oracle(which):
     assert e.value.code == ebit.EBIT_ERR_STATE
     graph.close()
     graphed.close()
+
+
+def test_pool_isolates_failing_requests():
+    """Four requests share a pool: one whose dt moves its markers more than half
+    a cell per sweep (a CFL error) and one admitted with an invalid state (an
+    offset outside [0, 1] on a marker edge, found by the device-side
+    validation of the asynchronous admission). The bulk status call reports
+    CFL and ARG for exactly those slots; they are evicted, and the other two
+    requests, stepped on in the same pool, stay equal to their oracle runs
+    every step."""
+    import torch
+
+    pool = ebit.EbitPool(max_grids=4, max_tiles=128, arena_bytes=128 << 20)
+    good = {}
+    st, u, v, dt = _pool_instance(48, 3, 21)
+    good[pool.admit(st, u, v, dt)] = _Ref(st, u, v, dt)
+    st, u, v, dt = _pool_instance(40, 2, 22)
+    cfl = pool.admit(st, u, v, 4.0 * dt)
+    st, u, v, dt = _pool_instance(36, 2, 23)
+    good[pool.admit(st, u, v, dt)] = _Ref(st, u, v, dt)
+    st, u, v, dt = _pool_instance(30, 2, 24)
+    jj, ii = np.nonzero(st.h_present())
+    bad = st.copy()
+    bad.hoff[jj[0], ii[0]] = 1.5
+    arg = pool.admit(bad, u, v, dt)
+    pool.step()
+    status = pool.status().cpu().numpy()
+    assert status[cfl] == ebit.EBIT_ERR_CFL and status[arg] == ebit.EBIT_ERR_ARG, status
+    assert all(status[s] == 0 for s in good), status
+    pool.retire(cfl)
+    pool.retire(arg)
+    ocnt = oracle.new_counters()
+    for r in good.values():
+        r.step(ocnt)
+    for k in range(5):
+        if k:
+            pool.step()
+            for r in good.values():
+                r.step(ocnt)
+        for s, r in good.items():
+            C, K, steps, status = pool.read(s)
+            assert status == 0 and steps == r.o.step
+            compare_state(pool.get_state(s), r.o, f"step {k} slot {s}")
+            Co = oracle.fraction(r.o)
+            Ko, _ = oracle.curvature(r.o, Co)
+            compare_fields(C, K, Co, Ko, r.o.nx, r.o.h, f"step {k} slot {s}")
+    torch.cuda.synchronize()
