@@ -98,3 +98,32 @@ def test_config5_served_request_sizes():
         Co = oracle.fraction(o)
         Ko, _ = oracle.curvature(o, Co)
         compare_fields(C, K, Co, Ko, o.nx, o.h, f"slot {s}")
+
+
+def _progress(msg):
+    """Progress of the long trajectory, flushed to a file under gpurun_out/
+    (pytest holds stdout until the test ends)."""
+    import os
+
+    os.makedirs("gpurun_out", exist_ok=True)
+    with open(os.path.join("gpurun_out", "full_trajectory_progress.log"), "a") as f:
+        f.write(msg + "\n")
+    print(msg, flush=True)
+
+
+def test_config3a_merging_pairs_4096_full_trajectory():
+    """Config 3a at full size for its whole 128-step trajectory (pairs merge in
+    the first steps, then the merged bodies are squeezed and annihilated at the
+    midlines): states against the oracle every 8 steps, C and kappa every 32,
+    counters at the end, with annihilations."""
+    w = I.merging_pairs(n=4096, pairs=500, nsteps=128)
+    ls = Lockstep(w.state, w.u, w.v)
+    for k in range(128):
+        last = k == 127
+        ls.step(w.dts[k], check_state=(k % 8 == 7 or last), check_fields=(k % 32 == 31 or last),
+                where=f"3a step {k}")
+        if k % 8 == 7:
+            _progress(f"[full] 3a step {k} ok {ls.worst}")
+    cnt = ls.compare_counters()
+    assert cnt["annihilated"] > 0 and cnt["markers"] > 0, cnt
+    _progress(f"[full] 3a 128 steps ok: {cnt}")
