@@ -52,6 +52,10 @@ def _load():
         for f in (lib.or_sweep, lib.or_step, lib.or_fraction, lib.or_curvature, lib.or_ns_fields,
                   lib.or_parabola_fit):
             f.restype = ctypes.c_int
+        lib.or_tie_log.argtypes = [ctypes.POINTER(ctypes.c_int32), ctypes.c_int64]
+        lib.or_tie_log.restype = None
+        lib.or_tie_count.argtypes = []
+        lib.or_tie_count.restype = ctypes.c_int64
         assert lib.or_counter_count() == len(COUNTERS)
         _lib = lib
     return _lib
@@ -77,28 +81,67 @@ def counters_dict(arr):
     return {k: int(v) for k, v in zip(COUNTERS, arr)}
 
 
-def sweep(st, u, v, dt, direction, counters=None, line=False):
+TIE_KINDS = {1: "landed offset at a node", 2: "crossing endpoint on the line", 3: "equal crossing heights",
+             4: "root on the chord", 5: "new offset at a node"}
+
+
+class _TieLog:
+    """Collects the oracle's tie locations during one call, as dicts with the
+    kind, the sweep direction and the edge in grid coordinates: ("H", i, j) or
+    ("V", i, j). Kind 1 concerns the sweep's aligned edge, kinds 2-5 its new
+    unaligned edge."""
+
+    def __init__(self, out, cap=1 << 16):
+        self.out, self.cap = out, cap
+
+    def __enter__(self):
+        if self.out is not None:
+            self.buf = np.zeros(4 * self.cap, np.int32)
+            _load().or_tie_log(self.buf.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), self.cap)
+        return self
+
+    def __exit__(self, *exc):
+        if self.out is None:
+            return False
+        lib = _load()
+        n = min(int(lib.or_tie_count()), self.cap)
+        lib.or_tie_log(None, 0)
+        for k in range(n):
+            kind, d, a, b = (int(x) for x in self.buf[4 * k:4 * k + 4])
+            aligned = kind == 1
+            if d == 0:
+                edge = ("H", a, b) if aligned else ("V", a, b)
+            else:
+                edge = ("V", b, a) if aligned else ("H", b, a)
+            self.out.append({"kind": kind, "what": TIE_KINDS[kind], "dir": d, "edge": edge})
+        return False
+
+
+def sweep(st, u, v, dt, direction, counters=None, line=False, ties=None):
     """One 1D sweep in place (direction 0 = x with u, 1 = y with v); line:
     EBIT-SL placement of the new unaligned markers instead of the circle fit."""
     _check(st)
     cnt = new_counters() if counters is None else counters
     u = np.ascontiguousarray(u, np.float64)
     v = np.ascontiguousarray(v, np.float64)
-    rc = _load().or_sweep(st.nx, st.ny, st.h, _p(st.c, _u8p), _p(st.cc, _u8p), _p(st.hoff, _f64p),
-                          _p(st.voff, _f64p), _p(u, _f64p), _p(v, _f64p), float(dt), int(direction),
-                          2 if line else 0, _p(cnt, _i64p))
+    with _TieLog(ties):
+        rc = _load().or_sweep(st.nx, st.ny, st.h, _p(st.c, _u8p), _p(st.cc, _u8p), _p(st.hoff, _f64p),
+                              _p(st.voff, _f64p), _p(u, _f64p), _p(v, _f64p), float(dt), int(direction),
+                              2 if line else 0, _p(cnt, _i64p))
     return rc, cnt
 
 
-def step(st, u, v, dt, xy_only=False, counters=None, line=False):
-    """One time step (two sweeps) in place; advances st.step. line: EBIT-SL."""
+def step(st, u, v, dt, xy_only=False, counters=None, line=False, ties=None):
+    """One time step (two sweeps) in place; advances st.step. line: EBIT-SL.
+    ties: a list that receives the locations of the step's ties."""
     _check(st)
     cnt = new_counters() if counters is None else counters
     u = np.ascontiguousarray(u, np.float64)
     v = np.ascontiguousarray(v, np.float64)
-    rc = _load().or_step(st.nx, st.ny, st.h, _p(st.c, _u8p), _p(st.cc, _u8p), _p(st.hoff, _f64p),
-                         _p(st.voff, _f64p), _p(u, _f64p), _p(v, _f64p), float(dt), int(st.step),
-                         (1 if xy_only else 0) | (2 if line else 0), _p(cnt, _i64p))
+    with _TieLog(ties):
+        rc = _load().or_step(st.nx, st.ny, st.h, _p(st.c, _u8p), _p(st.cc, _u8p), _p(st.hoff, _f64p),
+                             _p(st.voff, _f64p), _p(u, _f64p), _p(v, _f64p), float(dt), int(st.step),
+                             (1 if xy_only else 0) | (2 if line else 0), _p(cnt, _i64p))
     st.step += 1
     return rc, cnt
 

@@ -70,6 +70,42 @@ enum {
 };
 
 /* ------------------------------------------------------------------------- */
+/* Optional log of where ties happen (a decision within 1e-12 of degenerate:   */
+/* a landed or new offset at a node, a crossing endpoint on the line, two      */
+/* equal crossing heights, a root on the chord). Each entry is four int32:     */
+/* kind, sweep direction, and the edge in the sweep frame (a along the sweep,  */
+/* b across it): kind 1 the aligned edge (a, b), kinds 2-5 the new unaligned   */
+/* edge on line a, row b. The oracle is single-threaded; the log is a static. */
+/* ------------------------------------------------------------------------- */
+enum { TIE_LANDED = 1, TIE_ENDPOINT = 2, TIE_HEIGHTS = 3, TIE_ROOT_SIDE = 4, TIE_NEW_OFFSET = 5 };
+static int32_t *g_tie_log = NULL;
+static int64_t g_tie_cap = 0, g_tie_n = 0;
+static int g_tie_dir = 0, g_tie_a = 0, g_tie_b = 0;
+
+static void note_tie(int64_t *st, int kind, int a, int b) {
+  st[S_TIES]++;
+  if (g_tie_log && g_tie_n < g_tie_cap) {
+    int32_t *e = g_tie_log + 4 * g_tie_n;
+    e[0] = kind;
+    e[1] = g_tie_dir;
+    e[2] = a;
+    e[3] = b;
+  }
+  g_tie_n++;
+}
+
+/* Start logging into buf (cap entries of four int32; NULL stops logging) and
+ * clear the count. */
+void or_tie_log(int32_t *buf, int64_t cap) {
+  g_tie_log = buf;
+  g_tie_cap = buf ? cap : 0;
+  g_tie_n = 0;
+}
+
+/* Ties seen since or_tie_log (may exceed the capacity; only cap are kept). */
+int64_t or_tie_count(void) { return g_tie_n; }
+
+/* ------------------------------------------------------------------------- */
 /* The sweep frame: "a" runs along the sweep, "b" across it. For the x sweep   */
 /* (a,b) = (i,j); for the y sweep the arrays are transposed first.            */
 /* ------------------------------------------------------------------------- */
@@ -259,7 +295,7 @@ static int circle_root(double Xa, double Ya, double Xb, double Yb, double Xc, do
     double so = DX * (Yo - Y2) - DY * (Xo - X2);
     double s1 = DX * (r1 - Y2) - DY * (0.0 - X2);
     double s2 = DX * (r2 - Y2) - DY * (0.0 - X2);
-    if (fabs(s1) < TIE_EPS * L2 || fabs(s2) < TIE_EPS * L2) st[S_TIES]++;
+    if (fabs(s1) < TIE_EPS * L2 || fabs(s2) < TIE_EPS * L2) note_tie(st, TIE_ROOT_SIDE, g_tie_a, g_tie_b);
     int q1 = (s1 > 0.0 && so < 0.0) || (s1 < 0.0 && so > 0.0);
     int q2 = (s2 > 0.0 && so < 0.0) || (s2 < 0.0 && so > 0.0);
     if (q1 && !q2) r = r1;
@@ -385,7 +421,7 @@ static int sweep_frame(const frame *F, uint8_t *ncol_out, uint8_t *ncen, double 
         double sp = W.sp[ALE(F, keep, b)];
         double o = keep < a ? sp - 1.0 : (keep > a ? sp + 1.0 : sp);
         nal[ALE(F, a, b)] = o;
-        if (o < TIE_EPS || 1.0 - o < TIE_EPS) st[S_TIES]++;
+        if (o < TIE_EPS || 1.0 - o < TIE_EPS) note_tie(st, TIE_LANDED, a, b);
       }
     }
 
@@ -434,7 +470,7 @@ static int sweep_frame(const frame *F, uint8_t *ncol_out, uint8_t *ncen, double 
         }
         for (int x = 0; x < 3; x++)
           for (int y = x + 1; y < 3; y++)
-            if (fabs(ysl[x] - ysl[y]) < TIE_EPS) st[S_TIES]++;
+            if (fabs(ysl[x] - ysl[y]) < TIE_EPS) note_tie(st, TIE_HEIGHTS, a, b);
       }
       if (pick < 0) { /* reading: colours decide presence; place mid-edge */
         st[S_PARITY_FALLBACK]++;
@@ -442,7 +478,9 @@ static int sweep_frame(const frame *F, uint8_t *ncol_out, uint8_t *ncen, double 
         continue;
       }
       double X2 = X2v[pick], Y2 = Y2v[pick], X3 = X3v[pick], Y3 = Y3v[pick];
-      if (fabs(X2) < TIE_EPS || fabs(X3) < TIE_EPS) st[S_TIES]++;
+      if (fabs(X2) < TIE_EPS || fabs(X3) < TIE_EPS) note_tie(st, TIE_ENDPOINT, a, b);
+      g_tie_a = a; /* where a root-side tie inside the circle fit belongs */
+      g_tie_b = b;
       int p = cp[pick];
       mref m2 = edge_marker(p, b, cl[pick]), m3 = edge_marker(p, b, cr[pick]), m1, m4;
       int h1 = chain_neighbour(F, &W, p, b, cl[pick], &m1);
@@ -475,7 +513,7 @@ static int sweep_frame(const frame *F, uint8_t *ncol_out, uint8_t *ncen, double 
         }
       }
       nun[UNE(F, a, b)] = y;
-      if (y < TIE_EPS || 1.0 - y < TIE_EPS) st[S_TIES]++;
+      if (y < TIE_EPS || 1.0 - y < TIE_EPS) note_tie(st, TIE_NEW_OFFSET, a, b);
       size_t z = UNE(F, a, b);
       W.zhas[z] = 1;
       W.zP1[z] = m1;
@@ -574,6 +612,7 @@ int or_sweep(int nx, int ny, double h, uint8_t *c, uint8_t *cc, double *hoff, do
   const size_t n_h = (size_t)nx * (ny + 1), n_v = (size_t)(nx + 1) * ny;
   double lam = dt / h;
   int rc;
+  g_tie_dir = dir;
   if (dir == 0) {
     frame F = {nx, ny, c, cc, hoff, voff, u, lam, (flags >> 1) & 1};
     uint8_t *nc = malloc(n_nodes), *ncc = malloc(n_cells);

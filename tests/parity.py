@@ -3,6 +3,10 @@
 Contract: corner and centre colours (hence marker presence) bit-exact; marker
 offsets within 1e-12 cell widths; C within 1e-12 absolute; curvature within
 1e-10 * max(|kappa_oracle|, 1/(N h)) with NaN in the same cells; counters equal.
+A state mismatch that lies within 2.5 cells of a tie the oracle logged since
+the last comparison (a decision within 1e-12 of degenerate, where rounding may
+legitimately go either way) is recorded in `resyncs` and the GPU state is
+re-set from the oracle's; any other mismatch fails.
 """
 import numpy as np
 
@@ -44,6 +48,25 @@ def compare_fields(Cg, Kg, Co, Ko, n, h, where=""):
     return float(dc.max(initial=0)), float(dk.max(initial=0))
 
 
+def mismatch_points(g, o):
+    """Index-space points of every state difference (nodes, cell centres, edge
+    midpoints of offsets beyond the tolerance)."""
+    pts = [(float(i), float(j)) for j, i in np.argwhere(g.c != o.c)]
+    pts += [(i + 0.5, j + 0.5) for j, i in np.argwhere(g.cc != o.cc)]
+    pts += [(i + 0.5, float(j)) for j, i in np.argwhere((np.abs(g.hoff - o.hoff) > OFF_TOL) & o.h_present())]
+    pts += [(float(i), j + 0.5) for j, i in np.argwhere((np.abs(g.voff - o.voff) > OFF_TOL) & o.v_present())]
+    return pts
+
+
+def tie_points(ties):
+    return [(i + 0.5, float(j)) if kind == "H" else (float(i), j + 0.5) for kind, i, j in (t["edge"] for t in ties)]
+
+
+def all_near_ties(points, ties, radius=2.5):
+    tp = tie_points(ties)
+    return bool(points) and all(any(max(abs(x - a), abs(y - b)) <= radius for a, b in tp) for x, y in points)
+
+
 class Lockstep:
     """Runs the GPU library and the oracle side by side on one workload."""
 
@@ -61,16 +84,33 @@ class Lockstep:
         self.xy_only = bool(flags & 1)
         self.line = bool(flags & 2)
         self.ocnt = oracle.new_counters()
+        self.obase = oracle.new_counters()  # oracle counts at the last resync (the GPU's restart from zero)
         self.worst = {"off": 0.0, "C": 0.0, "K": 0.0}
+        self.ties = []  # tie locations since the last state comparison
+        self.resyncs = []
 
-    def step(self, dt, check_state=True, check_fields=True, where=""):
+    def step(self, dt, check_state=True, check_fields=True, where="", plant=None):
+        """One step on both sides. plant(o, ties), if given, edits the oracle's
+        state after its step (tests of the harness itself)."""
         self.g.advect(self.u, self.v, dt)
-        rc, _ = oracle.step(self.o, self.u_h, self.v_h, dt, xy_only=self.xy_only, counters=self.ocnt, line=self.line)
+        rc, _ = oracle.step(self.o, self.u_h, self.v_h, dt, xy_only=self.xy_only, counters=self.ocnt, line=self.line,
+                            ties=self.ties)
         assert rc == oracle.OK, f"{where}: oracle rc {rc}"
+        if plant is not None:
+            plant(self.o, self.ties)
         if check_state:
             gs = self.g.get_state()
             assert gs.step == self.o.step
-            self.worst["off"] = max(self.worst["off"], compare_state(gs, self.o, where))
+            try:
+                self.worst["off"] = max(self.worst["off"], compare_state(gs, self.o, where))
+            except AssertionError:
+                bad = mismatch_points(gs, self.o)
+                if not all_near_ties(bad, self.ties):
+                    raise
+                self.resyncs.append({"where": where, "mismatches": len(bad), "ties": len(self.ties)})
+                self.g.set_state(self.o)
+                self.obase = self.ocnt.copy()
+            self.ties = []
         if check_fields:
             self.fields(where)
 
@@ -87,6 +127,6 @@ class Lockstep:
         from paper_2309_00338_amd import ebit
 
         gc = {k: v for k, v in self.g.stats().items() if k not in ebit.SCHEDULE_COUNTERS}
-        oc = oracle.counters_dict(self.ocnt)
+        oc = oracle.counters_dict(self.ocnt - self.obase)
         assert gc == oc, {k: (gc[k], oc[k]) for k in gc if gc[k] != oc[k]}
         return gc

@@ -8,7 +8,7 @@ import pytest
 
 import oracle
 from paper_2309_00338_amd import inputs as I
-from tests.parity import Lockstep, compare_fields, compare_state
+from tests.parity import Lockstep, compare_fields, compare_state, tie_points
 
 pytestmark = pytest.mark.gpu
 
@@ -351,3 +351,44 @@ def test_wall_markers_hold_under_wall_normal_motion():
     ls.fields("initial")
     cnt = _run(ls, [dt] * 8)
     assert cnt["wall_violation"] >= 16, cnt
+
+
+def test_mismatch_at_a_tie_resyncs_and_elsewhere_fails():
+    """The harness's tie rule, exercised by editing the oracle's state after its
+    step (on the CPU): an offset difference on an edge where the oracle logged a
+    tie is recorded and the GPU is re-set from the oracle, after which both
+    sides agree again; the same difference far from every tie fails."""
+    w = I.merging_pairs(n=256, pairs=12, rmin=6.0, rmax=14.0, nsteps=40)
+    ls = Lockstep(w.state, w.u, w.v)
+    planted = []
+
+    def at_tie(o, ties):
+        if planted or not ties:
+            return
+        kind, i, j = ties[0]["edge"]
+        if kind == "H" and o.h_present()[j, i]:
+            o.hoff[j, i] = min(1.0, o.hoff[j, i] + 1e-9)
+            planted.append((kind, i, j))
+        elif kind == "V" and o.v_present()[j, i]:
+            o.voff[j, i] = min(1.0, o.voff[j, i] + 1e-9)
+            planted.append((kind, i, j))
+
+    for k in range(40):
+        ls.step(w.dts[k], check_fields=(k % 4 == 3), where=f"step {k}", plant=at_tie)
+        if planted and k > 8:
+            break
+    assert planted and len(ls.resyncs) == 1, (planted, ls.resyncs)
+    ls.compare_counters()
+
+    ls2 = Lockstep(w.state, w.u, w.v)
+
+    def far(o, ties):
+        tp = tie_points(ties)
+        jj, ii = np.nonzero(o.h_present())
+        for j, i in zip(jj, ii):
+            if all(max(abs(i + 0.5 - a), abs(j - b)) > 10 for a, b in tp):
+                o.hoff[j, i] = min(1.0, o.hoff[j, i] + 1e-9) if o.hoff[j, i] < 0.5 else o.hoff[j, i] - 1e-9
+                return
+
+    with pytest.raises(AssertionError):
+        ls2.step(w.dts[0], plant=far)

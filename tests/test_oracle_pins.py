@@ -802,3 +802,23 @@ def test_midpoint_time_factor_sums_to_zero_and_reverses_closer():
             assert oracle.step(st, w.u, w.v, d)[0] == oracle.OK
         shape[name] = e_shape(st, 0.5 * n, 0.75 * n, 0.15 * n)
     assert shape["mid"] < shape["start"]
+
+
+def test_tie_locations_are_logged_where_they_happen():
+    """Ties (Sec. 2.4 and 2.2 decisions within 1e-12 of degenerate) are counted
+    and located: a circle translated by exactly a quarter cell per sweep lands
+    markers exactly on nodes; every logged tie names an edge of the grid, the
+    log has as many entries as the counter, and some are landed offsets at a
+    node."""
+    st = I.init_state(48, 48, [I.Circle(24.0, 24.0, 10.0)], h=1.0 / 48)
+    u, v, dt = _uniform(st, 0.25, 0.25)
+    cnt = oracle.new_counters()
+    ties = []
+    for k in range(4):
+        assert oracle.step(st, u, v, dt, counters=cnt, ties=ties)[0] == oracle.OK
+    assert len(ties) == oracle.counters_dict(cnt)["ties"] > 0
+    for t in ties:
+        kind, i, j = t["edge"]
+        assert (kind == "H" and 0 <= i < 48 and 0 <= j <= 48) or (kind == "V" and 0 <= i <= 48 and 0 <= j < 48)
+    landed = [t for t in ties if t["kind"] == 1]
+    assert landed
