@@ -2,6 +2,8 @@
 benchmark times (same library calls, same tiles and persistent grids): two
 steps of each large workload, every node, edge, centre colour, C and kappa
 compared with the oracle."""
+import os
+
 import pytest
 
 from paper_2309_00338_amd import inputs as I
@@ -111,19 +113,48 @@ def _progress(msg):
     print(msg, flush=True)
 
 
+def _trajectory(w, nsteps, state_every, field_every, tag):
+    """The whole trajectory of workload w on both sides: states compared every
+    state_every steps, C and kappa every field_every, both at the last step,
+    counters at the end."""
+    ls = Lockstep(w.state, w.u, w.v)
+    for k in range(nsteps):
+        last = k == nsteps - 1
+        ls.step(w.dts[k], check_state=(k % state_every == state_every - 1 or last),
+                check_fields=(k % field_every == field_every - 1 or last), where=f"{tag} step {k}")
+        if k % state_every == state_every - 1:
+            _progress(f"[full] {tag} step {k} ok {ls.worst}")
+    cnt = ls.compare_counters()
+    _progress(f"[full] {tag} {nsteps} steps ok: {cnt} resyncs {ls.resyncs}")
+    return cnt
+
+
 def test_config3a_merging_pairs_4096_full_trajectory():
     """Config 3a at full size for its whole 128-step trajectory (pairs merge in
     the first steps, then the merged bodies are squeezed and annihilated at the
     midlines): states against the oracle every 8 steps, C and kappa every 32,
     counters at the end, with annihilations."""
-    w = I.merging_pairs(n=4096, pairs=500, nsteps=128)
-    ls = Lockstep(w.state, w.u, w.v)
-    for k in range(128):
-        last = k == 127
-        ls.step(w.dts[k], check_state=(k % 8 == 7 or last), check_fields=(k % 32 == 31 or last),
-                where=f"3a step {k}")
-        if k % 8 == 7:
-            _progress(f"[full] 3a step {k} ok {ls.worst}")
-    cnt = ls.compare_counters()
+    cnt = _trajectory(I.merging_pairs(n=4096, pairs=500, nsteps=128), 128, 8, 32, "3a")
     assert cnt["annihilated"] > 0 and cnt["markers"] > 0, cnt
-    _progress(f"[full] 3a 128 steps ok: {cnt}")
+
+
+# The two longest trajectories take the oracle several minutes each (about 7 s
+# per step at 8192^2), so they run when asked for.
+_long = pytest.mark.skipif(not os.environ.get("EBIT_LONG_PARITY"),
+                           reason="long trajectory (minutes of oracle time): set EBIT_LONG_PARITY=1")
+
+
+@_long
+def test_config2_large_grid_8192_full_trajectory():
+    """Config 2 at full size (8192^2, 2000 circles in the vortex) for its whole
+    64-step trajectory: states every 8 steps, C and kappa every 16."""
+    cnt = _trajectory(I.many_circles(n=8192, count=2000, nsteps=64), 64, 8, 16, "2")
+    assert cnt["markers"] > 0 and cnt["ghf_fit"] > 0, cnt
+
+
+@_long
+def test_config3b_cosine_4096_full_trajectory():
+    """Config 3b at full size (one cosine interface across 4096^2) for its
+    whole 128-step trajectory: states every 8 steps, C and kappa every 32."""
+    cnt = _trajectory(I.cosine_interface(n=4096, nsteps=128), 128, 8, 32, "3b")
+    assert cnt["markers"] > 0, cnt
