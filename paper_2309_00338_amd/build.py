@@ -13,7 +13,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT_DIR, "libebit.so")
-SOURCES = [os.path.join(CSRC, f) for f in ("ebit_kernels.hip", "ebit_runtime.hip")]
+SOURCES = [os.path.join(CSRC, f) for f in ("ebit_kernels.hip", "ebit_runtime.hip", "ebit_film.hip")]
 ARCH = "gfx950"
 
 FLAGS = [
