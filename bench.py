@@ -18,9 +18,12 @@ The same line carries the rest of the metric:
   served: a Poisson stream of requests (200/s, N log-uniform in [128, 2048],
       steady random fields, 16-256 steps each) through the pool, with
       arrival-to-result latency percentiles, against a plain per-request loop;
+  film: the two-markers-per-edge step on the topology-change workload (500
+      merging circle pairs on 4096^2, rupture gap 0.05 cells) against the
+      one-marker step on the same grid and flow;
   cpu_baseline: the CPU oracle timed on a bounded sample of the headline grid.
 
---workload single|batched|served runs one part alone (its own JSON line).
+--workload single|batched|served|film runs one part alone (its own JSON line).
 """
 import argparse
 import collections
@@ -231,6 +234,86 @@ def run_single(args):
         log("[bench] timing the CPU oracle on two steps of the same grid")
         out["cpu_baseline"] = cpu_baseline(w, 2)
     return out
+
+
+# ---------------------------------------------------------------------------
+# two markers per edge
+# ---------------------------------------------------------------------------
+def film_state_bytes(nx, ny):
+    """Bytes of one dense copy of the two-marker state: node and centre colours
+    (1 B each), and per H and V edge a count (1 B) and an offset pair (16 B)."""
+    nodes, cells, edges = (nx + 1) * (ny + 1), nx * ny, (ny + 1) * nx + ny * (nx + 1)
+    return {"write": nodes + cells + 17 * edges, "read_dense": nodes + cells + edges, "cells": cells}
+
+
+def run_film(args):
+    """The two-markers-per-edge step (include/ebit_film.h) on the topology-change
+    workload: 500 circle pairs driven into each other on 4096^2, rupture gap
+    delta = 0.05 cells, so the meeting walls form films that thin and rupture.
+    Timed with events on the handle's stream (advect + fraction per step),
+    beside the one-marker step (advect + fraction) on the same grid and flow."""
+    import torch
+
+    from paper_2309_00338_amd import ebit, film
+    from paper_2309_00338_amd import inputs as I
+
+    n, steps, warmup = args.film_n, args.film_steps, 2
+    t0 = time.perf_counter()
+    w = I.merging_pairs(n=n, pairs=args.film_pairs, nsteps=warmup + steps)
+    fs = film.FilmState.of(w.state)
+    log(f"[bench] film: {w.meta['pairs']} pairs on {n}^2 generated in {time.perf_counter() - t0:.1f}s")
+    dev = torch.device("cuda:0")
+    u = torch.from_numpy(w.u).to(dev)
+    v = torch.from_numpy(w.v).to(dev)
+    C = torch.empty((n, n), dtype=torch.float64, device=dev)
+
+    def timed(stream, adv, frac):
+        for k in range(warmup):
+            adv(w.dts[k])
+            frac()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for k in range(steps):
+            adv(w.dts[warmup + k])
+            frac()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e3 / steps
+
+    f = film.EbitFilm(fs, delta=args.film_delta, device=dev)
+    film_us = timed(f.stream, lambda dt: f.advect(u, v, dt), lambda: f.fraction(C))
+    assert f.sync() == 0
+    fst = f.stats()
+    f.close()
+    del f
+    torch.cuda.empty_cache()
+    g = ebit.EbitGrid(w.state, device=dev)
+    one_us = timed(g.stream, lambda dt: g.advect(u, v, dt), lambda: g.fraction(C))
+    g.sync()
+    g.close()
+    del g
+    torch.cuda.empty_cache()
+    sb = film_state_bytes(n, n)
+    # per sweep: the new copy written in full, the old colours and counts read in
+    # full (offsets and velocities only at markers: not counted); the fraction
+    # reads the colours and counts and writes C
+    step_bytes = 2 * (sb["write"] + sb["read_dense"]) + sb["read_dense"] + 8 * sb["cells"]
+    cells = sb["cells"]
+    log(f"[bench] film: {film_us:.1f} us/step (one marker per edge: {one_us:.1f})")
+    return {
+        "workload": f"two markers per edge: merging pairs {n}x{n} FP64, {w.meta['pairs']} pairs R~U[8,24] cells, "
+                    f"gap U[0.5,2], u=+-0.5 per pair plus shear, CFL 0.5, rupture gap {args.film_delta:g} cells",
+        "grid": [n, n], "steps": steps, "warmup": warmup, "delta": args.film_delta,
+        "us_per_step": film_us, "cell_steps_per_s": cells / (film_us * 1e-6),
+        "roofline": {"bound": "hbm", "kernel": "whole film step (10 sweep passes + fraction), dense state",
+                     "achieved": step_bytes / (film_us * 1e-6) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": step_bytes / (film_us * 1e-6) / 1e9 / HBM_PEAK_GBS,
+                     "alg_bytes_per_step": step_bytes},
+        "one_marker": {"us_per_step": one_us, "cell_steps_per_s": cells / (one_us * 1e-6),
+                       "what": "ebit_advect + ebit_fraction on the same grid and flow (tiled one-marker step)"},
+        "counters": fst,
+    }
 
 
 # ---------------------------------------------------------------------------
@@ -535,13 +618,17 @@ def main():
     ap.add_argument("--circles", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="keep the device-default launch schedule")
-    ap.add_argument("--workload", choices=("all", "single", "batched", "served"), default="all")
+    ap.add_argument("--workload", choices=("all", "single", "batched", "served", "film"), default="all")
     ap.add_argument("--grids", type=int, default=256, help="batched: number of grids")
     ap.add_argument("--batched-steps", type=int, default=8, help="batched: timed steps inside the full line")
     ap.add_argument("--served-seconds", type=float, default=1.5, help="served: seconds of arrivals")
     ap.add_argument("--plain-requests", type=int, default=60, help="served: requests of the plain loop")
     ap.add_argument("--rate", type=float, default=200.0, help="served: arrivals per second")
     ap.add_argument("--pool-tiles", type=int, default=1 << 18, help="served: tile capacity of the pool")
+    ap.add_argument("--film-n", type=int, default=4096, help="film: grid size")
+    ap.add_argument("--film-pairs", type=int, default=500, help="film: circle pairs")
+    ap.add_argument("--film-steps", type=int, default=8, help="film: timed steps")
+    ap.add_argument("--film-delta", type=float, default=0.05, help="film: rupture gap in cells")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized device buffer 5 times (a plain copy kernel of known size, "
                          "the reference for scaling hardware byte counters), then exit")
@@ -573,6 +660,11 @@ def main():
         print(json.dumps(line("batched", d, d["steps"], args.warmup, d["graph"]["us_per_step"] * 1e-3,
                               d["graph"]["cell_steps_per_s"])), flush=True)
         return
+    if args.workload == "film":
+        d = run_film(args)
+        print(json.dumps(line("film", d, d["steps"], d["warmup"], d["us_per_step"] * 1e-3, d["cell_steps_per_s"])),
+              flush=True)
+        return
     reqs = generate_requests(args, args.served_seconds) if args.workload in ("all", "served") else None
     if args.workload == "served":
         d = run_served(args, args.served_seconds, args.plain_requests, reqs)
@@ -583,6 +675,7 @@ def main():
     if args.workload == "all":
         out["batched"] = run_batched(args, args.batched_steps, 2)
         out["served"] = run_served(args, args.served_seconds, args.plain_requests, reqs)
+        out["film"] = run_film(args)
     print(json.dumps(out), flush=True)
 
 

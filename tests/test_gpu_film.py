@@ -253,3 +253,157 @@ def test_cfl_violation_is_reported_like_the_oracle():
     g = EbitFilm(FilmState.of(st), 0.05)
     g.advect(torch.from_numpy(u).to("cuda:0"), torch.from_numpy(v).to("cuda:0"), dt)
     assert g.sync() == ebit.EBIT_ERR_CFL
+
+
+def test_merging_pairs_match_oracle_every_step():
+    """Six circle pairs driven into each other on 128^2 (the topology-change
+    workload, scaled down) with a rupture gap of 0.05 cell: the facing walls
+    meet as pairs (films) that thin and rupture; colours, counts, offsets and C
+    equal the oracle's after every step."""
+    from paper_2309_00338_amd.film import FilmState
+
+    w = I.merging_pairs(n=128, pairs=6, rmin=6.0, rmax=14.0, nsteps=8)
+    ls = FilmLockstep(FilmState.of(w.state), w.u, w.v, 0.05)
+    for s in range(8):
+        ls.step(w.dts[s], f"pairs 128 step {s}")
+    got = ls.counters()
+    assert ls.pairs > 0 and got["annihilated"] > 0, (got, ls.pairs)
+
+
+_PAIRS = {}
+
+
+def _pairs_full(nsteps):
+    """The full-size topology-change workload (generated once per run)."""
+    if "w" not in _PAIRS:
+        _PAIRS["w"] = I.merging_pairs(n=4096, pairs=500, nsteps=8)
+    w = _PAIRS["w"]
+    assert w.meta["pairs"] == 500 and nsteps <= len(w.dts)
+    return w
+
+
+def _film_invariants(gs, where):
+    """Counts in {0, 1, 2}, odd exactly where the end colours differ; the
+    meaningful offsets in [0, 1] and ascending."""
+    assert gs.hn.max() <= 2 and gs.vn.max() <= 2, where
+    hd = gs.c[:, :-1] != gs.c[:, 1:]
+    vd = gs.c[:-1, :] != gs.c[1:, :]
+    assert np.array_equal((gs.hn & 1) == 1, hd) and np.array_equal((gs.vn & 1) == 1, vd), where
+    for n_, o in ((gs.hn, gs.ho), (gs.vn, gs.vo)):
+        for k in range(2):
+            m = n_ > k
+            assert ((o[..., k][m] >= 0.0) & (o[..., k][m] <= 1.0)).all(), where
+        two = n_ == 2
+        assert (o[..., 0][two] <= o[..., 1][two]).all(), where
+
+
+def test_full_size_pairs_without_films_equal_the_one_marker_path():
+    """The topology-change workload at full size (500 pairs on 4096^2) with
+    films forbidden: after each of 3 steps the film step's colours, centre
+    colours, counts and offsets equal the one-marker GPU step's bit for bit
+    (that step is itself checked against its oracle at this size), and so
+    does C."""
+    import torch
+
+    from paper_2309_00338_amd import ebit
+    from paper_2309_00338_amd.film import EbitFilm, FilmState
+
+    w = _pairs_full(3)
+    u = torch.from_numpy(w.u).to("cuda:0")
+    v = torch.from_numpy(w.v).to("cuda:0")
+    f = EbitFilm(FilmState.of(w.state), math.inf)
+    one = ebit.EbitGrid(w.state)
+    for k in range(3):
+        f.advect(u, v, w.dts[k])
+        one.advect(u, v, w.dts[k])
+        gs, os_ = f.get_state(), one.get_state()
+        assert np.array_equal(gs.c, os_.c) and np.array_equal(gs.cc, os_.cc), k
+        assert (gs.hn <= 1).all() and (gs.vn <= 1).all(), k
+        hp, vp = gs.hn == 1, gs.vn == 1
+        assert np.array_equal(gs.ho[..., 0][hp], os_.hoff[hp]) and np.array_equal(gs.vo[..., 0][vp], os_.voff[vp]), k
+    Cf = f.fraction().cpu().numpy()
+    Co = one.fraction().cpu().numpy()
+    assert np.abs(Cf - Co).max() < 1e-14
+    assert one.stats()["annihilated"] > 0
+    f.close()
+    one.close()
+
+
+def _quiet_crops(st, count, half_h, half_w, band, seed):
+    """Boxes of (2 half_h + 1) x (2 half_w + 1) cells centred on random inside
+    cells whose outer band of `band` cells holds no marker (no edge with
+    differing end colours), so what happens inside never reaches the box's
+    walls within a few steps."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    inside = np.argwhere(st.cc == 1)
+    hd = st.c[:, :-1] != st.c[:, 1:]
+    vd = st.c[:-1, :] != st.c[1:, :]
+    out = []
+    for k in rng.permutation(len(inside)):
+        j, i = (int(x) for x in inside[k])
+        j0, j1, i0, i1 = j - half_h, j + half_h, i - half_w, i + half_w
+        if j0 < 0 or i0 < 0 or j1 >= st.ny or i1 >= st.nx:
+            continue
+        if any(max(j0, a0) <= min(j1, a1) and max(i0, b0) <= min(i1, b1) for a0, a1, b0, b1 in out):
+            continue
+        # nodes of the box: rows j0 .. j1+1, columns i0 .. i1+1
+        H = hd[j0:j1 + 2, i0:i1 + 1]
+        V = vd[j0:j1 + 1, i0:i1 + 2]
+        inner = H[band:-band, band:-band].any() or V[band:-band, band:-band].any()
+        ring = H.sum() - H[band:-band, band:-band].sum() + V.sum() - V[band:-band, band:-band].sum()
+        if inner and ring == 0:
+            out.append((j0, j1, i0, i1))
+            if len(out) == count:
+                break
+    assert len(out) == count
+    return out
+
+
+def test_full_size_pairs_with_films_match_the_oracle_on_sampled_pairs():
+    """The same workload with a rupture gap of 0.05 cell for 4 steps: the whole
+    state keeps the film invariants after every step and films form; in three
+    sampled boxes around pairs (121 x 241 cells whose outer 12-cell band holds
+    no marker: a marker moves at most 2 cells in 4 steps and a sweep reads 2
+    cells around it) the state equals the film oracle run on that box alone
+    with the same faces, after every step."""
+    import torch
+
+    from paper_2309_00338_amd.film import EbitFilm, FilmState
+
+    steps, band = 4, 12
+    w = _pairs_full(steps)
+    fs0 = FilmState.of(w.state)
+    u = torch.from_numpy(w.u).to("cuda:0")
+    v = torch.from_numpy(w.v).to("cuda:0")
+    f = EbitFilm(fs0, 0.05)
+    crops = _quiet_crops(w.state, 3, 60, 120, band, seed=7)
+    ors = []
+    for (j0, j1, i0, i1) in crops:
+        sub = FilmState(i1 - i0 + 1, j1 - j0 + 1, fs0.h, fs0.c[j0:j1 + 2, i0:i1 + 2].copy(),
+                        fs0.cc[j0:j1 + 1, i0:i1 + 1].copy(), fs0.hn[j0:j1 + 2, i0:i1 + 1].copy(),
+                        fs0.ho[j0:j1 + 2, i0:i1 + 1].copy(), fs0.vn[j0:j1 + 1, i0:i1 + 2].copy(),
+                        fs0.vo[j0:j1 + 1, i0:i1 + 2].copy(), 0)
+        ors.append(_to_oracle(sub))
+    pairs = 0
+    for s in range(steps):
+        f.advect(u, v, w.dts[s])
+        gs = f.get_state()
+        _film_invariants(gs, f"step {s}")
+        pairs = max(pairs, int((gs.hn == 2).sum() + (gs.vn == 2).sum()))
+        for q, (j0, j1, i0, i1) in enumerate(crops):
+            ors[q] = T.step(ors[q], w.u[j0:j1 + 1, i0:i1 + 2], w.v[j0:j1 + 2, i0:i1 + 1], w.dts[s], 0.05)
+            o = _of_oracle(ors[q])
+            sh, sv = (slice(j0, j1 + 2), slice(i0, i1 + 1)), (slice(j0, j1 + 1), slice(i0, i1 + 2))
+            where = f"step {s} box {q} {crops[q]}"
+            assert np.array_equal(gs.c[j0:j1 + 2, i0:i1 + 2], o.c), where
+            assert np.array_equal(gs.cc[j0:j1 + 1, i0:i1 + 1], o.cc), where
+            assert np.array_equal(gs.hn[sh], o.hn) and np.array_equal(gs.vn[sv], o.vn), where
+            for k in range(2):
+                mh, mv = o.hn > k, o.vn > k
+                assert np.array_equal(gs.ho[sh][..., k][mh], o.ho[..., k][mh]), where
+                assert np.array_equal(gs.vo[sv][..., k][mv], o.vo[..., k][mv]), where
+            # nothing reached the box's walls
+            assert o.hn[:band].sum() + o.hn[-band:].sum() + o.vn[:, :band].sum() + o.vn[:, -band:].sum() == 0, where
+    assert pairs > 0
+    assert f.stats()["parity_fail"] == 0
+    f.close()
