@@ -1,9 +1,20 @@
 // Two markers per edge: the thin-film extension named at the end of Sec. 2.4
 // and in Sec. 4, in the reading stated in include/ebit_film.h.
 //
-// Each sweep is five plain passes over global memory, one lane per edge, node
-// or cell, in the physical (row-major) order of what the lane writes, so
-// every pass stores coalesced:
+// Each sweep is five passes over global memory, one lane per edge, node or
+// cell, in the physical (row-major) order of what the lane writes, so every
+// pass stores coalesced. A launch is two-dimensional: x runs along an array
+// row and each lane takes a run of consecutive rows of its column, so no lane
+// divides a 64-bit index and the run's reads issue together. Most of the grid
+// is away from the interface, and there a lane only copies counts and
+// colours: the per-edge scratch (advected offsets) and the new offset pairs
+// are written only for edges that hold markers. The two passes with heavy
+// per-element work (the crossing search with its circle fits, and the
+// fraction's polygons) are split: a quiet pass settles the elements with no
+// marker near and lists the others in its workgroup's own slots with a count,
+// and a heavy pass gives each wavefront the items of a few quiet workgroups,
+// one per lane, so the heavy work runs in full wavefronts (no atomics on
+// global memory anywhere).
 //   advect  aligned markers to s' = s + u dt/h (Eq. Eq_marker_dis), unaligned
 //           ones to their gray points (displacement only; walls hold);
 //   flip    a node changes colour once per marker that passes it (Sec. 2.3);
@@ -41,6 +52,52 @@ struct Buf {
   double2 *ho, *vo;
 };
 
+// Compaction of the elements of a row launch that need the heavy path,
+// without atomics on global memory: the quiet pass puts the (row, column) of
+// each such element in its workgroup's own slot range (as many slots as the
+// workgroup has elements) and their number in cnt; the heavy pass gives each
+// wavefront GW consecutive quiet workgroups and lets its lanes take their
+// items one each, so the heavy path runs with full wavefronts.
+struct Compact {
+  uint2 *slot;
+  uint32_t *cnt;
+};
+constexpr int GW = 8;  // quiet workgroups per heavy wavefront
+
+// The items of quiet workgroups b0 .. b0+GW-1 (those below nq), one per lane:
+// work(row, col) for each. `cap` is the slot range of one quiet workgroup.
+template <class Fn>
+__device__ __forceinline__ void walkItems(const Compact &W, uint32_t nq, uint32_t cap, Fn work) {
+  const int lane = (int)threadIdx.x;
+  const uint32_t b0 = blockIdx.x * GW;
+  const uint32_t mine = lane < GW && b0 + (uint32_t)lane < nq ? W.cnt[b0 + lane] : 0u;
+  uint32_t inc = mine;
+#pragma unroll
+  for (int d = 1; d < GW; d <<= 1) {
+    const uint32_t v = (uint32_t)__shfl_up((int)inc, d);
+    if (lane >= d) inc += v;
+  }
+  // exclusive offsets of the GW workgroups, wave-uniform
+  uint32_t e[GW];
+#pragma unroll
+  for (int q = 0; q < GW; q++) e[q] = (uint32_t)__builtin_amdgcn_readlane((int)(inc - mine), q);
+  const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)inc, GW - 1);
+  for (uint32_t i = (uint32_t)lane; i < total; i += 64u) {
+    // the last workgroup whose first item is at or before i (workgroups with
+    // no items share their successor's offset and are passed over)
+    int k = 0;
+    uint32_t base = 0;
+#pragma unroll
+    for (int q = 0; q < GW; q++)
+      if (e[q] <= i) {
+        k = q;
+        base = e[q];
+      }
+    const uint2 it = W.slot[(size_t)(b0 + (uint32_t)k) * cap + (i - base)];
+    work((int)it.x, (int)it.y);
+  }
+}
+
 struct SweepArgs {
   int nx, ny;
   double lam, delta;
@@ -52,6 +109,7 @@ struct SweepArgs {
   int8_t *res;        // 4 per unaligned edge: (right, left) results of kept crossings 0 and 1
   uint32_t *err;
   unsigned long long *ctr;
+  Compact wk;         // the edges of the crossing pass that need the search
 };
 
 // The sweep frame over a state copy. DIR 0: aligned edges are H, unaligned V;
@@ -69,28 +127,45 @@ struct Frame {
   __device__ size_t ale(int a, int b) const { return DIR == 0 ? (size_t)b * nx + a : (size_t)a * (nx + 1) + b; }
   __device__ size_t une(int a, int b) const { return DIR == 0 ? (size_t)b * (nx + 1) + a : (size_t)a * nx + b; }
   __device__ size_t cell(int a, int b) const { return DIR == 0 ? (size_t)b * nx + a : (size_t)a * nx + b; }
-  __device__ size_t nAl() const { return (size_t)na * (size_t)(nb + 1); }
-  __device__ size_t nUn() const { return (size_t)(na + 1) * (size_t)nb; }
-  // frame coordinates of a physical index
-  __device__ void alOf(size_t e, int &a, int &b) const {
-    if (DIR == 0) { b = (int)(e / (size_t)nx); a = (int)(e % (size_t)nx); }
-    else { a = (int)(e / (size_t)(nx + 1)); b = (int)(e % (size_t)(nx + 1)); }
-  }
-  __device__ void unOf(size_t e, int &a, int &b) const {
-    if (DIR == 0) { b = (int)(e / (size_t)(nx + 1)); a = (int)(e % (size_t)(nx + 1)); }
-    else { a = (int)(e / (size_t)nx); b = (int)(e % (size_t)nx); }
-  }
-  __device__ void nodeOf(size_t e, int &a, int &b) const {
-    if (DIR == 0) { b = (int)(e / (size_t)(nx + 1)); a = (int)(e % (size_t)(nx + 1)); }
-    else { a = (int)(e / (size_t)(nx + 1)); b = (int)(e % (size_t)(nx + 1)); }
-  }
-  __device__ void cellOf(size_t e, int &a, int &b) const {
-    if (DIR == 0) { b = (int)(e / (size_t)nx); a = (int)(e % (size_t)nx); }
-    else { a = (int)(e / (size_t)nx); b = (int)(e % (size_t)nx); }
-  }
 };
 
 __device__ __forceinline__ double pick(const double2 &v, int k) { return k == 0 ? v.x : v.y; }
+
+// Every array of the state is row-major; in the sweep frame its element
+// (row, col) is (a, b) = (col, row) for the x sweep and (row, col) for the y
+// sweep (the frame is the transposed grid).
+template <int DIR>
+__device__ __forceinline__ void frameOf(int row, int col, int &a, int &b) {
+  a = DIR == 0 ? col : row;
+  b = DIR == 0 ? row : col;
+}
+
+// A lane's run of K rows r0 .. r0+K-1 of its column (rows past `rows` are
+// skipped): first need(row) for every row, which reads only a few counts and
+// whose loads issue together (indices clamped to the last row, so every read
+// is inside the array), then quiet(row) for the rows that need nothing (the
+// plain copy away from the interface) and work(row) for the others.
+template <int K, class Need, class Quiet, class Work>
+__device__ __forceinline__ void rowRun(int r0, int rows, Need need, Quiet quiet, Work work) {
+  uint32_t busy = 0, in = 0;
+#pragma unroll
+  for (int k = 0; k < K; k++) {
+    const int row = r0 + k < rows ? r0 + k : rows - 1;
+    const uint32_t ok = r0 + k < rows ? 1u : 0u;
+    in |= ok << k;
+    busy |= (ok & (need(row) ? 1u : 0u)) << k;
+  }
+#pragma unroll
+  for (int k = 0; k < K; k++)
+    if (((in & ~busy) >> k) & 1u) quiet(r0 + k);
+  while (busy) {
+    const int k = __ffs(busy) - 1;
+    busy &= busy - 1u;
+    work(r0 + k);
+  }
+}
+constexpr int KR = 8;  // rows per lane in the plain passes
+constexpr int KX = 4;  // rows per lane in the crossing pass (seven counts per row)
 
 // Workgroup sums of the counters, one atomic per counter and workgroup.
 __device__ void addCounters(unsigned long long *ctr, const uint32_t *v) {
@@ -109,45 +184,59 @@ __device__ void addCounters(unsigned long long *ctr, const uint32_t *v) {
 template <int DIR>
 __global__ __launch_bounds__(BS) void k_film_advect(SweepArgs A) {
   const Frame<DIR> F(A.nx, A.ny, A.cur);
-  const size_t t = (size_t)blockIdx.x * BS + threadIdx.x;
   uint32_t err = 0, c[F_NCTR] = {0, 0, 0, 0, 0};
   auto V = [&](int a, int r) -> double {
     r = r < 0 ? 0 : (r > F.nb - 1 ? F.nb - 1 : r);
     return A.vel[F.une(a, r)];
   };
-  if (t < F.nAl()) {
-    int a, b;
-    F.alOf(t, a, b);
-    const int n = F.an[t];
-    const double2 o = F.ao[t];
-    double r[2] = {0.0, 0.0};
-    for (int k = 0; k < n; k++) {
-      const double s = pick(o, k);
-      const double ub = lerp(lerp(V(a, b - 1), V(a + 1, b - 1), s), lerp(V(a, b), V(a + 1, b), s), 0.5);
-      const double d = ub * A.lam;
-      if (fabs(d) > 0.5) err |= ERR_CFL;
-      r[k] = s + d;
-      if ((r[k] >= 1.0 && a + 1 >= F.na) || (r[k] < 0.0 && a == 0)) err |= ERR_DOMAIN;
+  // rows of the aligned array, then rows of the unaligned one
+  const int rA = DIR == 0 ? A.ny + 1 : A.ny, wA = DIR == 0 ? A.nx : A.nx + 1;
+  const int rU = DIR == 0 ? A.ny : A.ny + 1, wU = DIR == 0 ? A.nx + 1 : A.nx;
+  const int col = (int)(blockIdx.x * BS + threadIdx.x);
+  auto need = [&](int row) -> bool {
+    if (row < rA) return col < wA && F.an[(size_t)row * (size_t)wA + (size_t)col] != 0;
+    return col < wU && F.un[(size_t)(row - rA) * (size_t)wU + (size_t)col] != 0;
+  };
+  auto work = [&](int row) {
+    if (row < rA) {
+      const size_t t = (size_t)row * (size_t)wA + (size_t)col;
+      const int n = F.an[t];
+      int a, b;
+      frameOf<DIR>(row, col, a, b);
+      const double2 o = F.ao[t];
+      double r[2] = {0.0, 0.0};
+      for (int k = 0; k < n; k++) {
+        const double sv = pick(o, k);
+        const double ub = lerp(lerp(V(a, b - 1), V(a + 1, b - 1), sv), lerp(V(a, b), V(a + 1, b), sv), 0.5);
+        const double d = ub * A.lam;
+        if (fabs(d) > 0.5) err |= ERR_CFL;
+        r[k] = sv + d;
+        if ((r[k] >= 1.0 && a + 1 >= F.na) || (r[k] < 0.0 && a == 0)) err |= ERR_DOMAIN;
+      }
+      A.sp[t] = make_double2(r[0], r[1]);
+      c[F_MARKERS] += (uint32_t)n;
+    } else {
+      const int ur = row - rA;
+      const size_t e = (size_t)ur * (size_t)wU + (size_t)col;
+      const int n = F.un[e];
+      int a, b;
+      frameOf<DIR>(ur, col, a, b);
+      const double2 o = F.uo[e];
+      double r[2] = {0.0, 0.0};
+      for (int k = 0; k < n; k++) {
+        const double sv = pick(o, k);
+        const double ub = sv < 0.5 ? lerp(V(a, b - 1), V(a, b), sv + 0.5) : lerp(V(a, b), V(a, b + 1), sv - 0.5);
+        const double d = ub * A.lam;
+        if (fabs(d) > 0.5) err |= ERR_CFL;
+        r[k] = (a == 0 || a == F.na) ? 0.0 : d;
+      }
+      A.dv[e] = make_double2(r[0], r[1]);
+      c[F_MARKERS] += (uint32_t)n;
     }
-    A.sp[t] = make_double2(r[0], r[1]);
-    c[F_MARKERS] = (uint32_t)n;
-  } else if (t - F.nAl() < F.nUn()) {
-    const size_t e = t - F.nAl();
-    int a, b;
-    F.unOf(e, a, b);
-    const int n = F.un[e];
-    const double2 o = F.uo[e];
-    double r[2] = {0.0, 0.0};
-    for (int k = 0; k < n; k++) {
-      const double s = pick(o, k);
-      const double ub = s < 0.5 ? lerp(V(a, b - 1), V(a, b), s + 0.5) : lerp(V(a, b), V(a, b + 1), s - 0.5);
-      const double d = ub * A.lam;
-      if (fabs(d) > 0.5) err |= ERR_CFL;
-      r[k] = (a == 0 || a == F.na) ? 0.0 : d;
-    }
-    A.dv[e] = make_double2(r[0], r[1]);
-    c[F_MARKERS] = (uint32_t)n;
-  }
+  };
+  // edges without markers leave no scratch (nothing reads it for them)
+  for (int r0 = (int)blockIdx.y * KR; r0 < rA + rU; r0 += (int)gridDim.y * KR)
+    rowRun<KR>(r0, rA + rU, need, [](int) {}, work);
   if (err) atomicOr(A.err, err);
   addCounters(A.ctr, c);
 }
@@ -158,22 +247,40 @@ __global__ __launch_bounds__(BS) void k_film_advect(SweepArgs A) {
 template <int DIR>
 __global__ __launch_bounds__(BS) void k_film_flip(SweepArgs A) {
   const Frame<DIR> F(A.nx, A.ny, A.cur);
-  const size_t t = (size_t)blockIdx.x * BS + threadIdx.x;
-  if (t >= (size_t)(A.nx + 1) * (size_t)(A.ny + 1)) return;
-  int a, b;
-  F.nodeOf(t, a, b);
-  int flips = 0;
-  if (a >= 1) {
-    const size_t e = F.ale(a - 1, b);
-    const double2 s = A.sp[e];
-    for (int k = 0; k < F.an[e]; k++) flips += pick(s, k) >= 1.0 ? 1 : 0;
-  }
-  if (a < F.na) {
-    const size_t e = F.ale(a, b);
-    const double2 s = A.sp[e];
-    for (int k = 0; k < F.an[e]; k++) flips += pick(s, k) < 0.0 ? 1 : 0;
-  }
-  A.nxt.col[t] = (uint8_t)(F.col[t] ^ (uint8_t)(flips & 1));
+  const int col = (int)(blockIdx.x * BS + threadIdx.x);
+  if (col > A.nx) return;
+  auto at = [&](int row) { return (size_t)row * (size_t)(A.nx + 1) + (size_t)col; };
+  // a node flips once per marker that passes it: only the aligned edges on its
+  // two sides can carry one
+  auto need = [&](int row) -> bool {
+    int a, b;
+    frameOf<DIR>(row, col, a, b);
+    return (a >= 1 && F.an[F.ale(a - 1, b)] != 0) || (a < F.na && F.an[F.ale(a, b)] != 0);
+  };
+  auto quiet = [&](int row) { A.nxt.col[at(row)] = F.col[at(row)]; };
+  auto work = [&](int row) {
+    int a, b;
+    frameOf<DIR>(row, col, a, b);
+    int flips = 0;
+    if (a >= 1) {
+      const size_t e = F.ale(a - 1, b);
+      const int n = F.an[e];
+      if (n) {
+        const double2 sv = A.sp[e];
+        for (int k = 0; k < n; k++) flips += pick(sv, k) >= 1.0 ? 1 : 0;
+      }
+    }
+    if (a < F.na) {
+      const size_t e = F.ale(a, b);
+      const int n = F.an[e];
+      if (n) {
+        const double2 sv = A.sp[e];
+        for (int k = 0; k < n; k++) flips += pick(sv, k) < 0.0 ? 1 : 0;
+      }
+    }
+    A.nxt.col[at(row)] = (uint8_t)(F.col[at(row)] ^ (uint8_t)(flips & 1));
+  };
+  for (int r0 = (int)blockIdx.y * KR; r0 <= A.ny; r0 += (int)gridDim.y * KR) rowRun<KR>(r0, A.ny + 1, need, quiet, work);
 }
 
 // ---------------------------------------------------------------------------
@@ -182,11 +289,23 @@ __global__ __launch_bounds__(BS) void k_film_flip(SweepArgs A) {
 template <int DIR>
 __global__ __launch_bounds__(BS) void k_film_land(SweepArgs A) {
   const Frame<DIR> F(A.nx, A.ny, A.cur);
-  const size_t t = (size_t)blockIdx.x * BS + threadIdx.x;
   uint32_t c[F_NCTR] = {0, 0, 0, 0, 0};
-  if (t < F.nAl()) {
+  const int rA = DIR == 0 ? A.ny + 1 : A.ny, wA = DIR == 0 ? A.nx : A.nx + 1;
+  const int col = (int)(blockIdx.x * BS + threadIdx.x);
+  uint8_t *dn = DIR == 0 ? A.nxt.hn : A.nxt.vn;
+  double2 *dof = DIR == 0 ? A.nxt.ho : A.nxt.vo;
+  // landers can come only from the edge and its two neighbours on the row
+  auto need = [&](int row) -> bool {
     int a, b;
-    F.alOf(t, a, b);
+    frameOf<DIR>(row, col, a, b);
+    return (a >= 1 && F.an[F.ale(a - 1, b)] != 0) || F.an[F.ale(a, b)] != 0 ||
+           (a + 1 < F.na && F.an[F.ale(a + 1, b)] != 0);
+  };
+  auto quiet = [&](int row) { dn[(size_t)row * (size_t)wA + (size_t)col] = 0; };
+  auto work = [&](int row) {
+    const size_t t = (size_t)row * (size_t)wA + (size_t)col;
+    int a, b;
+    frameOf<DIR>(row, col, a, b);
     // landers in source order (a-1, a, a+1; first marker first), then a stable
     // insertion sort by position
     double o[6];
@@ -196,8 +315,10 @@ __global__ __launch_bounds__(BS) void k_film_land(SweepArgs A) {
     for (int q = a - 1; q <= a + 1; q++) {
       if (q < 0 || q >= F.na) continue;
       const size_t e = F.ale(q, b);
+      const int ne = F.an[e];
+      if (ne == 0) continue;
       const double2 s2 = A.sp[e];
-      for (int k = 0; k < F.an[e]; k++) {
+      for (int k = 0; k < ne; k++) {
         const double s = pick(s2, k);
         const int tgt = s >= 1.0 ? q + 1 : (s < 0.0 ? q - 1 : q);
         if (tgt != a) continue;
@@ -225,12 +346,12 @@ __global__ __launch_bounds__(BS) void k_film_land(SweepArgs A) {
       nk = 2;
     }
     for (int m = 0; m < n; m++) A.kept[2 * src[m] + kk[m]] = (uint8_t)(m >= lo && m < lo + nk);
-    uint8_t *dn = DIR == 0 ? A.nxt.hn : A.nxt.vn;
-    double2 *dof = DIR == 0 ? A.nxt.ho : A.nxt.vo;
     dn[t] = (uint8_t)nk;
-    dof[t] = make_double2(nk > 0 ? o[lo] : 0.0, nk > 1 ? o[lo + 1] : 0.0);
-    c[F_ANNIH] = (uint32_t)(n - nk);
-  }
+    if (nk > 0) dof[t] = make_double2(o[lo], nk > 1 ? o[lo + 1] : 0.0);
+    c[F_ANNIH] += (uint32_t)(n - nk);
+  };
+  if (col < wA)
+    for (int r0 = (int)blockIdx.y * KR; r0 < rA; r0 += (int)gridDim.y * KR) rowRun<KR>(r0, rA, need, quiet, work);
   addCounters(A.ctr, c);
 }
 
@@ -339,19 +460,53 @@ __device__ bool circleRoot(double Xa, double Ya, double Xb, double Yb, double Xc
 }
 
 template <int DIR>
-__global__ __launch_bounds__(BS) void k_film_cross(SweepArgs A) {
+__global__ __launch_bounds__(BS) void k_film_cross_quiet(SweepArgs A) {
   const Frame<DIR> F(A.nx, A.ny, A.cur);
-  const size_t t = (size_t)blockIdx.x * BS + threadIdx.x;
-  uint32_t c[F_NCTR] = {0, 0, 0, 0, 0};
-  if (t < F.nUn()) {
+  const int rU = DIR == 0 ? A.ny : A.ny + 1, wU = DIR == 0 ? A.nx + 1 : A.nx;
+  const int col = (int)(blockIdx.x * BS + threadIdx.x);
+  uint8_t *dn = DIR == 0 ? A.nxt.vn : A.nxt.hn;
+  // an interior edge whose two cells hold no marker: nothing crosses it, and
+  // no node of theirs flips (their aligned edges hold none), so it stays empty
+  auto need = [&](int row) -> bool {
     int a, b;
-    F.unOf(t, a, b);
-    uint8_t *dn = DIR == 0 ? A.nxt.vn : A.nxt.hn;
-    double2 *dof = DIR == 0 ? A.nxt.vo : A.nxt.ho;
+    frameOf<DIR>(row, col, a, b);
+    if (a == 0 || a == F.na) return true;
+    return (F.an[F.ale(a - 1, b)] | F.an[F.ale(a - 1, b + 1)] | F.an[F.ale(a, b)] | F.an[F.ale(a, b + 1)] |
+            F.un[F.une(a - 1, b)] | F.un[F.une(a, b)] | F.un[F.une(a + 1, b)]) != 0;
+  };
+  // the edges that need nothing are written here; the others go to the
+  // workgroup's slots for the search pass
+  const uint32_t blk = blockIdx.y * gridDim.x + blockIdx.x;
+  uint2 *slot = A.wk.slot + (size_t)blk * (BS * KX);
+  __shared__ uint32_t sN;
+  if (threadIdx.x == 0) sN = 0;
+  __syncthreads();
+  if (col < wU)
+    for (int r0 = (int)blockIdx.y * KX; r0 < rU; r0 += (int)gridDim.y * KX)
+      rowRun<KX>(r0, rU, need, [&](int row) { dn[(size_t)row * (size_t)wU + (size_t)col] = 0; },
+                 [&](int row) { slot[atomicAdd(&sN, 1u)] = make_uint2((uint32_t)row, (uint32_t)col); });
+  __syncthreads();
+  if (threadIdx.x == 0) A.wk.cnt[blk] = sN;
+}
+
+template <int DIR>
+__global__ __launch_bounds__(64) void k_film_cross(SweepArgs A, uint32_t nq) {
+  const Frame<DIR> F(A.nx, A.ny, A.cur);
+  uint32_t c[F_NCTR] = {0, 0, 0, 0, 0};
+  const int wU = DIR == 0 ? A.nx + 1 : A.nx;
+  uint8_t *dn = DIR == 0 ? A.nxt.vn : A.nxt.hn;
+  double2 *dof = DIR == 0 ? A.nxt.vo : A.nxt.ho;
+  // the edges the quiet pass listed: walls, and interior edges with markers
+  // in one of their two cells
+  auto work = [&](int row, int col) {
+    const size_t t = (size_t)row * (size_t)wU + (size_t)col;
+    int a, b;
+    frameOf<DIR>(row, col, a, b);
     if (a == 0 || a == F.na) {
       // walls keep their markers
-      dn[t] = F.un[t];
-      dof[t] = F.uo[t];
+      const int n = F.un[t];
+      dn[t] = (uint8_t)n;
+      if (n) dof[t] = F.uo[t];
     } else {
       // advected position of a marker in the frame of node (a, b), integer part first
       auto pos = [&](const Ref &r, double &X, double &Y) {
@@ -408,7 +563,7 @@ __global__ __launch_bounds__(BS) void k_film_cross(SweepArgs A) {
         }
       }
       const int nc0 = A.nxt.col[F.node(a, b)], nc1 = A.nxt.col[F.node(a, b + 1)];
-      if ((n & 1) != (nc0 != nc1 ? 1 : 0)) c[F_PARITY] = 1;
+      if ((n & 1) != (nc0 != nc1 ? 1 : 0)) c[F_PARITY] += 1;
       int lo = 0, nk = 0;
       if (n & 1) {
         lo = n / 2;
@@ -417,8 +572,8 @@ __global__ __launch_bounds__(BS) void k_film_cross(SweepArgs A) {
         lo = n / 2 - 1;
         nk = 2;
       }
-      if (n == 3) c[F_THREE] = 1;
-      c[F_ANNIH_UN] = (uint32_t)(n - nk);
+      if (n == 3) c[F_THREE] += 1;
+      c[F_ANNIH_UN] += (uint32_t)(n - nk);
       // chain neighbour: the partner, in the cell across edge e of cell (p, q),
       // of marker k of that edge
       auto partner = [&](int p, int q, int e, int k) -> Ref {
@@ -484,9 +639,10 @@ __global__ __launch_bounds__(BS) void k_film_cross(SweepArgs A) {
         ys[1] = tmp;
       }
       dn[t] = (uint8_t)nk;
-      dof[t] = make_double2(ys[0], ys[1]);
+      if (nk > 0) dof[t] = make_double2(ys[0], ys[1]);
     }
-  }
+  };
+  walkItems(A.wk, nq, BS * KX, work);
   addCounters(A.ctr, c);
 }
 
@@ -496,21 +652,33 @@ __global__ __launch_bounds__(BS) void k_film_cross(SweepArgs A) {
 template <int DIR>
 __global__ __launch_bounds__(BS) void k_film_centre(SweepArgs A) {
   const Frame<DIR> F(A.nx, A.ny, A.cur);
-  const size_t t = (size_t)blockIdx.x * BS + threadIdx.x;
-  if (t >= (size_t)A.nx * (size_t)A.ny) return;
-  int a, b;
-  F.cellOf(t, a, b);
+  const int col = (int)(blockIdx.x * BS + threadIdx.x);
+  if (col >= A.nx) return;
   const uint8_t *nn = DIR == 0 ? A.nxt.vn : A.nxt.hn;  // new unaligned counts (kept crossings)
-  int r = -1;
-  if (a >= 1) {
-    const size_t e = F.une(a, b);
-    for (int q = 0; q < nn[e] && r < 0; q++) r = A.res[4 * e + 2 * q] >= 0 ? A.res[4 * e + 2 * q] : -1;
-  }
-  if (r < 0 && a + 1 <= F.na - 1) {
-    const size_t e = F.une(a + 1, b);
-    for (int q = 0; q < nn[e] && r < 0; q++) r = A.res[4 * e + 2 * q + 1] >= 0 ? A.res[4 * e + 2 * q + 1] : -1;
-  }
-  A.nxt.cen[t] = r >= 0 ? (uint8_t)r : F.cen[t];
+  auto at = [&](int row) { return (size_t)row * (size_t)A.nx + (size_t)col; };
+  // a cell takes a new colour only from a kept crossing on its left or right line
+  auto need = [&](int row) -> bool {
+    int a, b;
+    frameOf<DIR>(row, col, a, b);
+    return (a >= 1 && nn[F.une(a, b)] != 0) || (a + 1 <= F.na - 1 && nn[F.une(a + 1, b)] != 0);
+  };
+  auto quiet = [&](int row) { A.nxt.cen[at(row)] = F.cen[at(row)]; };
+  auto work = [&](int row) {
+    const size_t t = at(row);
+    int a, b;
+    frameOf<DIR>(row, col, a, b);
+    int r = -1;
+    if (a >= 1) {
+      const size_t e = F.une(a, b);
+      for (int q = 0; q < nn[e] && r < 0; q++) r = A.res[4 * e + 2 * q] >= 0 ? A.res[4 * e + 2 * q] : -1;
+    }
+    if (r < 0 && a + 1 <= F.na - 1) {
+      const size_t e = F.une(a + 1, b);
+      for (int q = 0; q < nn[e] && r < 0; q++) r = A.res[4 * e + 2 * q + 1] >= 0 ? A.res[4 * e + 2 * q + 1] : -1;
+    }
+    A.nxt.cen[t] = r >= 0 ? (uint8_t)r : F.cen[t];
+  };
+  for (int r0 = (int)blockIdx.y * KR; r0 < A.ny; r0 += (int)gridDim.y * KR) rowRun<KR>(r0, A.ny, need, quiet, work);
 }
 
 // ---------------------------------------------------------------------------
@@ -527,16 +695,13 @@ __device__ __forceinline__ void pointOf(double tau, double &x, double &y) {
   else { x = 0.0; y = 4.0 - tau; }
 }
 
-__global__ __launch_bounds__(BS) void k_film_fraction(int nx, int ny, Buf S, double *C) {
-  const size_t t = (size_t)blockIdx.x * BS + threadIdx.x;
-  if (t >= (size_t)nx * (size_t)ny) return;
-  const Frame<0> F(nx, ny, S);
-  int p, q;
-  F.cellOf(t, p, q);
+// Volume fraction of cell (p, q) with markers on its boundary: the regions the
+// segments cut off, or the cell minus them.
+__device__ void cellFraction(const Frame<0> &F, int p, int q, double *out) {
   Bnd B;
   boundary<0>(F, p, q, B);
   if (B.n == 0) {
-    C[t] = (double)F.col[F.node(p, q)];
+    *out = (double)F.col[F.node(p, q)];
     return;
   }
   double cut = 0.0;
@@ -563,9 +728,37 @@ __global__ __launch_bounds__(BS) void k_film_fraction(int nx, int ny, Buf S, dou
     }
     cut += fabs(0.5 * ar);
   }
-  C[t] = F.cen[t] == 1 ? 1.0 - cut : cut;
+  *out = F.cen[F.cell(p, q)] == 1 ? 1.0 - cut : cut;
 }
 
+// a cell with no marker on its boundary has one colour
+__device__ __forceinline__ bool cellNeeds(const Frame<0> &F, int p, int q) {
+  return (F.an[F.ale(p, q)] | F.an[F.ale(p, q + 1)] | F.un[F.une(p, q)] | F.un[F.une(p + 1, q)]) != 0;
+}
+
+// the one-colour cells; the others go to the workgroup's slots
+__global__ __launch_bounds__(BS) void k_film_fraction_quiet(int nx, int ny, Buf S, double *C, Compact W) {
+  const int p = (int)(blockIdx.x * BS + threadIdx.x);
+  const Frame<0> F(nx, ny, S);
+  const uint32_t blk = blockIdx.y * gridDim.x + blockIdx.x;
+  uint2 *slot = W.slot + (size_t)blk * (BS * KR);
+  __shared__ uint32_t sN;
+  if (threadIdx.x == 0) sN = 0;
+  __syncthreads();
+  if (p < nx)
+    for (int r0 = (int)blockIdx.y * KR; r0 < ny; r0 += (int)gridDim.y * KR)
+      rowRun<KR>(r0, ny, [&](int q) { return cellNeeds(F, p, q); },
+                 [&](int q) { C[(size_t)q * (size_t)nx + p] = (double)F.col[F.node(p, q)]; },
+                 [&](int q) { slot[atomicAdd(&sN, 1u)] = make_uint2((uint32_t)q, (uint32_t)p); });
+  __syncthreads();
+  if (threadIdx.x == 0) W.cnt[blk] = sN;
+}
+
+// the cells with markers on their boundary that the quiet pass listed
+__global__ __launch_bounds__(64) void k_film_fraction(int nx, int ny, Buf S, double *C, Compact W, uint32_t nq) {
+  const Frame<0> F(nx, ny, S);
+  walkItems(W, nq, BS * KR, [&](int q, int p) { cellFraction(F, p, q, C + (size_t)q * (size_t)nx + p); });
+}
 // ---------------------------------------------------------------------------
 // host
 // ---------------------------------------------------------------------------
@@ -621,6 +814,7 @@ struct Layout {
   int8_t *res;
   uint32_t *err;
   unsigned long long *ctr;
+  Compact wk;
   size_t bytes;
 };
 
@@ -643,6 +837,13 @@ Layout carve(const ebit_grid &g, char *base) {
   L.res = c.take<int8_t>(4 * M);
   L.err = c.take<uint32_t>(1);
   L.ctr = c.take<unsigned long long>(F_NCTR);
+  // a count per workgroup of the widest, tallest quiet launch, and a slot per
+  // element of it
+  const size_t side = (nx > ny ? nx : ny) + 1;
+  const size_t bx = (side + BS - 1) / BS, runs = (side + KX - 1) / KX;
+  const size_t nq = bx * (runs < 32768 ? runs : 32768);
+  L.wk.cnt = c.take<uint32_t>(nq);
+  L.wk.slot = c.take<uint2>(nq * (BS * KX > BS * KR ? BS * KX : BS * KR));
   L.bytes = (c.off + 255) & ~(size_t)255;
   return L;
 }
@@ -678,7 +879,12 @@ int upload(ebit_film *f, const ebit_film_state *s) {
   return ok ? EBIT_OK : EBIT_ERR_DEVICE;
 }
 
-unsigned blocks(size_t n) { return (unsigned)((n + BS - 1) / BS); }
+// a launch over `rows` rows of `width` elements: x along a row, y over the rows
+// (grid rows stride the array's rows beyond the y limit)
+dim3 rowsGrid(size_t width, size_t rows, int k) {
+  const size_t runs = (rows + (size_t)k - 1) / (size_t)k;
+  return dim3((unsigned)((width + BS - 1) / BS), (unsigned)(runs < 32768 ? runs : 32768));
+}
 
 template <int DIR>
 int sweep(ebit_film *f, const double *vel, double lam) {
@@ -696,14 +902,19 @@ int sweep(ebit_film *f, const double *vel, double lam) {
   A.res = f->L.res;
   A.err = f->L.err;
   A.ctr = f->L.ctr;
+  A.wk = f->L.wk;
   const size_t nx = A.nx, ny = A.ny;
-  const size_t na = DIR == 0 ? nx : ny, nb = DIR == 0 ? ny : nx;
-  const size_t nAl = na * (nb + 1), nUn = (na + 1) * nb;
-  hipLaunchKernelGGL(k_film_advect<DIR>, dim3(blocks(nAl + nUn)), dim3(BS), 0, f->stream, A);
-  hipLaunchKernelGGL(k_film_flip<DIR>, dim3(blocks((nx + 1) * (ny + 1))), dim3(BS), 0, f->stream, A);
-  hipLaunchKernelGGL(k_film_land<DIR>, dim3(blocks(nAl)), dim3(BS), 0, f->stream, A);
-  hipLaunchKernelGGL(k_film_cross<DIR>, dim3(blocks(nUn)), dim3(BS), 0, f->stream, A);
-  hipLaunchKernelGGL(k_film_centre<DIR>, dim3(blocks(nx * ny)), dim3(BS), 0, f->stream, A);
+  // physical shapes (rows x width) of the frame's aligned and unaligned arrays
+  const size_t rA = DIR == 0 ? ny + 1 : ny, wA = DIR == 0 ? nx : nx + 1;
+  const size_t rU = DIR == 0 ? ny : ny + 1, wU = DIR == 0 ? nx + 1 : nx;
+  hipLaunchKernelGGL(k_film_advect<DIR>, rowsGrid(nx + 1, rA + rU, KR), dim3(BS), 0, f->stream, A);
+  hipLaunchKernelGGL(k_film_flip<DIR>, rowsGrid(nx + 1, ny + 1, KR), dim3(BS), 0, f->stream, A);
+  hipLaunchKernelGGL(k_film_land<DIR>, rowsGrid(wA, rA, KR), dim3(BS), 0, f->stream, A);
+  const dim3 gq = rowsGrid(wU, rU, KX);
+  const uint32_t nq = gq.x * gq.y;
+  hipLaunchKernelGGL(k_film_cross_quiet<DIR>, gq, dim3(BS), 0, f->stream, A);
+  hipLaunchKernelGGL(k_film_cross<DIR>, dim3((nq + GW - 1) / GW), dim3(64), 0, f->stream, A, nq);
+  hipLaunchKernelGGL(k_film_centre<DIR>, rowsGrid(nx, ny, KR), dim3(BS), 0, f->stream, A);
   if (hipGetLastError() != hipSuccess) return EBIT_ERR_DEVICE;
   f->cur ^= 1;
   return EBIT_OK;
@@ -766,9 +977,12 @@ int ebit_film_advect(ebit_film *f, const double *u_dev, const double *v_dev, dou
 
 int ebit_film_fraction(ebit_film *f, double *C_dev) {
   if (!f || !C_dev) return EBIT_ERR_ARG;
-  const size_t n = (size_t)f->g.nx * (size_t)f->g.ny;
-  hipLaunchKernelGGL(k_film_fraction, dim3(blocks(n)), dim3(BS), 0, f->stream, f->g.nx, f->g.ny, f->L.buf[f->cur],
-                     C_dev);
+  const dim3 gq = rowsGrid(f->g.nx, f->g.ny, KR);
+  const uint32_t nq = gq.x * gq.y;
+  hipLaunchKernelGGL(k_film_fraction_quiet, gq, dim3(BS), 0, f->stream, f->g.nx, f->g.ny, f->L.buf[f->cur], C_dev,
+                     f->L.wk);
+  hipLaunchKernelGGL(k_film_fraction, dim3((nq + GW - 1) / GW), dim3(64), 0, f->stream, f->g.nx, f->g.ny,
+                     f->L.buf[f->cur], C_dev, f->L.wk, nq);
   return hipGetLastError() == hipSuccess ? EBIT_OK : EBIT_ERR_DEVICE;
 }
 
@@ -786,7 +1000,14 @@ int ebit_film_get_state(ebit_film *f, const ebit_film_out *out) {
                   hipMemcpy(out->vcount, B.vn, V, hipMemcpyDeviceToHost) == hipSuccess &&
                   hipMemcpy(out->hoff, B.ho, H * sizeof(double2), hipMemcpyDeviceToHost) == hipSuccess &&
                   hipMemcpy(out->voff, B.vo, V * sizeof(double2), hipMemcpyDeviceToHost) == hipSuccess;
-  return ok ? EBIT_OK : EBIT_ERR_DEVICE;
+  if (!ok) return EBIT_ERR_DEVICE;
+  // the device writes offset pairs only for edges that hold markers: the
+  // slots past each edge's count read as 0
+  for (size_t e = 0; e < H; e++)
+    for (int k = out->hcount[e]; k < 2; k++) out->hoff[2 * e + k] = 0.0;
+  for (size_t e = 0; e < V; e++)
+    for (int k = out->vcount[e]; k < 2; k++) out->voff[2 * e + k] = 0.0;
+  return EBIT_OK;
 }
 
 int ebit_film_set_state(ebit_film *f, const ebit_film_state *s, int64_t step) {
