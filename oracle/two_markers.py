@@ -2,9 +2,9 @@
 
 Sec. 2.4 allows one marker per cell edge, so two markers landing on one edge
 annihilate and a film thinner than a cell disappears; the paper names the
-remedy, more markers per edge (the end of Sec. 2.4 and the kinematic extension
-of Sec. 4: "two markers per edge ... thin strips of fluid"), without giving the
-algorithm. This module is the reading written out for small grids, in plain
+remedy, more markers per edge (the end of Sec. 2.4, and Sec. 4, where it is
+the kinematic extension proposed for thin layers of one fluid), without giving
+the algorithm. This module is the reading written out for small grids, in plain
 Python FP64 with the same expression orders as the one-marker oracle
 (oracle/ebit_oracle.c), which it reduces to exactly when films may not form
 (rupture gap delta = inf); only the tests import it.
