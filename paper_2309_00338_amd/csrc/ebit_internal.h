@@ -144,9 +144,20 @@ __host__ __device__ inline SweepView sweep_view(const Inst &I, uint32_t cur, int
 }
 
 // counts per compaction slot: active tiles of x-sweeping grids, of
-// y-sweeping grids, near tiles, fit jobs of the x and y sweeps
-constexpr int NSLOT = 8;
-enum { CNT_ACT_X = 0, CNT_ACT_Y = 1, CNT_NEAR = 2, CNT_JOBS_X = 3, CNT_JOBS_Y = 4, CNT_FRAC = 5 };
+// y-sweeping grids, near tiles, fit jobs of the x and y sweeps, tiles of the
+// fraction pass. Each count has a 256-byte line of its own: every compaction
+// workgroup and every sweep workgroup's job flush adds to them with returning
+// atomics, and atomics on one line are served one after the other.
+constexpr int CNT_LINE = 64;
+enum {
+  CNT_ACT_X = 0 * CNT_LINE,
+  CNT_ACT_Y = 1 * CNT_LINE,
+  CNT_NEAR = 2 * CNT_LINE,
+  CNT_JOBS_X = 3 * CNT_LINE,
+  CNT_JOBS_Y = 4 * CNT_LINE,
+  CNT_FRAC = 5 * CNT_LINE
+};
+constexpr int NSLOT = 6 * CNT_LINE;
 
 // Arguments of the kernels of one sweep direction (sweep, fit, centre). The
 // x direction reads the active list and the job list from the front, the y
