@@ -1046,7 +1046,7 @@ __device__ __forceinline__ NearTests nearTests(const uint16_t *__restrict__ has,
   return t;
 }
 
-constexpr int CPT = 4;  // tiles per thread in the compaction
+constexpr int CPT = 8;  // tiles per thread in the compaction
 
 // nearPrev bits: 0 near at the latest compaction, 1 near at the one before.
 // After a sweep the latest becomes the one before; a compaction without a
@@ -1085,26 +1085,31 @@ __device__ void compactBlock(const CompactArgs &C, uint32_t blk) {
     fracBits |= (uint32_t)nt.fr << q;
   };
   if (ONE) {
-    // one grid: every load of the thread's tiles first (indices clamped into
-    // the tile range), then the tests and stores
+    // one grid: every load of a group of the thread's tiles first (indices
+    // clamped into the tile range), then the tests and stores
     const Inst &I = C.one;
-    NearTests nt[CPT];
-    uint32_t pv[CPT];
-    int colour[CPT];
+    constexpr int CG = 4;
+    static_assert(CPT % CG == 0, "whole groups");
 #pragma unroll
-    for (int q = 0; q < CPT; q++) {
-      const uint32_t t = min(base + q, C.ntiles - 1u);
-      const uint32_t lt = t - I.tile0;
-      const int tx = (int)(lt % (uint32_t)I.ntx), ty = (int)(lt / (uint32_t)I.ntx);
-      nt[q] = nearTests(C.has + I.tile0, tx, ty, I.ntx, I.nty);
-      pv[q] = C.nearPrev[t];
-      colour[q] = colAt(gp(I.col[C.cur]), I.nx, tx * TS, ty * TS);
-    }
+    for (int q0 = 0; q0 < CPT; q0 += CG) {
+      NearTests nt[CG];
+      uint32_t pv[CG];
+      int colour[CG];
 #pragma unroll
-    for (int q = 0; q < CPT; q++) {
-      const uint32_t t = base + q;
-      kq[q] = 0;
-      if (t < C.ntiles) finish(q, t, I, nt[q], pv[q], colour[q]);
+      for (int k = 0; k < CG; k++) {
+        const uint32_t t = min(base + q0 + k, C.ntiles - 1u);
+        const uint32_t lt = t - I.tile0;
+        const int tx = (int)(lt % (uint32_t)I.ntx), ty = (int)(lt / (uint32_t)I.ntx);
+        nt[k] = nearTests(C.has + I.tile0, tx, ty, I.ntx, I.nty);
+        pv[k] = C.nearPrev[t];
+        colour[k] = colAt(gp(I.col[C.cur]), I.nx, tx * TS, ty * TS);
+      }
+#pragma unroll
+      for (int k = 0; k < CG; k++) {
+        const uint32_t t = base + q0 + k;
+        kq[q0 + k] = 0;
+        if (t < C.ntiles) finish(q0 + k, t, I, nt[k], pv[k], colour[k]);
+      }
     }
   } else {
     for (int q = 0; q < CPT; q++) {
