@@ -133,7 +133,7 @@ struct Engine {
   uint2 *jobs = nullptr;
   unsigned long long *ctr = nullptr;
   GhfEntry *ghf = nullptr;      // cells left for the parabola fit, 4 entries per tile at most
-  uint32_t *ghfCnt = nullptr;   // entry counts of the two curvature-launch parities
+  uint32_t *ghfCnt = nullptr;   // entry counts of the two curvature-launch parities, a line each
   uint32_t ghfPar = 0;          // parity of the next curvature launch
   int ghfBlocks = 0;
   // the fraction pass's linear fill: (first chunk, grid) per live grid (several
@@ -275,7 +275,7 @@ void carve_engine(Engine *e, char *base, Carve &c) {
   e->jobs = c.take<uint2>(base, e->jobCap);
   e->ctr = c.take<unsigned long long>(base, (size_t)CTR_PARTS * CTR_STRIDE);
   e->ghf = c.take<GhfEntry>(base, 4 * (size_t)e->ntiles);
-  e->ghfCnt = c.take<uint32_t>(base, 2);
+  e->ghfCnt = c.take<uint32_t>(base, 2 * CNT_LINE);
   e->fillTab = c.take<uint2>(base, e->maxGrids);
 }
 
@@ -364,7 +364,7 @@ int engine_reset(Engine *e) {
   HIPCHK(hipMemsetAsync(e->counts, 0, 2 * NSLOT * sizeof(uint32_t), e->stream));
   HIPCHK(hipMemsetAsync(e->ctr, 0, CTR_PARTS * CTR_STRIDE * sizeof(unsigned long long), e->stream));
   HIPCHK(hipMemsetAsync(e->errs, 0, e->maxGrids * sizeof(uint32_t), e->stream));
-  HIPCHK(hipMemsetAsync(e->ghfCnt, 0, 2 * sizeof(uint32_t), e->stream));
+  HIPCHK(hipMemsetAsync(e->ghfCnt, 0, 2 * CNT_LINE * sizeof(uint32_t), e->stream));
   e->ghfPar = 0;
   HIPCHK(launch_clear_tiles(e->tileInst, e->has, e->nearPrev, e->tinfo, 0, e->ntiles, e->stream));
   e->slot = 1;
@@ -533,8 +533,8 @@ int engine_frac(Engine *e, int mode, const double *Cin, double *Cout, double *Ko
   // a curvature launch appends to its parity's count (zeroed by the launch
   // before it) and zeroes the other one for the launch after it
   a.ghf = e->ghf;
-  a.ghfCount = e->ghfCnt + e->ghfPar;
-  a.ghfClear = e->ghfCnt + (e->ghfPar ^ 1u);
+  a.ghfCount = e->ghfCnt + CNT_LINE * e->ghfPar;
+  a.ghfClear = e->ghfCnt + CNT_LINE * (e->ghfPar ^ 1u);
   a.fillTab = e->fillTab;
   a.fillGrids = e->fillGrids;
   a.one = e->hinst[0];
@@ -1426,7 +1426,7 @@ int ebit_step_static(const ebit_grid *grid, uint8_t *node_color_dev, uint8_t *ce
   HIPCHK(launch_fill_u32(e->counts, 0u, 2 * NSLOT, st));
   HIPCHK(launch_fill_u32((uint32_t *)e->ctr, 0u, 2 * (size_t)CTR_PARTS * CTR_STRIDE, st));
   HIPCHK(launch_fill_u32(e->errs, 0u, 1, st));
-  HIPCHK(launch_fill_u32(e->ghfCnt, 0u, 2, st));
+  HIPCHK(launch_fill_u32(e->ghfCnt, 0u, 2 * CNT_LINE, st));
   HIPCHK(launch_clear_tiles(e->tileInst, e->has, e->nearPrev, e->tinfo, 0, e->ntiles, st));
   HIPCHK(launch_put_inst(I, e->dinst, st));
   HIPCHK(launch_import_state(I, node_color_dev, cell_color_dev, hoff_dev, voff_dev, st));
