@@ -34,7 +34,8 @@
  * exception crosses this boundary. Argument errors are returned immediately.
  * Errors detected on the device (EBIT_ERR_CFL: some marker would move more
  * than half a cell in one sweep; EBIT_ERR_DOMAIN: a marker would leave the
- * grid) are latched and returned by the next ebit_sync, ebit_get_state or
+ * grid; EBIT_ERR_NOMEM: a fit-job queue outgrew its part of the workspace,
+ * which the sizing of ebit_workspace_bytes rules out) are latched and returned by the next ebit_sync, ebit_get_state or
  * ebit_stats call; the state is then undefined until ebit_set_state.
  *
  * Ownership. The caller owns every device buffer (workspace, u, v, C, K) and
@@ -137,7 +138,9 @@ int ebit_get_schedule(const ebit_handle *h, ebit_schedule *out);
 int ebit_set_schedule(ebit_handle *h, const ebit_schedule *s);
 
 /* Bytes of device workspace a grid needs (both state buffers, tile tables,
- * lists, counters, sweep scratch). Returns EBIT_ERR_ARG for an invalid grid. */
+ * lists, counters, sweep scratch). Returns EBIT_ERR_ARG for an invalid grid,
+ * or one whose fit-job list would pass 32-bit indices (above about
+ * 46000 x 46000 cells). */
 int ebit_workspace_bytes(const ebit_grid *grid, size_t *bytes);
 
 /* Validate the host state `init`, upload it into the caller's device

@@ -51,7 +51,10 @@ constexpr int CTR_PARTS = 64;
 constexpr int CTR_STRIDE = 32;
 static_assert(NCOUNTERS <= CTR_STRIDE, "counters fit one partition");
 
-enum : uint32_t { ERRBIT_CFL = 1u, ERRBIT_DOMAIN = 2u, ERRBIT_ARG = 4u };  // ARG: an invalid imported state
+// ARG: an invalid imported state; CAP: a fit-job queue ran past its region
+// (the per-tile bound on queued jobs rules it out; reported as a workspace
+// too small)
+enum : uint32_t { ERRBIT_CFL = 1u, ERRBIT_DOMAIN = 2u, ERRBIT_ARG = 4u, ERRBIT_CAP = 8u };
 enum : uint32_t { INST_XY = 1u, INST_LINE = 2u };  // x then y every step; straight-line placement
 
 // tile info bits written by the compaction, read by the fraction pass and
@@ -143,21 +146,31 @@ __host__ __device__ inline SweepView sweep_view(const Inst &I, uint32_t cur, int
   return w;
 }
 
+// Fit-job queues of one sweep direction. One grid whose sweep launch is a
+// multiple of 8 workgroups splits its active list into 8 shares, one per XCD
+// (workgroups are dispatched round-robin over the XCDs), and the workgroups of
+// share q queue their jobs on queue q, in region q of the job list; any other
+// engine uses one queue. A tile queues at most TS * TS jobs per sweep (one per
+// interior line it owns and row), so a region of TS * TS * ceil(tiles / 8)
+// entries holds any share's jobs.
+constexpr uint32_t NJQ = 8;
+
 // counts per compaction slot: active tiles of x-sweeping grids, of
-// y-sweeping grids, near tiles, fit jobs of the x and y sweeps, tiles of the
-// fraction pass. Each count has a 256-byte line of its own: every compaction
-// workgroup and every sweep workgroup's job flush adds to them with returning
-// atomics, and atomics on one line are served one after the other.
+// y-sweeping grids, near tiles, tiles of the fraction pass, then the NJQ
+// job-queue counts of the x sweep and those of the y sweep. Each count has a
+// 256-byte line of its own: every compaction workgroup and every sweep
+// workgroup's job flush adds to them with returning atomics, and atomics on
+// one line are served one after the other.
 constexpr int CNT_LINE = 64;
 enum {
   CNT_ACT_X = 0 * CNT_LINE,
   CNT_ACT_Y = 1 * CNT_LINE,
   CNT_NEAR = 2 * CNT_LINE,
-  CNT_JOBS_X = 3 * CNT_LINE,
-  CNT_JOBS_Y = 4 * CNT_LINE,
-  CNT_FRAC = 5 * CNT_LINE
+  CNT_FRAC = 3 * CNT_LINE,
+  CNT_JOBS_X = 4 * CNT_LINE,
+  CNT_JOBS_Y = (4 + (int)NJQ) * CNT_LINE
 };
-constexpr int NSLOT = 6 * CNT_LINE;
+constexpr int NSLOT = (4 + 2 * (int)NJQ) * CNT_LINE;
 
 // Arguments of the kernels of one sweep direction (sweep, fit, centre). The
 // x direction reads the active list and the job list from the front, the y
@@ -175,7 +188,9 @@ struct SweepArgs {
   uint16_t *has;             // per tile: where its markers sit
   uint2 *jobs;               // fit jobs: (grid, unaligned-edge index)
   uint32_t jobCap;           // length of the job list
-  uint32_t *njobs;           // fit jobs of this direction
+  uint32_t *njobs;           // job counts of this direction's queues, CNT_LINE apart
+  uint32_t jobQ;             // queues in use (1 or NJQ), the same for both directions
+  uint32_t jobRegion;        // entries of each queue's region
   uint32_t minChunk;         // several grids: tiles per sweep workgroup, at least
   unsigned long long *ctr;
   // one grid: the centre rules of the step's first sweep, when they are left

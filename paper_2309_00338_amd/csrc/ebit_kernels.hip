@@ -475,6 +475,34 @@ struct Counts {
   }
 };
 
+// The fit jobs of one sweep direction, numbered 0 .. total()-1 across its
+// queues: job w of queue q is entry q * region + (w - beg[q]), counted from
+// the direction's end of the list. The queue counts are uniform, so the
+// lookup is a few compares per lane.
+static_assert(NJQ == NXCD, "one job queue per XCD share");
+struct JobIndex {
+  uint32_t beg[NJQ + 1];
+  uint32_t region;
+  __device__ JobIndex(const uint32_t *counts, uint32_t nq, uint32_t reg) : region(reg) {
+    beg[0] = 0;
+#pragma unroll
+    for (uint32_t q = 0; q < NJQ; q++) beg[q + 1] = beg[q] + (q < nq ? counts[CNT_LINE * q] : 0u);
+  }
+  __device__ uint32_t total() const { return beg[NJQ]; }
+  __device__ uint32_t entry(uint32_t w) const {
+    // the last queue starting at or before w holds it (empty queues in
+    // between start where the next one does)
+    uint32_t base = 0, off = 0;
+#pragma unroll
+    for (uint32_t q = 1; q < NJQ; q++)
+      if (w >= beg[q]) {
+        base = q * region;
+        off = beg[q];
+      }
+    return base + (w - off);
+  }
+};
+
 // New unaligned marker on interior line a, row b (present by the new
 // colours): its offset, and the centre-CV results for the cell right of the
 // line (cell a) and left of it (cell a-1): -1 or the new centre colour.
@@ -634,12 +662,20 @@ __global__ __launch_bounds__(SWEEP_BS, 8) void k_sweep(SweepArgs A, const Inst *
   if (tid == 0) sNJob = 0;
   if (tid < NH) sRow[tid] = 0;
   const Counts cnt{sCnt};
-  // the queued jobs go to the fit kernel's list with one reservation
+  // the queued jobs go to this workgroup's queue of the fit kernel's list
+  // with one reservation (entries past the queue's region, which the per-tile
+  // bound rules out, are dropped and flagged)
+  uint32_t jq = 0;
   auto flushJobs = [&]() {
     const uint32_t n = sNJob;
-    if (tid == 0) sJobBase = atomicAdd(A.njobs, n);
+    if (tid == 0) sJobBase = atomicAdd(A.njobs + CNT_LINE * jq, n);
     __syncthreads();
-    for (uint32_t w = tid; w < n; w += blockDim.x) A.jobs[DIR == 0 ? sJobBase + w : A.jobCap - 1u - (sJobBase + w)] = sJob[w];
+    for (uint32_t w = tid; w < n; w += blockDim.x) {
+      const uint32_t k = sJobBase + w;
+      const uint32_t e = jq * A.jobRegion + k;
+      if (k < A.jobRegion) A.jobs[DIR == 0 ? e : A.jobCap - 1u - e] = sJob[w];
+      else atomicOr(ONE ? A.one.err : inst[sJob[w].x].err, ERRBIT_CAP);
+    }
     __syncthreads();
     if (tid == 0) sNJob = 0;
   };
@@ -688,6 +724,9 @@ __global__ __launch_bounds__(SWEEP_BS, 8) void k_sweep(SweepArgs A, const Inst *
     itBeg = x * share + blockIdx.x / NXCD;
     itEnd = min(ntile, (x + 1u) * share);
     itStep = per;
+    // the share's fit jobs go to queue x: returning atomics on one count
+    // serialise, and thousands of workgroups flush near the sweep's end
+    if (A.jobQ == NJQ) jq = x;
   } else if (ONE) {
     itBeg = blockIdx.x;
     itEnd = ntile;
@@ -716,9 +755,11 @@ __global__ __launch_bounds__(SWEEP_BS, 8) void k_sweep(SweepArgs A, const Inst *
     // the centre rules of the step's first sweep (the other direction, whose
     // jobs sit at the other end of the list), while the first tile's colours
     // are on their way
-    const uint32_t nj = *A.pendJobs;
-    for (uint32_t w = blockIdx.x * blockDim.x + tid; w < nj; w += gridDim.x * blockDim.x)
-      centreJob<1 - DIR>(A.pend, A.jobs[DIR == 1 ? w : A.jobCap - 1u - w].y, cnt);
+    const JobIndex J(A.pendJobs, A.jobQ, A.jobRegion);
+    for (uint32_t w = blockIdx.x * blockDim.x + tid; w < J.total(); w += gridDim.x * blockDim.x) {
+      const uint32_t e = J.entry(w);
+      centreJob<1 - DIR>(A.pend, A.jobs[DIR == 1 ? e : A.jobCap - 1u - e].y, cnt);
+    }
   }
 
   for (uint32_t it = itBeg; it < itEnd; it += itStep) {
@@ -1067,8 +1108,10 @@ __device__ void compactBlock(const CompactArgs &C, uint32_t blk) {
     other[CNT_ACT_Y] = 0;
     other[CNT_NEAR] = 0;
     other[CNT_FRAC] = 0;
-    mine[CNT_JOBS_X] = 0;
-    mine[CNT_JOBS_Y] = 0;
+    for (uint32_t q = 0; q < NJQ; q++) {
+      mine[CNT_JOBS_X + CNT_LINE * q] = 0;
+      mine[CNT_JOBS_Y + CNT_LINE * q] = 0;
+    }
   }
   const uint32_t base = (blk * blockDim.x + tid) * CPT;
   uint32_t actBits = 0, dirBits = 0, nearBits = 0, fracBits = 0;
@@ -1183,12 +1226,13 @@ __global__ __launch_bounds__(256) void k_fit(SweepArgs A, const Inst *__restrict
   if (tid < NCOUNTERS) sCnt[tid] = 0;
   __syncthreads();
   const Counts cnt{sCnt};
-  const uint32_t nj = *A.njobs;
+  const JobIndex J(A.njobs, A.jobQ, A.jobRegion);
+  const uint32_t nj = J.total();
   const uint32_t fb = blockIdx.x - compactBlocks;
   const uint32_t stride = (gridDim.x - compactBlocks) * blockDim.x;
   for (uint32_t w0 = fb * blockDim.x; w0 < nj; w0 += stride) {
-    const uint32_t w = w0 + tid;
-    const uint2 jb = w < nj ? A.jobs[DIR == 0 ? w : A.jobCap - 1u - w] : make_uint2(NO_INST, 0u);
+    const uint32_t w = w0 + tid, e = J.entry(w);
+    const uint2 jb = w < nj ? A.jobs[DIR == 0 ? e : A.jobCap - 1u - e] : make_uint2(NO_INST, 0u);
     if (ONE) {
       if (w < nj) fitJob<DIR>(A.one, jb.y, cnt);
     } else {
@@ -1248,11 +1292,12 @@ __global__ __launch_bounds__(256) void k_centre(SweepArgs A, const Inst *__restr
   if (tid < NCOUNTERS) sCnt[tid] = 0;
   __syncthreads();
   const Counts cnt{sCnt};
-  const uint32_t nj = *A.njobs;
+  const JobIndex J(A.njobs, A.jobQ, A.jobRegion);
+  const uint32_t nj = J.total();
   const uint32_t stride = gridDim.x * blockDim.x;
   for (uint32_t w0 = blockIdx.x * blockDim.x; w0 < nj; w0 += stride) {
-    const uint32_t w = w0 + tid;
-    const uint2 jb = w < nj ? A.jobs[DIR == 0 ? w : A.jobCap - 1u - w] : make_uint2(NO_INST, 0u);
+    const uint32_t w = w0 + tid, e = J.entry(w);
+    const uint2 jb = w < nj ? A.jobs[DIR == 0 ? e : A.jobCap - 1u - e] : make_uint2(NO_INST, 0u);
     if (ONE) {
       if (w < nj) centreJob<DIR>(A.one, jb.y, cnt);
     } else {

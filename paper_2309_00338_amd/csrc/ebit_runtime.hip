@@ -60,20 +60,27 @@ bool grid_ok(const ebit_grid *g) {
 }
 
 uint32_t tiles_of(const ebit_grid &g) { return (uint32_t)(((g.nx + TS - 1) / TS) * ((g.ny + TS - 1) / TS)); }
+
+constexpr uint32_t MAX_POOL_TILES = (1u << 24) - 1u;  // keeps the job list within 32-bit indices
+constexpr uint32_t JOBS_PER_TILE = TS * TS;            // interior unaligned edges a tile owns, at most
+
+// Job-queue region of an engine of one grid: a share of its active list (at
+// most ceil(tiles / NJQ) tiles) queues at most JOBS_PER_TILE jobs per tile.
+size_t one_job_region(const ebit_grid &g) { return (size_t)JOBS_PER_TILE * ((tiles_of(g) + NJQ - 1) / NJQ); }
+
 // Fit-job list entries a grid needs. A sweep queues one job per new interior
 // unaligned marker: at most (nx-1)*ny for an x sweep, nx*(ny-1) for a y sweep.
 // With several grids each grid sweeps one direction per phase and its centre
 // rules run before the next phase, so one direction's bound suffices. An
 // engine of one grid leaves the first sweep's jobs in the list (read from the
 // other end) until the second sweep's launch has run their centre rules, so
-// both directions' jobs are alive at once and the list holds both bounds.
+// both directions' jobs are alive at once, and each direction queues them in
+// NJQ regions: the list holds 2 NJQ regions (at least both directions'
+// bounds, since a region covers TS * TS cells of every tile of a share).
 size_t jobs_of(const ebit_grid &g, bool both) {
   const size_t x = (size_t)(g.nx - 1) * g.ny, y = (size_t)g.nx * (g.ny - 1);
-  return both ? x + y : std::max(x, y);
+  return both ? 2 * NJQ * one_job_region(g) : std::max(x, y);
 }
-
-constexpr uint32_t MAX_POOL_TILES = (1u << 24) - 1u;  // keeps the job list within 32-bit indices
-constexpr uint32_t JOBS_PER_TILE = TS * TS;            // interior unaligned edges a tile owns, at most
 
 // Host records of an engine's grids. One grid is held inline, so that an
 // engine of one grid needs no heap memory (the entry point that allocates
@@ -451,6 +458,17 @@ int engine_sweep(Engine *e, int phase, const double *u, const double *v, const d
   a.has = e->has;
   a.jobs = e->jobs;
   a.jobCap = e->jobCap;
+  // one grid swept in 8 XCD shares: a queue per share; else one queue, of
+  // half the list (one grid: each direction's end) or all of it (several
+  // grids: the x- and y-sweeping grids' jobs together stay within it)
+  if (e->one) {
+    const uint32_t reg = (uint32_t)one_job_region(e->grids[0]);
+    a.jobQ = e->sweepBlocks % (int)NJQ == 0 ? NJQ : 1u;
+    a.jobRegion = a.jobQ == NJQ ? reg : NJQ * reg;
+  } else {
+    a.jobQ = 1;
+    a.jobRegion = e->jobCap;
+  }
   a.minChunk = e->used.sweep_min_chunk;
   a.ctr = e->ctr;
   a.pendJobs = nullptr;
@@ -583,6 +601,7 @@ int engine_ns(Engine *e, const double *C, const double *K, const ebit_fluid *f, 
 
 int status_of(uint32_t bits) {
   if (bits & ERRBIT_ARG) return EBIT_ERR_ARG;
+  if (bits & ERRBIT_CAP) return EBIT_ERR_NOMEM;
   if (bits & ERRBIT_CFL) return EBIT_ERR_CFL;
   if (bits & ERRBIT_DOMAIN) return EBIT_ERR_DOMAIN;
   return EBIT_OK;
@@ -793,7 +812,9 @@ extern "C" {
 // ---------------------------------------------------------------------------
 int ebit_workspace_bytes(const ebit_grid *grid, size_t *bytes) {
   if (!grid_ok(grid) || !bytes) return EBIT_ERR_ARG;
-  *bytes = engine_bytes(tiles_of(*grid), 1, (uint32_t)jobs_of(*grid, true)) + grid_bytes(*grid);
+  const size_t nj = jobs_of(*grid, true);
+  if (nj >= 0xffffffffull) return EBIT_ERR_ARG;  // job list past 32-bit indices
+  *bytes = engine_bytes(tiles_of(*grid), 1, (uint32_t)nj) + grid_bytes(*grid);
   return EBIT_OK;
 }
 
@@ -1394,7 +1415,7 @@ int ebit_step_static(const ebit_grid *grid, uint8_t *node_color_dev, uint8_t *ce
       !K_dev || !status_dev || !isfinite(dt) || step < 0)
     return EBIT_ERR_ARG;
   size_t need = 0;
-  ebit_workspace_bytes(grid, &need);
+  if (ebit_workspace_bytes(grid, &need) != EBIT_OK) return EBIT_ERR_ARG;
   if (need > (size_t)EBIT_STATIC_SCRATCH_BYTES) return EBIT_ERR_NOMEM;
   StaticSlot *S = nullptr;
   int rc = static_slot(&S);
