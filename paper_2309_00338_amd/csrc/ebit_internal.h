@@ -149,10 +149,11 @@ __host__ __device__ inline SweepView sweep_view(const Inst &I, uint32_t cur, int
 // Fit-job queues of one sweep direction. One grid whose sweep launch is a
 // multiple of 8 workgroups splits its active list into 8 shares, one per XCD
 // (workgroups are dispatched round-robin over the XCDs), and the workgroups of
-// share q queue their jobs on queue q, in region q of the job list; any other
-// engine uses one queue. A tile queues at most TS * TS jobs per sweep (one per
-// interior line it owns and row), so a region of TS * TS * ceil(tiles / 8)
-// entries holds any share's jobs.
+// share q queue their jobs on queue q, in region q of the job list. A tile
+// queues at most TS * TS jobs per sweep (one per interior line it owns and
+// row), so a region of TS * TS * ceil(tiles / 8) entries holds any share's
+// jobs. Several grids: workgroup b queues on queue b % 8, in regions whose
+// bound follows from the sweep's chunking (the runtime's multi_job_span).
 constexpr uint32_t NJQ = 8;
 
 // counts per compaction slot: active tiles of x-sweeping grids, of
@@ -187,10 +188,10 @@ struct SweepArgs {
   const uint32_t *count;     // active tiles of this direction
   uint16_t *has;             // per tile: where its markers sit
   uint2 *jobs;               // fit jobs: (grid, unaligned-edge index)
-  uint32_t jobCap;           // length of the job list
   uint32_t *njobs;           // job counts of this direction's queues, CNT_LINE apart
   uint32_t jobQ;             // queues in use (1 or NJQ), the same for both directions
   uint32_t jobRegion;        // entries of each queue's region
+  uint32_t jobTop;           // the y direction's entry e is list slot jobTop - 1 - e
   uint32_t minChunk;         // several grids: tiles per sweep workgroup, at least
   unsigned long long *ctr;
   // one grid: the centre rules of the step's first sweep, when they are left

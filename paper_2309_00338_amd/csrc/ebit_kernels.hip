@@ -673,7 +673,7 @@ __global__ __launch_bounds__(SWEEP_BS, 8) void k_sweep(SweepArgs A, const Inst *
     for (uint32_t w = tid; w < n; w += blockDim.x) {
       const uint32_t k = sJobBase + w;
       const uint32_t e = jq * A.jobRegion + k;
-      if (k < A.jobRegion) A.jobs[DIR == 0 ? e : A.jobCap - 1u - e] = sJob[w];
+      if (k < A.jobRegion) A.jobs[DIR == 0 ? e : A.jobTop - 1u - e] = sJob[w];
       else atomicOr(ONE ? A.one.err : inst[sJob[w].x].err, ERRBIT_CAP);
     }
     __syncthreads();
@@ -739,6 +739,8 @@ __global__ __launch_bounds__(SWEEP_BS, 8) void k_sweep(SweepArgs A, const Inst *
     itBeg = min(ntile, blockIdx.x * chunk);
     itEnd = min(ntile, itBeg + chunk);
     itStep = 1;
+    // queue b % 8: its workgroups' chunks make at most a share plus a chunk
+    if (A.jobQ == NJQ) jq = blockIdx.x % NJQ;
   }
   if (tid < NTILES_LDS && itBeg + tid * itStep < itEnd) sTiles[tid] = entry(itBeg + tid * itStep);
   __syncthreads();
@@ -758,7 +760,7 @@ __global__ __launch_bounds__(SWEEP_BS, 8) void k_sweep(SweepArgs A, const Inst *
     const JobIndex J(A.pendJobs, A.jobQ, A.jobRegion);
     for (uint32_t w = blockIdx.x * blockDim.x + tid; w < J.total(); w += gridDim.x * blockDim.x) {
       const uint32_t e = J.entry(w);
-      centreJob<1 - DIR>(A.pend, A.jobs[DIR == 1 ? e : A.jobCap - 1u - e].y, cnt);
+      centreJob<1 - DIR>(A.pend, A.jobs[DIR == 1 ? e : A.jobTop - 1u - e].y, cnt);
     }
   }
 
@@ -1232,7 +1234,7 @@ __global__ __launch_bounds__(256) void k_fit(SweepArgs A, const Inst *__restrict
   const uint32_t stride = (gridDim.x - compactBlocks) * blockDim.x;
   for (uint32_t w0 = fb * blockDim.x; w0 < nj; w0 += stride) {
     const uint32_t w = w0 + tid, e = J.entry(w);
-    const uint2 jb = w < nj ? A.jobs[DIR == 0 ? e : A.jobCap - 1u - e] : make_uint2(NO_INST, 0u);
+    const uint2 jb = w < nj ? A.jobs[DIR == 0 ? e : A.jobTop - 1u - e] : make_uint2(NO_INST, 0u);
     if (ONE) {
       if (w < nj) fitJob<DIR>(A.one, jb.y, cnt);
     } else {
@@ -1297,7 +1299,7 @@ __global__ __launch_bounds__(256) void k_centre(SweepArgs A, const Inst *__restr
   const uint32_t stride = gridDim.x * blockDim.x;
   for (uint32_t w0 = blockIdx.x * blockDim.x; w0 < nj; w0 += stride) {
     const uint32_t w = w0 + tid, e = J.entry(w);
-    const uint2 jb = w < nj ? A.jobs[DIR == 0 ? e : A.jobCap - 1u - e] : make_uint2(NO_INST, 0u);
+    const uint2 jb = w < nj ? A.jobs[DIR == 0 ? e : A.jobTop - 1u - e] : make_uint2(NO_INST, 0u);
     if (ONE) {
       if (w < nj) centreJob<DIR>(A.one, jb.y, cnt);
     } else {

@@ -82,6 +82,30 @@ size_t jobs_of(const ebit_grid &g, bool both) {
   return both ? 2 * NJQ * one_job_region(g) : std::max(x, y);
 }
 
+// Job-queue span of an engine of several grids. A sweep launch hands
+// workgroup b a contiguous chunk of c = max(ceil(n / G), m) of its n active
+// tiles (G workgroups, m the minimum chunk) and b queues on queue b % NJQ, so
+// queue q takes at most c ceil(ceil(n / c) / NJQ) < n / NJQ + c tiles, and at
+// most n. The x- and y-sweep launches of a phase share the list from both
+// ends (n_x + n_y <= N tiles), queue q of the one and NJQ-1-q of the other in
+// span q, which therefore holds JOBS_PER_TILE min(N, ceil(N / NJQ) + 1 + 2 c)
+// entries, c taken at N.
+size_t multi_job_span(uint32_t N, uint32_t G, uint32_t m) {
+  const size_t c = std::max<size_t>((N + (size_t)G - 1) / std::max<uint32_t>(G, 1u), std::max<uint32_t>(m, 1u));
+  return (size_t)JOBS_PER_TILE * std::min<size_t>(N, (N + NJQ - 1) / NJQ + 1 + 2 * c);
+}
+// the list of several grids (or a pool's N tiles) is sized for NJQ spans at
+// the default schedule on a GPU of at least this many sweep workgroups; a
+// smaller launch, or a larger minimum chunk, falls back to one queue
+constexpr uint32_t REF_SWEEP_BLOCKS = 2048;
+constexpr uint32_t REF_MIN_CHUNK = 8;
+// entries for N tiles whose one-queue bound is `single`: the larger of the
+// two, unless the spans would pass 32-bit indices
+size_t multi_job_cap(uint32_t N, size_t single) {
+  const size_t q = NJQ * multi_job_span(N, REF_SWEEP_BLOCKS, REF_MIN_CHUNK);
+  return q < 0xffffffffull ? std::max(single, q) : single;
+}
+
 // Host records of an engine's grids. One grid is held inline, so that an
 // engine of one grid needs no heap memory (the entry point that allocates
 // nothing relies on it); more grids live on the heap.
@@ -457,17 +481,23 @@ int engine_sweep(Engine *e, int phase, const double *u, const double *v, const d
   a.list = e->actList;
   a.has = e->has;
   a.jobs = e->jobs;
-  a.jobCap = e->jobCap;
-  // one grid swept in 8 XCD shares: a queue per share; else one queue, of
-  // half the list (one grid: each direction's end) or all of it (several
-  // grids: the x- and y-sweeping grids' jobs together stay within it)
+  // one grid swept in 8 XCD shares: a queue per share, the y sweep's regions
+  // mirrored from the list's end; else one queue, of half the list. Several
+  // grids: a queue per workgroup residue b % NJQ in spans of the list, the
+  // y-sweeping grids' queues mirrored from the spans' end, when the spans fit
+  // the list; else one queue over all of it (the x- and y-sweeping grids'
+  // jobs together stay within it)
   if (e->one) {
     const uint32_t reg = (uint32_t)one_job_region(e->grids[0]);
     a.jobQ = e->sweepBlocks % (int)NJQ == 0 ? NJQ : 1u;
     a.jobRegion = a.jobQ == NJQ ? reg : NJQ * reg;
+    a.jobTop = e->jobCap;
   } else {
-    a.jobQ = 1;
-    a.jobRegion = e->jobCap;
+    const size_t span = multi_job_span(e->ntiles, (uint32_t)e->sweepBlocks, e->used.sweep_min_chunk);
+    const bool q = NJQ * span <= e->jobCap;
+    a.jobQ = q ? NJQ : 1u;
+    a.jobRegion = q ? (uint32_t)span : e->jobCap;
+    a.jobTop = q ? (uint32_t)(NJQ * span) : e->jobCap;
   }
   a.minChunk = e->used.sweep_min_chunk;
   a.ctr = e->ctr;
@@ -672,7 +702,9 @@ int batch_sizes(int n, const ebit_grid *grids, uint32_t *ntiles, uint32_t *jobCa
     nj += jobs_of(grids[k], n == 1);
     gb += grid_bytes(grids[k]);
   }
-  if (nt >= 0xffffffffull || nj >= 0xffffffffull) return EBIT_ERR_ARG;
+  if (nt >= 0xffffffffull) return EBIT_ERR_ARG;
+  if (n > 1) nj = multi_job_cap((uint32_t)nt, nj);
+  if (nj >= 0xffffffffull) return EBIT_ERR_ARG;
   *ntiles = (uint32_t)nt;
   *jobCap = (uint32_t)nj;
   *gridBytes = gb;
@@ -763,7 +795,7 @@ size_t pool_grid_bytes(const ebit_grid &g) {
   return grid_bytes(g) + align256(ny * (nx + 1) * 8) + align256((ny + 1) * nx * 8) + 2 * align256(nx * ny * 8) + 256;
 }
 size_t pool_table_bytes(int max_grids, uint32_t max_tiles) {
-  return engine_bytes(max_tiles, (uint32_t)max_grids, max_tiles * JOBS_PER_TILE) +
+  return engine_bytes(max_tiles, (uint32_t)max_grids, (uint32_t)multi_job_cap(max_tiles, (size_t)max_tiles * JOBS_PER_TILE)) +
          align256((size_t)max_grids * sizeof(double));
 }
 }  // namespace
@@ -1203,7 +1235,7 @@ int ebit_pool_create(int max_grids, uint32_t max_tiles, void *ws_dev, size_t ws_
   e->ntiles = max_tiles;
   e->maxGrids = (uint32_t)max_grids;
   e->one = false;
-  e->jobCap = max_tiles * JOBS_PER_TILE;
+  e->jobCap = (uint32_t)multi_job_cap(max_tiles, (size_t)max_tiles * JOBS_PER_TILE);
   e->stream = (hipStream_t)hip_stream;
   Carve c;
   carve_engine(e, (char *)ws_dev, c);
