@@ -645,7 +645,7 @@ def main():
         print(json.dumps({"calibrate_copy_bytes": nbytes, "copies": 5}), flush=True)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+        print(json.dumps({"error": "the benchmark drives one GPU (one process per GPU); --gpus must be 1",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
 
