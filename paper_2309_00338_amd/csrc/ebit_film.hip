@@ -42,6 +42,9 @@ namespace ebit_film_impl {
 
 constexpr uint32_t ERR_CFL = 1u, ERR_DOMAIN = 2u;
 enum { F_MARKERS = 0, F_ANNIH, F_ANNIH_UN, F_THREE, F_PARITY, F_NCTR };
+// counter partitions, a 256-byte line each (summed on the host)
+constexpr int F_PARTS = 64, F_STRIDE = 32;
+static_assert(F_NCTR <= F_STRIDE, "counters fit one partition");
 constexpr int BS = 256;
 
 __device__ __forceinline__ double lerp(double a, double b, double t) { return a + t * (b - a); }
@@ -167,7 +170,10 @@ __device__ __forceinline__ void rowRun(int r0, int rows, Need need, Quiet quiet,
 constexpr int KR = 8;  // rows per lane in the plain passes
 constexpr int KX = 4;  // rows per lane in the crossing pass (seven counts per row)
 
-// Workgroup sums of the counters, one atomic per counter and workgroup.
+// Workgroup sums of the counters, one atomic per counter and workgroup, into
+// partition (linear workgroup index) % F_PARTS: atomics on one line are
+// served one after another, and the thousands of workgroups of a pass end at
+// about the same time.
 __device__ void addCounters(unsigned long long *ctr, const uint32_t *v) {
   __shared__ uint32_t s[F_NCTR];
   if (threadIdx.x < F_NCTR) s[threadIdx.x] = 0;
@@ -175,7 +181,9 @@ __device__ void addCounters(unsigned long long *ctr, const uint32_t *v) {
   for (int k = 0; k < F_NCTR; k++)
     if (v[k]) atomicAdd(&s[k], v[k]);
   __syncthreads();
-  if (threadIdx.x < F_NCTR && s[threadIdx.x]) atomicAdd(&ctr[threadIdx.x], (unsigned long long)s[threadIdx.x]);
+  const uint32_t part = (blockIdx.x + blockIdx.y * gridDim.x) % (uint32_t)F_PARTS;
+  if (threadIdx.x < F_NCTR && s[threadIdx.x])
+    atomicAdd(&ctr[part * F_STRIDE + threadIdx.x], (unsigned long long)s[threadIdx.x]);
 }
 
 // ---------------------------------------------------------------------------
@@ -836,7 +844,7 @@ Layout carve(const ebit_grid &g, char *base) {
   L.kept = c.take<uint8_t>(2 * M);
   L.res = c.take<int8_t>(4 * M);
   L.err = c.take<uint32_t>(1);
-  L.ctr = c.take<unsigned long long>(F_NCTR);
+  L.ctr = c.take<unsigned long long>((size_t)F_PARTS * F_STRIDE);
   // a count per workgroup of the widest, tallest quiet launch, and a slot per
   // element of it
   const size_t side = (nx > ny ? nx : ny) + 1;
@@ -874,7 +882,7 @@ int upload(ebit_film *f, const ebit_film_state *s) {
             hipMemcpyAsync(B.ho, s->hoff, H * sizeof(double2), hipMemcpyHostToDevice, f->stream) == hipSuccess &&
             hipMemcpyAsync(B.vo, s->voff, V * sizeof(double2), hipMemcpyHostToDevice, f->stream) == hipSuccess &&
             hipMemsetAsync(f->L.err, 0, sizeof(uint32_t), f->stream) == hipSuccess &&
-            hipMemsetAsync(f->L.ctr, 0, F_NCTR * sizeof(unsigned long long), f->stream) == hipSuccess &&
+            hipMemsetAsync(f->L.ctr, 0, (size_t)F_PARTS * F_STRIDE * sizeof(unsigned long long), f->stream) == hipSuccess &&
             hipStreamSynchronize(f->stream) == hipSuccess;
   return ok ? EBIT_OK : EBIT_ERR_DEVICE;
 }
@@ -1023,8 +1031,10 @@ int ebit_film_stats(ebit_film *f, ebit_film_counters *out) {
   if (!f || !out) return EBIT_ERR_ARG;
   const int rc = latched(f);
   if (rc) return rc;
-  unsigned long long c[F_NCTR];
-  if (hipMemcpy(c, f->L.ctr, sizeof c, hipMemcpyDeviceToHost) != hipSuccess) return EBIT_ERR_DEVICE;
+  unsigned long long p[F_PARTS * F_STRIDE], c[F_NCTR] = {0, 0, 0, 0, 0};
+  if (hipMemcpy(p, f->L.ctr, sizeof p, hipMemcpyDeviceToHost) != hipSuccess) return EBIT_ERR_DEVICE;
+  for (int q = 0; q < F_PARTS; q++)
+    for (int k = 0; k < F_NCTR; k++) c[k] += p[q * F_STRIDE + k];
   out->markers = (int64_t)c[F_MARKERS];
   out->annihilated = (int64_t)c[F_ANNIH];
   out->annihilated_unaligned = (int64_t)c[F_ANNIH_UN];
