@@ -369,7 +369,7 @@ int ebit_pool_destroy(ebit_pool *p);
  * per GPU, EBIT_STATIC_SCRATCH_BYTES long, held from the library's first use
  * on that GPU until the process ends; nothing is allocated, neither by this
  * call nor by the library on its behalf. Grids whose ebit_workspace_bytes
- * exceed EBIT_STATIC_SCRATCH_BYTES (about 1060 x 1060 cells) are rejected
+ * exceed EBIT_STATIC_SCRATCH_BYTES (about 1056 x 1056 cells) are rejected
  * with EBIT_ERR_NOMEM before any device work.
  *
  * Asynchronous on hip_stream (NULL = default stream): the call returns after

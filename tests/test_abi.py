@@ -56,6 +56,14 @@ def test_workspace_bytes_and_argument_errors():
         ebit.workspace_bytes(64, 64, -1.0)
     with pytest.raises(ebit.EbitError):
         ebit.workspace_bytes(64, 64, 1 / 64, flags=8)
+    # the fit-job list of one grid (2 directions x 8 queue regions of 256
+    # entries per tile of a share) must stay within 32-bit indices: about
+    # 46000^2 cells; beyond, the grid is refused rather than sized modulo 2^32
+    big = ebit.workspace_bytes(46000, 46000, 1 / 46000)
+    assert big > 8 * 2 * 46000 * 46001 * 2
+    with pytest.raises(ebit.EbitError) as e:
+        ebit.workspace_bytes(46400, 46400, 1 / 46400)
+    assert e.value.code == ebit.EBIT_ERR_ARG
     lib = ebit.lib()
     # create with a null workspace or null state fails before any device call
     g = ebit.ebit_grid(16, 16, 1 / 16, 0)
