@@ -354,3 +354,50 @@ def test_pool_isolates_failing_requests():
             Ko, _ = oracle.curvature(r.o, Co)
             compare_fields(C, K, Co, Ko, r.o.nx, r.o.h, f"step {k} slot {s}")
     torch.cuda.synchronize()
+
+
+def _psi_faces(st):
+    x = np.arange(st.nx + 1) / st.nx
+    y = np.arange(st.ny + 1) / st.ny
+    psi = (np.sin(np.pi * x)[None, :] ** 2) * (np.sin(np.pi * y)[:, None] ** 2) / np.pi
+    psi[0, :] = psi[-1, :] = 0.0
+    psi[:, 0] = psi[:, -1] = 0.0
+    return I.faces_from_psi(psi, st.h)
+
+
+def test_batch_of_checkerboards_fills_the_job_queues():
+    """Alternating node colours in every grid of a batch: every interior edge
+    queues a fit job each sweep, the most a tile can queue. With several grids
+    the sweep's workgroups queue on 8 queues whose regions are bounded from the
+    sweep's chunking; none may overflow (an overflow latches EBIT_ERR_NOMEM),
+    and every grid matches its oracle run step by step."""
+    import torch
+
+    inst = []
+    for k, (nx, ny) in enumerate(((64, 64), (48, 40), (33, 20), (80, 16))):
+        st = I.checkerboard(nx, ny, seed=21 + k)
+        u, v = _psi_faces(st)
+        dt = 0.2 * st.h / max(np.abs(u).max(), np.abs(v).max())
+        inst.append((st, u, v, [dt] * 4))
+    b = ebit.EbitBatch([s for s, _, _, _ in inst])
+    U, V = b.pack_velocities([u for _, u, _, _ in inst], [v for _, _, v, _ in inst])
+    dts = torch.tensor([[d[k] for _, _, _, d in inst] for k in range(4)], dtype=torch.float64, device="cuda:0")
+    C, K = b.new_fields()
+    orc = [s.copy() for s, _, _, _ in inst]
+    ocnt = oracle.new_counters()
+    for k in range(4):
+        b.advect(U, V, dts[k])
+        for g, (st, u, v, d) in enumerate(inst):
+            assert oracle.step(orc[g], u, v, d[k], counters=ocnt)[0] == oracle.OK
+        b.fraction_curvature(C, K)
+        torch.cuda.synchronize()
+        for g in range(len(inst)):
+            compare_state(b.get_state(g), orc[g], f"grid {g} step {k}")
+            Co = oracle.fraction(orc[g])
+            Ko, _ = oracle.curvature(orc[g], Co, counters=ocnt)
+            compare_fields(b.field(C, g).cpu().numpy(), b.field(K, g).cpu().numpy(), Co, Ko, orc[g].nx, orc[g].h,
+                           f"grid {g} step {k}")
+    assert b.sync() == [0] * len(inst)
+    gc = {k: v for k, v in b.stats().items() if k not in ebit.SCHEDULE_COUNTERS}
+    assert gc == oracle.counters_dict(ocnt)
+    assert gc["cv_set"] > 1000, gc
