@@ -1569,8 +1569,9 @@ static_assert(FILL_CHUNK % FRAC_BS == 0, "whole rounds per fill thread");
 constexpr uint32_t FILL_TI_LDS = 2048;  // tile-info bytes a fill workgroup stages
 constexpr int NS_FILL_TILES = 16;
 
-// The uniform cells' C and kappa: a linear pass over each grid's arrays,
-// FILL_CHUNK consecutive elements per workgroup (16 per thread, 256 apart),
+// The uniform cells' C and kappa of several grids packed back to back: a
+// linear pass over each grid's arrays, FILL_CHUNK consecutive elements per
+// workgroup (16 per thread, 256 apart),
 // so that each wavefront store covers whole 128-byte lines whatever the row
 // length and however the grids are packed. Element (x, y) belongs to tile
 // (x / 16, y / 16); elements of tiles with a cut cell are left to the near
@@ -1620,6 +1621,55 @@ __device__ __forceinline__ void fracLinearFill(const FracArgs &A, const Inst &I,
   }
 }
 
+// One grid whose rows are not whole lines (nx not a multiple of 16, or an
+// output not line-aligned): the array seen with a virtual row pitch P = nx
+// rounded up to 16, which makes every virtual row start on a line boundary
+// (given a line-aligned base), and filled like the per-tile fill below: fill
+// workgroup f takes 256-element run f % nseg of virtual rows 16 (f / nseg) ..
+// + 15, a lane one virtual column. A lane's element e then steps by P per
+// virtual row, and its real (x, y) = divmod(e, nx) by one row and D = P - nx
+// columns (wrapping into the next row), so it needs no division past the
+// first; each wavefront store covers whole lines. The fill shares the CUs
+// with the near tiles, so its work per store is what counts: the linear
+// fill's per-element division cost the 8190^2 fraction call ~20 us.
+template <int MODE>
+__device__ __forceinline__ void fracPitchFill(const FracArgs &A, const Inst &I, uint32_t f) {
+  const int nx = I.nx, ny = I.ny;
+  const size_t n = (size_t)nx * (size_t)ny;
+  const size_t P = ((size_t)nx + 15) & ~(size_t)15;
+  const uint32_t nseg = (uint32_t)((P + 255) / 256);
+  const size_t g = f / nseg;
+  const uint32_t vc = (f % nseg) * 256u + threadIdx.x;
+  if (vc >= P) return;  // lanes past the last run's virtual row (no barrier follows)
+  size_t e = g * 16 * P + vc;
+  if (e >= n) return;
+  const int D = (int)(P - (size_t)nx);
+  int y = (int)(e / (size_t)nx), x = (int)(e - (size_t)y * (size_t)nx);
+  // every element's tile info first, then the stores
+  uint8_t ti[16];
+  size_t ee[16];
+#pragma unroll
+  for (int i = 0; i < 16; i++) {
+    ee[i] = e;
+    ti[i] = e < n ? A.tinfo[I.tile0 + (uint32_t)(y >> 4) * (uint32_t)I.ntx + (uint32_t)(x >> 4)] : (uint8_t)TI_FRAC;
+    e += P;
+    y += 1;
+    x += D;
+    if (x >= nx) {
+      x -= nx;
+      y += 1;
+    }
+  }
+  double *Cp = (MODE & 1) ? A.Cout + I.coff : nullptr;
+  double *Kp = (MODE & 2) ? A.Kout + I.koff : nullptr;
+#pragma unroll
+  for (int i = 0; i < 16; i++) {
+    if (ti[i] & TI_FRAC) continue;
+    if (MODE & 1) __builtin_nontemporal_store((ti[i] & TI_COLOUR) ? 1.0 : 0.0, &Cp[ee[i]]);
+    if (MODE & 2) __builtin_nontemporal_store(0.0, &Kp[ee[i]]);
+  }
+}
+
 // One grid whose 16-cell tile rows are whole 128-byte lines (nx a multiple of
 // 16, both outputs line-aligned): a fill workgroup takes 16 consecutive tiles
 // of a tile row, a lane a column, and stores 16 rows. Tiles of a row start at
@@ -1666,7 +1716,7 @@ __global__ __launch_bounds__(FRAC_BS, 8) void k_frac_curv(FracArgs A, const Inst
     if (ONE && wholeLineRows<MODE>(A, A.one)) {
       fracTileFill<MODE>(A, A.one, f);
     } else if (ONE) {
-      fracLinearFill<MODE>(A, A.one, f, sTi);
+      fracPitchFill<MODE>(A, A.one, f);
     } else {
       // the grid of chunk f: the last table entry starting at or before it
       uint32_t lo = 0, hi = A.fillGrids;

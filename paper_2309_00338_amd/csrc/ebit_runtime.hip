@@ -369,10 +369,14 @@ bool schedule_ok(const ebit_schedule *s) {
 // (pageable source), so rebuilding it later is safe.
 int engine_fill_table(Engine *e) {
   if (e->one) {
-    // the linear fill's chunks, or 16 tiles per workgroup when tile rows are
-    // whole lines (decided in the kernel from the output alignment)
+    // 16 tiles per workgroup when tile rows are whole lines, else 16 virtual
+    // rows of pitch nx rounded up to 16 by 256 columns (decided in the kernel
+    // from the output alignment)
+    const Inst &I0 = e->hinst[0];
+    const size_t P = ((size_t)I0.nx + 15) & ~(size_t)15;
+    const size_t vrows = ((size_t)I0.nx * (size_t)I0.ny + P - 1) / P;
     e->fillGrids = 1;
-    e->fillTotal = std::max(fill_chunks((size_t)e->hinst[0].nx * (size_t)e->hinst[0].ny), (e->ntiles + 15u) / 16u);
+    e->fillTotal = std::max((uint32_t)(((vrows + 15) / 16) * ((P + 255) / 256)), (e->ntiles + 15u) / 16u);
     return EBIT_OK;
   }
   e->fillHost.clear();
