@@ -240,10 +240,9 @@ struct FracArgs {
   GhfEntry *ghf;             // cells left for the parabola fit (4 entries per tile at most)
   uint32_t *ghfCount;        // entries of this launch (zero on entry)
   uint32_t *ghfClear;        // the other launch parity's count, zeroed by this launch
-  // the uniform cells' fill, a linear pass over each grid's C and kappa in
-  // chunks of FILL_CHUNK elements: entry k of fillTab is (first chunk, grid)
-  // of the k-th grid with cells (ascending first chunks); fillGrids entries
-  // (one grid: no table)
+  // the uniform cells' fill, pitch_chunks workgroups per grid: entry k of
+  // fillTab is (first fill workgroup, grid) of the k-th grid with cells
+  // (ascending first workgroups); fillGrids entries (one grid: no table)
   const uint2 *fillTab;
   uint32_t fillGrids;
   Inst one;                  // the descriptor itself when the engine holds one grid
@@ -289,9 +288,15 @@ hipError_t launch_clear_tiles(uint32_t *tileInst, uint16_t *has, uint8_t *nearPr
                               uint32_t ntiles, hipStream_t s);
 hipError_t launch_compact(bool one, const CompactArgs &a, hipStream_t s);
 hipError_t launch_frac_curv(int mode, bool one, const FracArgs &a, int grid, hipStream_t s);
-// elements of C (and kappa) one fill workgroup writes
+// elements of C (and kappa) one per-tile fill workgroup writes (16 tiles)
 constexpr uint32_t FILL_CHUNK = 4096;
-inline uint32_t fill_chunks(size_t cells) { return (uint32_t)((cells + FILL_CHUNK - 1) / FILL_CHUNK); }
+// fill workgroups of one grid's uniform cells: 16 virtual rows of pitch nx
+// rounded up to 16 by 256 columns each (the pitched fill of k_frac_curv)
+inline uint32_t pitch_chunks(int nx, int ny) {
+  const size_t P = ((size_t)nx + 15) & ~(size_t)15;
+  const size_t vrows = ((size_t)nx * (size_t)ny + P - 1) / P;
+  return (uint32_t)(((vrows + 15) / 16) * ((P + 255) / 256));
+}
 int ns_fill_blocks(uint32_t ntiles);
 // workgroups of the linear uniform-part passes of k_ns for one nx x ny grid
 int ns_linear_blocks(int nx, int ny);

@@ -1565,64 +1565,11 @@ __device__ bool ghfFit(int nx, int ny, double h, int i, int j, int gx, int gy, G
 // along a grid row. MODE 1: C only; 2: kappa from the caller's C; 3: both.
 constexpr int FRAC_BS = 256;
 constexpr int NEAR_ENT = 16;  // tile entries a near workgroup keeps in LDS
-static_assert(FILL_CHUNK % FRAC_BS == 0, "whole rounds per fill thread");
-constexpr uint32_t FILL_TI_LDS = 2048;  // tile-info bytes a fill workgroup stages
 constexpr int NS_FILL_TILES = 16;
 
-// The uniform cells' C and kappa of several grids packed back to back: a
-// linear pass over each grid's arrays, FILL_CHUNK consecutive elements per
-// workgroup (16 per thread, 256 apart),
-// so that each wavefront store covers whole 128-byte lines whatever the row
-// length and however the grids are packed. Element (x, y) belongs to tile
-// (x / 16, y / 16); elements of tiles with a cut cell are left to the near
-// workgroups. The stores are streaming (non-temporal): the write stream of a
-// large grid then does not evict the marker data the next step's sweeps and
-// fits read. The owner tiles' info is loaded 16 at a time before the stores.
-template <int MODE>
-__device__ __forceinline__ void fracLinearFill(const FracArgs &A, const Inst &I, uint32_t chunk, uint8_t *sTi) {
-  constexpr int NE_T = (int)(FILL_CHUNK / FRAC_BS);
-  const int nx = I.nx, ny = I.ny;
-  const size_t n = (size_t)nx * (size_t)ny;
-  const size_t k0 = (size_t)chunk * FILL_CHUNK;
-  if (k0 >= n) return;  // workgroup-uniform: no barrier below is skipped by part of it
-  // the info bytes of the chunk's tile rows (one contiguous run of the tile
-  // table) in LDS, when they fit
-  const int yf = (int)(k0 / (size_t)nx), yl = (int)(min(n - 1, k0 + FILL_CHUNK - 1) / (size_t)nx);
-  const uint32_t t0 = I.tile0 + (uint32_t)(yf / TS) * (uint32_t)I.ntx;
-  const uint32_t nt = (uint32_t)(yl / TS - yf / TS + 1) * (uint32_t)I.ntx;
-  const bool staged = nt <= FILL_TI_LDS;
-  if (staged)
-    for (uint32_t t = threadIdx.x; t < nt; t += FRAC_BS) sTi[t] = A.tinfo[t0 + t];
-  __syncthreads();
-  size_t k = k0 + threadIdx.x;
-  int y = (int)(k / (size_t)nx), x = (int)(k - (size_t)y * (size_t)nx);
-  uint32_t tix[NE_T];
-#pragma unroll
-  for (int i = 0; i < NE_T; i++) {
-    tix[i] = (uint32_t)(min(y, ny - 1) / TS - yf / TS) * (uint32_t)I.ntx + (uint32_t)(x / TS);
-    x += FRAC_BS;
-    while (x >= nx) {
-      x -= nx;
-      y++;
-    }
-  }
-  uint8_t ti[NE_T];
-#pragma unroll
-  for (int i = 0; i < NE_T; i++)
-    ti[i] = k + (size_t)FRAC_BS * i < n ? (staged ? sTi[tix[i]] : A.tinfo[t0 + tix[i]]) : (uint8_t)TI_FRAC;
-  double *Cp = (MODE & 1) ? A.Cout + I.coff : nullptr;
-  double *Kp = (MODE & 2) ? A.Kout + I.koff : nullptr;
-#pragma unroll
-  for (int i = 0; i < NE_T; i++) {
-    if (ti[i] & TI_FRAC) continue;
-    const size_t e = k + (size_t)FRAC_BS * i;
-    if (MODE & 1) __builtin_nontemporal_store((ti[i] & TI_COLOUR) ? 1.0 : 0.0, &Cp[e]);
-    if (MODE & 2) __builtin_nontemporal_store(0.0, &Kp[e]);
-  }
-}
-
-// One grid whose rows are not whole lines (nx not a multiple of 16, or an
-// output not line-aligned): the array seen with a virtual row pitch P = nx
+// A grid whose rows are not whole lines (nx not a multiple of 16, or an
+// output not line-aligned), and every grid of several (each grid's arrays
+// start on a 256-byte boundary of the packed fields): the array seen with a virtual row pitch P = nx
 // rounded up to 16, which makes every virtual row start on a line boundary
 // (given a line-aligned base), and filled like the per-tile fill below: fill
 // workgroup f takes 256-element run f % nseg of virtual rows 16 (f / nseg) ..
@@ -1711,7 +1658,6 @@ __global__ __launch_bounds__(FRAC_BS, 8) void k_frac_curv(FracArgs A, const Inst
   const int tid = threadIdx.x;
   if ((int)blockIdx.x >= A.nearBlocks) {
     // --- uniform cells: linear fill -------------------------------------------
-    __shared__ uint8_t sTi[FILL_TI_LDS];
     uint32_t f = blockIdx.x - (uint32_t)A.nearBlocks;
     if (ONE && wholeLineRows<MODE>(A, A.one)) {
       fracTileFill<MODE>(A, A.one, f);
@@ -1726,7 +1672,7 @@ __global__ __launch_bounds__(FRAC_BS, 8) void k_frac_curv(FracArgs A, const Inst
         else hi = mid;
       }
       const uint2 t = A.fillTab[lo];
-      fracLinearFill<MODE>(A, inst[t.y], f - t.x, sTi);
+      fracPitchFill<MODE>(A, inst[t.y], f - t.x);
     }
     return;
   }

@@ -372,11 +372,8 @@ int engine_fill_table(Engine *e) {
     // 16 tiles per workgroup when tile rows are whole lines, else 16 virtual
     // rows of pitch nx rounded up to 16 by 256 columns (decided in the kernel
     // from the output alignment)
-    const Inst &I0 = e->hinst[0];
-    const size_t P = ((size_t)I0.nx + 15) & ~(size_t)15;
-    const size_t vrows = ((size_t)I0.nx * (size_t)I0.ny + P - 1) / P;
     e->fillGrids = 1;
-    e->fillTotal = std::max((uint32_t)(((vrows + 15) / 16) * ((P + 255) / 256)), (e->ntiles + 15u) / 16u);
+    e->fillTotal = std::max(pitch_chunks(e->hinst[0].nx, e->hinst[0].ny), (e->ntiles + 15u) / 16u);
     return EBIT_OK;
   }
   e->fillHost.clear();
@@ -384,7 +381,7 @@ int engine_fill_table(Engine *e) {
   for (uint32_t k = 0; k < e->maxGrids; k++) {
     if (!e->live[k]) continue;
     e->fillHost.push_back(make_uint2(total, k));
-    total += fill_chunks((size_t)e->hinst[k].nx * (size_t)e->hinst[k].ny);
+    total += pitch_chunks(e->hinst[k].nx, e->hinst[k].ny);
   }
   e->fillGrids = (uint32_t)e->fillHost.size();
   e->fillTotal = total;
