@@ -1574,9 +1574,10 @@ constexpr int NS_FILL_TILES = 16;
 // (given a line-aligned base), and filled like the per-tile fill below: fill
 // workgroup f takes 256-element run f % nseg of virtual rows 16 (f / nseg) ..
 // + 15, a lane one virtual column. A lane's element e then steps by P per
-// virtual row, and its real (x, y) = divmod(e, nx) by one row and D = P - nx
-// columns (wrapping into the next row), so it needs no division past the
-// first; each wavefront store covers whole lines. The fill shares the CUs
+// virtual row, and its real (x, y) = divmod(e, nx) by Q = P / nx rows and
+// R = P % nx columns, wrapping at most once into the next row (R < nx; Q is 1
+// for rows of 16 cells or more, and up to 4 for rows narrower than 8), so it
+// needs no division past the first; each wavefront store covers whole lines. The fill shares the CUs
 // with the near tiles, so its work per store is what counts: the linear
 // fill's per-element division cost the 8190^2 fraction call ~20 us.
 template <int MODE>
@@ -1590,7 +1591,7 @@ __device__ __forceinline__ void fracPitchFill(const FracArgs &A, const Inst &I, 
   if (vc >= P) return;  // lanes past the last run's virtual row (no barrier follows)
   size_t e = g * 16 * P + vc;
   if (e >= n) return;
-  const int D = (int)(P - (size_t)nx);
+  const int Q = (int)((uint32_t)P / (uint32_t)nx), R = (int)P - Q * nx;
   int y = (int)(e / (size_t)nx), x = (int)(e - (size_t)y * (size_t)nx);
   // every element's tile info first, then the stores
   uint8_t ti[16];
@@ -1600,8 +1601,8 @@ __device__ __forceinline__ void fracPitchFill(const FracArgs &A, const Inst &I, 
     ee[i] = e;
     ti[i] = e < n ? A.tinfo[I.tile0 + (uint32_t)(y >> 4) * (uint32_t)I.ntx + (uint32_t)(x >> 4)] : (uint8_t)TI_FRAC;
     e += P;
-    y += 1;
-    x += D;
+    y += Q;
+    x += R;
     if (x >= nx) {
       x -= nx;
       y += 1;

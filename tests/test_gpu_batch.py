@@ -401,3 +401,38 @@ def test_batch_of_checkerboards_fills_the_job_queues():
     gc = {k: v for k, v in b.stats().items() if k not in ebit.SCHEDULE_COUNTERS}
     assert gc == oracle.counters_dict(ocnt)
     assert gc["cv_set"] > 1000, gc
+
+
+def test_batch_with_narrow_grids():
+    """Grids narrower than 8 cells packed between ordinary ones: the uniform
+    fill's virtual rows of 16 elements span several rows of a narrow grid. The
+    outputs start as NaN so that a cell the fill skips shows too."""
+    import torch
+
+    grids = []
+    for nx in (5, 4, 7, 6):
+        grids.append(I.init_state(nx, 160, [I.Ellipse(nx / 2 + 0.07, 80.3, 9.0, 40.0, 0.0)], h=1.0 / 160))
+    grids.insert(2, I.init_state(37, 53, [I.Ellipse(18.3, 26.1, 11.0, 7.0, 0.4)], h=1.0 / 53))
+    faces = [I.uniform_faces(s.nx, s.ny, 0.0, 0.3) for s in grids]
+    b = ebit.EbitBatch(grids)
+    U, V = b.pack_velocities([u for u, _ in faces], [v for _, v in faces])
+    dt = [0.4 / s.ny for s in grids]
+    dts = torch.tensor(dt, dtype=torch.float64, device="cuda:0")
+    orc = [s.copy() for s in grids]
+    for k in range(4):
+        b.advect(U, V, dts)
+        for g, s in enumerate(orc):
+            rc, _ = oracle.step(s, faces[g][0], faces[g][1], dt[g])
+            assert rc == oracle.OK
+        C, K = b.new_fields()
+        C.fill_(float("nan"))
+        K.fill_(float("nan"))
+        b.fraction_curvature(C, K)
+        torch.cuda.synchronize()
+        for g, s in enumerate(orc):
+            compare_state(b.get_state(g), s, f"grid {g} step {k}")
+            Co = oracle.fraction(s)
+            Ko, _ = oracle.curvature(s, Co)
+            compare_fields(b.field(C, g).cpu().numpy(), b.field(K, g).cpu().numpy(), Co, Ko, s.nx, s.h,
+                           f"grid {g} step {k}")
+    assert b.sync() == [0] * len(grids)

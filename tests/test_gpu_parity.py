@@ -281,6 +281,34 @@ def test_wide_rows_fraction_and_curvature(nx, ny):
     _run(ls, [0.4 / nx] * 4)
 
 
+def _narrow_state(nx, ny=160):
+    """A grid narrower than 8 cells holding a band of colour 1 across its whole
+    width (an ellipse cut by both side walls): uniform tiles of colour 0 below
+    and above, of colour 1 inside, near tiles only at the band's two ends."""
+    return I.init_state(nx, ny, [I.Ellipse(nx / 2 + 0.07, 80.3, 9.0, 40.0, 0.0)], h=1.0 / ny)
+
+
+@pytest.mark.parametrize("nx", [4, 5, 6, 7])
+def test_narrow_grids_uniform_fill(nx):
+    """Rows narrower than 8 cells: one 16-element virtual row of the uniform
+    fill spans several grid rows (a lane's step wraps more than one row). The
+    outputs start as NaN so that a cell the fill skips shows too."""
+    import torch
+
+    st = _narrow_state(nx)
+    u, v = I.uniform_faces(nx, st.ny, 0.0, 0.3)
+    ls = Lockstep(st, u, v)
+    for k in range(4):
+        ls.step(0.4 / st.ny, check_state=True, check_fields=False, where=f"step {k}")
+        C = torch.full((st.ny, nx), float("nan"), dtype=torch.float64, device="cuda:0")
+        K = torch.full((st.ny, nx), float("nan"), dtype=torch.float64, device="cuda:0")
+        ls.g.fraction_curvature(C, K)
+        Co = oracle.fraction(ls.o)
+        Ko, _ = oracle.curvature(ls.o, Co)
+        assert (Co[:32] == 0).all() and (Co[48:112] == 1).all() and (Co[128:] == 0).all()
+        compare_fields(C.cpu().numpy(), K.cpu().numpy(), Co, Ko, nx, st.h, f"{nx}x{st.ny} step {k}")
+
+
 @pytest.mark.parametrize("case", ["vortex64", "circles512", "ragged37x53", "narrow5x40", "wide300x6",
                                   "wide1030x40", "wide1024x24", "wide2050x20"])
 def test_ns_fields_match_oracle(case):
