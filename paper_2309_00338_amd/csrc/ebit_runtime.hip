@@ -168,9 +168,16 @@ struct Engine {
   uint32_t ghfPar = 0;          // parity of the next curvature launch
   int ghfBlocks = 0;
   // the fraction pass's linear fill: (first chunk, grid) per live grid (several
-  // grids only), its host source and the chunk total
+  // grids only) and the chunk total. Its host source is a ring of slots, each
+  // rewritten only once the stream has passed that slot's last copy: a pool's
+  // steps do not wait on the stream, and a copy from pageable memory may read
+  // its source only when the stream reaches it.
   uint2 *fillTab = nullptr;
-  std::vector<uint2> fillHost;
+  static constexpr int FILL_RING = 4;
+  std::vector<uint2> fillHost[FILL_RING];
+  hipEvent_t fillDone[FILL_RING] = {};
+  bool fillQueued[FILL_RING] = {};
+  int fillNext = 0;
   uint32_t fillGrids = 0, fillTotal = 0;
   // host mirror
   GridRecords<Inst> hinst;
@@ -184,6 +191,13 @@ struct Engine {
   int pendDir = 0;
   SweepArgs pendArgs{};  // to launch them on their own when no second sweep follows
   int64_t epoch = 0, fracEpoch = -1;
+  Engine() = default;
+  Engine(const Engine &) = delete;
+  Engine &operator=(const Engine &) = delete;
+  ~Engine() {
+    for (hipEvent_t ev : fillDone)
+      if (ev) (void)hipEventDestroy(ev);
+  }
 };
 
 namespace {
@@ -376,18 +390,26 @@ int engine_fill_table(Engine *e) {
     e->fillTotal = std::max(pitch_chunks(e->hinst[0].nx, e->hinst[0].ny), (e->ntiles + 15u) / 16u);
     return EBIT_OK;
   }
-  e->fillHost.clear();
+  const int r = e->fillNext;
+  if (!e->fillDone[r]) HIPCHK(hipEventCreateWithFlags(&e->fillDone[r], hipEventDisableTiming));
+  if (e->fillQueued[r]) HIPCHK(hipEventSynchronize(e->fillDone[r]));
+  e->fillQueued[r] = false;
+  std::vector<uint2> &h = e->fillHost[r];
+  h.clear();
   uint32_t total = 0;
   for (uint32_t k = 0; k < e->maxGrids; k++) {
     if (!e->live[k]) continue;
-    e->fillHost.push_back(make_uint2(total, k));
+    h.push_back(make_uint2(total, k));
     total += pitch_chunks(e->hinst[k].nx, e->hinst[k].ny);
   }
-  e->fillGrids = (uint32_t)e->fillHost.size();
+  e->fillGrids = (uint32_t)h.size();
   e->fillTotal = total;
-  if (e->fillGrids)
-    HIPCHK(hipMemcpyAsync(e->fillTab, e->fillHost.data(), e->fillGrids * sizeof(uint2), hipMemcpyHostToDevice,
-                          e->stream));
+  if (e->fillGrids) {
+    HIPCHK(hipMemcpyAsync(e->fillTab, h.data(), e->fillGrids * sizeof(uint2), hipMemcpyHostToDevice, e->stream));
+    HIPCHK(hipEventRecord(e->fillDone[r], e->stream));
+    e->fillQueued[r] = true;
+    e->fillNext = (r + 1) % Engine::FILL_RING;
+  }
   return EBIT_OK;
 }
 
