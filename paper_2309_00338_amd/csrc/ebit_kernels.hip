@@ -483,10 +483,12 @@ static_assert(NJQ == NXCD, "one job queue per XCD share");
 struct JobIndex {
   uint32_t beg[NJQ + 1];
   uint32_t region;
+  // a count past its region (reservations whose entries were dropped, the
+  // grid's error latched) is read as the region: no job outside it is read
   __device__ JobIndex(const uint32_t *counts, uint32_t nq, uint32_t reg) : region(reg) {
     beg[0] = 0;
 #pragma unroll
-    for (uint32_t q = 0; q < NJQ; q++) beg[q + 1] = beg[q] + (q < nq ? counts[CNT_LINE * q] : 0u);
+    for (uint32_t q = 0; q < NJQ; q++) beg[q + 1] = beg[q] + (q < nq ? min(counts[CNT_LINE * q], reg) : 0u);
   }
   __device__ uint32_t total() const { return beg[NJQ]; }
   __device__ uint32_t entry(uint32_t w) const {

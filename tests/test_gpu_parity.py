@@ -310,7 +310,7 @@ def test_narrow_grids_uniform_fill(nx):
 
 
 @pytest.mark.parametrize("case", ["vortex64", "circles512", "ragged37x53", "narrow5x40", "wide300x6",
-                                  "wide1030x40", "wide1024x24", "wide2050x20"])
+                                  "wide1030x40", "wide1024x24", "wide2050x20", "band4x160", "band7x160"])
 def test_ns_fields_match_oracle(case):
     """rho, mu and the surface-tension face forces from the GPU C and kappa,
     against the oracle from the oracle's C and kappa, after a few steps."""
@@ -326,6 +326,11 @@ def test_ns_fields_match_oracle(case):
         st = I.init_state(37, 53, [I.Ellipse(18.3, 26.1, 11.0, 7.0, 0.4)], h=1.0 / 53)
         u, v = I.uniform_faces(37, 53, 0.3, -0.2)
         dts = [0.5 / 53] * 6
+    elif case.startswith("band"):
+        # uniform tiles of both colours in rows narrower than 8 cells
+        st = _narrow_state(int(case[4:].split("x")[0]))
+        u, v = I.uniform_faces(st.nx, st.ny, 0.0, 0.3)
+        dts = [0.4 / st.ny] * 4
     elif case.startswith("wide") and int(case[4:].split("x")[0]) >= 1024:
         # rows of at least one wavefront run of the uniform pass: runs inside
         # a row and runs across a row end (and a tile row), face rows nx + 1
