@@ -221,11 +221,12 @@ def test_colliding_circles_keep_pairs_where_they_meet():
     ls.counters()
 
 
-@pytest.mark.parametrize("nx,ny,seed,delta", [(32, 32, 34, 0.02), (37, 23, 42, 0.05), (24, 29, 32, 0.0)])
+@pytest.mark.parametrize("nx,ny,seed,delta", [(32, 32, 34, 0.02), (37, 23, 42, 0.05), (24, 29, 32, 0.0),
+                                               (5, 40, 1, 0.05), (40, 5, 1, 0.05)])
 def test_random_colouring_under_sheared_faces(nx, ny, seed, delta):
     """Random colourings under faces whose sign alternates between rows: films
     form and rupture, three-crossing edges occur, on square and ragged grids
-    (delta = 0 keeps every even landing)."""
+    and on grids narrower than a tile (delta = 0 keeps every even landing)."""
     from paper_2309_00338_amd.film import FilmState
 
     st = I.random_colouring(nx, ny, seed=seed)
