@@ -436,3 +436,16 @@ def test_batch_with_narrow_grids():
             compare_fields(b.field(C, g).cpu().numpy(), b.field(K, g).cpu().numpy(), Co, Ko, s.nx, s.h,
                            f"grid {g} step {k}")
     assert b.sync() == [0] * len(grids)
+    # the consumers' uniform part on the same grids (from the last C and kappa)
+    from tests.test_gpu_parity import _ns_compare
+
+    fl = (1000.0, 1.2, 1e-3, 1.8e-5, 0.07)
+    rho, mu, fx, fy = b.ns_fields(C, K, *fl)
+    for g, s in enumerate(orc):
+        nx, ny = s.nx, s.ny
+        Co = oracle.fraction(s)
+        Ko, _ = oracle.curvature(s, Co)
+        got = (b.field(rho, g), b.field(mu, g),
+               fx[b.u_off[g]:b.u_off[g] + ny * (nx + 1)].view(ny, nx + 1),
+               fy[b.v_off[g]:b.v_off[g] + (ny + 1) * nx].view(ny + 1, nx))
+        _ns_compare(got, oracle.ns_fields(s, Co, Ko, *fl), f"grid {g}", kappa=Ko, sigma=fl[4], h=s.h, n=max(nx, ny))
